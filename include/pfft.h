@@ -1,0 +1,151 @@
+/*
+ * pfft.h -- C ABI of the MI355X (gfx950) pre-corrected-FFT loop-analysis
+ * RL extractor.
+ *
+ * The library computes the magneto-quasi-static surface-integral-equation
+ * model of Zhu, Chen & Yang ("An SIE Formulation with Triangular
+ * Discretization and Loop Analysis for Parameter Extraction of Arbitrarily
+ * Shaped Interconnects"): modified RWG currents on a closed triangle mesh
+ * (Sec. II-C), the circuit graph and fundamental-loop basis (Sec. III), the
+ * preconditioned GMRES solve (Sec. IV-A) with the pFFT matrix-vector product
+ * (Sec. IV-B) and port R/L extraction (Sec. V).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units SI, time convention e^{j omega t}, mu = mu0 = 4 pi 1e-7 H/m.
+ * Complex numbers are interleaved (re, im) IEEE doubles ("complex128").
+ * Branch space: the b mesh edges, numbered in lexicographic order of
+ *   (lower vertex id, higher vertex id); T+ of an edge is its lower triangle
+ *   index; the coefficient is the current (A) from T+ to T- (Eq. RWG without
+ *   the edge length).
+ * Loop space: the l = b - n' + s + p fundamental loops (Eq. FinalME), one per
+ *   link, links numbered in branch order (mesh edges, then one zero-impedance
+ *   source branch per port, from the sink node to the source node).  Each
+ *   contact face (a port's source or sink triangle set) is one node whose id
+ *   is its lowest triangle index; the spanning tree is the breadth-first
+ *   forest rooted at each conductor's lowest node id, neighbours visited in
+ *   (neighbour id, branch id) order.
+ * Device buffers are caller-owned and must stay valid until the stream has
+ *   executed the call; host arrays are borrowed for the duration of the call.
+ * Every entry point returns a pfft_status; on failure pfft_last_error()
+ *   gives a thread-local message.  No exceptions cross the ABI.
+ * Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef PFFT_H
+#define PFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pfft_ctx pfft_ctx; /* opaque; owns every internal device buffer */
+
+typedef enum {
+  PFFT_OK = 0,
+  PFFT_EINVAL = -1,   /* bad argument (null pointer, size, option)             */
+  PFFT_ETOPO = -2,    /* non-manifold edge, degenerate triangle, overlapping
+                         contacts, port source/sink on different conductors   */
+  PFFT_ENOMEM = -3,   /* device or host allocation failed                      */
+  PFFT_EDEVICE = -4,  /* HIP runtime error                                     */
+  PFFT_ENOCONV = -5,  /* GMRES reached maxit before the tolerance              */
+  PFFT_EFACTOR = -6   /* zero pivot in the preconditioner factorization       */
+} pfft_status;
+
+/* Problem description (Sec. V: mesh, conductivity, ports, frequencies). */
+typedef struct {
+  int32_t nv;            /* vertices                                           */
+  const double *V;       /* [nv][3] coordinates in metres (host)               */
+  int32_t nt;            /* triangles                                          */
+  const int32_t *T;      /* [nt][3] vertex ids, counter-clockwise seen from
+                            outside (closed 2-manifold, host)                  */
+  int32_t nport;         /* ports p (>= 0)                                     */
+  const int32_t *src_off;/* [nport+1] CSR offsets into src_tri                 */
+  const int32_t *src_tri;/* source-face triangle ids of each port              */
+  const int32_t *snk_off;/* [nport+1] CSR offsets into snk_tri                 */
+  const int32_t *snk_tri;/* sink-face triangle ids of each port                */
+  double sigma;          /* conductivity (S/m), e.g. 5.8e7                     */
+  double mu_r;           /* relative permeability (1.0)                        */
+  int32_t grid[3];       /* pFFT grid nodes N_x, N_y, N_z (Sec. IV-B)          */
+  int32_t stencil;       /* stencil order O_s (only 4 is supported)            */
+  double near_kappa;     /* near-field radius in units of (O_s-1) max h (1.5)  */
+  int32_t grid_fp64;     /* 1: grid convolution in FP64, 0: FP32 complex       */
+  int32_t contact_zs;    /* 0: ideal contacts (Z_s = 0 on contact faces), 1: Z_s*/
+  int32_t max_rhs_chunk; /* right-hand sides per grid pass; 0 = automatic      */
+} pfft_problem;
+
+/* Build a context: topology, loop basis, Gram blocks, grid and projection
+ * weights, kernel spectrum, near-field pre-correction (Sec. II-IV).  Work that
+ * needs the GPU runs on hip_stream (a hipStream_t, may be NULL).  *out is
+ * owned by the caller and released with pfft_destroy. */
+pfft_status pfft_setup(const pfft_problem *pb, void *hip_stream, pfft_ctx **out);
+
+/* out[0..9] = n, n', b, l, s, p, nnz of the near-field matrix, N_g,
+ *             near triangle pairs, device bytes held by the context. */
+pfft_status pfft_sizes(const pfft_ctx *c, int64_t out[10]);
+
+/* Flags of pfft_matvec. */
+#define PFFT_FAR_ONLY   1  /* only the grid term I H B (no near field)          */
+#define PFFT_NEAR_ONLY  2  /* only the pre-corrected near field L_d              */
+#define PFFT_PRECOND    4  /* loop space: return P^-1 (Z_l x) (Eqs. Precond,
+                              LoopWithP)                                       */
+#define PFFT_PRECOND_ONLY 8 /* loop space: return P^-1 x                         */
+
+/* y = op(x) for nrhs right-hand sides (Eqs. CurT, Lb, VolT).
+ * space 0: branch space, y = K x with K the pFFT approximation of the
+ *          kernel matrix int int f_i . f_j / |r - r'| (no 1/(4 pi), no
+ *          j omega mu); x, y are complex128 [nrhs][b]; omega unused.
+ * space 1: loop space, y = Z_l(omega_r) x = A [Z_s(omega_r) G +
+ *          (j omega_r mu / 4 pi) K] A^T x for right-hand side r; x, y are
+ *          complex128 [nrhs][l]; omega is a host array [nrhs] (rad/s).
+ * x_dev, y_dev: device pointers (must not alias); launched on hip_stream. */
+pfft_status pfft_matvec(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t space,
+                        int32_t flags, const void *x_dev, void *y_dev, void *hip_stream);
+
+/* Solve A Z_b A^T I_l = V_l (Eq. FinalME) for every (frequency, port):
+ * V_l = 1 V on the port's source loop, other ports shorted (Sec. V), with
+ * right-preconditioned flexible GMRES (restart `restart`, x0 = 0, relative
+ * true-residual tolerance tol).  precond: 0 none, 1 the paper's P = A Z_b^N A^T
+ * (Eq. Precond), 2 P plus the learned correction loaded with
+ * pfft_precond_load (falls back to 1 when none is loaded or it misbehaves).
+ * Y_out: host complex128 [nfreq][nport][nport], Y[f][j][k] = I_l of port j's
+ * loop when port k is driven.  iters_out, relres_out: host [nfreq][nport]
+ * (may be NULL).  Returns PFFT_ENOCONV if some right-hand side missed tol
+ * (outputs still written). */
+pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol,
+                        int32_t maxit, int32_t restart, int32_t precond, void *Y_out,
+                        int32_t *iters_out, double *relres_out, void *hip_stream);
+
+/* Z = Y^-1, R = Re Z, L = Im Z / omega per frequency (Sec. V).  Y: host
+ * complex128 [nfreq][nport][nport]; R_out, L_out: host [nfreq][nport][nport].
+ * Pure host function; no context.  PFFT_EINVAL if some Y is singular. */
+pfft_status extract_RL(int32_t nfreq, int32_t nport, const double *freq_hz, const void *Y,
+                       double *R_out, double *L_out);
+
+/* Learned preconditioner correction: load bf16 weights (layout documented in
+ * pfft_mlp_layout) used by solve_ports(precond = 2). */
+pfft_status pfft_precond_load(pfft_ctx *c, const void *weights_bf16, int64_t nbytes);
+
+void pfft_destroy(pfft_ctx *c);
+const char *pfft_last_error(void);
+
+/* Host-only inspection of the setup (no device work): builds the topology,
+ * loop basis, Gram blocks, grid weights and near-field pre-correction of
+ * pfft_setup and copies named arrays out.  Names (element type): "sizes"
+ * (int64[10], as pfft_sizes), "links", "port_loop", "tplus", "tminus",
+ * "node_of_tri", "parent", "parent_branch", "pre", "sub", "anchor" (int32),
+ * "M0" [n][64], "M1" [n][64][3], "gram_val" [b][5], "near_val", "kdiag",
+ * "grid" (double[9]: N, h, x0), "gram_col" [b][5], "near_col" (int32),
+ * "near_rowptr" (int64[b+1]).  pfft_host_get writes *len_bytes always and
+ * copies when dst is non-null and cap_bytes is large enough. */
+typedef struct pfft_host_model pfft_host_model;
+pfft_status pfft_host_setup(const pfft_problem *pb, pfft_host_model **out);
+pfft_status pfft_host_get(const pfft_host_model *h, const char *name, void *dst, int64_t cap_bytes,
+                          int64_t *len_bytes);
+void pfft_host_free(pfft_host_model *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

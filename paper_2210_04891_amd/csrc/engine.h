@@ -1,0 +1,61 @@
+// Context of the C ABI: host model, device arrays, workspaces.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pfft.h"
+#include "kernels.h"
+#include "model.h"
+
+namespace pfft {
+
+struct DeviceError {
+  int code;
+  std::string msg;
+};
+
+void set_error(const std::string &msg);
+void hip_ok(hipError_t e, const char *what);
+
+struct Precond;   // nodal-route preconditioner factors (one per frequency)
+struct Learned;   // learned correction network
+
+}  // namespace pfft
+
+struct pfft_ctx {
+  pfft::HostModel m;
+  int grid_fp64 = 0;
+  double sigma = 5.8e7, mu_r = 1.0;
+  int max_chunk = 0;
+  int device = 0;
+  std::vector<void *> allocs;
+  size_t dev_bytes = 0;
+  pfft::LoopMaps lm{};
+  pfft::GridMaps gm{};
+  pfft::CombineMaps cm{};
+  // per-matvec workspace, sized for ws_R right-hand sides
+  int ws_R = 0;
+  std::vector<void *> ws_allocs;
+  double2 *ws_alpha = nullptr, *ws_scan = nullptr, *ws_part = nullptr, *ws_U = nullptr,
+          *ws_yb = nullptr, *ws_coef = nullptr;
+  void *ws_J = nullptr, *ws_Q = nullptr, *ws_T1 = nullptr, *ws_T2 = nullptr;
+  std::vector<double2> host_coef;
+  // solver state
+  pfft::Precond *pre = nullptr;
+  pfft::Learned *learned = nullptr;
+
+  void *dalloc(size_t bytes);
+  size_t per_rhs_bytes() const;
+  int chunk_for(int R) const;
+  void ensure_workspace(int R);
+  // y = op(x) for R right-hand sides already resident on the device
+  void matvec(int R, const double *omega, int space, int flags, const double2 *x, double2 *y,
+              hipStream_t st);
+};
+
+// P^-1 (Z_l x) or P^-1 x in loop space (defined with the solver)
+pfft_status pfft_internal_precond_matvec(pfft_ctx *c, int R, const double *omega, int flags,
+                                         const double2 *x, double2 *y, hipStream_t st);
+void pfft_ctx_free(pfft_ctx *c);

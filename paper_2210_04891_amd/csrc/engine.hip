@@ -1,0 +1,519 @@
+// C ABI: context setup, device upload, kernel spectrum, pFFT matvec.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+
+#include "engine.h"
+
+namespace pfft {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+void hip_ok(hipError_t e, const char *what) {
+  if (e != hipSuccess) {
+    int code = (e == hipErrorOutOfMemory) ? PFFT_ENOMEM : PFFT_EDEVICE;
+    throw DeviceError{code, std::string(what) + ": " + hipGetErrorString(e)};
+  }
+}
+
+static constexpr double MU0 = 4e-7 * M_PI;
+
+}  // namespace pfft
+
+using namespace pfft;
+
+void *pfft_ctx::dalloc(size_t bytes) {
+  void *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hip_ok(hipMalloc(&p, bytes), "hipMalloc");
+  allocs.push_back(p);
+  dev_bytes += bytes;
+  return p;
+}
+
+template <typename V>
+static V *upload(pfft_ctx *c, const std::vector<V> &h, hipStream_t st) {
+  V *d = (V *)c->dalloc(h.size() * sizeof(V));
+  if (!h.empty()) hip_ok(hipMemcpyAsync(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, st), "upload");
+  hip_ok(hipStreamSynchronize(st), "upload sync");
+  return d;
+}
+
+size_t pfft_ctx::per_rhs_bytes() const {
+  size_t vs = grid_fp64 ? sizeof(double2) : sizeof(float2);
+  size_t N = (size_t)m.dims[0] * m.dims[1] * m.dims[2];
+  return 16 * ((size_t)m.b * 2 + (m.nn + 1) + 4 * (size_t)m.n + 2) + vs * (4 * (size_t)m.n + 21 * N);
+}
+
+int pfft_ctx::chunk_for(int R) const {
+  int cap = max_chunk;
+  if (cap <= 0) {
+    size_t budget = (size_t)24 << 30;
+    cap = (int)std::max<size_t>(1, budget / per_rhs_bytes());
+  }
+  return std::max(1, std::min(R, cap));
+}
+
+void pfft_ctx::ensure_workspace(int R) {
+  if (R <= ws_R) return;
+  for (void *p : ws_allocs) hipFree(p);
+  ws_allocs.clear();
+  auto al = [&](size_t bytes) {
+    void *p = nullptr;
+    hip_ok(hipMalloc(&p, bytes ? bytes : 16), "hipMalloc workspace");
+    ws_allocs.push_back(p);
+    return p;
+  };
+  size_t vs = grid_fp64 ? sizeof(double2) : sizeof(float2);
+  size_t N = (size_t)m.dims[0] * m.dims[1] * m.dims[2];
+  ws_alpha = (double2 *)al(sizeof(double2) * (size_t)R * m.b);
+  ws_yb = (double2 *)al(sizeof(double2) * (size_t)R * m.b);
+  ws_scan = (double2 *)al(sizeof(double2) * (size_t)R * (m.nn + 1));
+  ws_part = (double2 *)al(sizeof(double2) * scan_partials_size(m.nn + 1, R));
+  ws_U = (double2 *)al(sizeof(double2) * (size_t)R * m.n * 4);
+  ws_coef = (double2 *)al(sizeof(double2) * 2 * (size_t)R);
+  ws_J = al(vs * (size_t)R * m.n * 4);
+  ws_Q = al(vs * (size_t)R * 3 * N);
+  ws_T1 = al(vs * (size_t)R * 6 * N);
+  ws_T2 = al(vs * (size_t)R * 12 * N);
+  ws_R = R;
+}
+
+void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const double2 *x, double2 *y,
+                      hipStream_t st) {
+  const int dim = space == 1 ? m.l : m.b;
+  const int Rc = chunk_for(R);
+  ensure_workspace(Rc);
+  int mode = 0;
+  if (!(flags & PFFT_NEAR_ONLY)) mode |= 1;
+  if (!(flags & PFFT_FAR_ONLY)) mode |= 2;
+  if (space == 1) mode |= 4;
+  host_coef.resize(2 * (size_t)Rc);
+  for (int r0 = 0; r0 < R; r0 += Rc) {
+    int Rn = std::min(Rc, R - r0);
+    const double2 *xc = x + (size_t)r0 * dim;
+    double2 *yc = y + (size_t)r0 * dim;
+    const double2 *alpha;
+    if (space == 1) {
+      loop_to_branch(lm, xc, ws_alpha, ws_scan, ws_part, Rn, st);
+      alpha = ws_alpha;
+    } else {
+      alpha = xc;
+    }
+    if (mode & 1) {
+      if (grid_fp64) {
+        tri_currents<double>(gm, alpha, (double2 *)ws_J, Rn, st);
+        project<double>(gm, (double2 *)ws_J, (double2 *)ws_Q, Rn, st);
+        convolve<double>(gm, (double2 *)ws_Q, (double2 *)ws_T1, (double2 *)ws_T2, Rn, st);
+        interp_tri<double>(gm, (double2 *)ws_Q, ws_U, Rn, st);
+      } else {
+        tri_currents<float>(gm, alpha, (float2 *)ws_J, Rn, st);
+        project<float>(gm, (float2 *)ws_J, (float2 *)ws_Q, Rn, st);
+        convolve<float>(gm, (float2 *)ws_Q, (float2 *)ws_T1, (float2 *)ws_T2, Rn, st);
+        interp_tri<float>(gm, (float2 *)ws_Q, ws_U, Rn, st);
+      }
+    }
+    double2 *zs = ws_coef, *jw = ws_coef + Rc;
+    if (space == 1) {
+      for (int r = 0; r < Rn; ++r) {
+        double om = omega[r0 + r];
+        double a = std::sqrt(om * MU0 * mu_r / (2.0 * sigma));
+        host_coef[r] = make_double2(a, a);
+        host_coef[Rc + r] = make_double2(0.0, om * MU0 * mu_r / (4.0 * M_PI));
+      }
+      hip_ok(hipMemcpyAsync(ws_coef, host_coef.data(), sizeof(double2) * 2 * Rc, hipMemcpyHostToDevice, st),
+             "coef upload");
+      combine(cm, alpha, ws_U, zs, jw, ws_yb, Rn, mode, st);
+      branch_to_loop(lm, ws_yb, yc, ws_scan, ws_part, Rn, st);
+    } else {
+      combine(cm, alpha, ws_U, zs, jw, yc, Rn, mode, st);
+    }
+  }
+  hip_ok(hipGetLastError(), "matvec launch");
+}
+
+// ---------------------------------------------------------------------------
+// setup: host model -> device maps
+// ---------------------------------------------------------------------------
+static void build_device(pfft_ctx *c, hipStream_t st) {
+  HostModel &m = c->m;
+  const int nn = m.nn, b = m.b, n = m.n, l = m.l;
+  // ---- A^T maps
+  std::vector<int> inj_cnt(nn + 1, 0);
+  for (int i = 0; i < l; ++i) {
+    int e = m.links[i];
+    if (m.bu[e] == m.bv[e]) continue;
+    inj_cnt[m.pre[m.bv[e]] + 1]++;
+    inj_cnt[m.pre[m.bu[e]] + 1]++;
+  }
+  for (int k = 0; k < nn; ++k) inj_cnt[k + 1] += inj_cnt[k];
+  std::vector<int> inj_link(inj_cnt[nn]);
+  std::vector<int8_t> inj_sgn(inj_cnt[nn]);
+  {
+    std::vector<int> f(inj_cnt.begin(), inj_cnt.end() - 1);
+    for (int i = 0; i < l; ++i) {
+      int e = m.links[i];
+      if (m.bu[e] == m.bv[e]) continue;
+      int kv = m.pre[m.bv[e]], ku = m.pre[m.bu[e]];
+      inj_link[f[kv]] = i;
+      inj_sgn[f[kv]++] = 1;
+      inj_link[f[ku]] = i;
+      inj_sgn[f[ku]++] = -1;
+    }
+  }
+  std::vector<int> link_of_branch(b + m.p, -1);
+  for (int i = 0; i < l; ++i) link_of_branch[m.links[i]] = i;
+  std::vector<int> child_of_twig(b + m.p, -1);
+  for (int y = 0; y < nn; ++y)
+    if (m.parent_branch[y] >= 0) child_of_twig[m.parent_branch[y]] = y;
+  std::vector<int> br_a(b), br_lo(b, 0), br_hi(b, 0);
+  std::vector<int8_t> br_sg(b, 0);
+  for (int e = 0; e < b; ++e) {
+    if (!m.twig[e]) {
+      br_a[e] = link_of_branch[e];
+    } else {
+      int y = child_of_twig[e];
+      br_a[e] = -1;
+      br_lo[e] = m.pre[y];
+      br_hi[e] = m.pre[y] + m.sub[y];
+      br_sg[e] = (m.bu[e] == y) ? 1 : -1;
+    }
+  }
+  // ---- A maps
+  std::vector<int> pos_branch(nn, -1);
+  std::vector<int8_t> pos_sign(nn, 0);
+  std::vector<int> end_cnt(nn + 1, 0);
+  for (int k = 0; k < nn; ++k) {
+    int z = m.order[k];
+    int e = m.parent_branch[z];
+    if (e >= 0) {
+      pos_branch[k] = e;
+      pos_sign[k] = (m.bu[e] == z) ? 1 : -1;
+      int kend = m.pre[z] + m.sub[z];
+      if (kend < nn) end_cnt[kend + 1]++;
+    }
+  }
+  for (int k = 0; k < nn; ++k) end_cnt[k + 1] += end_cnt[k];
+  std::vector<int> end_pos(end_cnt[nn]);
+  {
+    std::vector<int> f(end_cnt.begin(), end_cnt.end() - 1);
+    for (int k = 0; k < nn; ++k) {
+      int z = m.order[k];
+      if (m.parent_branch[z] < 0) continue;
+      int kend = m.pre[z] + m.sub[z];
+      if (kend < nn) end_pos[f[kend]++] = k;
+    }
+  }
+  std::vector<int> link_upos(l, -1), link_vpos(l, -1);
+  for (int i = 0; i < l; ++i) {
+    int e = m.links[i];
+    if (m.bu[e] != m.bv[e]) {
+      link_upos[i] = m.pre[m.bu[e]];
+      link_vpos[i] = m.pre[m.bv[e]];
+    }
+  }
+  LoopMaps &lm = c->lm;
+  lm.nn = nn;
+  lm.b = b;
+  lm.l = l;
+  lm.inj_off = upload(c, inj_cnt, st);
+  lm.inj_link = upload(c, inj_link, st);
+  lm.inj_sgn = upload(c, inj_sgn, st);
+  lm.br_a = upload(c, br_a, st);
+  lm.br_lo = upload(c, br_lo, st);
+  lm.br_hi = upload(c, br_hi, st);
+  lm.br_sg = upload(c, br_sg, st);
+  lm.pos_branch = upload(c, pos_branch, st);
+  lm.pos_sign = upload(c, pos_sign, st);
+  lm.end_off = upload(c, end_cnt, st);
+  lm.end_pos = upload(c, end_pos, st);
+  lm.link_branch = upload(c, m.links, st);
+  lm.link_upos = upload(c, link_upos, st);
+  lm.link_vpos = upload(c, link_vpos, st);
+  // ---- grid maps
+  GridMaps &g = c->gm;
+  g.n = n;
+  g.b = b;
+  for (int d = 0; d < 3; ++d) g.dims[d] = m.dims[d];
+  const long N = (long)m.dims[0] * m.dims[1] * m.dims[2];
+  g.N = (int)N;
+  std::vector<double> inv2A(n);
+  for (int t = 0; t < n; ++t) inv2A[t] = 1.0 / (2.0 * m.area[t]);
+  g.tri_edge = upload(c, m.tri_edge, st);
+  g.tri_sign = upload(c, m.tri_sign, st);
+  g.inv2A = upload(c, inv2A, st);
+  g.pl = upload(c, m.pl, st);
+  g.anchor = upload(c, m.anchor, st);
+  std::vector<int> pg_off(N + 1, 0);
+  auto node_of = [&](int t, int k) {
+    int i = k >> 4, j = (k >> 2) & 3, q = k & 3;
+    return ((long)(m.anchor[3 * t] + i) * m.dims[1] + (m.anchor[3 * t + 1] + j)) * m.dims[2] +
+           (m.anchor[3 * t + 2] + q);
+  };
+  for (int t = 0; t < n; ++t)
+    for (int k = 0; k < 64; ++k) pg_off[node_of(t, k) + 1]++;
+  for (long q = 0; q < N; ++q) pg_off[q + 1] += pg_off[q];
+  std::vector<int> pg_tri(pg_off[N]);
+  std::vector<double> pg_w(4 * (size_t)pg_off[N]);
+  {
+    std::vector<int> f(pg_off.begin(), pg_off.end() - 1);
+    for (int t = 0; t < n; ++t)
+      for (int k = 0; k < 64; ++k) {
+        long node = node_of(t, k);
+        int q = f[node]++;
+        pg_tri[q] = t;
+        pg_w[4 * (size_t)q] = m.M0[64 * (size_t)t + k];
+        for (int cc = 0; cc < 3; ++cc) pg_w[4 * (size_t)q + 1 + cc] = m.M1[192 * (size_t)t + 3 * k + cc];
+      }
+  }
+  std::vector<double> tri_w(256 * (size_t)n);
+  for (int t = 0; t < n; ++t)
+    for (int k = 0; k < 64; ++k) {
+      tri_w[256 * (size_t)t + 4 * k] = m.M0[64 * (size_t)t + k];
+      for (int cc = 0; cc < 3; ++cc) tri_w[256 * (size_t)t + 4 * k + 1 + cc] = m.M1[192 * (size_t)t + 3 * k + cc];
+    }
+  g.pg_off = upload(c, pg_off, st);
+  g.pg_tri = upload(c, pg_tri, st);
+  if (c->grid_fp64) {
+    g.pg_w = upload(c, pg_w, st);
+    g.tri_w = upload(c, tri_w, st);
+  } else {
+    std::vector<float> a(pg_w.begin(), pg_w.end()), bb(tri_w.begin(), tri_w.end());
+    g.pg_w = upload(c, a, st);
+    g.tri_w = upload(c, bb, st);
+  }
+  // ---- kernel spectrum: FFT of the circulant-embedded grid Green's function
+  {
+    int d2[3] = {2 * m.dims[0], 2 * m.dims[1], 2 * m.dims[2]};
+    size_t tot = (size_t)d2[0] * d2[1] * d2[2];
+    std::vector<double2> H(tot);
+    for (int i = 0; i < d2[0]; ++i) {
+      double ox = (i < m.dims[0] ? i : i - d2[0]) * m.h[0];
+      bool ux = i == m.dims[0];
+      for (int j = 0; j < d2[1]; ++j) {
+        double oy = (j < m.dims[1] ? j : j - d2[1]) * m.h[1];
+        bool uy = j == m.dims[1];
+        for (int k = 0; k < d2[2]; ++k) {
+          double oz = (k < m.dims[2] ? k : k - d2[2]) * m.h[2];
+          bool uz = k == m.dims[2];
+          double R = std::sqrt(ox * ox + oy * oy + oz * oz);
+          double v = (ux || uy || uz || R == 0.0) ? 0.0 : 1.0 / R;
+          H[((size_t)i * d2[1] + j) * d2[2] + k] = make_double2(v, 0.0);
+        }
+      }
+    }
+    double2 *dH = nullptr;
+    hip_ok(hipMalloc(&dH, tot * sizeof(double2)), "hipMalloc spectrum");
+    hip_ok(hipMemcpyAsync(dH, H.data(), tot * sizeof(double2), hipMemcpyHostToDevice, st), "upload H");
+    fft3_full_fp64(dH, d2, st);
+    size_t oct = (size_t)(m.dims[0] + 1) * (m.dims[1] + 1) * (m.dims[2] + 1);
+    if (c->grid_fp64) {
+      double *gh = (double *)c->dalloc(oct * sizeof(double));
+      fold_spectrum<double>(dH, gh, m.dims, st);
+      g.ghat = gh;
+    } else {
+      float *gh = (float *)c->dalloc(oct * sizeof(float));
+      fold_spectrum<float>(dH, gh, m.dims, st);
+      g.ghat = gh;
+    }
+    hip_ok(hipStreamSynchronize(st), "spectrum");
+    hipFree(dH);
+  }
+  // ---- combine maps
+  CombineMaps &cm = c->cm;
+  cm.b = b;
+  cm.n = n;
+  std::vector<int> efar_t(2 * (size_t)b);
+  std::vector<double> efar_s(2 * (size_t)b), efar_pl(6 * (size_t)b);
+  for (int e = 0; e < b; ++e)
+    for (int side = 0; side < 2; ++side) {
+      int t = side == 0 ? m.tplus[e] : m.tminus[e];
+      int i = 0;
+      while (m.tri_edge[3 * t + i] != e) ++i;
+      efar_t[2 * e + side] = t;
+      efar_s[2 * e + side] = m.tri_sign[3 * t + i] / (2.0 * m.area[t]);
+      for (int d = 0; d < 3; ++d) efar_pl[6 * (size_t)e + 3 * side + d] = m.pl[9 * t + 3 * i + d];
+    }
+  cm.efar_t = upload(c, efar_t, st);
+  cm.efar_s = upload(c, efar_s, st);
+  cm.efar_pl = upload(c, efar_pl, st);
+  cm.nf_rowptr = upload(c, m.nf_rowptr, st);
+  cm.nf_col = upload(c, m.nf_col, st);
+  cm.nf_val = upload(c, m.nf_val, st);
+  cm.gram_col = upload(c, m.gram_col, st);
+  cm.gram_val = upload(c, m.gram_val, st);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *pfft_last_error(void) { return g_err.c_str(); }
+
+pfft_status pfft_setup(const pfft_problem *pb, void *hip_stream, pfft_ctx **out) {
+  if (!pb || !out) {
+    set_error("pfft_setup: null argument");
+    return PFFT_EINVAL;
+  }
+  *out = nullptr;
+  pfft_ctx *c = nullptr;
+  try {
+    c = new pfft_ctx();
+    c->grid_fp64 = pb->grid_fp64 ? 1 : 0;
+    c->sigma = pb->sigma;
+    c->mu_r = pb->mu_r > 0 ? pb->mu_r : 1.0;
+    c->max_chunk = pb->max_rhs_chunk;
+    if (!(pb->sigma > 0)) throw SetupError{PFFT_EINVAL, "sigma must be positive"};
+    if (!(pb->near_kappa > 0)) throw SetupError{PFFT_EINVAL, "near_kappa must be positive"};
+    SetupOptions opt;
+    for (int d = 0; d < 3; ++d) opt.grid[d] = pb->grid[d];
+    opt.stencil = pb->stencil;
+    opt.kappa = pb->near_kappa;
+    opt.contact_zs = pb->contact_zs;
+    build_model(c->m, pb->V, pb->nv, pb->T, pb->nt, pb->nport, pb->src_off, pb->src_tri, pb->snk_off,
+                pb->snk_tri, opt);
+    hip_ok(hipGetDevice(&c->device), "hipGetDevice");
+    build_device(c, (hipStream_t)hip_stream);
+    *out = c;
+    return PFFT_OK;
+  } catch (const SetupError &e) {
+    set_error("pfft_setup: " + e.msg);
+    delete c;
+    return (pfft_status)e.code;
+  } catch (const DeviceError &e) {
+    set_error("pfft_setup: " + e.msg);
+    delete c;
+    return (pfft_status)e.code;
+  } catch (const std::bad_alloc &) {
+    set_error("pfft_setup: host allocation failed");
+    delete c;
+    return PFFT_ENOMEM;
+  }
+}
+
+pfft_status pfft_sizes(const pfft_ctx *c, int64_t out[10]) {
+  if (!c || !out) {
+    set_error("pfft_sizes: null argument");
+    return PFFT_EINVAL;
+  }
+  const HostModel &m = c->m;
+  out[0] = m.n;
+  out[1] = m.nn;
+  out[2] = m.b;
+  out[3] = m.l;
+  out[4] = m.s;
+  out[5] = m.p;
+  out[6] = m.nf_rowptr.empty() ? 0 : m.nf_rowptr.back();
+  out[7] = (int64_t)m.dims[0] * m.dims[1] * m.dims[2];
+  out[8] = m.npairs;
+  out[9] = (int64_t)c->dev_bytes;
+  return PFFT_OK;
+}
+
+pfft_status pfft_matvec(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t space, int32_t flags,
+                        const void *x_dev, void *y_dev, void *hip_stream) {
+  if (!c || !x_dev || !y_dev || nrhs < 0 || (space != 0 && space != 1)) {
+    set_error("pfft_matvec: bad argument");
+    return PFFT_EINVAL;
+  }
+  if (space == 1 && !omega && nrhs > 0) {
+    set_error("pfft_matvec: loop space needs omega");
+    return PFFT_EINVAL;
+  }
+  if ((flags & PFFT_FAR_ONLY) && (flags & PFFT_NEAR_ONLY)) {
+    set_error("pfft_matvec: FAR_ONLY and NEAR_ONLY are exclusive");
+    return PFFT_EINVAL;
+  }
+  if ((flags & (PFFT_PRECOND | PFFT_PRECOND_ONLY)) && space != 1) {
+    set_error("pfft_matvec: preconditioner flags need loop space");
+    return PFFT_EINVAL;
+  }
+  if (x_dev == y_dev) {
+    set_error("pfft_matvec: x and y must not alias");
+    return PFFT_EINVAL;
+  }
+  if (nrhs == 0) return PFFT_OK;
+  try {
+    hip_ok(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (flags & (PFFT_PRECOND | PFFT_PRECOND_ONLY)) {
+      return pfft_internal_precond_matvec(c, nrhs, omega, flags, (const double2 *)x_dev, (double2 *)y_dev, st);
+    }
+    c->matvec(nrhs, omega, space, flags, (const double2 *)x_dev, (double2 *)y_dev, st);
+    return PFFT_OK;
+  } catch (const DeviceError &e) {
+    set_error("pfft_matvec: " + e.msg);
+    return (pfft_status)e.code;
+  } catch (const SetupError &e) {
+    set_error("pfft_matvec: " + e.msg);
+    return (pfft_status)e.code;
+  }
+}
+
+pfft_status extract_RL(int32_t nfreq, int32_t nport, const double *freq_hz, const void *Y, double *R_out,
+                       double *L_out) {
+  if (nfreq < 0 || nport <= 0 || !freq_hz || !Y || !R_out || !L_out) {
+    set_error("extract_RL: bad argument");
+    return PFFT_EINVAL;
+  }
+  typedef std::complex<double> cd;
+  const cd *Yc = (const cd *)Y;
+  const int p = nport;
+  std::vector<cd> a(p * p), inv(p * p);
+  for (int f = 0; f < nfreq; ++f) {
+    for (int i = 0; i < p * p; ++i) a[i] = Yc[(size_t)f * p * p + i];
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) inv[i * p + j] = (i == j) ? 1.0 : 0.0;
+    // Gauss-Jordan with partial pivoting
+    for (int k = 0; k < p; ++k) {
+      int piv = k;
+      for (int i = k + 1; i < p; ++i)
+        if (std::abs(a[i * p + k]) > std::abs(a[piv * p + k])) piv = i;
+      if (std::abs(a[piv * p + k]) == 0.0) {
+        set_error("extract_RL: singular admittance matrix");
+        return PFFT_EINVAL;
+      }
+      if (piv != k)
+        for (int j = 0; j < p; ++j) {
+          std::swap(a[k * p + j], a[piv * p + j]);
+          std::swap(inv[k * p + j], inv[piv * p + j]);
+        }
+      cd d = a[k * p + k];
+      for (int j = 0; j < p; ++j) {
+        a[k * p + j] /= d;
+        inv[k * p + j] /= d;
+      }
+      for (int i = 0; i < p; ++i) {
+        if (i == k) continue;
+        cd fct = a[i * p + k];
+        if (fct == 0.0) continue;
+        for (int j = 0; j < p; ++j) {
+          a[i * p + j] -= fct * a[k * p + j];
+          inv[i * p + j] -= fct * inv[k * p + j];
+        }
+      }
+    }
+    double om = 2.0 * M_PI * freq_hz[f];
+    for (int i = 0; i < p * p; ++i) {
+      R_out[(size_t)f * p * p + i] = inv[i].real();
+      L_out[(size_t)f * p * p + i] = om > 0 ? inv[i].imag() / om : 0.0;
+    }
+  }
+  return PFFT_OK;
+}
+
+}  // extern "C"
+
+void pfft_ctx_free(pfft_ctx *c);
+
+extern "C" void pfft_destroy(pfft_ctx *c) {
+  if (!c) return;
+  pfft_ctx_free(c);
+}

@@ -1,0 +1,86 @@
+// Device kernels of the pFFT loop-space matrix-vector product (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pfft {
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+template <typename T> using V2 = typename vec2<T>::type;
+
+// ---- host launchers (all asynchronous on `st`) ----
+
+// Batched prefix sum over rows of complex128: out[r][k] = sum_{j<k} (exclusive)
+// or sum_{j<=k} (inclusive) of in[r][j], for R rows of length len, row stride ld.
+void scan_rows(const double2 *in, double2 *out, int len, int ld, int R, bool inclusive,
+               double2 *partials, hipStream_t st);
+size_t scan_partials_size(int len, int R);
+
+struct LoopMaps {
+  // loop -> branch (A^T): injections per preorder position, per-branch read-out
+  const int *inj_off, *inj_link;
+  const int8_t *inj_sgn;
+  const int *br_a, *br_lo, *br_hi;
+  const int8_t *br_sg;
+  // branch -> loop (A): twig drop per position, subtree-end lists, link ends
+  const int *pos_branch;
+  const int8_t *pos_sign;
+  const int *end_off, *end_pos;
+  const int *link_branch, *link_upos, *link_vpos;
+  int nn, b, l;
+};
+
+void loop_to_branch(const LoopMaps &mp, const double2 *x, double2 *alpha, double2 *scan,
+                    double2 *partials, int R, hipStream_t st);
+void branch_to_loop(const LoopMaps &mp, const double2 *yb, double2 *yl, double2 *scan,
+                    double2 *partials, int R, hipStream_t st);
+
+struct GridMaps {
+  int n, b, N, dims[3];
+  const int *tri_edge;
+  const int8_t *tri_sign;
+  const double *inv2A;   // [n] 1/(2A)
+  const double *pl;      // [n][3][3] vertex - centroid
+  const int *anchor;     // [n][3]
+  const int *pg_off;     // [N+1] node-major projection lists
+  const int *pg_tri;
+  const void *pg_w;      // [nnz][4] (M0, M1x, M1y, M1z) in T
+  const void *tri_w;     // [n][64][4] same weights, triangle-major, in T
+  const void *ghat;      // [(Nx+1)(Ny+1)(Nz+1)] real spectrum in T
+};
+
+template <typename T>
+void tri_currents(const GridMaps &g, const double2 *alpha, V2<T> *J, int R, hipStream_t st);
+template <typename T>
+void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st);
+template <typename T>
+void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStream_t st);
+template <typename T>
+void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStream_t st);
+
+// Full-length forward 3-D FFT of a (2Nx, 2Ny, 2Nz) complex128 array in place.
+void fft3_full_fp64(double2 *data, const int dims2[3], hipStream_t st);
+template <typename T>
+void fold_spectrum(const double2 *full, T *ghat, const int dims[3], hipStream_t st);
+
+struct CombineMaps {
+  int b, n;
+  const int *efar_t;        // [b][2] triangles T+, T-
+  const double *efar_s;     // [b][2] s / (2A)
+  const double *efar_pl;    // [b][2][3] free vertex - centroid
+  const int64_t *nf_rowptr;
+  const int *nf_col;
+  const double *nf_val;
+  const int *gram_col;      // [b][5]
+  const double *gram_val;
+};
+
+// y[r][e] = zs[r] * (G a)[e] + jw[r] * (far[e] + (L_d a)[e]); far from U.
+// mode bits: 1 far, 2 near, 4 gram (zs, jw ignored when gram bit is clear
+// and kscale = 1: y = far + near).
+void combine(const CombineMaps &c, const double2 *alpha, const double2 *U, const double2 *zs,
+             const double2 *jw, double2 *y, int R, int mode, hipStream_t st);
+
+}  // namespace pfft

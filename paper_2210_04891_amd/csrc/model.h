@@ -1,0 +1,77 @@
+// Host-side model built by pfft_setup: mesh topology, circuit graph and loop
+// basis, Gram blocks, pFFT grid weights and the near-field pre-correction.
+// Everything here is FP64/int and lives in host memory until uploaded.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace pfft {
+
+struct SetupError {
+  int code;
+  std::string msg;
+};
+
+struct HostModel {
+  // ---- mesh (Sec. II-B/C) ----
+  int nv = 0, n = 0, b = 0, p = 0;
+  std::vector<double> V;          // [nv][3]
+  std::vector<int> T;             // [n][3]
+  std::vector<double> area;       // [n]
+  std::vector<double> cen;        // [n][3]
+  std::vector<int> tri_edge;      // [n][3] edge opposite local vertex i
+  std::vector<int8_t> tri_sign;   // [n][3] +1 on T+, -1 on T-
+  std::vector<int> tplus, tminus; // [b]
+  // ---- circuit graph and loops (Sec. III) ----
+  int nn = 0;                     // n' nodes
+  int s = 0;                      // conductors
+  int l = 0;                      // loops = links
+  std::vector<uint8_t> contact;   // [n]
+  std::vector<int> node_of_tri;   // [n] compact node index
+  std::vector<int> bu, bv;        // [b+p] branch end nodes (compact)
+  std::vector<uint8_t> twig;      // [b+p]
+  std::vector<int> links;         // [l] branch id of each link
+  std::vector<int> port_loop;     // [p]
+  std::vector<int> parent, parent_branch; // [nn] (-1 at roots)
+  std::vector<int> pre, sub;      // [nn] preorder position and subtree size
+  std::vector<int> order;         // [nn] node at preorder position
+  // ---- Gram (second term of Eq. Zb) ----
+  std::vector<double> gram;       // [n][3][3] scaled blocks int f_i . f_j
+  std::vector<int> gram_col;      // [b][5]
+  std::vector<double> gram_val;   // [b][5] (contact faces weighted 0 or 1)
+  // ---- grid (Sec. IV-B) ----
+  int dims[3] = {0, 0, 0};
+  double h[3] = {0, 0, 0}, x0[3] = {0, 0, 0};
+  std::vector<int> anchor;        // [n][3]
+  std::vector<double> M0;         // [n][64]
+  std::vector<double> M1;         // [n][64][3]
+  std::vector<double> pl;         // [n][3][3] vertex - centroid
+  // ---- near field ----
+  std::vector<int> near_off;      // [n+1] ordered near lists incl. self
+  std::vector<int> near_tri;
+  int64_t npairs = 0;             // unordered near pairs incl. self
+  std::vector<int64_t> nf_rowptr; // [b+1]
+  std::vector<int> nf_col;
+  std::vector<double> nf_val;
+  // ---- diagonal of K for the preconditioner ----
+  std::vector<double> kdiag;      // [b]
+};
+
+struct SetupOptions {
+  int grid[3];
+  int stencil;
+  double kappa;
+  int contact_zs;
+};
+
+// Builds everything except the kernel spectrum (computed on the device).
+// Throws SetupError.
+void build_model(HostModel &m, const double *V, int nv, const int *T, int n, int nport,
+                 const int *src_off, const int *src_tri, const int *snk_off,
+                 const int *snk_tri, const SetupOptions &opt);
+
+// Closed-form flat-triangle potentials: V0 = int 1/R, V1 = int (r'-r)/R.
+void tri_potentials(const double r[3], const double Q[9], double *V0, double V1[3]);
+
+}  // namespace pfft

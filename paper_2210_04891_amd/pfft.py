@@ -1,0 +1,242 @@
+"""ctypes binding of libpfft.so (see include/pfft.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory (``data_ptr()``) and the HIP stream.
+The library must be built (``python -m paper_2210_04891_amd.build``); there is
+no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpfft.so")
+
+PFFT_FAR_ONLY = 1
+PFFT_NEAR_ONLY = 2
+PFFT_PRECOND = 4
+PFFT_PRECOND_ONLY = 8
+
+STATUS = {0: "PFFT_OK", -1: "PFFT_EINVAL", -2: "PFFT_ETOPO", -3: "PFFT_ENOMEM",
+          -4: "PFFT_EDEVICE", -5: "PFFT_ENOCONV", -6: "PFFT_EFACTOR"}
+
+EXPORTS = ("pfft_setup", "pfft_sizes", "pfft_matvec", "solve_ports", "extract_RL",
+           "pfft_precond_load", "pfft_destroy", "pfft_last_error",
+           "pfft_host_setup", "pfft_host_get", "pfft_host_free")
+
+
+class PfftError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int32), ("V", ctypes.c_void_p),
+                ("nt", ctypes.c_int32), ("T", ctypes.c_void_p),
+                ("nport", ctypes.c_int32),
+                ("src_off", ctypes.c_void_p), ("src_tri", ctypes.c_void_p),
+                ("snk_off", ctypes.c_void_p), ("snk_tri", ctypes.c_void_p),
+                ("sigma", ctypes.c_double), ("mu_r", ctypes.c_double),
+                ("grid", ctypes.c_int32 * 3), ("stencil", ctypes.c_int32),
+                ("near_kappa", ctypes.c_double),
+                ("grid_fp64", ctypes.c_int32), ("contact_zs", ctypes.c_int32),
+                ("max_rhs_chunk", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libpfft.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpfft.so is not built (run python -m paper_2210_04891_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.pfft_setup.argtypes = [ctypes.POINTER(_Problem), vp, ctypes.POINTER(vp)]
+    lib.pfft_setup.restype = i32
+    lib.pfft_sizes.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.pfft_sizes.restype = i32
+    lib.pfft_matvec.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp]
+    lib.pfft_matvec.restype = i32
+    lib.solve_ports.argtypes = [vp, i32, vp, dbl, i32, i32, i32, vp, vp, vp, vp]
+    lib.solve_ports.restype = i32
+    lib.extract_RL.argtypes = [i32, i32, vp, vp, vp, vp]
+    lib.extract_RL.restype = i32
+    lib.pfft_precond_load.argtypes = [vp, vp, i64]
+    lib.pfft_precond_load.restype = i32
+    lib.pfft_destroy.argtypes = [vp]
+    lib.pfft_destroy.restype = None
+    lib.pfft_last_error.argtypes = []
+    lib.pfft_last_error.restype = ctypes.c_char_p
+    lib.pfft_host_setup.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(vp)]
+    lib.pfft_host_setup.restype = i32
+    lib.pfft_host_get.argtypes = [vp, ctypes.c_char_p, vp, i64, ctypes.POINTER(i64)]
+    lib.pfft_host_get.restype = i32
+    lib.pfft_host_free.argtypes = [vp]
+    lib.pfft_host_free.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(code, allow=()):
+    if code != 0 and code not in allow:
+        raise PfftError(code, load().pfft_last_error().decode())
+    return code
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _problem(structure, grid, stencil, near_kappa, grid_fp64, sigma, mu_r, contact_zs,
+         max_rhs_chunk):
+    V = np.ascontiguousarray(structure.V, dtype=np.float64)
+    T = np.ascontiguousarray(structure.T, dtype=np.int32)
+    ports = list(structure.ports)
+    so = np.zeros(len(ports) + 1, np.int32)
+    ko = np.zeros(len(ports) + 1, np.int32)
+    for k, (s, t) in enumerate(ports):
+        so[k + 1] = so[k] + len(s)
+        ko[k + 1] = ko[k] + len(t)
+    st = np.ascontiguousarray(np.concatenate([np.asarray(s, np.int32) for s, _ in ports])
+                              if ports else np.zeros(1, np.int32), dtype=np.int32)
+    kt = np.ascontiguousarray(np.concatenate([np.asarray(t, np.int32) for _, t in ports])
+                              if ports else np.zeros(1, np.int32), dtype=np.int32)
+    keep = (V, T, so, ko, st, kt)
+    pb = _Problem()
+    pb.nv, pb.V = V.shape[0], V.ctypes.data
+    pb.nt, pb.T = T.shape[0], T.ctypes.data
+    pb.nport = len(ports)
+    pb.src_off, pb.src_tri = so.ctypes.data, st.ctypes.data
+    pb.snk_off, pb.snk_tri = ko.ctypes.data, kt.ctypes.data
+    pb.sigma, pb.mu_r = sigma, mu_r
+    for d in range(3):
+        pb.grid[d] = int(grid[d])
+    pb.stencil = stencil
+    pb.near_kappa = near_kappa
+    pb.grid_fp64 = 1 if grid_fp64 else 0
+    pb.contact_zs = 1 if contact_zs else 0
+    pb.max_rhs_chunk = max_rhs_chunk
+    return pb, keep
+
+
+class HostModel:
+    """Host-only setup (pfft_host_setup): topology, loop basis, Gram, grid
+    weights and near-field CSR, for inspection without a GPU."""
+
+    def __init__(self, structure, grid, stencil=4, near_kappa=1.5, contact_zs=False):
+        lib = load()
+        pb, self._keep = _problem(structure, grid, stencil, near_kappa, False, 5.8e7, 1.0,
+                                  contact_zs, 0)
+        h = ctypes.c_void_p()
+        _check(lib.pfft_host_setup(ctypes.byref(pb), ctypes.byref(h)))
+        self._h = h
+
+    def get(self, name, dtype):
+        lib = load()
+        n = ctypes.c_int64()
+        _check(lib.pfft_host_get(self._h, name.encode(), None, 0, ctypes.byref(n)))
+        out = np.empty(n.value // np.dtype(dtype).itemsize, dtype=dtype)
+        _check(lib.pfft_host_get(self._h, name.encode(), ctypes.c_void_p(out.ctypes.data),
+                                 n.value, ctypes.byref(n)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pfft_host_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A set-up problem (pfft_setup).  ``structure`` needs V (nv x 3, metres),
+    T (n x 3) and ports [(src_tris, snk_tris), ...]."""
+
+    def __init__(self, structure, grid, stencil=4, near_kappa=1.5, grid_fp64=False,
+                 sigma=5.8e7, mu_r=1.0, contact_zs=False, max_rhs_chunk=0, stream=None):
+        lib = load()
+        pb, self._keep = _problem(structure, grid, stencil, near_kappa, grid_fp64, sigma, mu_r,
+                                  contact_zs, max_rhs_chunk)
+        ports = list(structure.ports)
+        h = ctypes.c_void_p()
+        _check(lib.pfft_setup(ctypes.byref(pb), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.nport = len(ports)
+        self.sizes = self._sizes()
+
+    def _sizes(self):
+        out = (ctypes.c_int64 * 10)()
+        _check(load().pfft_sizes(self._h, out))
+        keys = ("n", "nprime", "b", "l", "s", "p", "nnz_near", "Ng", "near_pairs", "device_bytes")
+        return dict(zip(keys, [int(v) for v in out]))
+
+    def matvec(self, x, omega=None, space=1, flags=0, out=None, stream=None):
+        """y = op(x); x is a complex128 CUDA tensor [R, dim]."""
+        import torch
+        assert x.dtype == torch.complex128 and x.is_cuda and x.dim() == 2
+        x = x.contiguous()
+        R = x.shape[0]
+        dim = self.sizes["l"] if space == 1 else self.sizes["b"]
+        if x.shape[1] != dim:
+            raise ValueError("x has %d columns, expected %d" % (x.shape[1], dim))
+        y = torch.empty_like(x) if out is None else out
+        om = None
+        if space == 1:
+            om = np.ascontiguousarray(np.broadcast_to(np.asarray(omega, np.float64), (R,)))
+        _check(load().pfft_matvec(self._h, R, _ptr(om) if om is not None else None, space, flags,
+                                  ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                  _stream_handle(stream)))
+        return y
+
+    def solve_ports(self, freqs_hz, tol=1e-6, maxit=500, restart=60, precond=1, stream=None):
+        """Returns (Y [nf, p, p] complex128, iterations [nf, p], relres [nf, p], status)."""
+        f = np.ascontiguousarray(np.asarray(freqs_hz, np.float64).reshape(-1))
+        nf, p = f.size, self.nport
+        Y = np.zeros((nf, p, p), np.complex128)
+        it = np.zeros((nf, p), np.int32)
+        rr = np.zeros((nf, p), np.float64)
+        code = _check(load().solve_ports(self._h, nf, _ptr(f), tol, maxit, restart, precond,
+                                         _ptr(Y), _ptr(it), _ptr(rr), _stream_handle(stream)),
+                      allow=(-5,))
+        return Y, it, rr, code
+
+    def precond_load(self, weights_bf16):
+        w = np.ascontiguousarray(weights_bf16)
+        _check(load().pfft_precond_load(self._h, _ptr(w), w.nbytes))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pfft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def extract_RL(freqs_hz, Y):
+    f = np.ascontiguousarray(np.asarray(freqs_hz, np.float64).reshape(-1))
+    Y = np.ascontiguousarray(Y, dtype=np.complex128)
+    nf, p = Y.shape[0], Y.shape[1]
+    R = np.zeros((nf, p, p))
+    L = np.zeros((nf, p, p))
+    _check(load().extract_RL(nf, p, _ptr(f), _ptr(Y), _ptr(R), _ptr(L)))
+    return R, L

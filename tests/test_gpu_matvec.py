@@ -1,0 +1,168 @@
+"""GPU parity of the pFFT matrix-vector product against the oracle.
+
+Config-1 bar (2,000 triangles, grid 64 x 8 x 8, O_s = 4, kappa = 1.5).
+Tolerances:
+  * grid term (I H B) in FP64 vs the oracle's explicit B^T (H * B alpha):
+    1e-10 relative (rounding only);
+  * grid term in FP32 complex: 2e-6 relative (FP32 FFT rounding, log2 N ~ 14
+    passes of 6e-8);
+  * near-field term L_d: the library integrates the exact pair blocks with a
+    different outer rule than the oracle, so the bound is their quadrature
+    agreement (~1e-8 per block), checked at 1e-6 relative;
+  * full product vs the dense FP64 kernel: 1e-3 (the pFFT approximation).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+GRID = (64, 8, 8)
+
+
+def _ctx(s, grid=GRID, fp64=True, **kw):
+    import paper_2210_04891_amd as P
+    return P.Context(s, grid, stencil=4, near_kappa=1.5, grid_fp64=fp64, **kw)
+
+
+@pytest.fixture(scope="module")
+def c1_oracle(c1):
+    from oracle import pfft as PF
+    op = PF.PFFTOperator(c1["mesh"], GRID, 4, 1.5)
+    return dict(c1, op=op)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@gpu
+def test_sizes_match_oracle(c1_oracle):
+    ctx = _ctx(c1_oracle["s"])
+    sz = ctx.sizes
+    m, c = c1_oracle["mesh"], c1_oracle["circ"]
+    assert (sz["n"], sz["b"], sz["l"], sz["nprime"], sz["s"], sz["p"]) == \
+        (m.ntri, m.nedge, c.nloop, len(c.nodes), c.ncomp, c.nport)
+    assert sz["Ng"] == 64 * 8 * 8
+    assert sz["nnz_near"] == c1_oracle["op"].Ld.nnz
+
+
+@gpu
+@pytest.mark.parametrize("fp64,tol", [(True, 1e-10), (False, 2e-6)])
+def test_grid_term_matches_oracle(c1_oracle, fp64, tol):
+    import paper_2210_04891_amd as P
+    ctx = _ctx(c1_oracle["s"], fp64=fp64)
+    m = c1_oracle["mesh"]
+    X = W.complex_normal(0, (3, m.nedge))
+    y = ctx.matvec(_dev(X), space=0, flags=P.PFFT_FAR_ONLY).cpu().numpy()
+    for r in range(3):
+        ref = c1_oracle["op"].far(X[r])
+        assert _rel(y[r], ref) < tol
+
+
+@gpu
+def test_near_term_matches_oracle(c1_oracle):
+    import paper_2210_04891_amd as P
+    ctx = _ctx(c1_oracle["s"])
+    m = c1_oracle["mesh"]
+    X = W.complex_normal(1, (2, m.nedge))
+    y = ctx.matvec(_dev(X), space=0, flags=P.PFFT_NEAR_ONLY).cpu().numpy()
+    for r in range(2):
+        ref = c1_oracle["op"].Ld @ X[r]
+        assert _rel(y[r], ref) < 1e-6
+
+
+@gpu
+@pytest.mark.parametrize("fp64", [True, False])
+def test_full_product_within_1e3_of_dense_kernel(c1_oracle, fp64):
+    ctx = _ctx(c1_oracle["s"], fp64=fp64)
+    m, K = c1_oracle["mesh"], c1_oracle["K"]
+    X = W.complex_normal(0, (2, m.nedge))
+    y = ctx.matvec(_dev(X), space=0).cpu().numpy()
+    for r in range(2):
+        assert _rel(y[r], K @ X[r]) < 1e-3
+
+
+def _oracle_loop(c1o, Kop, omega, x):
+    """A [Z_s G + (j omega mu0/4 pi) K] A^T x with the given K operator."""
+    from oracle.mesh import gram_matrix
+    from oracle import solve as S
+    m, c = c1o["mesh"], c1o["circ"]
+    A = c.loop_matrix().toarray()
+    b = m.nedge
+    zs = S.surface_impedance(omega, 5.8e7)
+    G = gram_matrix(m, weight=S.triangle_impedance(m, c, 1.0).real)
+    ab = A.T @ x
+    yb = zs * (G @ ab[:b]) + 1j * omega * S.MU0 / (4 * np.pi) * Kop(ab[:b])
+    return A @ np.concatenate([yb, np.zeros(c.nport)])
+
+
+@gpu
+def test_loop_space_product(c1_oracle):
+    """Z_l x = A Z_b A^T x through the tree scans (Eqs. CurT, VolT), several
+    right-hand sides at different frequencies in one call."""
+    ctx = _ctx(c1_oracle["s"])
+    c = c1_oracle["circ"]
+    om = 2 * np.pi * np.array([1e8, 1e9, 1e10])
+    X = W.complex_normal(2, (3, c.nloop))
+    y = ctx.matvec(_dev(X), omega=om, space=1).cpu().numpy()
+    for r in range(3):
+        ref_p = _oracle_loop(c1_oracle, c1_oracle["op"].apply, om[r], X[r])
+        ref_d = _oracle_loop(c1_oracle, lambda a: c1_oracle["K"] @ a, om[r], X[r])
+        assert _rel(y[r], ref_p) < 1e-6
+        assert _rel(y[r], ref_d) < 1e-3
+
+
+@gpu
+def test_loop_transforms_alone(c1_oracle):
+    """With the grid term only, compare A^T/A against the explicit loop
+    matrix at FP64 rounding: y = A (j w/4pi K_far + Zs G) A^T x."""
+    import paper_2210_04891_amd as P
+    ctx = _ctx(c1_oracle["s"])
+    c = c1_oracle["circ"]
+    om = 2 * np.pi * 3e9
+    X = W.complex_normal(5, (1, c.nloop))
+    y = ctx.matvec(_dev(X), omega=[om], space=1, flags=P.PFFT_FAR_ONLY).cpu().numpy()
+    ref = _oracle_loop(c1_oracle, c1_oracle["op"].far, om, X[0])
+    assert _rel(y[0], ref) < 1e-10
+
+
+@gpu
+def test_chunking_and_determinism(c1_oracle):
+    """RHS chunks of 1 give the same bits as one batch; repeated calls are
+    bitwise identical (gather-only kernels, no atomics)."""
+    c = c1_oracle["circ"]
+    om = 2 * np.pi * np.array([1e9, 2e9, 4e9, 8e9])
+    X = _dev(W.complex_normal(3, (4, c.nloop)))
+    a = _ctx(c1_oracle["s"], fp64=False)
+    b = _ctx(c1_oracle["s"], fp64=False, max_rhs_chunk=1)
+    y1 = a.matvec(X, omega=om).cpu().numpy()
+    y2 = a.matvec(X, omega=om).cpu().numpy()
+    y3 = b.matvec(X, omega=om).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    assert np.array_equal(y1, y3)
+
+
+@gpu
+def test_bad_arguments_are_rejected(c1_oracle):
+    import paper_2210_04891_amd as P
+    ctx = _ctx(c1_oracle["s"])
+    c = c1_oracle["circ"]
+    X = _dev(W.complex_normal(3, (1, c.nloop)))
+    with pytest.raises(ValueError):
+        ctx.matvec(_dev(W.complex_normal(3, (1, c.nloop + 1))), omega=[1e9])
+    with pytest.raises(P.PfftError):
+        ctx.matvec(X, omega=[1e9], flags=P.PFFT_FAR_ONLY | P.PFFT_NEAR_ONLY)
+    with pytest.raises(P.PfftError):
+        _ctx(c1_oracle["s"], grid=(64, 8, 12))            # not a power of two
+    bad = W.config1_bar()
+    bad.T = bad.T[:-1]
+    with pytest.raises(P.PfftError) as ei:
+        _ctx(bad)
+    assert ei.value.code == -2

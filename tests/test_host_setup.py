@@ -1,0 +1,130 @@
+"""The library's host setup (pfft_host_setup, no GPU) against the oracle.
+
+Checks the loop basis conventions (so loop-space vectors of the two sides
+line up), the Gram blocks, the projection moments and the near-field
+pre-correction matrix L_d, whose exact pair integrals use a different outer
+quadrature than the oracle (agreement ~1e-8 relative, checked at 1e-6).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+P = pytest.importorskip("paper_2210_04891_amd")
+if not os.path.exists(P.LIB_PATH):
+    pytest.skip("libpfft.so not built", allow_module_level=True)
+
+
+def test_library_exports_every_declared_symbol():
+    """Every function include/pfft.h declares is exported by libpfft.so."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(P.LIB_PATH), "..", "include", "pfft.h")).read()
+    declared = set(re.findall(r"^\s*(?:pfft_status|void|const char \*)\s*\*?\s*(\w+)\(", hdr, re.M))
+    lib = P.load()
+    assert declared >= {"pfft_setup", "pfft_matvec", "solve_ports", "extract_RL"}
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(P.EXPORTS) == declared
+
+
+@pytest.fixture(scope="module")
+def c1_host():
+    s = W.config1_bar()
+    return s, P.HostModel(s, (64, 8, 8), 4, 1.5)
+
+
+def test_sizes_and_loop_basis_match_oracle(c1, c1_host):
+    s, h = c1_host
+    m, c = c1["mesh"], c1["circ"]
+    sz = h.get("sizes", np.int64)
+    assert list(sz[:6]) == [m.ntri, len(c.nodes), m.nedge, c.nloop, c.ncomp, c.nport]
+    assert np.array_equal(h.get("tplus", np.int32), m.tplus)
+    assert np.array_equal(h.get("tminus", np.int32), m.tminus)
+    assert np.array_equal(h.get("links", np.int32), c.links)
+    assert np.array_equal(h.get("port_loop", np.int32), c.port_loop)
+
+
+def test_wires_loop_basis_matches_oracle():
+    from oracle.mesh import RWGMesh
+    from oracle.circuit import Circuit
+    s = W.bond_wires(nwire=3, nseg=30)
+    m = RWGMesh(s.V, s.T)
+    c = Circuit(m, s.ports)
+    h = P.HostModel(s, (64, 32, 16), 4, 1.5)
+    assert np.array_equal(h.get("links", np.int32), c.links)
+    assert np.array_equal(h.get("port_loop", np.int32), c.port_loop)
+    sz = h.get("sizes", np.int64)
+    assert sz[4] == 3 and sz[3] == c.nloop
+
+
+def test_gram_matches_oracle(c1, c1_host):
+    from oracle.mesh import gram_matrix
+    from oracle import solve as S
+    s, h = c1_host
+    m, c = c1["mesh"], c1["circ"]
+    cols = h.get("gram_col", np.int32).reshape(-1, 5)
+    vals = h.get("gram_val", np.float64).reshape(-1, 5)
+    G = np.zeros((m.nedge, m.nedge))
+    for q in range(5):
+        np.add.at(G, (np.arange(m.nedge), cols[:, q]), vals[:, q])
+    ref = gram_matrix(m, weight=S.triangle_impedance(m, c, 1.0).real).toarray()
+    assert np.abs(G - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_projection_moments_match_oracle(c1, c1_host):
+    from oracle import pfft as PF
+    s, h = c1_host
+    m = c1["mesh"]
+    g = PF.Grid(m.V, (64, 8, 8), 4)
+    a, M0, M1 = PF.projection_moments(m, g)
+    assert np.array_equal(h.get("anchor", np.int32).reshape(-1, 3), a)
+    gr = h.get("grid", np.float64)
+    assert np.allclose(gr[3:6], g.h, rtol=1e-14) and np.allclose(gr[6:9], g.x0, rtol=1e-14)
+    assert np.allclose(h.get("M0", np.float64).reshape(-1, 64), M0, rtol=1e-11, atol=1e-11 * abs(M0).max())
+    assert np.allclose(h.get("M1", np.float64).reshape(-1, 64, 3), M1, rtol=1e-10,
+                       atol=1e-11 * abs(M1).max())
+
+
+def test_precorrection_matches_oracle(c1, c1_host):
+    """L_d (Eq. Lb, near part): same sparsity as the oracle, values within
+    1e-6 of the largest entry (independent outer quadratures)."""
+    import scipy.sparse as sp
+    from oracle import pfft as PF
+    s, h = c1_host
+    m = c1["mesh"]
+    rp = h.get("near_rowptr", np.int64)
+    col = h.get("near_col", np.int32)
+    val = h.get("near_val", np.float64)
+    Ld = sp.csr_matrix((val, col, rp), shape=(m.nedge, m.nedge))
+    g = PF.Grid(m.V, (64, 8, 8), 4)
+    ref = PF.precorrection(m, g, 1.5)
+    assert Ld.nnz == ref.nnz
+    assert abs(Ld - Ld.T).max() <= 1e-14 * abs(Ld).max()     # symmetric up to summation order
+    D = (Ld - ref).toarray()
+    assert np.abs(D).max() <= 1e-6 * abs(ref).max()
+
+
+def test_kernel_diagonal_matches_dense(c1, c1_host):
+    s, h = c1_host
+    kd = h.get("kdiag", np.float64)
+    ref = np.diag(c1["K"])
+    assert np.allclose(kd, ref, rtol=1e-6)
+
+
+def test_setup_rejects_bad_topology():
+    s = W.config1_bar()
+    bad = W.config1_bar()
+    bad.T = bad.T[:-1]
+    with pytest.raises(P.PfftError) as ei:
+        P.HostModel(bad, (64, 8, 8))
+    assert ei.value.code == -2
+    w = W.bond_wires(nwire=2, nseg=6)
+    w.ports = [(w.ports[0][0], w.ports[1][1])]
+    with pytest.raises(P.PfftError) as ei:
+        P.HostModel(w, (32, 16, 16))
+    assert ei.value.code == -2
+    with pytest.raises(P.PfftError) as ei:
+        P.HostModel(s, (64, 8, 12))
+    assert ei.value.code == -1
