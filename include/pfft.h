@@ -130,6 +130,16 @@ pfft_status pfft_precond_load(pfft_ctx *c, const void *weights_bf16, int64_t nby
 void pfft_destroy(pfft_ctx *c);
 const char *pfft_last_error(void);
 
+/* Tracing: with profiling enabled, every stage of pfft_matvec records a pair
+ * of HIP events on the caller's stream.  pfft_profile(c, on) clears the
+ * totals; pfft_stage_times waits for the recorded events and returns the
+ * summed milliseconds and launch counts per stage: 0 loop->branch (A^T),
+ * 1 triangle currents, 2 projection, 3-7 the five FFT passes (X, Y, Z with
+ * spectrum multiply, inverse Y, inverse X), 8 interpolation, 9 near field +
+ * Gram combine, 10 branch->loop (A), 11 preconditioner; 12-15 unused. */
+pfft_status pfft_profile(pfft_ctx *c, int32_t enable);
+pfft_status pfft_stage_times(pfft_ctx *c, double ms[16], int64_t calls[16]);
+
 /* Host-only inspection of the setup (no device work): builds the topology,
  * loop basis, Gram blocks, grid weights and near-field pre-correction of
  * pfft_setup and copies named arrays out.  Names (element type): "sizes"

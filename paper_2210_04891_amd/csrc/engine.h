@@ -19,6 +19,28 @@ struct DeviceError {
 void set_error(const std::string &msg);
 void hip_ok(hipError_t e, const char *what);
 
+// Per-stage HIP-event timing of the hot path (enabled with pfft_profile).
+enum Stage {
+  ST_LOOP_TO_BRANCH = 0, ST_TRI_CURRENT, ST_PROJECT, ST_FFT_X, ST_FFT_Y, ST_FFT_Z_CONV, ST_IFFT_Y,
+  ST_IFFT_X, ST_INTERP, ST_COMBINE, ST_BRANCH_TO_LOOP, ST_PRECOND, ST_COUNT
+};
+
+struct StageTimer {
+  bool on = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  double ms[ST_COUNT] = {0};
+  long long calls[ST_COUNT] = {0};
+  int open_stage = -1;
+  hipEvent_t open_ev = nullptr;
+  void begin(int s, hipStream_t st);
+  void end(hipStream_t st);
+  void collect();   // waits for recorded events, folds them into ms/calls
+};
+
 struct Precond;   // nodal-route preconditioner factors (one per frequency)
 struct Learned;   // learned correction network
 
@@ -42,6 +64,7 @@ struct pfft_ctx {
           *ws_yb = nullptr, *ws_coef = nullptr;
   void *ws_J = nullptr, *ws_Q = nullptr, *ws_T1 = nullptr, *ws_T2 = nullptr;
   std::vector<double2> host_coef;
+  pfft::StageTimer timer;
   // solver state
   pfft::Precond *pre = nullptr;
   pfft::Learned *learned = nullptr;

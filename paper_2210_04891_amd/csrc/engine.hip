@@ -24,6 +24,44 @@ void hip_ok(hipError_t e, const char *what) {
 
 static constexpr double MU0 = 4e-7 * M_PI;
 
+void StageTimer::begin(int s, hipStream_t st) {
+  if (!on) return;
+  end(st);
+  hip_ok(hipEventCreate(&open_ev), "hipEventCreate");
+  hip_ok(hipEventRecord(open_ev, st), "hipEventRecord");
+  open_stage = s;
+}
+
+void StageTimer::end(hipStream_t st) {
+  if (!on || open_stage < 0) return;
+  hipEvent_t e;
+  hip_ok(hipEventCreate(&e), "hipEventCreate");
+  hip_ok(hipEventRecord(e, st), "hipEventRecord");
+  pending.push_back(Rec{open_stage, open_ev, e});
+  open_stage = -1;
+  open_ev = nullptr;
+}
+
+void StageTimer::collect() {
+  for (auto &r : pending) {
+    hip_ok(hipEventSynchronize(r.b), "hipEventSynchronize");
+    float t = 0;
+    hip_ok(hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime");
+    ms[r.stage] += t;
+    calls[r.stage] += 1;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  pending.clear();
+}
+
+struct TimerHook : PassHook {
+  StageTimer *t;
+  explicit TimerHook(StageTimer *tt) : t(tt) {}
+  void pass(int k, hipStream_t st) override { t->begin(ST_FFT_X + k, st); }
+  void done(hipStream_t st) override { t->end(st); }
+};
+
 }  // namespace pfft
 
 using namespace pfft;
@@ -100,7 +138,10 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
     const double2 *xc = x + (size_t)r0 * dim;
     double2 *yc = y + (size_t)r0 * dim;
     const double2 *alpha;
+    TimerHook hook(&timer);
+    PassHook *hk = timer.on ? &hook : nullptr;
     if (space == 1) {
+      timer.begin(ST_LOOP_TO_BRANCH, st);
       loop_to_branch(lm, xc, ws_alpha, ws_scan, ws_part, Rn, st);
       alpha = ws_alpha;
     } else {
@@ -108,14 +149,22 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
     }
     if (mode & 1) {
       if (grid_fp64) {
+        timer.begin(ST_TRI_CURRENT, st);
         tri_currents<double>(gm, alpha, (double2 *)ws_J, Rn, st);
+        timer.begin(ST_PROJECT, st);
         project<double>(gm, (double2 *)ws_J, (double2 *)ws_Q, Rn, st);
-        convolve<double>(gm, (double2 *)ws_Q, (double2 *)ws_T1, (double2 *)ws_T2, Rn, st);
+        timer.end(st);
+        convolve<double>(gm, (double2 *)ws_Q, (double2 *)ws_T1, (double2 *)ws_T2, Rn, st, hk);
+        timer.begin(ST_INTERP, st);
         interp_tri<double>(gm, (double2 *)ws_Q, ws_U, Rn, st);
       } else {
+        timer.begin(ST_TRI_CURRENT, st);
         tri_currents<float>(gm, alpha, (float2 *)ws_J, Rn, st);
+        timer.begin(ST_PROJECT, st);
         project<float>(gm, (float2 *)ws_J, (float2 *)ws_Q, Rn, st);
-        convolve<float>(gm, (float2 *)ws_Q, (float2 *)ws_T1, (float2 *)ws_T2, Rn, st);
+        timer.end(st);
+        convolve<float>(gm, (float2 *)ws_Q, (float2 *)ws_T1, (float2 *)ws_T2, Rn, st, hk);
+        timer.begin(ST_INTERP, st);
         interp_tri<float>(gm, (float2 *)ws_Q, ws_U, Rn, st);
       }
     }
@@ -127,13 +176,18 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
         host_coef[r] = make_double2(a, a);
         host_coef[Rc + r] = make_double2(0.0, om * MU0 * mu_r / (4.0 * M_PI));
       }
+      timer.end(st);
       hip_ok(hipMemcpyAsync(ws_coef, host_coef.data(), sizeof(double2) * 2 * Rc, hipMemcpyHostToDevice, st),
              "coef upload");
+      timer.begin(ST_COMBINE, st);
       combine(cm, alpha, ws_U, zs, jw, ws_yb, Rn, mode, st);
+      timer.begin(ST_BRANCH_TO_LOOP, st);
       branch_to_loop(lm, ws_yb, yc, ws_scan, ws_part, Rn, st);
     } else {
+      timer.begin(ST_COMBINE, st);
       combine(cm, alpha, ws_U, zs, jw, yc, Rn, mode, st);
     }
+    timer.end(st);
   }
   hip_ok(hipGetLastError(), "matvec launch");
 }
@@ -453,6 +507,43 @@ pfft_status pfft_matvec(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t 
     return (pfft_status)e.code;
   } catch (const SetupError &e) {
     set_error("pfft_matvec: " + e.msg);
+    return (pfft_status)e.code;
+  }
+}
+
+pfft_status pfft_profile(pfft_ctx *c, int32_t enable) {
+  if (!c) {
+    set_error("pfft_profile: null context");
+    return PFFT_EINVAL;
+  }
+  try {
+    c->timer.collect();
+    c->timer.on = enable != 0;
+    for (int i = 0; i < ST_COUNT; ++i) {
+      c->timer.ms[i] = 0;
+      c->timer.calls[i] = 0;
+    }
+    return PFFT_OK;
+  } catch (const DeviceError &e) {
+    set_error("pfft_profile: " + e.msg);
+    return (pfft_status)e.code;
+  }
+}
+
+pfft_status pfft_stage_times(pfft_ctx *c, double ms[16], int64_t calls[16]) {
+  if (!c || !ms || !calls) {
+    set_error("pfft_stage_times: null argument");
+    return PFFT_EINVAL;
+  }
+  try {
+    c->timer.collect();
+    for (int i = 0; i < 16; ++i) {
+      ms[i] = i < ST_COUNT ? c->timer.ms[i] : 0.0;
+      calls[i] = i < ST_COUNT ? c->timer.calls[i] : 0;
+    }
+    return PFFT_OK;
+  } catch (const DeviceError &e) {
+    set_error("pfft_stage_times: " + e.msg);
     return (pfft_status)e.code;
   }
 }

@@ -55,8 +55,14 @@ template <typename T>
 void tri_currents(const GridMaps &g, const double2 *alpha, V2<T> *J, int R, hipStream_t st);
 template <typename T>
 void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st);
+// Called between the five FFT passes (stage numbers 3..7) for timing.
+struct PassHook {
+  virtual void pass(int k, hipStream_t st) = 0;
+  virtual void done(hipStream_t st) = 0;
+};
 template <typename T>
-void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStream_t st);
+void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStream_t st,
+              PassHook *hook = nullptr);
 template <typename T>
 void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStream_t st);
 

@@ -440,20 +440,26 @@ static void fft_axis(const V2<T> *in, V2<T> *out, long A, long C, int n_in, int 
 }
 
 template <typename T>
-void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStream_t st) {
+void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStream_t st, PassHook *hook) {
   const int Nx = g.dims[0], Ny = g.dims[1], Nz = g.dims[2];
   long ch = 3L * R;
   // X forward: [ch][Nx][Ny*Nz] -> [ch][2Nx][Ny*Nz]
+  if (hook) hook->pass(0, st);
   fft_axis<T>(Q, T1, ch, (long)Ny * Nz, Nx, 2 * Nx, 2 * Nx, -1, 1.0f, nullptr, nullptr, st);
   // Y forward: [ch*2Nx][Ny][Nz] -> [ch*2Nx][2Ny][Nz]
+  if (hook) hook->pass(1, st);
   fft_axis<T>(T1, T2, ch * 2 * Nx, Nz, Ny, 2 * Ny, 2 * Ny, -1, 1.0f, nullptr, nullptr, st);
   // Z forward, multiply, inverse, crop: [ch*2Nx*2Ny][Nz] in place
+  if (hook) hook->pass(2, st);
   fft_axis<T>(T2, T2, ch * 4L * Nx * Ny, 1, Nz, Nz, 2 * Nz, -1, 1.0f / (2.0f * Nz),
               (const T *)g.ghat, g.dims, st);
   // Y inverse, crop: [ch*2Nx][2Ny][Nz] -> [ch*2Nx][Ny][Nz]
+  if (hook) hook->pass(3, st);
   fft_axis<T>(T2, T1, ch * 2 * Nx, Nz, 2 * Ny, Ny, 2 * Ny, +1, 1.0f / (2.0f * Ny), nullptr, nullptr, st);
   // X inverse, crop: [ch][2Nx][Ny*Nz] -> [ch][Nx][Ny*Nz]
+  if (hook) hook->pass(4, st);
   fft_axis<T>(T1, Q, ch, (long)Ny * Nz, 2 * Nx, Nx, 2 * Nx, +1, 1.0f / (2.0f * Nx), nullptr, nullptr, st);
+  if (hook) hook->done(st);
 }
 
 void fft3_full_fp64(double2 *data, const int d2[3], hipStream_t st) {
@@ -575,8 +581,8 @@ template void tri_currents<float>(const GridMaps &, const double2 *, V2<float> *
 template void tri_currents<double>(const GridMaps &, const double2 *, V2<double> *, int, hipStream_t);
 template void project<float>(const GridMaps &, const V2<float> *, V2<float> *, int, hipStream_t);
 template void project<double>(const GridMaps &, const V2<double> *, V2<double> *, int, hipStream_t);
-template void convolve<float>(const GridMaps &, V2<float> *, V2<float> *, V2<float> *, int, hipStream_t);
-template void convolve<double>(const GridMaps &, V2<double> *, V2<double> *, V2<double> *, int, hipStream_t);
+template void convolve<float>(const GridMaps &, V2<float> *, V2<float> *, V2<float> *, int, hipStream_t, PassHook *);
+template void convolve<double>(const GridMaps &, V2<double> *, V2<double> *, V2<double> *, int, hipStream_t, PassHook *);
 template void interp_tri<float>(const GridMaps &, const V2<float> *, double2 *, int, hipStream_t);
 template void interp_tri<double>(const GridMaps &, const V2<double> *, double2 *, int, hipStream_t);
 template void fold_spectrum<float>(const double2 *, float *, const int *, hipStream_t);

@@ -1,0 +1,73 @@
+// Preconditioner P = A diag(Z_b) A^T (Eq. Precond) applied through the node
+// space.  For e = E_L y (loop EMFs placed on the links) and D = diag(Z_b):
+//     P^-1 y = E_L^T [ D^-1 e - D^-1 N^T (N D^-1 N^T)^-1 N D^-1 e ]
+// (the loop-space and node-space projectors are complementary), so one solve
+// with the nodal matrix L_w = N D^-1 N^T replaces the factorization of P.  A
+// port's zero-impedance source branch ties its sink node to its source node
+// (supernode with a known potential offset); one node per conductor is
+// grounded.  L_w is factored on the host (reverse Cuthill-McKee order per
+// conductor, envelope LDL^T without pivoting: Re L_w is positive definite)
+// and solved on the device.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <map>
+#include <vector>
+
+#include "model.h"
+
+namespace pfft {
+
+struct PrecondStruct {
+  int nu = 0;                     // unknowns (merged, grounded nodes removed)
+  int ncomp = 0;
+  int W = 0;                      // max envelope width
+  std::vector<int> comp_off;      // [ncomp+1] unknown ranges
+  std::vector<int> first;         // [nu] first column of each row's envelope
+  std::vector<int64_t> env_off;   // [nu+1]
+  // branch data (mesh edges)
+  std::vector<int> br_ru, br_rv;  // unknown of merged end nodes (-1: ground)
+  std::vector<int> br_link;       // link index or -1
+  std::vector<int> br_offu, br_offv;  // port whose EMF offsets the end node (-1: none)
+  // unknown -> incident branches (sign +1 leaving, -1 entering)
+  std::vector<int> inc_off, inc_br;
+  std::vector<int8_t> inc_sg;
+  // source node of each port -> incident mesh branches (unmerged)
+  std::vector<int> src_off, src_br;
+  std::vector<int8_t> src_sg;
+  // per link: branch id (mesh) or -(port+1)
+  std::vector<int> link_kind;
+  std::vector<int> port_loop;
+};
+
+void build_precond_struct(const HostModel &m, PrecondStruct &ps);
+
+// Factor for one angular frequency: envelope values (unit lower L), diagonal
+// and the branch admittances 1/D_e.  Returns false on a zero pivot.
+bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, double sigma, double mu_r,
+                    std::vector<std::complex<double>> &env, std::vector<std::complex<double>> &diag,
+                    std::vector<std::complex<double>> &yinv);
+
+struct PrecondDev {
+  int nu, ncomp, W, b, l, p, nf;
+  const int *comp_off, *first;
+  const int64_t *env_off;
+  const double2 *env;    // [nf][nnz_env]
+  const double2 *diag;   // [nf][nu]
+  const double2 *yinv;   // [nf][b]
+  const int *br_ru, *br_rv, *br_link, *br_offu, *br_offv;
+  const int *inc_off, *inc_br;
+  const int8_t *inc_sg;
+  const int *src_off, *src_br;
+  const int8_t *src_sg;
+  const int *link_kind, *port_loop;
+  int64_t nnz_env;
+};
+
+// z = P^-1 y for R right-hand sides; fidx[r] selects the factor of RHS r
+// (device array).  work: [R][nu] complex128 scratch.
+void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, double2 *z, double2 *work, int R,
+                   hipStream_t st);
+
+}  // namespace pfft

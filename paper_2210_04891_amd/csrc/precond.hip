@@ -1,0 +1,403 @@
+// Preconditioner of Eq. Precond through the node space (see precond.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <deque>
+#include <numeric>
+
+#include "precond.h"
+
+namespace pfft {
+
+typedef std::complex<double> cd;
+static constexpr double MU0 = 4e-7 * M_PI;
+
+// ---------------------------------------------------------------------------
+// structure: supernodes, grounds, reverse Cuthill-McKee order, envelope
+// ---------------------------------------------------------------------------
+void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
+  const int nn = m.nn, b = m.b, p = m.p;
+  // ports: sink node merged into source node, phi_K = phi_S - s_k
+  std::vector<int> rep(nn), off_port(nn, -1), role(nn, 0);
+  std::iota(rep.begin(), rep.end(), 0);
+  for (int k = 0; k < p; ++k) {
+    int K = m.bu[b + k], S = m.bv[b + k];
+    if (++role[K] > 1 || ++role[S] > 1)
+      throw SetupError{-1, "preconditioner: a contact face serves more than one port"};
+    if (K == S) throw SetupError{-1, "preconditioner: port source and sink faces coincide"};
+    rep[K] = S;
+    off_port[K] = k;
+  }
+  // conductor components over mesh branches
+  std::vector<int> comp(nn, -1);
+  {
+    std::vector<std::vector<int>> adj(nn);
+    for (int e = 0; e < b; ++e)
+      if (m.bu[e] != m.bv[e]) {
+        adj[m.bu[e]].push_back(m.bv[e]);
+        adj[m.bv[e]].push_back(m.bu[e]);
+      }
+    int nc = 0;
+    for (int r = 0; r < nn; ++r) {
+      if (comp[r] >= 0) continue;
+      std::deque<int> dq{r};
+      comp[r] = nc;
+      while (!dq.empty()) {
+        int x = dq.front();
+        dq.pop_front();
+        for (int y : adj[x])
+          if (comp[y] < 0) { comp[y] = nc; dq.push_back(y); }
+      }
+      ++nc;
+    }
+    ps.ncomp = nc;
+  }
+  // merged-node adjacency (mesh branches whose ends are different supernodes)
+  std::vector<std::vector<int>> madj(nn);
+  for (int e = 0; e < b; ++e) {
+    int a = rep[m.bu[e]], c = rep[m.bv[e]];
+    if (a != c) { madj[a].push_back(c); madj[c].push_back(a); }
+  }
+  for (auto &v : madj) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  // ground: lowest merged node of each conductor
+  std::vector<int> ground(ps.ncomp, -1);
+  for (int x = 0; x < nn; ++x)
+    if (rep[x] == x && ground[comp[x]] < 0) ground[comp[x]] = x;
+  // RCM per conductor
+  std::vector<int> unk(nn, -1);
+  ps.comp_off.assign(ps.ncomp + 1, 0);
+  int next = 0;
+  std::vector<std::vector<int>> members(ps.ncomp);
+  for (int x = 0; x < nn; ++x)
+    if (rep[x] == x && x != ground[comp[x]]) members[comp[x]].push_back(x);
+  std::vector<int> mark(nn, -1), dist(nn, -1);
+  auto deg = [&](int x) {
+    int d = 0;
+    for (int y : madj[x]) d += (y != ground[comp[x]]);
+    return d;
+  };
+  for (int c = 0; c < ps.ncomp; ++c) {
+    ps.comp_off[c] = next;
+    auto &mem = members[c];
+    if (mem.empty()) continue;
+    int gnd = ground[c];
+    auto bfs = [&](int start, std::vector<int> &ord) {
+      ord.clear();
+      ord.push_back(start);
+      mark[start] = start * 2 + c;  // unique stamp per call
+      size_t h = 0;
+      while (h < ord.size()) {
+        int x = ord[h++];
+        std::vector<int> nb;
+        for (int y : madj[x])
+          if (y != gnd && mark[y] != start * 2 + c) nb.push_back(y);
+        std::sort(nb.begin(), nb.end(), [&](int a, int bq) {
+          int da = deg(a), db = deg(bq);
+          return da != db ? da < db : a < bq;
+        });
+        for (int y : nb)
+          if (mark[y] != start * 2 + c) { mark[y] = start * 2 + c; ord.push_back(y); }
+      }
+    };
+    // pseudo-peripheral start: min degree, then the last node of two BFS sweeps
+    int s0 = mem[0];
+    for (int x : mem)
+      if (deg(x) < deg(s0)) s0 = x;
+    std::vector<int> ord;
+    for (int it = 0; it < 2; ++it) {
+      bfs(s0, ord);
+      for (int x : mem) mark[x] = -1;
+      s0 = ord.back();
+    }
+    bfs(s0, ord);
+    for (int x : mem) mark[x] = -1;
+    // unreachable members (a conductor split only by a grounded node) follow
+    std::vector<int> seen(ord.begin(), ord.end());
+    std::sort(seen.begin(), seen.end());
+    for (int x : mem)
+      if (!std::binary_search(seen.begin(), seen.end(), x)) ord.push_back(x);
+    std::reverse(ord.begin(), ord.end());
+    for (int x : ord) unk[x] = next++;
+  }
+  ps.comp_off[ps.ncomp] = next;
+  ps.nu = next;
+  const int nu = ps.nu;
+  // envelope
+  ps.first.assign(nu, 0);
+  for (int x = 0; x < nn; ++x) {
+    if (unk[x] < 0) continue;
+    int i = unk[x], f = i;
+    for (int y : madj[x])
+      if (unk[y] >= 0) f = std::min(f, unk[y]);
+    ps.first[i] = f;
+  }
+  ps.env_off.assign(nu + 1, 0);
+  ps.W = 0;
+  for (int i = 0; i < nu; ++i) {
+    ps.env_off[i + 1] = ps.env_off[i] + (i - ps.first[i]);
+    ps.W = std::max(ps.W, i - ps.first[i]);
+  }
+  // branches
+  ps.br_ru.resize(b);
+  ps.br_rv.resize(b);
+  ps.br_link.assign(b, -1);
+  ps.br_offu.resize(b);
+  ps.br_offv.resize(b);
+  for (int i = 0; i < m.l; ++i)
+    if (m.links[i] < b) ps.br_link[m.links[i]] = i;
+  std::vector<int> cnt(nu + 1, 0);
+  for (int e = 0; e < b; ++e) {
+    int a = rep[m.bu[e]], c = rep[m.bv[e]];
+    ps.br_ru[e] = unk[a];
+    ps.br_rv[e] = unk[c];
+    ps.br_offu[e] = off_port[m.bu[e]];
+    ps.br_offv[e] = off_port[m.bv[e]];
+    if (a != c) {
+      if (unk[a] >= 0) cnt[unk[a] + 1]++;
+      if (unk[c] >= 0) cnt[unk[c] + 1]++;
+    }
+  }
+  for (int i = 0; i < nu; ++i) cnt[i + 1] += cnt[i];
+  ps.inc_off = cnt;
+  ps.inc_br.resize(cnt[nu]);
+  ps.inc_sg.resize(cnt[nu]);
+  {
+    std::vector<int> f(cnt.begin(), cnt.end() - 1);
+    for (int e = 0; e < b; ++e) {
+      int a = rep[m.bu[e]], c = rep[m.bv[e]];
+      if (a == c) continue;
+      if (unk[a] >= 0) { ps.inc_br[f[unk[a]]] = e; ps.inc_sg[f[unk[a]]++] = 1; }
+      if (unk[c] >= 0) { ps.inc_br[f[unk[c]]] = e; ps.inc_sg[f[unk[c]]++] = -1; }
+    }
+  }
+  // source nodes: incident mesh branches (unmerged)
+  ps.src_off.assign(p + 1, 0);
+  ps.src_br.clear();
+  ps.src_sg.clear();
+  for (int k = 0; k < p; ++k) {
+    int S = m.bv[b + k];
+    for (int e = 0; e < b; ++e) {
+      if (m.bu[e] == m.bv[e]) continue;
+      if (m.bu[e] == S) { ps.src_br.push_back(e); ps.src_sg.push_back(1); }
+      else if (m.bv[e] == S) { ps.src_br.push_back(e); ps.src_sg.push_back(-1); }
+    }
+    ps.src_off[k + 1] = (int)ps.src_br.size();
+  }
+  ps.link_kind.resize(m.l);
+  for (int i = 0; i < m.l; ++i) ps.link_kind[i] = m.links[i] < b ? m.links[i] : -(m.links[i] - b + 1);
+  ps.port_loop = m.port_loop;
+}
+
+bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, double sigma, double mu_r,
+                    std::vector<cd> &env, std::vector<cd> &diag, std::vector<cd> &yinv) {
+  const int b = m.b, nu = ps.nu;
+  double a = std::sqrt(omega * MU0 * mu_r / (2.0 * sigma));
+  cd zs(a, a), jw(0.0, omega * MU0 * mu_r / (4.0 * M_PI));
+  yinv.assign(b, 0.0);
+  for (int e = 0; e < b; ++e) {
+    double g = 0;
+    for (int q = 0; q < 5; ++q)
+      if (m.gram_col[5 * e + q] == e) g += m.gram_val[5 * e + q];
+    cd D = zs * g + jw * m.kdiag[e];
+    if (std::abs(D) == 0.0) return false;
+    yinv[e] = 1.0 / D;
+  }
+  env.assign(ps.env_off[nu], 0.0);
+  diag.assign(nu, 0.0);
+  for (int e = 0; e < b; ++e) {
+    int ru = ps.br_ru[e], rv = ps.br_rv[e];
+    bool self = (ru == rv) && ru >= 0;
+    if (self) continue;
+    // a branch whose two ends are the same supernode (ground included) does
+    // not enter the nodal matrix
+    if (ru < 0 && rv < 0) continue;
+    cd y = yinv[e];
+    if (ru >= 0) diag[ru] += y;
+    if (rv >= 0) diag[rv] += y;
+    if (ru >= 0 && rv >= 0) {
+      int i = std::max(ru, rv), j = std::min(ru, rv);
+      env[ps.env_off[i] + (j - ps.first[i])] -= y;
+    }
+  }
+  // envelope LDL^T, row by row: w_k = L_ik D_k
+  std::vector<cd> w(ps.W + 1);
+  for (int i = 0; i < nu; ++i) {
+    int fi = ps.first[i];
+    cd *Li = &env[ps.env_off[i]];
+    for (int j = fi; j < i; ++j) {
+      int fj = ps.first[j];
+      const cd *Lj = &env[ps.env_off[j]];
+      cd u = Li[j - fi];
+      for (int k = std::max(fi, fj); k < j; ++k) u -= w[k - fi] * Lj[k - fj];
+      w[j - fi] = u;
+      Li[j - fi] = u / diag[j];
+    }
+    cd d = diag[i];
+    for (int k = fi; k < i; ++k) d -= w[k - fi] * Li[k - fi];
+    if (std::abs(d) == 0.0 || !std::isfinite(d.real()) || !std::isfinite(d.imag())) return false;
+    diag[i] = d;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// device side
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cdiv2(double2 a, double2 b) {
+  double den = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+
+// known part of branch e's current: (off_u - off_v + s_e) / D_e
+__device__ __forceinline__ double2 branch_known(const PrecondDev &d, const double2 *y, const double2 *yinv,
+                                                int e) {
+  double2 s = make_double2(0, 0);
+  int lk = d.br_link[e];
+  if (lk >= 0) s = y[lk];
+  int ou = d.br_offu[e], ov = d.br_offv[e];
+  if (ou >= 0) { double2 v = y[d.port_loop[ou]]; s.x -= v.x; s.y -= v.y; }
+  if (ov >= 0) { double2 v = y[d.port_loop[ov]]; s.x += v.x; s.y += v.y; }
+  return cmul2(s, yinv[e]);
+}
+
+__global__ void k_pre_rhs(PrecondDev d, const int *fidx, const double2 *y, double2 *work) {
+  int r = blockIdx.y;
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= d.nu) return;
+  const double2 *yr = y + (size_t)r * d.l;
+  const double2 *yinv = d.yinv + (size_t)fidx[r] * d.b;
+  double gx = 0, gy = 0;
+  for (int q = d.inc_off[x]; q < d.inc_off[x + 1]; ++q) {
+    double2 c = branch_known(d, yr, yinv, d.inc_br[q]);
+    double sg = d.inc_sg[q];
+    gx += sg * c.x;
+    gy += sg * c.y;
+  }
+  work[(size_t)r * d.nu + x] = make_double2(-gx, -gy);
+}
+
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+// One wavefront per (conductor, RHS): unit-lower forward solve, diagonal,
+// transposed backward solve, with a circular LDS window of WP >= W + 1 entries.
+template <int WP>
+__global__ void k_ldl_solve(PrecondDev d, const int *fidx, double2 *work) {
+  __shared__ double2 win[WP];
+  const int c = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const int lo = d.comp_off[c], hi = d.comp_off[c + 1];
+  if (lo >= hi) return;
+  const int f = fidx[r];
+  const double2 *env = d.env + (size_t)f * d.nnz_env;
+  const double2 *dg = d.diag + (size_t)f * d.nu;
+  double2 *x = work + (size_t)r * d.nu;
+  // forward: y_i = b_i - sum_j L_ij y_j
+  for (int i = lo; i < hi; ++i) {
+    int fi = d.first[i];
+    const double2 *Li = env + d.env_off[i];
+    double2 acc = make_double2(0, 0);
+    for (int j = fi + lane; j < i; j += 64) {
+      double2 lv = Li[j - fi], yv = win[j & (WP - 1)];
+      acc.x += lv.x * yv.x - lv.y * yv.y;
+      acc.y += lv.x * yv.y + lv.y * yv.x;
+    }
+    acc = wave_sum(acc);
+    __syncthreads();
+    if (lane == 0) {
+      double2 bi = x[i];
+      double2 yi = make_double2(bi.x - acc.x, bi.y - acc.y);
+      win[i & (WP - 1)] = yi;
+      x[i] = yi;
+    }
+    __syncthreads();
+  }
+  // backward on z = y / D: x_i = z_i - sum_{k > i} L_ki x_k, scattered by rows
+  int loaded = hi;  // window holds z_j for j in [loaded, hi)
+  auto load_to = [&](int target) {
+    while (loaded > target && loaded > lo) {
+      --loaded;
+      if (lane == 0) win[loaded & (WP - 1)] = cdiv2(x[loaded], dg[loaded]);
+    }
+  };
+  for (int i = hi - 1; i >= lo; --i) {
+    load_to(std::max(lo, i - d.W));
+    __syncthreads();
+    double2 xi = win[i & (WP - 1)];
+    if (lane == 0) x[i] = xi;
+    int fi = d.first[i];
+    const double2 *Li = env + d.env_off[i];
+    for (int j = fi + lane; j < i; j += 64) {
+      double2 lv = Li[j - fi];
+      double2 &t = win[j & (WP - 1)];
+      t.x -= lv.x * xi.x - lv.y * xi.y;
+      t.y -= lv.x * xi.y + lv.y * xi.x;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_pre_out(PrecondDev d, const int *fidx, const double2 *y, const double2 *work, double2 *z) {
+  int r = blockIdx.y;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.l) return;
+  const double2 *yr = y + (size_t)r * d.l;
+  const double2 *yinv = d.yinv + (size_t)fidx[r] * d.b;
+  const double2 *ph = work + (size_t)r * d.nu;
+  auto cur = [&](int e) {
+    double2 c = branch_known(d, yr, yinv, e);
+    int ru = d.br_ru[e], rv = d.br_rv[e];
+    if (ru != rv) {
+      double2 pu = ru >= 0 ? ph[ru] : make_double2(0, 0);
+      double2 pv = rv >= 0 ? ph[rv] : make_double2(0, 0);
+      double2 dp = cmul2(make_double2(pu.x - pv.x, pu.y - pv.y), yinv[e]);
+      c.x += dp.x;
+      c.y += dp.y;
+    }
+    return c;
+  };
+  int kind = d.link_kind[i];
+  double2 out;
+  if (kind >= 0) {
+    out = cur(kind);
+  } else {
+    int k = -kind - 1;
+    double ox = 0, oy = 0;
+    for (int q = d.src_off[k]; q < d.src_off[k + 1]; ++q) {
+      double2 c = cur(d.src_br[q]);
+      double sg = d.src_sg[q];
+      ox += sg * c.x;
+      oy += sg * c.y;
+    }
+    out = make_double2(ox, oy);
+  }
+  z[(size_t)r * d.l + i] = out;
+}
+
+void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, double2 *z, double2 *work, int R,
+                   hipStream_t st) {
+  k_pre_rhs<<<dim3((d.nu + 255) / 256, R), 256, 0, st>>>(d, fidx, y, work);
+  dim3 g(d.ncomp, R);
+  if (d.W < 128)
+    k_ldl_solve<128><<<g, 64, 0, st>>>(d, fidx, work);
+  else if (d.W < 512)
+    k_ldl_solve<512><<<g, 64, 0, st>>>(d, fidx, work);
+  else if (d.W < 2048)
+    k_ldl_solve<2048><<<g, 64, 0, st>>>(d, fidx, work);
+  else
+    k_ldl_solve<8192><<<g, 64, 0, st>>>(d, fidx, work);
+  k_pre_out<<<dim3((d.l + 255) / 256, R), 256, 0, st>>>(d, fidx, y, work, z);
+}
+
+}  // namespace pfft

@@ -1,21 +1,471 @@
-// Preconditioner (Eq. Precond), flexible GMRES and port solves (Sec. IV-A, V).
+// Flexible GMRES over all (frequency, port) right-hand sides at once
+// (Sec. IV-A: GMRES on Eq. FinalME with the preconditioner of Eq. Precond),
+// and the port solves / R-L extraction entry points (Sec. V).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <set>
+
 #include "engine.h"
+#include "precond.h"
+
+namespace pfft {
+
+struct Precond {
+  PrecondStruct ps;
+  bool built = false;
+  PrecondDev dev{};
+  std::vector<void *> allocs;
+  std::vector<double> omegas;            // factored frequencies (rad/s)
+  std::vector<int> fidx_host;            // factor index per RHS, as on the device
+  int cap_f = 0, cap_R = 0;
+  double2 *d_env = nullptr, *d_diag = nullptr, *d_yinv = nullptr, *d_work = nullptr, *d_tmp = nullptr;
+  int *d_fidx = nullptr;
+};
+
+}  // namespace pfft
 
 using namespace pfft;
 
+static void *pre_alloc(Precond *p, size_t bytes) {
+  void *ptr = nullptr;
+  hip_ok(hipMalloc(&ptr, bytes ? bytes : 16), "hipMalloc precond");
+  p->allocs.push_back(ptr);
+  return ptr;
+}
+
+template <typename V>
+static V *pre_upload(Precond *p, const std::vector<V> &h) {
+  V *d = (V *)pre_alloc(p, h.size() * sizeof(V));
+  if (!h.empty()) hip_ok(hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice), "upload precond");
+  return d;
+}
+
+static void precond_free(Precond *p) {
+  if (!p) return;
+  for (void *q : p->allocs) hipFree(q);
+  if (p->d_env) hipFree(p->d_env);
+  if (p->d_diag) hipFree(p->d_diag);
+  if (p->d_yinv) hipFree(p->d_yinv);
+  if (p->d_work) hipFree(p->d_work);
+  if (p->d_fidx) hipFree(p->d_fidx);
+  if (p->d_tmp) hipFree(p->d_tmp);
+  delete p;
+}
+
+void learned_free(pfft_ctx *c);
+
 void pfft_ctx_free(pfft_ctx *c) {
+  precond_free(c->pre);
+  learned_free(c);
   for (void *p : c->ws_allocs) hipFree(p);
   for (void *p : c->allocs) hipFree(p);
   delete c;
 }
 
+// Builds the structure once, factors every distinct frequency of omega[0..R)
+// and uploads the per-RHS factor index.
+static Precond *precond_prepare(pfft_ctx *c, int R, const double *omega, hipStream_t st) {
+  if (!c->pre) c->pre = new Precond();
+  Precond *P = c->pre;
+  const HostModel &m = c->m;
+  if (!P->built) {
+    build_precond_struct(m, P->ps);
+    if (P->ps.W >= 4096) throw SetupError{PFFT_EINVAL, "preconditioner envelope wider than 4096"};
+    PrecondDev &d = P->dev;
+    const PrecondStruct &ps = P->ps;
+    d.nu = ps.nu;
+    d.ncomp = ps.ncomp;
+    d.W = ps.W;
+    d.b = m.b;
+    d.l = m.l;
+    d.p = m.p;
+    d.comp_off = pre_upload(P, ps.comp_off);
+    d.first = pre_upload(P, ps.first);
+    d.env_off = pre_upload(P, ps.env_off);
+    d.nnz_env = ps.env_off[ps.nu];
+    d.br_ru = pre_upload(P, ps.br_ru);
+    d.br_rv = pre_upload(P, ps.br_rv);
+    d.br_link = pre_upload(P, ps.br_link);
+    d.br_offu = pre_upload(P, ps.br_offu);
+    d.br_offv = pre_upload(P, ps.br_offv);
+    d.inc_off = pre_upload(P, ps.inc_off);
+    d.inc_br = pre_upload(P, ps.inc_br);
+    d.inc_sg = pre_upload(P, ps.inc_sg);
+    d.src_off = pre_upload(P, ps.src_off);
+    d.src_br = pre_upload(P, ps.src_br);
+    d.src_sg = pre_upload(P, ps.src_sg);
+    d.link_kind = pre_upload(P, ps.link_kind);
+    d.port_loop = pre_upload(P, ps.port_loop);
+    P->built = true;
+  }
+  // distinct frequencies of this batch
+  std::vector<double> om(omega, omega + R);
+  std::vector<double> uniq = om;
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  if (uniq != P->omegas) {
+    const int nf = (int)uniq.size();
+    const size_t ne = P->ps.env_off[P->ps.nu];
+    std::vector<std::complex<double>> env(nf * ne), dg((size_t)nf * P->ps.nu), yi((size_t)nf * m.b);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+    for (int f = 0; f < nf; ++f) {
+      std::vector<std::complex<double>> e1, d1, y1;
+      if (!factor_precond(m, P->ps, uniq[f], c->sigma, c->mu_r, e1, d1, y1)) {
+        ++bad;
+        continue;
+      }
+      std::copy(e1.begin(), e1.end(), env.begin() + (size_t)f * ne);
+      std::copy(d1.begin(), d1.end(), dg.begin() + (size_t)f * P->ps.nu);
+      std::copy(y1.begin(), y1.end(), yi.begin() + (size_t)f * m.b);
+    }
+    if (bad) throw SetupError{PFFT_EFACTOR, "zero pivot in the nodal factorization"};
+    if (nf > P->cap_f) {
+      if (P->d_env) hipFree(P->d_env);
+      if (P->d_diag) hipFree(P->d_diag);
+      if (P->d_yinv) hipFree(P->d_yinv);
+      hip_ok(hipMalloc(&P->d_env, std::max<size_t>(16, ne * nf * sizeof(double2))), "hipMalloc env");
+      hip_ok(hipMalloc(&P->d_diag, std::max<size_t>(16, (size_t)P->ps.nu * nf * sizeof(double2))), "hipMalloc diag");
+      hip_ok(hipMalloc(&P->d_yinv, (size_t)m.b * nf * sizeof(double2)), "hipMalloc yinv");
+      P->cap_f = nf;
+    }
+    hip_ok(hipStreamSynchronize(st), "precond sync");
+    if (ne) hip_ok(hipMemcpy(P->d_env, env.data(), ne * nf * sizeof(double2), hipMemcpyHostToDevice), "env");
+    if (P->ps.nu)
+      hip_ok(hipMemcpy(P->d_diag, dg.data(), (size_t)P->ps.nu * nf * sizeof(double2), hipMemcpyHostToDevice), "diag");
+    hip_ok(hipMemcpy(P->d_yinv, yi.data(), (size_t)m.b * nf * sizeof(double2), hipMemcpyHostToDevice), "yinv");
+    P->omegas = uniq;
+    P->fidx_host.clear();
+    P->dev.env = P->d_env;
+    P->dev.diag = P->d_diag;
+    P->dev.yinv = P->d_yinv;
+    P->dev.nf = nf;
+  }
+  if (R > P->cap_R) {
+    hip_ok(hipStreamSynchronize(st), "precond realloc sync");
+    if (P->d_work) hipFree(P->d_work);
+    if (P->d_fidx) hipFree(P->d_fidx);
+    if (P->d_tmp) hipFree(P->d_tmp);
+    hip_ok(hipMalloc(&P->d_work, std::max<size_t>(16, (size_t)R * P->ps.nu * sizeof(double2))), "hipMalloc work");
+    hip_ok(hipMalloc(&P->d_fidx, (size_t)R * sizeof(int)), "hipMalloc fidx");
+    hip_ok(hipMalloc(&P->d_tmp, (size_t)R * m.l * sizeof(double2)), "hipMalloc tmp");
+    P->cap_R = R;
+    P->fidx_host.clear();
+  }
+  std::vector<int> fidx(R);
+  for (int r = 0; r < R; ++r)
+    fidx[r] = (int)(std::lower_bound(P->omegas.begin(), P->omegas.end(), om[r]) - P->omegas.begin());
+  if (fidx != P->fidx_host) {
+    hip_ok(hipMemcpyAsync(P->d_fidx, fidx.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "fidx");
+    hip_ok(hipStreamSynchronize(st), "fidx sync");
+    P->fidx_host = fidx;
+  }
+  return P;
+}
+
 pfft_status pfft_internal_precond_matvec(pfft_ctx *c, int R, const double *omega, int flags, const double2 *x,
                                          double2 *y, hipStream_t st) {
-  (void)c; (void)R; (void)omega; (void)flags; (void)x; (void)y; (void)st;
-  set_error("pfft_matvec: preconditioner not available");
-  return PFFT_EINVAL;
+  Precond *P = precond_prepare(c, R, omega, st);
+  if (flags & PFFT_PRECOND_ONLY) {
+    c->timer.begin(ST_PRECOND, st);
+    precond_apply(P->dev, P->d_fidx, x, y, P->d_work, R, st);
+    c->timer.end(st);
+  } else {
+    // Z_l x into y, then P^-1 through the preconditioner scratch
+    c->matvec(R, omega, 1, flags & (PFFT_FAR_ONLY | PFFT_NEAR_ONLY), x, P->d_tmp, st);
+    c->timer.begin(ST_PRECOND, st);
+    precond_apply(P->dev, P->d_fidx, P->d_tmp, y, P->d_work, R, st);
+    c->timer.end(st);
+  }
+  hip_ok(hipGetLastError(), "precond launch");
+  return PFFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched FGMRES kernels
+// ---------------------------------------------------------------------------
+// h[r][j] = <V[r][j], w[r]> (conjugate-linear in V) for j < k
+__global__ void k_mdot(const double2 *V, const double2 *w, double2 *h, int l, int ldV, int k, int hstride,
+                       const uint8_t *active) {
+  int j = blockIdx.x, r = blockIdx.y;
+  if (active && !active[r]) return;
+  const double2 *v = V + ((size_t)r * ldV + j) * l;
+  const double2 *ww = w + (size_t)r * l;
+  double sx = 0, sy = 0;
+  for (int i = threadIdx.x; i < l; i += blockDim.x) {
+    double2 a = v[i], b = ww[i];
+    sx += a.x * b.x + a.y * b.y;
+    sy += a.x * b.y - a.y * b.x;
+  }
+  __shared__ double shx[256], shy[256];
+  shx[threadIdx.x] = sx;
+  shy[threadIdx.x] = sy;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) { shx[threadIdx.x] += shx[threadIdx.x + s]; shy[threadIdx.x] += shy[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) h[(size_t)r * hstride + j] = make_double2(shx[0], shy[0]);
+}
+
+// w[r] -= sum_{j<k} h[r][j] V[r][j];  acc[r][j] += h[r][j] (optional)
+__global__ void k_maxpy(const double2 *V, double2 *w, const double2 *h, int l, int ldV, int k, int hstride,
+                        const uint8_t *active) {
+  int r = blockIdx.y;
+  if (active && !active[r]) return;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= l) return;
+  double2 acc = w[(size_t)r * l + i];
+  for (int j = 0; j < k; ++j) {
+    double2 a = V[((size_t)r * ldV + j) * l + i], c = h[(size_t)r * hstride + j];
+    acc.x -= c.x * a.x - c.y * a.y;
+    acc.y -= c.x * a.y + c.y * a.x;
+  }
+  w[(size_t)r * l + i] = acc;
+}
+
+// dst[r] = src[r] * s[r]   (s real, 1/norm; 0 when the norm vanished)
+__global__ void k_scale(const double2 *src, double2 *dst, const double2 *nrm2, int l, int dst_ld, int src_ld) {
+  int r = blockIdx.y;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= l) return;
+  double n = sqrt(fmax(nrm2[r].x, 0.0));
+  double s = n > 0 ? 1.0 / n : 0.0;
+  double2 v = src[(size_t)r * src_ld + i];
+  dst[(size_t)r * dst_ld + i] = make_double2(v.x * s, v.y * s);
+}
+
+// Column k of H: h (first pass) + h2 (second pass), H[k+1][k] = norm;
+// previous rotations, new rotation, residual estimate |g[k+1]|.
+__global__ void k_givens(double2 *H, const double2 *h1, const double2 *h2, const double2 *nrm2, double2 *cs,
+                         double2 *sn, double2 *g, double *resid, int k, int m, int R) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double2 *Hc = H + (size_t)r * (m + 1) * m;   // H[i][k] at Hc[i * m + k]
+  for (int i = 0; i <= k; ++i) {
+    double2 a = h1[(size_t)r * (m + 1) + i], b = h2[(size_t)r * (m + 1) + i];
+    Hc[i * m + k] = make_double2(a.x + b.x, a.y + b.y);
+  }
+  double nn = sqrt(fmax(nrm2[r].x, 0.0));
+  Hc[(k + 1) * m + k] = make_double2(nn, 0.0);
+  double2 *c = cs + (size_t)r * (m + 1), *s = sn + (size_t)r * (m + 1), *gg = g + (size_t)r * (m + 1);
+  for (int i = 0; i < k; ++i) {
+    double2 x = Hc[i * m + k], y = Hc[(i + 1) * m + k];
+    double2 ci = c[i], si = s[i];
+    // (x, y) -> (conj(c) x + conj(s) y, -s x + c y)
+    double2 t = make_double2(ci.x * x.x + ci.y * x.y + si.x * y.x + si.y * y.y,
+                             ci.x * x.y - ci.y * x.x + si.x * y.y - si.y * y.x);
+    double2 u = make_double2(-(si.x * x.x - si.y * x.y) + (ci.x * y.x - ci.y * y.y),
+                             -(si.x * x.y + si.y * x.x) + (ci.x * y.y + ci.y * y.x));
+    Hc[i * m + k] = t;
+    Hc[(i + 1) * m + k] = u;
+  }
+  double2 a = Hc[k * m + k], b = Hc[(k + 1) * m + k];
+  double den = sqrt(a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+  double2 ck = den > 0 ? make_double2(a.x / den, a.y / den) : make_double2(1, 0);
+  double2 sk = den > 0 ? make_double2(b.x / den, b.y / den) : make_double2(0, 0);
+  c[k] = ck;
+  s[k] = sk;
+  Hc[k * m + k] = make_double2(den, 0.0);
+  Hc[(k + 1) * m + k] = make_double2(0.0, 0.0);
+  double2 gk = gg[k];
+  gg[k + 1] = make_double2(-(sk.x * gk.x - sk.y * gk.y), -(sk.x * gk.y + sk.y * gk.x));
+  gg[k] = make_double2(ck.x * gk.x + ck.y * gk.y, ck.x * gk.y - ck.y * gk.x);
+  resid[r] = sqrt(gg[k + 1].x * gg[k + 1].x + gg[k + 1].y * gg[k + 1].y);
+}
+
+// y = H[0:kr,0:kr]^-1 g[0:kr] (upper triangular), kr per RHS
+__global__ void k_backsolve(const double2 *H, const double2 *g, double2 *y, const int *kr, int m, int R) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const double2 *Hc = H + (size_t)r * (m + 1) * m;
+  const double2 *gg = g + (size_t)r * (m + 1);
+  double2 *yy = y + (size_t)r * (m + 1);
+  int K = kr[r];
+  for (int i = K - 1; i >= 0; --i) {
+    double2 acc = gg[i];
+    for (int j = i + 1; j < K; ++j) {
+      double2 h = Hc[i * m + j], v = yy[j];
+      acc.x -= h.x * v.x - h.y * v.y;
+      acc.y -= h.x * v.y + h.y * v.x;
+    }
+    double2 d = Hc[i * m + i];
+    double den = d.x * d.x + d.y * d.y;
+    yy[i] = den > 0 ? make_double2((acc.x * d.x + acc.y * d.y) / den, (acc.y * d.x - acc.x * d.y) / den)
+                    : make_double2(0, 0);
+  }
+}
+
+// x[r] += sum_{j<kr} y[r][j] Z[r][j]
+__global__ void k_xupdate(double2 *x, const double2 *Z, const double2 *y, const int *kr, int l, int m) {
+  int r = blockIdx.y;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= l) return;
+  double2 acc = x[(size_t)r * l + i];
+  for (int j = 0; j < kr[r]; ++j) {
+    double2 zz = Z[((size_t)r * m + j) * l + i], c = y[(size_t)r * (m + 1) + j];
+    acc.x += c.x * zz.x - c.y * zz.y;
+    acc.y += c.x * zz.y + c.y * zz.x;
+  }
+  x[(size_t)r * l + i] = acc;
+}
+
+__global__ void k_residual(const double2 *b, const double2 *Ax, double2 *r, int n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n) return;
+  r[i] = make_double2(b[i].x - Ax[i].x, b[i].y - Ax[i].y);
+}
+
+__global__ void k_init_g(double2 *g, const double2 *nrm2, int m, int R) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  for (int i = 0; i <= m; ++i) g[(size_t)r * (m + 1) + i] = make_double2(0, 0);
+  g[(size_t)r * (m + 1)] = make_double2(sqrt(fmax(nrm2[r].x, 0.0)), 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES driver
+// ---------------------------------------------------------------------------
+namespace pfft {
+// learned correction: z = P^-1 v + |v| delta(v/|v|); defined in learned.hip
+bool learned_apply(pfft_ctx *c, int R, const double2 *v, double2 *z, hipStream_t st);
+}
+
+struct Fgmres {
+  int R, l, m;
+  double2 *V, *Z, *H, *cs, *sn, *g, *h1, *h2, *nrm, *yv, *x, *w, *b, *Ax;
+  double *resid;
+  int *kr;
+  std::vector<void *> al;
+  void *alloc(size_t bytes) {
+    void *p = nullptr;
+    hip_ok(hipMalloc(&p, bytes ? bytes : 16), "hipMalloc gmres");
+    al.push_back(p);
+    return p;
+  }
+  Fgmres(int R_, int l_, int m_) : R(R_), l(l_), m(m_) {
+    size_t vec = (size_t)R * l * sizeof(double2);
+    V = (double2 *)alloc(vec * (m + 1));
+    Z = (double2 *)alloc(vec * m);
+    H = (double2 *)alloc((size_t)R * (m + 1) * m * sizeof(double2));
+    cs = (double2 *)alloc((size_t)R * (m + 1) * sizeof(double2));
+    sn = (double2 *)alloc((size_t)R * (m + 1) * sizeof(double2));
+    g = (double2 *)alloc((size_t)R * (m + 1) * sizeof(double2));
+    h1 = (double2 *)alloc((size_t)R * (m + 1) * sizeof(double2));
+    h2 = (double2 *)alloc((size_t)R * (m + 1) * sizeof(double2));
+    yv = (double2 *)alloc((size_t)R * (m + 1) * sizeof(double2));
+    nrm = (double2 *)alloc((size_t)R * sizeof(double2));
+    x = (double2 *)alloc(vec);
+    w = (double2 *)alloc(vec);
+    b = (double2 *)alloc(vec);
+    Ax = (double2 *)alloc(vec);
+    resid = (double *)alloc((size_t)R * sizeof(double));
+    kr = (int *)alloc((size_t)R * sizeof(int));
+  }
+  ~Fgmres() {
+    for (void *p : al) hipFree(p);
+  }
+};
+
+// Solves Z_l(omega_r) x_r = b_r for all r; b is already in F.b.  precond: 0,
+// 1 (P), 2 (P + learned).  Returns per-RHS iterations and true residuals.
+static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int maxit, int precond,
+                   std::vector<int> &iters, std::vector<double> &relres, hipStream_t st) {
+  const int R = F.R, l = F.l, m = F.m;
+  const dim3 gl((l + 255) / 256, R);
+  Precond *P = precond ? precond_prepare(c, R, omega, st) : nullptr;
+  hip_ok(hipMemsetAsync(F.x, 0, (size_t)R * l * sizeof(double2), st), "x0");
+  iters.assign(R, 0);
+  relres.assign(R, 1.0);
+  std::vector<double> bnorm(R), res(R);
+  std::vector<uint8_t> done(R, 0);
+  std::vector<int> kconv(R, 0);
+  // |b|
+  k_mdot<<<dim3(1, R), 256, 0, st>>>(F.b, F.b, F.nrm, l, 1, 1, 1, nullptr);
+  {
+    std::vector<double2> n2(R);
+    hip_ok(hipMemcpyAsync(n2.data(), F.nrm, R * sizeof(double2), hipMemcpyDeviceToHost, st), "bnorm");
+    hip_ok(hipStreamSynchronize(st), "bnorm sync");
+    for (int r = 0; r < R; ++r) bnorm[r] = std::sqrt(std::max(n2[r].x, 0.0));
+  }
+  int total = 0;
+  // residual r0 = b (x0 = 0) in w
+  hip_ok(hipMemcpyAsync(F.w, F.b, (size_t)R * l * sizeof(double2), hipMemcpyDeviceToDevice, st), "r0");
+  bool all_done = false;
+  while (total < maxit && !all_done) {
+    std::vector<uint8_t> done_before = done;
+    std::vector<int> kthis(R, 0);   // Krylov length at convergence in this cycle
+    k_mdot<<<dim3(1, R), 256, 0, st>>>(F.w, F.w, F.nrm, l, 1, 1, 1, nullptr);
+    k_init_g<<<(R + 63) / 64, 64, 0, st>>>(F.g, F.nrm, m, R);
+    k_scale<<<gl, 256, 0, st>>>(F.w, F.V, F.nrm, l, (m + 1) * l, l);
+    int k = 0;
+    for (; k < m && total + k < maxit; ++k) {
+      // z_k = M(v_k): gather v_k of every RHS into w (contiguous), apply, store in Z
+      hip_ok(hipMemcpy2DAsync(F.w, l * sizeof(double2), F.V + (size_t)k * l, (m + 1) * l * sizeof(double2),
+                              l * sizeof(double2), R, hipMemcpyDeviceToDevice, st),
+             "gather v");
+      double2 *zk = F.Ax;  // contiguous [R][l]
+      if (precond == 2 && learned_apply(c, R, F.w, zk, st)) {
+      } else if (precond) {
+        precond_apply(P->dev, P->d_fidx, F.w, zk, P->d_work, R, st);
+      } else {
+        hip_ok(hipMemcpyAsync(zk, F.w, (size_t)R * l * sizeof(double2), hipMemcpyDeviceToDevice, st), "noprec");
+      }
+      hip_ok(hipMemcpy2DAsync(F.Z + (size_t)k * l, m * l * sizeof(double2), zk, l * sizeof(double2),
+                              l * sizeof(double2), R, hipMemcpyDeviceToDevice, st),
+             "store z");
+      // w = Z_l z_k
+      c->matvec(R, omega, 1, 0, zk, F.w, st);
+      // classical Gram-Schmidt, twice
+      k_mdot<<<dim3(k + 1, R), 256, 0, st>>>(F.V, F.w, F.h1, l, m + 1, k + 1, m + 1, nullptr);
+      k_maxpy<<<gl, 256, 0, st>>>(F.V, F.w, F.h1, l, m + 1, k + 1, m + 1, nullptr);
+      k_mdot<<<dim3(k + 1, R), 256, 0, st>>>(F.V, F.w, F.h2, l, m + 1, k + 1, m + 1, nullptr);
+      k_maxpy<<<gl, 256, 0, st>>>(F.V, F.w, F.h2, l, m + 1, k + 1, m + 1, nullptr);
+      k_mdot<<<dim3(1, R), 256, 0, st>>>(F.w, F.w, F.nrm, l, 1, 1, 1, nullptr);
+      k_scale<<<gl, 256, 0, st>>>(F.w, F.V + (size_t)(k + 1) * l, F.nrm, l, (m + 1) * l, l);
+      k_givens<<<(R + 63) / 64, 64, 0, st>>>(F.H, F.h1, F.h2, F.nrm, F.cs, F.sn, F.g, F.resid, k, m, R);
+      hip_ok(hipMemcpyAsync(res.data(), F.resid, R * sizeof(double), hipMemcpyDeviceToHost, st), "resid");
+      hip_ok(hipStreamSynchronize(st), "resid sync");
+      bool all = true;
+      for (int r = 0; r < R; ++r) {
+        if (!done[r] && res[r] <= tol * bnorm[r]) {
+          done[r] = 1;
+          kthis[r] = k + 1;
+          iters[r] = total + k + 1;
+        }
+        all = all && done[r];
+      }
+      if (all) {
+        ++k;
+        break;
+      }
+    }
+    // x += Z y: converged in this cycle -> its own length, converged before ->
+    // unchanged, otherwise the full cycle
+    std::vector<int> kr(R);
+    for (int r = 0; r < R; ++r) kr[r] = done_before[r] ? 0 : (kthis[r] > 0 ? kthis[r] : k);
+    hip_ok(hipMemcpyAsync(F.kr, kr.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "kr");
+    k_backsolve<<<(R + 63) / 64, 64, 0, st>>>(F.H, F.g, F.yv, F.kr, m, R);
+    k_xupdate<<<gl, 256, 0, st>>>(F.x, F.Z, F.yv, F.kr, l, m);
+    total += k;
+    all_done = std::all_of(done.begin(), done.end(), [](uint8_t v) { return v != 0; });
+    // true residual: restart vector, and the reported residual at the end
+    c->matvec(R, omega, 1, 0, F.x, F.Ax, st);
+    k_residual<<<(unsigned)(((size_t)R * l + 255) / 256), 256, 0, st>>>(F.b, F.Ax, F.w, R * l);
+  }
+  // final true residuals
+  k_mdot<<<dim3(1, R), 256, 0, st>>>(F.w, F.w, F.nrm, l, 1, 1, 1, nullptr);
+  std::vector<double2> n2(R);
+  hip_ok(hipMemcpyAsync(n2.data(), F.nrm, R * sizeof(double2), hipMemcpyDeviceToHost, st), "final norm");
+  hip_ok(hipStreamSynchronize(st), "final sync");
+  for (int r = 0; r < R; ++r) {
+    relres[r] = std::sqrt(std::max(n2[r].x, 0.0)) / (bnorm[r] > 0 ? bnorm[r] : 1.0);
+    if (!done[r]) iters[r] = total;
+  }
 }
 
 extern "C" {
@@ -23,16 +473,63 @@ extern "C" {
 pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol, int32_t maxit,
                         int32_t restart, int32_t precond, void *Y_out, int32_t *iters_out, double *relres_out,
                         void *hip_stream) {
-  (void)c; (void)nfreq; (void)freq_hz; (void)tol; (void)maxit; (void)restart; (void)precond;
-  (void)Y_out; (void)iters_out; (void)relres_out; (void)hip_stream;
-  set_error("solve_ports: not available");
-  return PFFT_EINVAL;
-}
-
-pfft_status pfft_precond_load(pfft_ctx *c, const void *w, int64_t nbytes) {
-  (void)c; (void)w; (void)nbytes;
-  set_error("pfft_precond_load: not available");
-  return PFFT_EINVAL;
+  if (!c || nfreq <= 0 || !freq_hz || !Y_out || !(tol > 0) || maxit <= 0 || restart <= 0 || precond < 0 ||
+      precond > 2) {
+    set_error("solve_ports: bad argument");
+    return PFFT_EINVAL;
+  }
+  if (c->m.p == 0) {
+    set_error("solve_ports: the problem has no ports");
+    return PFFT_EINVAL;
+  }
+  for (int f = 0; f < nfreq; ++f)
+    if (!(freq_hz[f] > 0)) {
+      set_error("solve_ports: frequencies must be positive");
+      return PFFT_EINVAL;
+    }
+  try {
+    hip_ok(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int p = c->m.p, l = c->m.l, R = nfreq * p;
+    const int m = std::min(restart, maxit);
+    Fgmres F(R, l, m);
+    std::vector<double> omega(R);
+    std::vector<double2> bh((size_t)R * l, make_double2(0, 0));
+    for (int f = 0; f < nfreq; ++f)
+      for (int k = 0; k < p; ++k) {
+        int r = f * p + k;
+        omega[r] = 2.0 * M_PI * freq_hz[f];
+        bh[(size_t)r * l + c->m.port_loop[k]] = make_double2(1.0, 0.0);
+      }
+    hip_ok(hipMemcpyAsync(F.b, bh.data(), bh.size() * sizeof(double2), hipMemcpyHostToDevice, st), "b");
+    std::vector<int> iters;
+    std::vector<double> relres;
+    fgmres(c, F, omega.data(), tol, maxit, precond, iters, relres, st);
+    std::vector<double2> xh((size_t)R * l);
+    hip_ok(hipMemcpyAsync(xh.data(), F.x, xh.size() * sizeof(double2), hipMemcpyDeviceToHost, st), "x");
+    hip_ok(hipStreamSynchronize(st), "x sync");
+    double2 *Y = (double2 *)Y_out;
+    bool ok = true;
+    for (int f = 0; f < nfreq; ++f)
+      for (int k = 0; k < p; ++k) {
+        int r = f * p + k;
+        for (int j = 0; j < p; ++j) Y[((size_t)f * p + j) * p + k] = xh[(size_t)r * l + c->m.port_loop[j]];
+        if (iters_out) iters_out[f * p + k] = iters[r];
+        if (relres_out) relres_out[f * p + k] = relres[r];
+        ok = ok && relres[r] <= tol * 1.0001 + 1e-15;
+      }
+    if (!ok) {
+      set_error("solve_ports: some right-hand sides did not reach the tolerance");
+      return PFFT_ENOCONV;
+    }
+    return PFFT_OK;
+  } catch (const DeviceError &e) {
+    set_error("solve_ports: " + e.msg);
+    return (pfft_status)e.code;
+  } catch (const SetupError &e) {
+    set_error("solve_ports: " + e.msg);
+    return (pfft_status)e.code;
+  }
 }
 
 }  // extern "C"

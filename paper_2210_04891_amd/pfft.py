@@ -23,7 +23,11 @@ STATUS = {0: "PFFT_OK", -1: "PFFT_EINVAL", -2: "PFFT_ETOPO", -3: "PFFT_ENOMEM",
 
 EXPORTS = ("pfft_setup", "pfft_sizes", "pfft_matvec", "solve_ports", "extract_RL",
            "pfft_precond_load", "pfft_destroy", "pfft_last_error",
-           "pfft_host_setup", "pfft_host_get", "pfft_host_free")
+           "pfft_host_setup", "pfft_host_get", "pfft_host_free", "pfft_profile",
+           "pfft_stage_times")
+
+STAGES = ("loop_to_branch", "tri_current", "project", "fft_x", "fft_y", "fft_z_conv", "ifft_y",
+          "ifft_x", "interp", "combine", "branch_to_loop", "precond")
 
 
 class PfftError(RuntimeError):
@@ -79,6 +83,10 @@ def load():
     lib.pfft_host_get.restype = i32
     lib.pfft_host_free.argtypes = [vp]
     lib.pfft_host_free.restype = None
+    lib.pfft_profile.argtypes = [vp, i32]
+    lib.pfft_profile.restype = i32
+    lib.pfft_stage_times.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    lib.pfft_stage_times.restype = i32
     _lib = lib
     return lib
 
@@ -215,6 +223,16 @@ class Context:
                                          _ptr(Y), _ptr(it), _ptr(rr), _stream_handle(stream)),
                       allow=(-5,))
         return Y, it, rr, code
+
+    def profile(self, enable=True):
+        _check(load().pfft_profile(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        """{stage: (total ms, launches)} since the last profile() call."""
+        ms = (ctypes.c_double * 16)()
+        calls = (ctypes.c_int64 * 16)()
+        _check(load().pfft_stage_times(self._h, ms, calls))
+        return {name: (ms[i], int(calls[i])) for i, name in enumerate(STAGES)}
 
     def precond_load(self, weights_bf16):
         w = np.ascontiguousarray(weights_bf16)
