@@ -143,10 +143,11 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
     if (space == 1) {
       timer.begin(ST_LOOP_TO_BRANCH, st);
       loop_to_branch(lm, xc, ws_alpha, ws_scan, ws_part, Rn, st);
-      alpha = ws_alpha;
     } else {
-      alpha = xc;
+      timer.begin(ST_LOOP_TO_BRANCH, st);
+      transpose(xc, ws_alpha, Rn, m.b, st);
     }
+    alpha = ws_alpha;
     if (mode & 1) {
       if (grid_fp64) {
         timer.begin(ST_TRI_CURRENT, st);
@@ -185,7 +186,9 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
       branch_to_loop(lm, ws_yb, yc, ws_scan, ws_part, Rn, st);
     } else {
       timer.begin(ST_COMBINE, st);
-      combine(cm, alpha, ws_U, zs, jw, yc, Rn, mode, st);
+      combine(cm, alpha, ws_U, zs, jw, ws_yb, Rn, mode, st);
+      timer.begin(ST_BRANCH_TO_LOOP, st);
+      transpose(ws_yb, yc, m.b, Rn, st);
     }
     timer.end(st);
   }

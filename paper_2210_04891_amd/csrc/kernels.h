@@ -32,10 +32,13 @@ struct LoopMaps {
   int nn, b, l;
 };
 
+// x, yl: loop vectors [R][l]; alpha, yb: branch vectors RHS-contiguous [b][R].
 void loop_to_branch(const LoopMaps &mp, const double2 *x, double2 *alpha, double2 *scan,
                     double2 *partials, int R, hipStream_t st);
 void branch_to_loop(const LoopMaps &mp, const double2 *yb, double2 *yl, double2 *scan,
                     double2 *partials, int R, hipStream_t st);
+// out[c][r] = in[r][c] (complex128)
+void transpose(const double2 *in, double2 *out, int rows, int cols, hipStream_t st);
 
 struct GridMaps {
   int n, b, N, dims[3];
@@ -51,6 +54,7 @@ struct GridMaps {
   const void *ghat;      // [(Nx+1)(Ny+1)(Nz+1)] real spectrum in T
 };
 
+// alpha [b][R] -> J [R][n][4]
 template <typename T>
 void tri_currents(const GridMaps &g, const double2 *alpha, V2<T> *J, int R, hipStream_t st);
 template <typename T>
@@ -63,6 +67,7 @@ struct PassHook {
 template <typename T>
 void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStream_t st,
               PassHook *hook = nullptr);
+// phi [R][3][N] -> U [n][R][4]
 template <typename T>
 void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStream_t st);
 
@@ -83,7 +88,8 @@ struct CombineMaps {
   const double *gram_val;
 };
 
-// y[r][e] = zs[r] * (G a)[e] + jw[r] * (far[e] + (L_d a)[e]); far from U.
+// y[e][r] = zs[r] * (G a)[e] + jw[r] * (far[e] + (L_d a)[e]); far from U;
+// alpha, y RHS-contiguous [b][R], U [n][R][4].
 // mode bits: 1 far, 2 near, 4 gram (zs, jw ignored when gram bit is clear
 // and kscale = 1: y = far + near).
 void combine(const CombineMaps &c, const double2 *alpha, const double2 *U, const double2 *zs,

@@ -151,11 +151,12 @@ __global__ void k_inject(LoopMaps mp, const double2 *x, double2 *scan) {
   scan[(size_t)r * (mp.nn + 1) + k] = make_double2(sx, sy);
 }
 
-// after the exclusive scan: twig current = +-(P[hi] - P[lo]), link current = x
-__global__ void k_branch_out(LoopMaps mp, const double2 *x, const double2 *pfx, double2 *alpha) {
-  int r = blockIdx.y;
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= mp.b) return;
+// after the exclusive scan: twig current = +-(P[hi] - P[lo]), link current = x;
+// output alpha is RHS-contiguous: alpha[e][r]
+__global__ void k_branch_out(LoopMaps mp, const double2 *x, const double2 *pfx, double2 *alpha, int R) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)mp.b * R) return;
+  int e = (int)(idx / R), r = (int)(idx - (long)e * R);
   int a = mp.br_a[e];
   double2 v;
   if (a >= 0) {
@@ -166,47 +167,47 @@ __global__ void k_branch_out(LoopMaps mp, const double2 *x, const double2 *pfx, 
     double sg = mp.br_sg[e];
     v = make_double2(sg * (hi.x - lo.x), sg * (hi.y - lo.y));
   }
-  alpha[(size_t)r * mp.b + e] = v;
+  alpha[idx] = v;
 }
 
 void loop_to_branch(const LoopMaps &mp, const double2 *x, double2 *alpha, double2 *scan,
                     double2 *partials, int R, hipStream_t st) {
   k_inject<<<dim3(cdiv(mp.nn + 1, 256), R), 256, 0, st>>>(mp, x, scan);
   scan_rows(scan, scan, mp.nn + 1, mp.nn + 1, R, false, partials, st);
-  k_branch_out<<<dim3(cdiv(mp.b, 256), R), 256, 0, st>>>(mp, x, scan, alpha);
+  k_branch_out<<<cdiv((long)mp.b * R, 256), 256, 0, st>>>(mp, x, scan, alpha, R);
 }
 
 // ===========================================================================
 // A: branch voltages -> loop voltages (Eq. VolT) by a potential scan
 // ===========================================================================
-__device__ __forceinline__ double2 twig_drop(const LoopMaps &mp, const double2 *yb, int pos) {
+__device__ __forceinline__ double2 twig_drop(const LoopMaps &mp, const double2 *yb, int R, int pos) {
   int e = mp.pos_branch[pos];
   if (e < 0) return make_double2(0, 0);
-  double2 v = yb[e];
+  double2 v = yb[(size_t)e * R];
   double sg = mp.pos_sign[pos];
   return make_double2(sg * v.x, sg * v.y);
 }
 
-__global__ void k_drop_diff(LoopMaps mp, const double2 *yb, double2 *scan) {
+__global__ void k_drop_diff(LoopMaps mp, const double2 *yb, double2 *scan, int R) {
   int r = blockIdx.y;
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= mp.nn) return;
-  const double2 *y = yb + (size_t)r * mp.b;
-  double2 d = twig_drop(mp, y, k);
+  const double2 *y = yb + r;   // yb[e][r]
+  double2 d = twig_drop(mp, y, R, k);
   for (int q = mp.end_off[k]; q < mp.end_off[k + 1]; ++q) {
-    double2 z = twig_drop(mp, y, mp.end_pos[q]);
+    double2 z = twig_drop(mp, y, R, mp.end_pos[q]);
     d.x -= z.x;
     d.y -= z.y;
   }
   scan[(size_t)r * (mp.nn + 1) + k] = d;
 }
 
-__global__ void k_link_out(LoopMaps mp, const double2 *yb, const double2 *D, double2 *yl) {
+__global__ void k_link_out(LoopMaps mp, const double2 *yb, const double2 *D, double2 *yl, int R) {
   int r = blockIdx.y;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= mp.l) return;
   int e = mp.link_branch[i];
-  double2 v = e < mp.b ? yb[(size_t)r * mp.b + e] : make_double2(0, 0);
+  double2 v = e < mp.b ? yb[(size_t)e * R + r] : make_double2(0, 0);
   int up = mp.link_upos[i], vp = mp.link_vpos[i];
   if (up >= 0) {
     const double2 *Dr = D + (size_t)r * (mp.nn + 1);
@@ -218,23 +219,22 @@ __global__ void k_link_out(LoopMaps mp, const double2 *yb, const double2 *D, dou
 
 void branch_to_loop(const LoopMaps &mp, const double2 *yb, double2 *yl, double2 *scan,
                     double2 *partials, int R, hipStream_t st) {
-  k_drop_diff<<<dim3(cdiv(mp.nn, 256), R), 256, 0, st>>>(mp, yb, scan);
+  k_drop_diff<<<dim3(cdiv(mp.nn, 256), R), 256, 0, st>>>(mp, yb, scan, R);
   scan_rows(scan, scan, mp.nn, mp.nn + 1, R, true, partials, st);
-  k_link_out<<<dim3(cdiv(mp.l, 256), R), 256, 0, st>>>(mp, yb, scan, yl);
+  k_link_out<<<dim3(cdiv(mp.l, 256), R), 256, 0, st>>>(mp, yb, scan, yl, R);
 }
 
 // ===========================================================================
 // per-triangle current moments: J = (c0, d) / (2A), c0 = sum s a, d = sum s a (p - c)
 // ===========================================================================
 template <typename T>
-__global__ void k_tri_current(GridMaps g, const double2 *alpha, V2<T> *J) {
-  int r = blockIdx.y;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.n) return;
-  const double2 *a = alpha + (size_t)r * g.b;
+__global__ void k_tri_current(GridMaps g, const double2 *alpha, V2<T> *J, int R) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)g.n * R) return;
+  int t = (int)(idx / R), r = (int)(idx - (long)t * R);
   double c0x = 0, c0y = 0, dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0};
   for (int i = 0; i < 3; ++i) {
-    double2 v = a[g.tri_edge[3 * t + i]];
+    double2 v = alpha[(size_t)g.tri_edge[3 * t + i] * R + r];
     double s = g.tri_sign[3 * t + i];
     c0x += s * v.x;
     c0y += s * v.y;
@@ -252,7 +252,7 @@ __global__ void k_tri_current(GridMaps g, const double2 *alpha, V2<T> *J) {
 
 template <typename T>
 void tri_currents(const GridMaps &g, const double2 *alpha, V2<T> *J, int R, hipStream_t st) {
-  k_tri_current<T><<<dim3(cdiv(g.n, 256), R), 256, 0, st>>>(g, alpha, J);
+  k_tri_current<T><<<cdiv((long)g.n * R, 256), 256, 0, st>>>(g, alpha, J, R);
 }
 
 // ===========================================================================
@@ -331,9 +331,12 @@ __global__ void k_fft_axis(FftArgs a, const V2<T> *in, V2<T> *out, const T *ghat
   extern __shared__ unsigned char smraw[];
   V2<T> *tw = (V2<T> *)smraw;               // Lf/2 twiddles exp(-2 pi i k / Lf)
   V2<T> *sm = tw + (a.Lf >> 1);              // CW x Lf
+  long *ibase = (long *)(sm + (size_t)a.CW * a.Lf);   // per line: input base
+  long *obase = ibase + a.CW;                          // per line: output base
+  int *grow = (int *)(obase + a.CW);                   // per line: spectrum row (fused)
   const int Lf = a.Lf, CW = a.CW;
-  long nlines = (long)a.A * a.C;
-  long line0 = (long)blockIdx.x * CW;
+  const long nlines = (long)a.A * a.C;
+  const long line0 = (long)blockIdx.x * CW;
   for (int k = threadIdx.x; k < (Lf >> 1); k += blockDim.x) {
     T sn, cs;
     if (sizeof(T) == 4) {
@@ -349,17 +352,40 @@ __global__ void k_fft_axis(FftArgs a, const V2<T> *in, V2<T> *out, const T *ghat
     }
     tw[k] = cmk<T>(cs, -sn);
   }
+  for (int cw = threadIdx.x; cw < CW; cw += blockDim.x) {
+    long line = line0 + cw;
+    if (line >= nlines) {
+      ibase[cw] = -1;
+      continue;
+    }
+    long aa = line / a.C, cc = line - aa * a.C;
+    ibase[cw] = aa * a.n_in * a.C + cc;
+    obase[cw] = aa * a.n_out * a.C + cc;
+    if (a.fused) {
+      long ky = line % a.two_ny, kx = (line / a.two_ny) % a.two_nx;
+      int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
+      int fy = ky <= a.ny ? (int)ky : a.two_ny - (int)ky;
+      grow[cw] = (fx * (a.ny + 1) + fy) * (a.nz + 1);
+    }
+  }
   for (int k = threadIdx.x; k < CW * Lf; k += blockDim.x) sm[k] = cmk<T>(0, 0);
   __syncthreads();
   // load (bit-reversed placement)
-  for (int idx = threadIdx.x; idx < CW * a.n_in; idx += blockDim.x) {
-    int cw, k;
-    if (a.C == 1) { cw = idx / a.n_in; k = idx - cw * a.n_in; }
-    else { k = idx / CW; cw = idx - k * CW; }
-    long line = line0 + cw;
-    if (line >= nlines) continue;
-    long aa = line / a.C, cc = line - aa * a.C;
-    sm[cw * Lf + brev(k, a.logL)] = in[(aa * a.n_in + k) * a.C + cc];
+  const int nin = a.n_in;
+  if (a.C == 1) {
+    for (int idx = threadIdx.x; idx < CW * nin; idx += blockDim.x) {
+      int cw = idx / nin, k = idx - cw * nin;
+      long b0 = ibase[cw];
+      if (b0 < 0) continue;
+      sm[cw * Lf + brev(k, a.logL)] = in[b0 + k];
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < CW * nin; idx += blockDim.x) {
+      int k = idx / CW, cw = idx - k * CW;
+      long b0 = ibase[cw];
+      if (b0 < 0) continue;
+      sm[cw * Lf + brev(k, a.logL)] = in[b0 + (long)k * a.C];
+    }
   }
   __syncthreads();
   lds_fft<T>(sm, tw, CW, Lf, a.logL, a.sign);
@@ -367,14 +393,9 @@ __global__ void k_fft_axis(FftArgs a, const V2<T> *in, V2<T> *out, const T *ghat
     // multiply by the real, even spectrum and transform back
     for (int idx = threadIdx.x; idx < CW * Lf; idx += blockDim.x) {
       int cw = idx / Lf, k = idx - cw * Lf;
-      long line = line0 + cw;
-      if (line >= nlines) continue;
-      long ky = line % a.two_ny, kx = (line / a.two_ny) % a.two_nx;
-      int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
-      int fy = ky <= a.ny ? (int)ky : a.two_ny - (int)ky;
+      if (ibase[cw] < 0) continue;
       int fz = k <= a.nz ? k : Lf - k;
-      T gv = ghat[((long)fx * (a.ny + 1) + fy) * (a.nz + 1) + fz];
-      sm[idx] = cscale<T>(sm[idx], gv);
+      sm[idx] = cscale<T>(sm[idx], ghat[grow[cw] + fz]);
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < CW * Lf; idx += blockDim.x) {
@@ -390,15 +411,21 @@ __global__ void k_fft_axis(FftArgs a, const V2<T> *in, V2<T> *out, const T *ghat
     lds_fft<T>(sm, tw, CW, Lf, a.logL, +1);
   }
   // store
-  T sc = (T)a.scale;
-  for (int idx = threadIdx.x; idx < CW * a.n_out; idx += blockDim.x) {
-    int cw, k;
-    if (a.C == 1) { cw = idx / a.n_out; k = idx - cw * a.n_out; }
-    else { k = idx / CW; cw = idx - k * CW; }
-    long line = line0 + cw;
-    if (line >= nlines) continue;
-    long aa = line / a.C, cc = line - aa * a.C;
-    out[(aa * a.n_out + k) * a.C + cc] = cscale<T>(sm[cw * Lf + k], sc);
+  const T sc = (T)a.scale;
+  const int nout = a.n_out;
+  if (a.C == 1) {
+    for (int idx = threadIdx.x; idx < CW * nout; idx += blockDim.x) {
+      int cw = idx / nout, k = idx - cw * nout;
+      long b0 = obase[cw];
+      if (ibase[cw] < 0) continue;
+      out[b0 + k] = cscale<T>(sm[cw * Lf + k], sc);
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < CW * nout; idx += blockDim.x) {
+      int k = idx / CW, cw = idx - k * CW;
+      if (ibase[cw] < 0) continue;
+      out[obase[cw] + (long)k * a.C] = cscale<T>(sm[cw * Lf + k], sc);
+    }
   }
 }
 
@@ -419,7 +446,7 @@ static void fft_axis(const V2<T> *in, V2<T> *out, long A, long C, int n_in, int 
   a.Lf = Lf;
   a.logL = ilog2(Lf);
   int per_line = Lf * (int)sizeof(V2<T>);
-  int cw = (65536 - (Lf / 2) * (int)sizeof(V2<T>)) / per_line;
+  int cw = (65536 - (Lf / 2) * (int)sizeof(V2<T>)) / (per_line + 20);
   if (cw < 1) cw = 1;
   if (cw > 64) cw = 64;
   if (C > 1 && cw > C) cw = (int)C;
@@ -435,7 +462,8 @@ static void fft_axis(const V2<T> *in, V2<T> *out, long A, long C, int n_in, int 
     a.two_ny = 2 * dims[1];
   }
   long lines = A * C;
-  size_t shm = (size_t)(Lf / 2) * sizeof(V2<T>) + (size_t)cw * Lf * sizeof(V2<T>);
+  size_t shm = (size_t)(Lf / 2) * sizeof(V2<T>) + (size_t)cw * Lf * sizeof(V2<T>) +
+               (size_t)cw * (2 * sizeof(long) + sizeof(int));
   k_fft_axis<T><<<cdiv(lines, cw), 256, shm, st>>>(a, in, out, ghat);
 }
 
@@ -513,7 +541,7 @@ __global__ void k_interp_tri(GridMaps g, const V2<T> *phi, double2 *U) {
       uy[c] += m0 * v.y;
     }
   }
-  double2 *o = U + ((size_t)r * g.n + t) * 4;
+  double2 *o = U + ((size_t)t * gridDim.y + r) * 4;   // U[t][r][4]
   o[0] = make_double2(s1x, s1y);
   for (int c = 0; c < 3; ++c) o[1 + c] = make_double2(ux[c], uy[c]);
 }
@@ -526,19 +554,21 @@ void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStrea
 // ===========================================================================
 // edge phase: far field from the two triangles, near-field CSR, Gram, combine
 // ===========================================================================
+// One thread per (edge, RHS), RHS fastest: the near-field row's values and
+// columns are shared by the RHS lanes and each gathered column alpha[col][.]
+// is one contiguous segment, so every load of the sparse product coalesces.
 __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U, const double2 *zs,
-                          const double2 *jw, double2 *y, int n, int mode) {
-  int r = blockIdx.y;
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= c.b) return;
-  const double2 *a = alpha + (size_t)r * c.b;
+                          const double2 *jw, double2 *y, int R, int mode) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)c.b * R) return;
+  int e = (int)(idx / R), r = (int)(idx - (long)e * R);
   double kx = 0, ky = 0;
   if (mode & 1) {
     for (int side = 0; side < 2; ++side) {
       int t = c.efar_t[2 * e + side];
       double s = c.efar_s[2 * e + side];
       const double *p = c.efar_pl + 6 * (size_t)e + 3 * side;
-      const double2 *u = U + ((size_t)r * n + t) * 4;
+      const double2 *u = U + ((size_t)t * R + r) * 4;
       double vx = u[0].x - (p[0] * u[1].x + p[1] * u[2].x + p[2] * u[3].x);
       double vy = u[0].y - (p[0] * u[1].y + p[1] * u[2].y + p[2] * u[3].y);
       kx += s * vx;
@@ -546,9 +576,10 @@ __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U,
     }
   }
   if (mode & 2) {
-    for (int64_t q = c.nf_rowptr[e]; q < c.nf_rowptr[e + 1]; ++q) {
+    const int64_t q1 = c.nf_rowptr[e + 1];
+    for (int64_t q = c.nf_rowptr[e]; q < q1; ++q) {
       double v = c.nf_val[q];
-      double2 x = a[c.nf_col[q]];
+      double2 x = alpha[(size_t)c.nf_col[q] * R + r];
       kx += v * x.x;
       ky += v * x.y;
     }
@@ -558,7 +589,7 @@ __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U,
     double gx = 0, gy = 0;
     for (int q = 0; q < 5; ++q) {
       double v = c.gram_val[5 * e + q];
-      double2 x = a[c.gram_col[5 * e + q]];
+      double2 x = alpha[(size_t)c.gram_col[5 * e + q] * R + r];
       gx += v * x.x;
       gy += v * x.y;
     }
@@ -568,12 +599,31 @@ __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U,
   } else {
     out = make_double2(kx, ky);
   }
-  y[(size_t)r * c.b + e] = out;
+  y[idx] = out;
 }
 
 void combine(const CombineMaps &c, const double2 *alpha, const double2 *U, const double2 *zs,
              const double2 *jw, double2 *y, int R, int mode, hipStream_t st) {
-  k_combine<<<dim3(cdiv(c.b, 256), R), 256, 0, st>>>(c, alpha, U, zs, jw, y, c.n, mode);
+  k_combine<<<cdiv((long)c.b * R, 256), 256, 0, st>>>(c, alpha, U, zs, jw, y, R, mode);
+}
+
+// out[c][r] = in[r][c] for a rows x cols complex128 matrix, 32 x 32 LDS tiles
+__global__ void k_transpose(const double2 *in, double2 *out, int rows, int cols) {
+  __shared__ double2 tile[32][33];
+  int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    int r = r0 + k, c = c0 + threadIdx.x;
+    if (r < rows && c < cols) tile[k][threadIdx.x] = in[(size_t)r * cols + c];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    int c = c0 + k, r = r0 + threadIdx.x;
+    if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[threadIdx.x][k];
+  }
+}
+
+void transpose(const double2 *in, double2 *out, int rows, int cols, hipStream_t st) {
+  k_transpose<<<dim3(cdiv(cols, 32), cdiv(rows, 32)), dim3(32, 8), 0, st>>>(in, out, rows, cols);
 }
 
 // explicit instantiations
