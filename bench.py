@@ -124,6 +124,10 @@ def main():
     value = R * args.steps / dt
     # roofline of the dominant kernel (by total time inside the timed region)
     nbytes = stage_bytes(sz, R)
+    if stages.get("fft_z_conv", (0, 0))[1] == 0 and stages.get("fft_y", (0, 0))[1] > 0:
+        # fused (Y, Z + spectrum, inverse Z, inverse Y) plane kernel: reads and
+        # writes the 2 N_g points of each channel once
+        nbytes["fft_y"] = 3 * R * sz["Ng"] * 8 * 4
     dom = max((k for k in stages if stages[k][1] > 0), key=lambda k: stages[k][0])
     ms, calls = stages[dom]
     avg_s = ms / 1e3 / calls
@@ -154,6 +158,8 @@ def main():
                    "near_nnz": sz["nnz_near"], "setup_s": round(t_setup, 2)},
         "roofline": roof,
         "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]},
+        "device": {"name": torch.cuda.get_device_name(0),
+                   "lds_per_block": getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", None)},
     }
     if not args.no_sweep:
         t1 = time.perf_counter()

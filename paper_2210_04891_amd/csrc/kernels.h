@@ -54,7 +54,7 @@ struct GridMaps {
   const void *ghat;      // [(Nx+1)(Ny+1)(Nz+1)] real spectrum in T
 };
 
-// alpha [b][R] -> J [R][n][4]
+// alpha [b][R] -> J [n][R][4]
 template <typename T>
 void tri_currents(const GridMaps &g, const double2 *alpha, V2<T> *J, int R, hipStream_t st);
 template <typename T>

@@ -4,6 +4,8 @@
 // reproducible run to run.  Complex numbers are float2/double2 (re, im).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace pfft {
@@ -245,7 +247,7 @@ __global__ void k_tri_current(GridMaps g, const double2 *alpha, V2<T> *J, int R)
     }
   }
   double f = g.inv2A[t];
-  V2<T> *o = J + ((size_t)r * g.n + t) * 4;
+  V2<T> *o = J + (size_t)idx * 4;   // J[t][r][4]
   o[0] = cmk<T>((T)(c0x * f), (T)(c0y * f));
   for (int c = 0; c < 3; ++c) o[1 + c] = cmk<T>((T)(dx[c] * f), (T)(dy[c] * f));
 }
@@ -258,173 +260,312 @@ void tri_currents(const GridMaps &g, const double2 *alpha, V2<T> *J, int R, hipS
 // ===========================================================================
 // projection (Eq. Projection): node-major gather, Q_c[g] = sum J0 M1_c - J_c M0
 // ===========================================================================
+constexpr int PRG = 8;   // right-hand sides per thread in the projection
+
 template <typename T>
-__global__ void k_project(GridMaps g, const V2<T> *J, V2<T> *Q) {
-  int r = blockIdx.y;
-  int node = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_project(GridMaps g, const V2<T> *J, V2<T> *Q, int R) {
+  const int r0 = blockIdx.y * PRG;
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= g.N) return;
-  const V2<T> *Jr = J + (size_t)r * g.n * 4;
+  const int nr = min(PRG, R - r0);
   const T *w = (const T *)g.pg_w;
-  V2<T> q0 = cmk<T>(0, 0), q1 = q0, q2 = q0;
+  T acc[PRG][6];
+#pragma unroll
+  for (int q = 0; q < PRG; ++q)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[q][c] = 0;
   for (int k = g.pg_off[node]; k < g.pg_off[node + 1]; ++k) {
-    int t = g.pg_tri[k];
-    T m0 = w[4 * (size_t)k], m1x = w[4 * (size_t)k + 1], m1y = w[4 * (size_t)k + 2], m1z = w[4 * (size_t)k + 3];
-    const V2<T> *jt = Jr + 4 * (size_t)t;
-    V2<T> j0 = jt[0], jx = jt[1], jy = jt[2], jz = jt[3];
-    q0.x += j0.x * m1x - jx.x * m0;
-    q0.y += j0.y * m1x - jx.y * m0;
-    q1.x += j0.x * m1y - jy.x * m0;
-    q1.y += j0.y * m1y - jy.y * m0;
-    q2.x += j0.x * m1z - jz.x * m0;
-    q2.y += j0.y * m1z - jz.y * m0;
+    const int t = g.pg_tri[k];
+    const T m0 = w[4 * (size_t)k], m1x = w[4 * (size_t)k + 1], m1y = w[4 * (size_t)k + 2],
+            m1z = w[4 * (size_t)k + 3];
+    const V2<T> *jt = J + ((size_t)t * R + r0) * 4;
+#pragma unroll
+    for (int q = 0; q < PRG; ++q) {
+      if (q < nr) {
+        V2<T> j0 = jt[4 * q], jx = jt[4 * q + 1], jy = jt[4 * q + 2], jz = jt[4 * q + 3];
+        acc[q][0] += j0.x * m1x - jx.x * m0;
+        acc[q][1] += j0.y * m1x - jx.y * m0;
+        acc[q][2] += j0.x * m1y - jy.x * m0;
+        acc[q][3] += j0.y * m1y - jy.y * m0;
+        acc[q][4] += j0.x * m1z - jz.x * m0;
+        acc[q][5] += j0.y * m1z - jz.y * m0;
+      }
+    }
   }
-  V2<T> *Qr = Q + (size_t)r * 3 * g.N;
-  Qr[node] = q0;
-  Qr[g.N + node] = q1;
-  Qr[2 * (size_t)g.N + node] = q2;
+#pragma unroll
+  for (int q = 0; q < PRG; ++q) {
+    if (q < nr) {
+      V2<T> *Qr = Q + (size_t)(r0 + q) * 3 * g.N;
+      Qr[node] = cmk<T>(acc[q][0], acc[q][1]);
+      Qr[g.N + node] = cmk<T>(acc[q][2], acc[q][3]);
+      Qr[2 * (size_t)g.N + node] = cmk<T>(acc[q][4], acc[q][5]);
+    }
+  }
 }
 
 template <typename T>
 void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st) {
-  k_project<T><<<dim3(cdiv(g.N, 256), R), 256, 0, st>>>(g, J, Q);
+  k_project<T><<<dim3(cdiv(g.N, 256), cdiv(R, PRG)), 256, 0, st>>>(g, J, Q, R);
 }
 
 // ===========================================================================
-// LDS-staged radix-2 FFT along one axis of a [A][L][C] tensor
+// FFT along one axis of a [A][L][C] tensor: Stockham autosort passes of
+// radix 8 (then 4 / 2), butterflies in registers, one LDS exchange per pass
 // ===========================================================================
-// A workgroup transforms CW consecutive lines (line = a * C + c).  Input
-// holds n_in points per line (zero padding up to Lf), output keeps the first
-// n_out points.  mul != nullptr: forward FFT, multiply by the folded real
-// spectrum, inverse FFT (the fused last-axis convolution).
+// A workgroup transforms LB consecutive lines (line = a * C + c), staged
+// through LDS so global loads and stores are coalesced: for C == 1 the tile
+// is one contiguous block, otherwise each row of the tile is LB consecutive
+// elements.  Input holds n_in points per line (zero padding up to Lf), the
+// output keeps the first n_out points.  fused: forward transform, multiply by
+// the folded real spectrum, inverse transform (last-axis convolution).
 struct FftArgs {
-  int A, C, n_in, n_out, Lf, logL, CW;
+  int A, C, n_in, n_out, Lf, LB, ldl;   // ldl: LDS stride of one line (Lf + 1)
+  int lb_sh, lf_sh;                     // log2 LB, log2 Lf
   int sign;         // -1 forward, +1 inverse
   float scale;      // applied on output
-  // fused multiply: spectrum index (kx, ky) from the line index
   int fused, two_nx, two_ny, nx, ny, nz;
 };
 
-__device__ __forceinline__ unsigned brev(unsigned k, int logL) { return __brev(k) >> (32 - logL); }
+// in-register DFT of size Rdx, forward (sign -1) or inverse (+1)
+template <typename T, int Rdx>
+__device__ __forceinline__ void dft(V2<T> *v, int sign) {
+  if (Rdx == 2) {
+    V2<T> a = v[0], b = v[1];
+    v[0] = cadd<T>(a, b);
+    v[1] = csub<T>(a, b);
+  } else if (Rdx == 4) {
+    V2<T> a0 = cadd<T>(v[0], v[2]), a1 = csub<T>(v[0], v[2]);
+    V2<T> b0 = cadd<T>(v[1], v[3]), b1 = csub<T>(v[1], v[3]);
+    // multiply b1 by -i (forward) or +i (inverse)
+    V2<T> b1r = sign < 0 ? cmk<T>(b1.y, -b1.x) : cmk<T>(-b1.y, b1.x);
+    v[0] = cadd<T>(a0, b0);
+    v[2] = csub<T>(a0, b0);
+    v[1] = cadd<T>(a1, b1r);
+    v[3] = csub<T>(a1, b1r);
+  } else {  // 8 = 2 x 4: even/odd halves, then twiddles W8^k
+    V2<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft<T, 4>(e, sign);
+    dft<T, 4>(o, sign);
+    const T h = (T)0.70710678118654752440;
+    // W8^1 = (h, -h) forward, (h, h) inverse; W8^2 = -i / +i; W8^3 = (-h, -h) / (-h, h)
+    V2<T> o1 = sign < 0 ? cmk<T>(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x))
+                        : cmk<T>(h * (o[1].x - o[1].y), h * (o[1].y + o[1].x));
+    V2<T> o2 = sign < 0 ? cmk<T>(o[2].y, -o[2].x) : cmk<T>(-o[2].y, o[2].x);
+    V2<T> o3 = sign < 0 ? cmk<T>(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y))
+                        : cmk<T>(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y));
+    v[0] = cadd<T>(e[0], o[0]);
+    v[4] = csub<T>(e[0], o[0]);
+    v[1] = cadd<T>(e[1], o1);
+    v[5] = csub<T>(e[1], o1);
+    v[2] = cadd<T>(e[2], o2);
+    v[6] = csub<T>(e[2], o2);
+    v[3] = cadd<T>(e[3], o3);
+    v[7] = csub<T>(e[3], o3);
+  }
+}
 
-template <typename T>
-__device__ void lds_fft(V2<T> *sm, const V2<T> *tw, int CW, int Lf, int logL, int sign) {
-  int half_tot = Lf >> 1;
-  for (int s = 1; s <= logL; ++s) {
-    int len = 1 << s, half = len >> 1;
-    int tstride = Lf >> s;
-    for (int idx = threadIdx.x; idx < CW * half_tot; idx += blockDim.x) {
-      int cw = idx / half_tot, j = idx - cw * half_tot;
-      int grp = j >> (s - 1), pos = j & (half - 1);
-      int i0 = cw * Lf + grp * len + pos, i1 = i0 + half;
-      V2<T> w = tw[pos * tstride];
-      if (sign > 0) w.y = -w.y;
-      V2<T> u = sm[i0], v = cmul<T>(sm[i1], w);
-      sm[i0] = cadd<T>(u, v);
-      sm[i1] = csub<T>(u, v);
+// One Stockham pass of radix Rdx over 2^lb_sh lines of length 2^lf_sh held
+// in LDS, element (line, k) at sm[line * ls + k * es] (in place: every thread
+// reads its butterflies into registers before anyone writes).  The
+// butterfly loop is unrolled so the register arrays are never indexed at run
+// time; at most 8192 points per call (32 per thread).
+template <typename T, int Rdx>
+__device__ __forceinline__ void stockham_pass(V2<T> *sm, const V2<T> *tw, int lb_sh, int ls, int es, int lf_sh,
+                                              int Ns, int sign) {
+  constexpr int MAXB = 32 / Rdx;
+  const int Lf = 1 << lf_sh;
+  const int nb = Lf / Rdx;                       // butterflies per line
+  const int total = nb << lb_sh;
+  const int LBm = (1 << lb_sh) - 1;
+  const int tstep = Lf / (Ns * Rdx);
+  V2<T> v[MAXB][Rdx];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    int idx = threadIdx.x + q * 256;
+    if (idx < total) {
+      int line = idx & LBm, j = idx >> lb_sh;
+      const V2<T> *x = sm + line * ls;
+      int k = j & (Ns - 1);
+#pragma unroll
+      for (int i = 0; i < Rdx; ++i) {
+        V2<T> a = x[(j + i * nb) * es];
+        if (i > 0 && Ns > 1) {
+          V2<T> w = tw[(i * k * tstep) & (Lf - 1)];
+          if (sign > 0) w.y = -w.y;
+          a = cmul<T>(a, w);
+        }
+        v[q][i] = a;
+      }
+      dft<T, Rdx>(v[q], sign);
     }
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    int idx = threadIdx.x + q * 256;
+    if (idx < total) {
+      int line = idx & LBm, j = idx >> lb_sh;
+      V2<T> *y = sm + line * ls;
+      int k = j & (Ns - 1);
+      int base = (j - k) * Rdx + k;
+#pragma unroll
+      for (int i = 0; i < Rdx; ++i) y[(base + i * Ns) * es] = v[q][i];
+    }
+  }
+  __syncthreads();
+}
+
+// Full Stockham transform (radix 8 passes, then one 4 or 2); tw holds the
+// 2^lf_sh twiddles of this length.
+template <typename T>
+__device__ __forceinline__ void stockham(V2<T> *sm, const V2<T> *tw, int lb_sh, int ls, int es, int lf_sh,
+                                         int sign) {
+  const int Lf = 1 << lf_sh;
+  int Ns = 1;
+  while (Ns * 8 <= Lf) {
+    stockham_pass<T, 8>(sm, tw, lb_sh, ls, es, lf_sh, Ns, sign);
+    Ns *= 8;
+  }
+  if (Ns * 4 <= Lf) {
+    stockham_pass<T, 4>(sm, tw, lb_sh, ls, es, lf_sh, Ns, sign);
+    Ns *= 4;
+  }
+  if (Ns * 2 <= Lf) {
+    stockham_pass<T, 2>(sm, tw, lb_sh, ls, es, lf_sh, Ns, sign);
+    Ns *= 2;
   }
 }
 
 template <typename T>
-__global__ void k_fft_axis(FftArgs a, const V2<T> *in, V2<T> *out, const T *ghat) {
-  extern __shared__ unsigned char smraw[];
-  V2<T> *tw = (V2<T> *)smraw;               // Lf/2 twiddles exp(-2 pi i k / Lf)
-  V2<T> *sm = tw + (a.Lf >> 1);              // CW x Lf
-  long *ibase = (long *)(sm + (size_t)a.CW * a.Lf);   // per line: input base
-  long *obase = ibase + a.CW;                          // per line: output base
-  int *grow = (int *)(obase + a.CW);                   // per line: spectrum row (fused)
-  const int Lf = a.Lf, CW = a.CW;
-  const long nlines = (long)a.A * a.C;
-  const long line0 = (long)blockIdx.x * CW;
-  for (int k = threadIdx.x; k < (Lf >> 1); k += blockDim.x) {
-    T sn, cs;
+__device__ __forceinline__ void fill_twiddles(V2<T> *tw, int Lf) {
+  for (int k = threadIdx.x; k < Lf; k += blockDim.x) {
     if (sizeof(T) == 4) {
       float sf, cf;
       sincospif(2.0f * (float)k / (float)Lf, &sf, &cf);
-      sn = sf;
-      cs = cf;
+      tw[k] = cmk<T>((T)cf, (T)-sf);
     } else {
       double sd, cd;
       sincospi(2.0 * (double)k / (double)Lf, &sd, &cd);
-      sn = (T)sd;
-      cs = (T)cd;
-    }
-    tw[k] = cmk<T>(cs, -sn);
-  }
-  for (int cw = threadIdx.x; cw < CW; cw += blockDim.x) {
-    long line = line0 + cw;
-    if (line >= nlines) {
-      ibase[cw] = -1;
-      continue;
-    }
-    long aa = line / a.C, cc = line - aa * a.C;
-    ibase[cw] = aa * a.n_in * a.C + cc;
-    obase[cw] = aa * a.n_out * a.C + cc;
-    if (a.fused) {
-      long ky = line % a.two_ny, kx = (line / a.two_ny) % a.two_nx;
-      int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
-      int fy = ky <= a.ny ? (int)ky : a.two_ny - (int)ky;
-      grow[cw] = (fx * (a.ny + 1) + fy) * (a.nz + 1);
+      tw[k] = cmk<T>((T)cd, (T)-sd);
     }
   }
-  for (int k = threadIdx.x; k < CW * Lf; k += blockDim.x) sm[k] = cmk<T>(0, 0);
+}
+
+// Fused middle of the convolution for one (channel, kx) plane held in LDS:
+// forward FFT along y (only the Nz non-zero columns), forward FFT along z,
+// multiply by the real spectrum, inverse along z, inverse along y (only the
+// Nz columns that are kept), crop to Ny x Nz.  In place on a [.][Ny][Nz]
+// plane: reads and writes 2 Ny Nz points per channel instead of 10.
+struct YZArgs {
+  int ny, nz, ly_sh, lz_sh, pitch, nx, two_nx;
+  float scale;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fft_yz(YZArgs a, V2<T> *data, const T *ghat) {
+  extern __shared__ unsigned char smraw[];
+  const int Ly = 1 << a.ly_sh, Lz = 1 << a.lz_sh, P = a.pitch;
+  V2<T> *twy = (V2<T> *)smraw;
+  V2<T> *twz = twy + Ly;
+  V2<T> *sm = twz + Lz;                     // Ly rows x pitch
+  const long plane = blockIdx.x;            // (channel, kx)
+  const int kx = (int)(plane & (a.two_nx - 1));
+  V2<T> *io = data + plane * (long)a.ny * a.nz;
+  fill_twiddles<T>(twy, Ly);
+  fill_twiddles<T>(twz, Lz);
+  for (int idx = threadIdx.x; idx < Ly * P; idx += blockDim.x) sm[idx] = cmk<T>(0, 0);
   __syncthreads();
-  // load (bit-reversed placement)
+  for (int idx = threadIdx.x; idx < a.ny * a.nz; idx += blockDim.x) {
+    int y = idx / a.nz, z = idx - y * a.nz;
+    sm[y * P + z] = io[idx];
+  }
+  __syncthreads();
+  const int nz_sh = a.lz_sh - 1;
+  // Y forward on the Nz non-zero columns: lines = columns (stride 1), elements stride P
+  stockham<T>(sm, twy, nz_sh, 1, P, a.ly_sh, -1);
+  // Z forward on all Ly rows
+  stockham<T>(sm, twz, a.ly_sh, P, 1, a.lz_sh, -1);
+  const int fx = kx <= a.nx ? kx : a.two_nx - kx;
+  const int ny1 = Ly / 2 + 1, nz1 = Lz / 2 + 1;
+  const T *gx = ghat + (long)fx * ny1 * nz1;
+  for (int idx = threadIdx.x; idx < Ly * Lz; idx += blockDim.x) {
+    int ky = idx >> a.lz_sh, kz = idx & (Lz - 1);
+    int fy = ky < ny1 ? ky : Ly - ky;
+    int fz = kz < nz1 ? kz : Lz - kz;
+    sm[ky * P + kz] = cscale<T>(sm[ky * P + kz], gx[fy * nz1 + fz]);
+  }
+  __syncthreads();
+  stockham<T>(sm, twz, a.ly_sh, P, 1, a.lz_sh, +1);
+  stockham<T>(sm, twy, nz_sh, 1, P, a.ly_sh, +1);
+  const T sc = (T)a.scale;
+  for (int idx = threadIdx.x; idx < a.ny * a.nz; idx += blockDim.x) {
+    int y = idx / a.nz, z = idx - y * a.nz;
+    io[idx] = cscale<T>(sm[y * P + z], sc);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fft_axis(FftArgs a, const V2<T> *in, V2<T> *out, const T *ghat) {
+  extern __shared__ unsigned char smraw[];
+  V2<T> *tw = (V2<T> *)smraw;                  // Lf twiddles exp(-2 pi i k / Lf)
+  V2<T> *sm = tw + a.Lf;                       // LB lines, stride ldl
+  const int Lf = a.Lf, LB = a.LB, ldl = a.ldl, C = a.C;
+  const long nlines = (long)a.A * C;
+  const long line0 = (long)blockIdx.x * LB;
+  const int nl = (int)min((long)LB, nlines - line0);   // valid lines in this tile
+  fill_twiddles<T>(tw, Lf);
+  // coalesced load of the tile; zero padding beyond n_in
   const int nin = a.n_in;
-  if (a.C == 1) {
-    for (int idx = threadIdx.x; idx < CW * nin; idx += blockDim.x) {
-      int cw = idx / nin, k = idx - cw * nin;
-      long b0 = ibase[cw];
-      if (b0 < 0) continue;
-      sm[cw * Lf + brev(k, a.logL)] = in[b0 + k];
+  if (C == 1) {
+    const V2<T> *src = in + line0 * nin;       // nl * nin contiguous elements
+    for (int idx = threadIdx.x; idx < LB * Lf; idx += blockDim.x) {
+      int line = idx / Lf, k = idx - line * Lf;
+      V2<T> v = cmk<T>(0, 0);
+      if (line < nl && k < nin) v = src[(long)line * nin + k];
+      sm[line * ldl + k] = v;
     }
   } else {
-    for (int idx = threadIdx.x; idx < CW * nin; idx += blockDim.x) {
-      int k = idx / CW, cw = idx - k * CW;
-      long b0 = ibase[cw];
-      if (b0 < 0) continue;
-      sm[cw * Lf + brev(k, a.logL)] = in[b0 + (long)k * a.C];
+    // lines line0..line0+nl-1 have the same a when C % LB == 0 (enforced)
+    long aa = line0 / C, cc = line0 - aa * C;
+    const V2<T> *src = in + aa * (long)nin * C + cc;
+    for (int idx = threadIdx.x; idx < LB * Lf; idx += blockDim.x) {
+      int k = idx / LB, line = idx - k * LB;
+      V2<T> v = cmk<T>(0, 0);
+      if (line < nl && k < nin) v = src[(long)k * C + line];
+      sm[line * ldl + k] = v;
     }
   }
   __syncthreads();
-  lds_fft<T>(sm, tw, CW, Lf, a.logL, a.sign);
+  stockham<T>(sm, tw, a.lb_sh, ldl, 1, a.lf_sh, a.sign);
   if (a.fused) {
-    // multiply by the real, even spectrum and transform back
-    for (int idx = threadIdx.x; idx < CW * Lf; idx += blockDim.x) {
-      int cw = idx / Lf, k = idx - cw * Lf;
-      if (ibase[cw] < 0) continue;
+    for (int idx = threadIdx.x; idx < LB * Lf; idx += blockDim.x) {
+      int line = idx / Lf, k = idx - line * Lf;
+      if (line >= nl) continue;
+      long gl = line0 + line;
+      int ky = (int)(gl & (a.two_ny - 1)), kx = (int)((gl / a.two_ny) & (a.two_nx - 1));
+      int fx = kx <= a.nx ? kx : a.two_nx - kx;
+      int fy = ky <= a.ny ? ky : a.two_ny - ky;
       int fz = k <= a.nz ? k : Lf - k;
-      sm[idx] = cscale<T>(sm[idx], ghat[grow[cw] + fz]);
+      sm[line * ldl + k] = cscale<T>(sm[line * ldl + k], ghat[((long)fx * (a.ny + 1) + fy) * (a.nz + 1) + fz]);
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < CW * Lf; idx += blockDim.x) {
-      int cw = idx / Lf, k = idx - cw * Lf;
-      int kb = brev(k, a.logL);
-      if (k < kb) {
-        V2<T> t0 = sm[cw * Lf + k];
-        sm[cw * Lf + k] = sm[cw * Lf + kb];
-        sm[cw * Lf + kb] = t0;
-      }
-    }
-    __syncthreads();
-    lds_fft<T>(sm, tw, CW, Lf, a.logL, +1);
+    stockham<T>(sm, tw, a.lb_sh, ldl, 1, a.lf_sh, +1);
   }
-  // store
+  // coalesced store of the first n_out points
   const T sc = (T)a.scale;
   const int nout = a.n_out;
-  if (a.C == 1) {
-    for (int idx = threadIdx.x; idx < CW * nout; idx += blockDim.x) {
-      int cw = idx / nout, k = idx - cw * nout;
-      long b0 = obase[cw];
-      if (ibase[cw] < 0) continue;
-      out[b0 + k] = cscale<T>(sm[cw * Lf + k], sc);
+  if (C == 1) {
+    V2<T> *dst = out + line0 * nout;
+    for (int idx = threadIdx.x; idx < nl * nout; idx += blockDim.x) {
+      int line = idx / nout, k = idx - line * nout;
+      dst[(long)line * nout + k] = cscale<T>(sm[line * ldl + k], sc);
     }
   } else {
-    for (int idx = threadIdx.x; idx < CW * nout; idx += blockDim.x) {
-      int k = idx / CW, cw = idx - k * CW;
-      if (ibase[cw] < 0) continue;
-      out[obase[cw] + (long)k * a.C] = cscale<T>(sm[cw * Lf + k], sc);
+    long aa = line0 / C, cc = line0 - aa * C;
+    V2<T> *dst = out + aa * (long)nout * C + cc;
+    for (int idx = threadIdx.x; idx < LB * nout; idx += blockDim.x) {
+      int k = idx / LB, line = idx - k * LB;
+      if (line < nl) dst[(long)k * C + line] = cscale<T>(sm[line * ldl + k], sc);
     }
   }
 }
@@ -433,6 +574,29 @@ static int ilog2(int v) {
   int r = 0;
   while ((1 << r) < v) ++r;
   return r;
+}
+
+// Largest dynamic LDS allocation one workgroup may request (capped at 128 KB).
+static int lds_budget() {
+  static int v = -1;
+  if (v < 0) {
+    int dev = 0, q = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) q = 65536;
+    v = std::max(65536, std::min(q, 131072));
+  }
+  return v;
+}
+
+// Raises a kernel's dynamic LDS limit above 64 KB once; false if refused.
+static bool allow_lds(const void *fn, int bytes) {
+  if (bytes <= 65536) return true;
+  if (bytes > lds_budget()) return false;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
 }
 
 template <typename T>
@@ -444,13 +608,26 @@ static void fft_axis(const V2<T> *in, V2<T> *out, long A, long C, int n_in, int 
   a.n_in = n_in;
   a.n_out = n_out;
   a.Lf = Lf;
-  a.logL = ilog2(Lf);
-  int per_line = Lf * (int)sizeof(V2<T>);
-  int cw = (65536 - (Lf / 2) * (int)sizeof(V2<T>)) / (per_line + 20);
-  if (cw < 1) cw = 1;
-  if (cw > 64) cw = 64;
-  if (C > 1 && cw > C) cw = (int)C;
-  a.CW = cw;
+  a.ldl = Lf + 1;
+  // tile of LB lines within the LDS budget; at most 8 butterflies per thread
+  // in the pass with the smallest radix (radix 8 passes, then one 4 or 2)
+  const int vs = (int)sizeof(V2<T>);
+  static int lds_max = -1;
+  if (lds_max < 0) lds_max = allow_lds((const void *)k_fft_axis<T>, lds_budget()) ? lds_budget() : 65536;
+  int lb = (lds_max / vs - Lf) / a.ldl;
+  lb = std::min(lb, 8192 / Lf);                // 32 points per thread per pass
+  if (lb < 1) lb = 1;
+  int p2 = 1;
+  while (p2 * 2 <= lb) p2 *= 2;
+  lb = p2;
+  if (C > 1) {
+    while (lb > 1 && (C % lb) != 0) lb /= 2;  // a tile never straddles two values of a
+  } else {
+    lb = std::min(lb, 64);
+  }
+  a.LB = lb;
+  a.lb_sh = ilog2(lb);
+  a.lf_sh = ilog2(Lf);
   a.sign = sign;
   a.scale = scale;
   a.fused = ghat != nullptr;
@@ -462,9 +639,8 @@ static void fft_axis(const V2<T> *in, V2<T> *out, long A, long C, int n_in, int 
     a.two_ny = 2 * dims[1];
   }
   long lines = A * C;
-  size_t shm = (size_t)(Lf / 2) * sizeof(V2<T>) + (size_t)cw * Lf * sizeof(V2<T>) +
-               (size_t)cw * (2 * sizeof(long) + sizeof(int));
-  k_fft_axis<T><<<cdiv(lines, cw), 256, shm, st>>>(a, in, out, ghat);
+  size_t shm = (size_t)Lf * vs + (size_t)lb * a.ldl * vs;
+  k_fft_axis<T><<<cdiv(lines, lb), 256, shm, st>>>(a, in, out, ghat);
 }
 
 template <typename T>
@@ -474,6 +650,27 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
   // X forward: [ch][Nx][Ny*Nz] -> [ch][2Nx][Ny*Nz]
   if (hook) hook->pass(0, st);
   fft_axis<T>(Q, T1, ch, (long)Ny * Nz, Nx, 2 * Nx, 2 * Nx, -1, 1.0f, nullptr, nullptr, st);
+  const int vs = (int)sizeof(V2<T>);
+  const int pitch = 2 * Nz + 1;
+  const size_t yz_lds = (size_t)(2 * Ny + 2 * Nz + 2 * Ny * pitch) * vs;
+  if (4L * Ny * Nz <= 8192 && allow_lds((const void *)k_fft_yz<T>, (int)yz_lds)) {
+    // fused Y, Z(+ spectrum), inverse Z, inverse Y on each (channel, kx) plane
+    if (hook) hook->pass(1, st);
+    YZArgs y{};
+    y.ny = Ny;
+    y.nz = Nz;
+    y.ly_sh = ilog2(2 * Ny);
+    y.lz_sh = ilog2(2 * Nz);
+    y.pitch = pitch;
+    y.nx = Nx;
+    y.two_nx = 2 * Nx;
+    y.scale = 1.0f / (4.0f * Ny * Nz);
+    k_fft_yz<T><<<(unsigned)(ch * 2 * Nx), 256, yz_lds, st>>>(y, T1, (const T *)g.ghat);
+    if (hook) hook->pass(4, st);
+    fft_axis<T>(T1, Q, ch, (long)Ny * Nz, 2 * Nx, Nx, 2 * Nx, +1, 1.0f / (2.0f * Nx), nullptr, nullptr, st);
+    if (hook) hook->done(st);
+    return;
+  }
   // Y forward: [ch*2Nx][Ny][Nz] -> [ch*2Nx][2Ny][Nz]
   if (hook) hook->pass(1, st);
   fft_axis<T>(T1, T2, ch * 2 * Nx, Nz, Ny, 2 * Ny, 2 * Ny, -1, 1.0f, nullptr, nullptr, st);
@@ -518,37 +715,57 @@ void fold_spectrum(const double2 *full, T *ghat, const int dims[3], hipStream_t 
 // interpolation (Eq. interpolation, I = B^T), triangle phase:
 // U = (sum_c sum_g M1_c phi_c, sum_g M0 phi_x, ... phi_y, ... phi_z)
 // ===========================================================================
+constexpr int IRG = 4;   // right-hand sides per thread in the interpolation
+
 template <typename T>
-__global__ void k_interp_tri(GridMaps g, const V2<T> *phi, double2 *U) {
-  int r = blockIdx.y;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_interp_tri(GridMaps g, const V2<T> *phi, double2 *U, int R) {
+  const int r0 = blockIdx.y * IRG;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.n) return;
+  const int nr = min(IRG, R - r0);
   const int Ny = g.dims[1], Nz = g.dims[2];
-  const V2<T> *P = phi + (size_t)r * 3 * g.N;
   const T *w = (const T *)g.tri_w + (size_t)t * 256;
-  int ax = g.anchor[3 * t], ay = g.anchor[3 * t + 1], az = g.anchor[3 * t + 2];
-  double s1x = 0, s1y = 0, ux[3] = {0, 0, 0}, uy[3] = {0, 0, 0};
+  const int ax = g.anchor[3 * t], ay = g.anchor[3 * t + 1], az = g.anchor[3 * t + 2];
+  double acc[IRG][8];
+#pragma unroll
+  for (int q = 0; q < IRG; ++q)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[q][c] = 0;
   for (int k = 0; k < 64; ++k) {
-    int i = k >> 4, j = (k >> 2) & 3, l = k & 3;
-    long node = ((long)(ax + i) * Ny + (ay + j)) * Nz + (az + l);
-    double m0 = w[4 * k];
-    for (int c = 0; c < 3; ++c) {
-      V2<T> v = P[(size_t)c * g.N + node];
-      double m1 = w[4 * k + 1 + c];
-      s1x += m1 * v.x;
-      s1y += m1 * v.y;
-      ux[c] += m0 * v.x;
-      uy[c] += m0 * v.y;
+    const int i = k >> 4, j = (k >> 2) & 3, l = k & 3;
+    const long node = ((long)(ax + i) * Ny + (ay + j)) * Nz + (az + l);
+    const double m0 = w[4 * k], m1x = w[4 * k + 1], m1y = w[4 * k + 2], m1z = w[4 * k + 3];
+#pragma unroll
+    for (int q = 0; q < IRG; ++q) {
+      if (q < nr) {
+        const V2<T> *P = phi + (size_t)(r0 + q) * 3 * g.N + node;
+        V2<T> vx = P[0], vy = P[g.N], vz = P[2 * (size_t)g.N];
+        acc[q][0] += m1x * vx.x + m1y * vy.x + m1z * vz.x;
+        acc[q][1] += m1x * vx.y + m1y * vy.y + m1z * vz.y;
+        acc[q][2] += m0 * vx.x;
+        acc[q][3] += m0 * vx.y;
+        acc[q][4] += m0 * vy.x;
+        acc[q][5] += m0 * vy.y;
+        acc[q][6] += m0 * vz.x;
+        acc[q][7] += m0 * vz.y;
+      }
     }
   }
-  double2 *o = U + ((size_t)t * gridDim.y + r) * 4;   // U[t][r][4]
-  o[0] = make_double2(s1x, s1y);
-  for (int c = 0; c < 3; ++c) o[1 + c] = make_double2(ux[c], uy[c]);
+#pragma unroll
+  for (int q = 0; q < IRG; ++q) {
+    if (q < nr) {
+      double2 *o = U + ((size_t)t * R + r0 + q) * 4;   // U[t][r][4]
+      o[0] = make_double2(acc[q][0], acc[q][1]);
+      o[1] = make_double2(acc[q][2], acc[q][3]);
+      o[2] = make_double2(acc[q][4], acc[q][5]);
+      o[3] = make_double2(acc[q][6], acc[q][7]);
+    }
+  }
 }
 
 template <typename T>
 void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStream_t st) {
-  k_interp_tri<T><<<dim3(cdiv(g.n, 128), R), 128, 0, st>>>(g, phi, U);
+  k_interp_tri<T><<<dim3(cdiv(g.n, 128), cdiv(R, IRG)), 128, 0, st>>>(g, phi, U, R);
 }
 
 // ===========================================================================

@@ -22,10 +22,18 @@ namespace pfft {
 struct PrecondStruct {
   int nu = 0;                     // unknowns (merged, grounded nodes removed)
   int ncomp = 0;
-  int W = 0;                      // max envelope width
+  int W = 0;                      // max envelope width of the band rows
   std::vector<int> comp_off;      // [ncomp+1] unknown ranges
+  std::vector<int> comp_mid;      // [ncomp] first dense (supernode) row of each conductor:
+                                  // rows [comp_off, comp_mid) form a narrow band,
+                                  // rows [comp_mid, comp_off+1) are supernodes ordered last
   std::vector<int> first;         // [nu] first column of each row's envelope
   std::vector<int64_t> env_off;   // [nu+1]
+  // column profile of L: column j spans rows j+1 .. clast[j] (zeros where a
+  // row's envelope starts later)
+  int Wc = 0;
+  std::vector<int> clast;         // [nu]
+  std::vector<int64_t> col_off;   // [nu+1]
   // branch data (mesh edges)
   std::vector<int> br_ru, br_rv;  // unknown of merged end nodes (-1: ground)
   std::vector<int> br_link;       // link index or -1
@@ -45,15 +53,23 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps);
 
 // Factor for one angular frequency: envelope values (unit lower L), diagonal
 // and the branch admittances 1/D_e.  Returns false on a zero pivot.
+// The solve kernel reads L in two padded layouts (no per-row offsets):
+//   rowpad[i][t] = L(i, i-1-t) for t < W   (zero outside row i's envelope)
+//   colpad[j][t] = L(j+1+t, j) for t < Wc  (zero outside column j's profile)
 bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, double sigma, double mu_r,
-                    std::vector<std::complex<double>> &env, std::vector<std::complex<double>> &diag,
-                    std::vector<std::complex<double>> &yinv);
+                    std::vector<std::complex<double>> &rowpad, std::vector<std::complex<double>> &diag,
+                    std::vector<std::complex<double>> &yinv, std::vector<std::complex<double>> &colpad,
+                    std::vector<std::complex<double>> &full);
 
 struct PrecondDev {
-  int nu, ncomp, W, b, l, p, nf;
-  const int *comp_off, *first;
-  const int64_t *env_off;
-  const double2 *env;    // [nf][nnz_env]
+  int nu, ncomp, W, Wc, b, l, p, nf;
+  const int *comp_off, *comp_mid, *first, *clast;
+  int64_t nnz_full;
+  const double2 *full;   // [nf][env_off[nu]] row envelopes (used for supernode rows)
+  const int64_t *env_off, *col_off;
+  int64_t nnz_col;       // nu * Wc
+  const double2 *colenv; // [nf][nu][Wc] padded columns
+  const double2 *env;    // [nf][nu][W] padded rows
   const double2 *diag;   // [nf][nu]
   const double2 *yinv;   // [nf][b]
   const int *br_ru, *br_rv, *br_link, *br_offu, *br_offv;

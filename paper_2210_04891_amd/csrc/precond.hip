@@ -71,19 +71,28 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
   std::vector<int> unk(nn, -1);
   ps.comp_off.assign(ps.ncomp + 1, 0);
   int next = 0;
-  std::vector<std::vector<int>> members(ps.ncomp);
+  // supernodes (a port's source node with its sink merged in) tie the two
+  // ends of a conductor together; they are ordered after the band
+  std::vector<uint8_t> dense(nn, 0);
+  for (int k = 0; k < p; ++k) dense[m.bv[b + k]] = 1;
+  std::vector<std::vector<int>> members(ps.ncomp), dmembers(ps.ncomp);
   for (int x = 0; x < nn; ++x)
-    if (rep[x] == x && x != ground[comp[x]]) members[comp[x]].push_back(x);
+    if (rep[x] == x && x != ground[comp[x]]) (dense[x] ? dmembers : members)[comp[x]].push_back(x);
+  ps.comp_mid.assign(ps.ncomp, 0);
   std::vector<int> mark(nn, -1), dist(nn, -1);
   auto deg = [&](int x) {
     int d = 0;
-    for (int y : madj[x]) d += (y != ground[comp[x]]);
+    for (int y : madj[x]) d += (y != ground[comp[x]] && !dense[y]);
     return d;
   };
   for (int c = 0; c < ps.ncomp; ++c) {
     ps.comp_off[c] = next;
     auto &mem = members[c];
-    if (mem.empty()) continue;
+    if (mem.empty()) {
+      ps.comp_mid[c] = next;
+      for (int x : dmembers[c]) unk[x] = next++;
+      continue;
+    }
     int gnd = ground[c];
     auto bfs = [&](int start, std::vector<int> &ord) {
       ord.clear();
@@ -94,7 +103,7 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
         int x = ord[h++];
         std::vector<int> nb;
         for (int y : madj[x])
-          if (y != gnd && mark[y] != start * 2 + c) nb.push_back(y);
+          if (y != gnd && !dense[y] && mark[y] != start * 2 + c) nb.push_back(y);
         std::sort(nb.begin(), nb.end(), [&](int a, int bq) {
           int da = deg(a), db = deg(bq);
           return da != db ? da < db : a < bq;
@@ -122,6 +131,8 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
       if (!std::binary_search(seen.begin(), seen.end(), x)) ord.push_back(x);
     std::reverse(ord.begin(), ord.end());
     for (int x : ord) unk[x] = next++;
+    ps.comp_mid[c] = next;
+    for (int x : dmembers[c]) unk[x] = next++;
   }
   ps.comp_off[ps.ncomp] = next;
   ps.nu = next;
@@ -135,11 +146,26 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
       if (unk[y] >= 0) f = std::min(f, unk[y]);
     ps.first[i] = f;
   }
+  std::vector<uint8_t> band(nu, 1);
+  for (int c = 0; c < ps.ncomp; ++c)
+    for (int i = ps.comp_mid[c]; i < ps.comp_off[c + 1]; ++i) band[i] = 0;
   ps.env_off.assign(nu + 1, 0);
   ps.W = 0;
   for (int i = 0; i < nu; ++i) {
     ps.env_off[i + 1] = ps.env_off[i] + (i - ps.first[i]);
-    ps.W = std::max(ps.W, i - ps.first[i]);
+    if (band[i]) ps.W = std::max(ps.W, i - ps.first[i]);
+  }
+  // column profile over band rows only (supernode rows are handled apart)
+  ps.clast.resize(nu);
+  for (int j = 0; j < nu; ++j) ps.clast[j] = j;
+  for (int i = 0; i < nu; ++i)
+    if (band[i])
+      for (int j = ps.first[i]; j < i; ++j) ps.clast[j] = std::max(ps.clast[j], i);
+  ps.col_off.assign(nu + 1, 0);
+  ps.Wc = 0;
+  for (int j = 0; j < nu; ++j) {
+    ps.col_off[j + 1] = ps.col_off[j] + (ps.clast[j] - j);
+    ps.Wc = std::max(ps.Wc, ps.clast[j] - j);
   }
   // branches
   ps.br_ru.resize(b);
@@ -193,7 +219,8 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
 }
 
 bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, double sigma, double mu_r,
-                    std::vector<cd> &env, std::vector<cd> &diag, std::vector<cd> &yinv) {
+                    std::vector<cd> &rowpad, std::vector<cd> &diag, std::vector<cd> &yinv, std::vector<cd> &colpad,
+                    std::vector<cd> &env) {
   const int b = m.b, nu = ps.nu;
   double a = std::sqrt(omega * MU0 * mu_r / (2.0 * sigma));
   cd zs(a, a), jw(0.0, omega * MU0 * mu_r / (4.0 * M_PI));
@@ -223,8 +250,10 @@ bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, d
       env[ps.env_off[i] + (j - ps.first[i])] -= y;
     }
   }
-  // envelope LDL^T, row by row: w_k = L_ik D_k
-  std::vector<cd> w(ps.W + 1);
+  // envelope LDL^T, row by row: w_k = L_ik D_k (supernode rows are the widest)
+  int wmax = 1;
+  for (int i = 0; i < nu; ++i) wmax = std::max(wmax, i - ps.first[i] + 1);
+  std::vector<cd> w(wmax);
   for (int i = 0; i < nu; ++i) {
     int fi = ps.first[i];
     cd *Li = &env[ps.env_off[i]];
@@ -240,6 +269,22 @@ bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, d
     for (int k = fi; k < i; ++k) d -= w[k - fi] * Li[k - fi];
     if (std::abs(d) == 0.0 || !std::isfinite(d.real()) || !std::isfinite(d.imag())) return false;
     diag[i] = d;
+  }
+  const int W = std::max(ps.W, 1), Wc = std::max(ps.Wc, 1);
+  rowpad.assign((size_t)nu * W, 0.0);
+  colpad.assign((size_t)nu * Wc, 0.0);
+  for (int i = 0; i < nu; ++i) {
+    if (i - ps.first[i] > W) continue;             // supernode row: kept in env only
+    if (ps.clast[i] < i) continue;
+    bool is_band = true;
+    for (int c = 0; c < ps.ncomp; ++c)
+      if (i >= ps.comp_mid[c] && i < ps.comp_off[c + 1]) is_band = false;
+    if (!is_band) continue;
+    for (int j = ps.first[i]; j < i; ++j) {
+      cd v = env[ps.env_off[i] + (j - ps.first[i])];
+      rowpad[(size_t)i * W + (i - 1 - j)] = v;
+      colpad[(size_t)j * Wc + (i - j - 1)] = v;
+    }
   }
   return true;
 }
@@ -291,60 +336,168 @@ __device__ __forceinline__ double2 wave_sum(double2 v) {
   return v;
 }
 
-// One wavefront per (conductor, RHS): unit-lower forward solve, diagonal,
-// transposed backward solve, with a circular LDS window of WP >= W + 1 entries.
+// One wavefront per (conductor, RHS).  Band rows [lo, mid): unit-lower
+// forward solve column by column (y_i = acc_i, then acc_k -= L_ki y_i) and
+// transposed backward solve row by row (x_i final, then z_j -= L_ij x_i),
+// both as scatters into a circular LDS window of WP entries, so the
+// row-to-row chain holds no reductions; L is read in padded layouts, PF rows
+// per block, the next block's values fetched while the current one is
+// solved.  Supernode rows [mid, hi) come last: forward as dot products over
+// their full rows, backward as scatters over their full rows.
+constexpr int PF = 16;
+
+// The solve runs as one wavefront, whose LDS operations complete in program
+// order; this fence keeps the compiler from reordering LDS accesses across
+// rows without waiting on outstanding global stores (which a workgroup
+// barrier would).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int WP>
-__global__ void k_ldl_solve(PrecondDev d, const int *fidx, double2 *work) {
+__global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx, double2 *work) {
   __shared__ double2 win[WP];
   const int c = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
-  const int lo = d.comp_off[c], hi = d.comp_off[c + 1];
+  const int lo = d.comp_off[c], hi = d.comp_off[c + 1], mid = d.comp_mid[c];
   if (lo >= hi) return;
   const int f = fidx[r];
-  const double2 *env = d.env + (size_t)f * d.nnz_env;
+  const int W = max(d.W, 1), Wc = max(d.Wc, 1);
+  const double2 *rowp = d.env + (size_t)f * d.nu * W;
+  const double2 *colp = d.colenv + (size_t)f * d.nu * Wc;
+  const double2 *full = d.full + (size_t)f * d.nnz_full;
   const double2 *dg = d.diag + (size_t)f * d.nu;
   double2 *x = work + (size_t)r * d.nu;
-  // forward: y_i = b_i - sum_j L_ij y_j
-  for (int i = lo; i < hi; ++i) {
-    int fi = d.first[i];
-    const double2 *Li = env + d.env_off[i];
-    double2 acc = make_double2(0, 0);
-    for (int j = fi + lane; j < i; j += 64) {
-      double2 lv = Li[j - fi], yv = win[j & (WP - 1)];
+  const double2 zero = make_double2(0, 0);
+  double2 cur[PF], nxt[PF];
+  // ---- forward, band rows
+  if (lo < mid) {
+    int loaded_hi = lo;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) cur[q] = (lo + q < mid && lane < Wc) ? colp[(size_t)(lo + q) * Wc + lane] : zero;
+    for (int i0 = lo; i0 < mid; i0 += PF) {
+      const int nb = min(PF, mid - i0);
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        int i = i0 + PF + q;
+        nxt[q] = (i < mid && lane < Wc) ? colp[(size_t)i * Wc + lane] : zero;
+      }
+      const int need = min(mid, i0 + nb + Wc);
+      while (loaded_hi < need) {
+        const int cnt = min(64, need - loaded_hi);
+        if (lane < cnt) win[(loaded_hi + lane) & (WP - 1)] = x[loaded_hi + lane];
+        loaded_hi += cnt;
+      }
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        if (q < nb) {
+        const int i = i0 + q;
+        const double2 yi = win[i & (WP - 1)];
+        if (lane == 0) x[i] = yi;
+        if (lane < Wc && i + 1 + lane < mid) {
+          double2 &t = win[(i + 1 + lane) & (WP - 1)];
+          t.x -= cur[q].x * yi.x - cur[q].y * yi.y;
+          t.y -= cur[q].x * yi.y + cur[q].y * yi.x;
+        }
+        for (int t2 = 64 + lane; t2 < Wc && i + 1 + t2 < mid; t2 += 64) {   // columns taller than 64
+          double2 l2 = colp[(size_t)i * Wc + t2];
+          double2 &t = win[(i + 1 + t2) & (WP - 1)];
+          t.x -= l2.x * yi.x - l2.y * yi.y;
+          t.y -= l2.x * yi.y + l2.y * yi.x;
+        }
+        wave_sync();
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PF; ++q) cur[q] = nxt[q];
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  // ---- forward, supernode rows: y_s = b_s - sum_j L_sj y_j over the full row
+  for (int s = mid; s < hi; ++s) {
+    const int fs = d.first[s];
+    const double2 *Ls = full + d.env_off[s];
+    double2 acc = zero;
+    for (int j = fs + lane; j < s; j += 64) {
+      double2 lv = Ls[j - fs], yv = x[j];
       acc.x += lv.x * yv.x - lv.y * yv.y;
       acc.y += lv.x * yv.y + lv.y * yv.x;
     }
     acc = wave_sum(acc);
-    __syncthreads();
     if (lane == 0) {
-      double2 bi = x[i];
-      double2 yi = make_double2(bi.x - acc.x, bi.y - acc.y);
-      win[i & (WP - 1)] = yi;
-      x[i] = yi;
+      double2 bs = x[s];
+      x[s] = make_double2(bs.x - acc.x, bs.y - acc.y);
     }
+    __threadfence();
     __syncthreads();
   }
-  // backward on z = y / D: x_i = z_i - sum_{k > i} L_ki x_k, scattered by rows
-  int loaded = hi;  // window holds z_j for j in [loaded, hi)
-  auto load_to = [&](int target) {
-    while (loaded > target && loaded > lo) {
-      --loaded;
-      if (lane == 0) win[loaded & (WP - 1)] = cdiv2(x[loaded], dg[loaded]);
+  // ---- diagonal: z = y / D
+  for (int i = lo + lane; i < hi; i += 64) x[i] = cdiv2(x[i], dg[i]);
+  __threadfence();
+  __syncthreads();
+  // ---- backward, supernode rows (last rows first): scatter over the full row
+  for (int s = hi - 1; s >= mid; --s) {
+    const int fs = d.first[s];
+    const double2 *Ls = full + d.env_off[s];
+    const double2 xs = x[s];
+    for (int j = fs + lane; j < s; j += 64) {
+      double2 lv = Ls[j - fs], t = x[j];
+      t.x -= lv.x * xs.x - lv.y * xs.y;
+      t.y -= lv.x * xs.y + lv.y * xs.x;
+      x[j] = t;
     }
-  };
-  for (int i = hi - 1; i >= lo; --i) {
-    load_to(std::max(lo, i - d.W));
+    __threadfence();
     __syncthreads();
-    double2 xi = win[i & (WP - 1)];
-    if (lane == 0) x[i] = xi;
-    int fi = d.first[i];
-    const double2 *Li = env + d.env_off[i];
-    for (int j = fi + lane; j < i; j += 64) {
-      double2 lv = Li[j - fi];
-      double2 &t = win[j & (WP - 1)];
-      t.x -= lv.x * xi.x - lv.y * xi.y;
-      t.y -= lv.x * xi.y + lv.y * xi.x;
+  }
+  // ---- backward, band rows
+  if (lo < mid) {
+    int loaded = mid;  // window holds z_j for j in [loaded, mid)
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      int i = mid - 1 - q;
+      cur[q] = (i >= lo && lane < W) ? rowp[(size_t)i * W + lane] : zero;
     }
-    __syncthreads();
+    for (int i0 = mid - 1; i0 >= lo; i0 -= PF) {
+      const int nb = min(PF, i0 - lo + 1);
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        int i = i0 - PF - q;
+        nxt[q] = (i >= lo && lane < W) ? rowp[(size_t)i * W + lane] : zero;
+      }
+      const int target = max(lo, i0 - (nb - 1) - W);
+      while (loaded > target) {
+        const int cnt = min(64, loaded - target);
+        const int j = loaded - 1 - lane;
+        if (lane < cnt) win[j & (WP - 1)] = x[j];
+        loaded -= cnt;
+      }
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        if (q < nb) {
+        const int i = i0 - q;
+        const double2 xi = win[i & (WP - 1)];
+        if (lane == 0) x[i] = xi;
+        if (lane < W && i - 1 - lane >= lo) {
+          double2 &t = win[(i - 1 - lane) & (WP - 1)];
+          t.x -= cur[q].x * xi.x - cur[q].y * xi.y;
+          t.y -= cur[q].x * xi.y + cur[q].y * xi.x;
+        }
+        for (int t2 = 64 + lane; t2 < W && i - 1 - t2 >= lo; t2 += 64) {
+          double2 l2 = rowp[(size_t)i * W + t2];
+          double2 &t = win[(i - 1 - t2) & (WP - 1)];
+          t.x -= l2.x * xi.x - l2.y * xi.y;
+          t.y -= l2.x * xi.y + l2.y * xi.x;
+        }
+        wave_sync();
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PF; ++q) cur[q] = nxt[q];
+    }
   }
 }
 
@@ -388,15 +541,19 @@ __global__ void k_pre_out(PrecondDev d, const int *fidx, const double2 *y, const
 void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, double2 *z, double2 *work, int R,
                    hipStream_t st) {
   k_pre_rhs<<<dim3((d.nu + 255) / 256, R), 256, 0, st>>>(d, fidx, y, work);
+  // the window must hold max(W, Wc) + PF entries: a block of PF rows reaches
+  // W (backward) or Wc (forward) beyond its last row while its own rows are
+  // still pending
   dim3 g(d.ncomp, R);
-  if (d.W < 128)
+  const int span = std::max(d.W, d.Wc) + PF;
+  if (span < 128)
     k_ldl_solve<128><<<g, 64, 0, st>>>(d, fidx, work);
-  else if (d.W < 512)
+  else if (span < 512)
     k_ldl_solve<512><<<g, 64, 0, st>>>(d, fidx, work);
-  else if (d.W < 2048)
+  else if (span < 2048)
     k_ldl_solve<2048><<<g, 64, 0, st>>>(d, fidx, work);
   else
-    k_ldl_solve<8192><<<g, 64, 0, st>>>(d, fidx, work);
+    k_ldl_solve<4096><<<g, 64, 0, st>>>(d, fidx, work);
   k_pre_out<<<dim3((d.l + 255) / 256, R), 256, 0, st>>>(d, fidx, y, work, z);
 }
 

@@ -301,7 +301,7 @@ static void build_grid(HostModel &m, const SetupOptions &opt) {
   double hmax = 0;
   for (int d = 0; d < 3; ++d) {
     m.dims[d] = opt.grid[d];
-    if (m.dims[d] < 8 || m.dims[d] > 1024) fail(-1, "grid dimension out of range [8, 1024]");
+    if (m.dims[d] < 8 || m.dims[d] > 512) fail(-1, "grid dimension out of range [8, 512]");
     if ((m.dims[d] & (m.dims[d] - 1)) != 0) fail(-1, "grid dimensions must be powers of two");
     double ext = hi[d] - lo[d];
     m.h[d] = ext > 0 ? ext / (m.dims[d] - opt.stencil) : 0.0;

@@ -22,7 +22,8 @@ struct Precond {
   std::vector<double> omegas;            // factored frequencies (rad/s)
   std::vector<int> fidx_host;            // factor index per RHS, as on the device
   int cap_f = 0, cap_R = 0;
-  double2 *d_env = nullptr, *d_diag = nullptr, *d_yinv = nullptr, *d_work = nullptr, *d_tmp = nullptr;
+  double2 *d_env = nullptr, *d_diag = nullptr, *d_yinv = nullptr, *d_work = nullptr, *d_tmp = nullptr,
+          *d_colenv = nullptr, *d_full = nullptr;
   int *d_fidx = nullptr;
 };
 
@@ -53,6 +54,8 @@ static void precond_free(Precond *p) {
   if (p->d_work) hipFree(p->d_work);
   if (p->d_fidx) hipFree(p->d_fidx);
   if (p->d_tmp) hipFree(p->d_tmp);
+  if (p->d_colenv) hipFree(p->d_colenv);
+  if (p->d_full) hipFree(p->d_full);
   delete p;
 }
 
@@ -74,19 +77,26 @@ static Precond *precond_prepare(pfft_ctx *c, int R, const double *omega, hipStre
   const HostModel &m = c->m;
   if (!P->built) {
     build_precond_struct(m, P->ps);
-    if (P->ps.W >= 4096) throw SetupError{PFFT_EINVAL, "preconditioner envelope wider than 4096"};
+    if (std::max(P->ps.W, P->ps.Wc) + 8 >= 4096)
+      throw SetupError{PFFT_EINVAL, "preconditioner envelope wider than 4087"};
     PrecondDev &d = P->dev;
     const PrecondStruct &ps = P->ps;
     d.nu = ps.nu;
     d.ncomp = ps.ncomp;
     d.W = ps.W;
+    d.Wc = ps.Wc;
+    d.clast = pre_upload(P, ps.clast);
+    d.col_off = pre_upload(P, ps.col_off);
+    d.nnz_col = (int64_t)ps.nu * std::max(ps.Wc, 1);
     d.b = m.b;
     d.l = m.l;
     d.p = m.p;
     d.comp_off = pre_upload(P, ps.comp_off);
+    d.comp_mid = pre_upload(P, ps.comp_mid);
+    d.nnz_full = ps.env_off[ps.nu];
     d.first = pre_upload(P, ps.first);
     d.env_off = pre_upload(P, ps.env_off);
-    d.nnz_env = ps.env_off[ps.nu];
+    d.nnz_env = (int64_t)ps.nu * std::max(ps.W, 1);
     d.br_ru = pre_upload(P, ps.br_ru);
     d.br_rv = pre_upload(P, ps.br_rv);
     d.br_link = pre_upload(P, ps.br_link);
@@ -109,26 +119,34 @@ static Precond *precond_prepare(pfft_ctx *c, int R, const double *omega, hipStre
   uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
   if (uniq != P->omegas) {
     const int nf = (int)uniq.size();
-    const size_t ne = P->ps.env_off[P->ps.nu];
-    std::vector<std::complex<double>> env(nf * ne), dg((size_t)nf * P->ps.nu), yi((size_t)nf * m.b);
+    const size_t ne = (size_t)P->ps.nu * std::max(P->ps.W, 1), nc = (size_t)P->ps.nu * std::max(P->ps.Wc, 1);
+    const size_t nfull = P->ps.env_off[P->ps.nu];
+    std::vector<std::complex<double>> env(nf * ne), dg((size_t)nf * P->ps.nu), yi((size_t)nf * m.b),
+        ce((size_t)nf * nc), fe((size_t)nf * nfull);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
     for (int f = 0; f < nf; ++f) {
-      std::vector<std::complex<double>> e1, d1, y1;
-      if (!factor_precond(m, P->ps, uniq[f], c->sigma, c->mu_r, e1, d1, y1)) {
+      std::vector<std::complex<double>> e1, d1, y1, c1, f1;
+      if (!factor_precond(m, P->ps, uniq[f], c->sigma, c->mu_r, e1, d1, y1, c1, f1)) {
         ++bad;
         continue;
       }
       std::copy(e1.begin(), e1.end(), env.begin() + (size_t)f * ne);
       std::copy(d1.begin(), d1.end(), dg.begin() + (size_t)f * P->ps.nu);
       std::copy(y1.begin(), y1.end(), yi.begin() + (size_t)f * m.b);
+      std::copy(c1.begin(), c1.end(), ce.begin() + (size_t)f * nc);
+      std::copy(f1.begin(), f1.end(), fe.begin() + (size_t)f * nfull);
     }
     if (bad) throw SetupError{PFFT_EFACTOR, "zero pivot in the nodal factorization"};
     if (nf > P->cap_f) {
       if (P->d_env) hipFree(P->d_env);
       if (P->d_diag) hipFree(P->d_diag);
       if (P->d_yinv) hipFree(P->d_yinv);
+      if (P->d_colenv) hipFree(P->d_colenv);
+      if (P->d_full) hipFree(P->d_full);
+      hip_ok(hipMalloc(&P->d_full, std::max<size_t>(16, nfull * nf * sizeof(double2))), "hipMalloc full");
       hip_ok(hipMalloc(&P->d_env, std::max<size_t>(16, ne * nf * sizeof(double2))), "hipMalloc env");
+      hip_ok(hipMalloc(&P->d_colenv, std::max<size_t>(16, nc * nf * sizeof(double2))), "hipMalloc colenv");
       hip_ok(hipMalloc(&P->d_diag, std::max<size_t>(16, (size_t)P->ps.nu * nf * sizeof(double2))), "hipMalloc diag");
       hip_ok(hipMalloc(&P->d_yinv, (size_t)m.b * nf * sizeof(double2)), "hipMalloc yinv");
       P->cap_f = nf;
@@ -138,11 +156,15 @@ static Precond *precond_prepare(pfft_ctx *c, int R, const double *omega, hipStre
     if (P->ps.nu)
       hip_ok(hipMemcpy(P->d_diag, dg.data(), (size_t)P->ps.nu * nf * sizeof(double2), hipMemcpyHostToDevice), "diag");
     hip_ok(hipMemcpy(P->d_yinv, yi.data(), (size_t)m.b * nf * sizeof(double2), hipMemcpyHostToDevice), "yinv");
+    if (nc) hip_ok(hipMemcpy(P->d_colenv, ce.data(), nc * nf * sizeof(double2), hipMemcpyHostToDevice), "colenv");
+    if (nfull) hip_ok(hipMemcpy(P->d_full, fe.data(), nfull * nf * sizeof(double2), hipMemcpyHostToDevice), "full");
     P->omegas = uniq;
     P->fidx_host.clear();
     P->dev.env = P->d_env;
     P->dev.diag = P->d_diag;
     P->dev.yinv = P->d_yinv;
+    P->dev.colenv = P->d_colenv;
+    P->dev.full = P->d_full;
     P->dev.nf = nf;
   }
   if (R > P->cap_R) {
