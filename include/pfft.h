@@ -91,6 +91,8 @@ pfft_status pfft_sizes(const pfft_ctx *c, int64_t out[10]);
 #define PFFT_PRECOND    4  /* loop space: return P^-1 (Z_l x) (Eqs. Precond,
                               LoopWithP)                                       */
 #define PFFT_PRECOND_ONLY 8 /* loop space: return P^-1 x                         */
+#define PFFT_LEARNED_ONLY 16 /* loop space: return M(x) = P^-1 x plus the learned
+                              correction (P^-1 x when no network is loaded)   */
 
 /* y = op(x) for nrhs right-hand sides (Eqs. CurT, Lb, VolT).
  * space 0: branch space, y = K x with K the pFFT approximation of the
@@ -123,9 +125,80 @@ pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, doubl
 pfft_status extract_RL(int32_t nfreq, int32_t nport, const double *freq_hz, const void *Y,
                        double *R_out, double *L_out);
 
-/* Learned preconditioner correction: load bf16 weights (layout documented in
- * pfft_mlp_layout) used by solve_ports(precond = 2). */
-pfft_status pfft_precond_load(pfft_ctx *c, const void *weights_bf16, int64_t nbytes);
+/* ---- Learned correction of the preconditioner (solve_ports precond = 2) ----
+ * Not part of the paper: a per-loop network refines M(v) = P^-1 v inside
+ * flexible GMRES (Sec. IV-A's P stays the fallback).  For a right-hand side
+ * with loop vector v (length l) and z = P^-1 v, let s_v = sqrt(l)/|v|,
+ * s_z = sqrt(l)/|z| (2-norms).  Loop i gets the features
+ *   x_i = ( Re v_i s_v, Im v_i s_v, Re z_i s_z, Im z_i s_z,
+ *           (log10 f - 8)/2, [i is a port source link], [i is a contact
+ *           self-loop], Re D_e/|D_e| of its link branch e (0 for a port) )
+ * (D_e = Z_b(e,e) of Eq. Zb), rounded to bf16, and the network
+ *   y_i = W3 relu(W2 relu(W1 x_i + b1) + b2) + b3      (2 outputs)
+ * gives M(v)_i = z_i + (y_i0 + j y_i1)/s_z.  If some y of a right-hand side
+ * is not finite or sum_i |y_i|^2 > 16 l, that right-hand side keeps z.
+ * The matrix products run on the matrix cores with bf16 operands and FP32
+ * accumulation.  Inference stores activations as bf16; training keeps them
+ * in FP32 and feeds each as a bf16 hi + lo pair (about 16 mantissa bits).
+ *
+ * Weight blob (little endian), exchanged by pfft_precond_load/_save:
+ *   int32 magic 0x504D4C50, int32 F (= 8), int32 H (hidden width), int32 O (= 2)
+ *   bf16 W1[H][F], W2[H][H], W3[O][H]   (row-major), zero-padded to 4 bytes
+ *   float32 b1[H], b2[H], b3[O]
+ * size = 16 + 4*ceil((H*F + H*H + O*H)/2) + 4*(2H + O) bytes.            */
+
+/* Load weights (host blob, copied).  PFFT_EINVAL on a malformed blob. */
+pfft_status pfft_precond_load(pfft_ctx *c, const void *blob, int64_t nbytes);
+
+/* Copy the current weights into buf (host) when cap_bytes suffices; *nbytes
+ * always receives the blob size.  PFFT_EINVAL when no network exists. */
+pfft_status pfft_precond_save(pfft_ctx *c, void *buf, int64_t cap_bytes, int64_t *nbytes);
+
+/* Training pairs from the solver itself: one cycle of plain-P FGMRES
+ * (x0 = 0, no restart, at most maxit steps, tolerance tol) on every
+ * (frequency, port).  Its Arnoldi relation Z_l z_k = sum_i H[i][k] v_i with
+ * z_k = P^-1 v_k gives the exact errors e_k = Z_l^-1 v_k of the Krylov
+ * vectors the preconditioner is applied to, by the backward recursion
+ *   e_0 = x / |b|,   e_{k+1} = (z_k - sum_{i<=k} H[i][k] e_i) / H[k+1][k]
+ * from the final iterate x; a pair is kept while |r_k| >= 1e3 |r_final|
+ * (the error of x, amplified by the recursion, stays below ~1e-3).  Its rows
+ * are the features of v = v_k and the targets t_i = (g e_i - z_i) s_z with
+ * g = <z,z>/<z,e> (the component of g e along z equals z, so the target is
+ * the change of direction that GMRES can use).  Rows are appended to the
+ * context's training set; *rows_out (may be NULL) receives the set size.
+ * Device memory: about 2 maxit nfreq p l complex128 for the Krylov basis. */
+pfft_status pfft_learned_collect(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol,
+                                 int32_t maxit, int64_t *rows_out, void *hip_stream);
+
+/* Adam (beta 0.9/0.999, eps 1e-8, step lr) on minibatches of `batch` rows
+ * drawn uniformly (counter-based hash of seed, step, row) from the training
+ * set.  Loss: mean over the collected right-hand sides of
+ * sum_i |y_i - t_i|^2 / sum_i |t_i|^2, estimated per minibatch.  A network
+ * of width `hidden` is initialised (seeded) when none exists.  loss_out:
+ * host [steps] (may be NULL).  PFFT_EINVAL when the training set is empty. */
+pfft_status pfft_learned_train(pfft_ctx *c, int32_t steps, int32_t batch, int32_t hidden, double lr,
+                               uint64_t seed, float *loss_out, void *hip_stream);
+
+/* Drops the training set (weights stay). */
+pfft_status pfft_learned_clear(pfft_ctx *c);
+
+/* Since the weights were loaded or initialised: out[0] = right-hand-side
+ * applications of the network, out[1] = of those, numeric fallbacks to
+ * P^-1, out[2] = right-hand sides that solve_ports switched back to plain P
+ * because their residual fell more slowly over two steps than the plain
+ * preconditioner's median per-step factor measured by pfft_learned_collect
+ * (times 1.1; no switching when nothing was collected in this context). */
+pfft_status pfft_learned_stats(pfft_ctx *c, int64_t out[3]);
+
+/* Context-free evaluation of the network with gradients (training
+ * precision), for checks:
+ * X_dev bf16 [rows][F], T_dev, Y_dev float32 [rows][2], w_dev float32 [rows]
+ * (device); loss = sum_i w_i |y_i - t_i|^2 (host double), grad_dev float32
+ * device [H*F + H*H + 2*H + 2*H + 2] ordered W1, W2, W3, b1, b2, b3.  The
+ * blob is a host pointer.  Allocates and frees its own scratch; synchronous. */
+pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const void *X_dev,
+                          const float *T_dev, const float *w_dev, float *Y_dev, float *grad_dev,
+                          double *loss_out, void *hip_stream);
 
 void pfft_destroy(pfft_ctx *c);
 const char *pfft_last_error(void);

@@ -488,7 +488,8 @@ pfft_status pfft_matvec(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t 
     set_error("pfft_matvec: FAR_ONLY and NEAR_ONLY are exclusive");
     return PFFT_EINVAL;
   }
-  if ((flags & (PFFT_PRECOND | PFFT_PRECOND_ONLY)) && space != 1) {
+  const int pre_flags = PFFT_PRECOND | PFFT_PRECOND_ONLY | PFFT_LEARNED_ONLY;
+  if ((flags & pre_flags) && space != 1) {
     set_error("pfft_matvec: preconditioner flags need loop space");
     return PFFT_EINVAL;
   }
@@ -500,7 +501,7 @@ pfft_status pfft_matvec(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t 
   try {
     hip_ok(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t st = (hipStream_t)hip_stream;
-    if (flags & (PFFT_PRECOND | PFFT_PRECOND_ONLY)) {
+    if (flags & pre_flags) {
       return pfft_internal_precond_matvec(c, nrhs, omega, flags, (const double2 *)x_dev, (double2 *)y_dev, st);
     }
     c->matvec(nrhs, omega, space, flags, (const double2 *)x_dev, (double2 *)y_dev, st);

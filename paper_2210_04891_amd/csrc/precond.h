@@ -86,4 +86,30 @@ struct PrecondDev {
 void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, double2 *z, double2 *work, int R,
                    hipStream_t st);
 
+// Preconditioner state of a context: structure (built once), factors of the
+// distinct frequencies of the current batch, per-RHS factor index.
+struct Precond {
+  PrecondStruct ps;
+  bool built = false;
+  PrecondDev dev{};
+  std::vector<void *> allocs;
+  std::vector<double> omegas;            // factored frequencies (rad/s)
+  std::vector<int> fidx_host;            // factor index per RHS, as on the device
+  int cap_f = 0, cap_R = 0;
+  double2 *d_env = nullptr, *d_diag = nullptr, *d_yinv = nullptr, *d_work = nullptr, *d_tmp = nullptr,
+          *d_colenv = nullptr, *d_full = nullptr;
+  int *d_fidx = nullptr;
+};
+
 }  // namespace pfft
+
+struct pfft_ctx;
+
+namespace pfft {
+// Builds the structure once, factors every distinct frequency of omega[0..R)
+// (host, rad/s) and uploads the per-RHS factor index; returns the context's
+// preconditioner.
+Precond *precond_prepare(pfft_ctx *c, int R, const double *omega, hipStream_t st);
+
+}  // namespace pfft
+

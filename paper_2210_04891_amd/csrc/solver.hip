@@ -6,28 +6,13 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <functional>
 #include <map>
 #include <set>
 
 #include "engine.h"
+#include "learned.h"
 #include "precond.h"
-
-namespace pfft {
-
-struct Precond {
-  PrecondStruct ps;
-  bool built = false;
-  PrecondDev dev{};
-  std::vector<void *> allocs;
-  std::vector<double> omegas;            // factored frequencies (rad/s)
-  std::vector<int> fidx_host;            // factor index per RHS, as on the device
-  int cap_f = 0, cap_R = 0;
-  double2 *d_env = nullptr, *d_diag = nullptr, *d_yinv = nullptr, *d_work = nullptr, *d_tmp = nullptr,
-          *d_colenv = nullptr, *d_full = nullptr;
-  int *d_fidx = nullptr;
-};
-
-}  // namespace pfft
 
 using namespace pfft;
 
@@ -59,8 +44,6 @@ static void precond_free(Precond *p) {
   delete p;
 }
 
-void learned_free(pfft_ctx *c);
-
 void pfft_ctx_free(pfft_ctx *c) {
   precond_free(c->pre);
   learned_free(c);
@@ -71,7 +54,7 @@ void pfft_ctx_free(pfft_ctx *c) {
 
 // Builds the structure once, factors every distinct frequency of omega[0..R)
 // and uploads the per-RHS factor index.
-static Precond *precond_prepare(pfft_ctx *c, int R, const double *omega, hipStream_t st) {
+Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStream_t st) {
   if (!c->pre) c->pre = new Precond();
   Precond *P = c->pre;
   const HostModel &m = c->m;
@@ -192,7 +175,11 @@ static Precond *precond_prepare(pfft_ctx *c, int R, const double *omega, hipStre
 pfft_status pfft_internal_precond_matvec(pfft_ctx *c, int R, const double *omega, int flags, const double2 *x,
                                          double2 *y, hipStream_t st) {
   Precond *P = precond_prepare(c, R, omega, st);
-  if (flags & PFFT_PRECOND_ONLY) {
+  if (flags & PFFT_LEARNED_ONLY) {
+    c->timer.begin(ST_PRECOND, st);
+    if (!learned_apply(c, R, omega, x, y, nullptr, st)) precond_apply(P->dev, P->d_fidx, x, y, P->d_work, R, st);
+    c->timer.end(st);
+  } else if (flags & PFFT_PRECOND_ONLY) {
     c->timer.begin(ST_PRECOND, st);
     precond_apply(P->dev, P->d_fidx, x, y, P->d_work, R, st);
     c->timer.end(st);
@@ -264,7 +251,7 @@ __global__ void k_scale(const double2 *src, double2 *dst, const double2 *nrm2, i
 // Column k of H: h (first pass) + h2 (second pass), H[k+1][k] = norm;
 // previous rotations, new rotation, residual estimate |g[k+1]|.
 __global__ void k_givens(double2 *H, const double2 *h1, const double2 *h2, const double2 *nrm2, double2 *cs,
-                         double2 *sn, double2 *g, double *resid, int k, int m, int R) {
+                         double2 *sn, double2 *g, double *resid, int k, int m, int R, double2 *Hraw) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   double2 *Hc = H + (size_t)r * (m + 1) * m;   // H[i][k] at Hc[i * m + k]
@@ -274,6 +261,10 @@ __global__ void k_givens(double2 *H, const double2 *h1, const double2 *h2, const
   }
   double nn = sqrt(fmax(nrm2[r].x, 0.0));
   Hc[(k + 1) * m + k] = make_double2(nn, 0.0);
+  if (Hraw) {   // unrotated column k (Arnoldi relation Z_l z_k = sum_i H[i][k] v_i)
+    double2 *Hr = Hraw + (size_t)r * (m + 1) * m;
+    for (int i = 0; i <= k + 1; ++i) Hr[i * m + k] = Hc[i * m + k];
+  }
   double2 *c = cs + (size_t)r * (m + 1), *s = sn + (size_t)r * (m + 1), *gg = g + (size_t)r * (m + 1);
   for (int i = 0; i < k; ++i) {
     double2 x = Hc[i * m + k], y = Hc[(i + 1) * m + k];
@@ -352,14 +343,10 @@ __global__ void k_init_g(double2 *g, const double2 *nrm2, int m, int R) {
 // ---------------------------------------------------------------------------
 // FGMRES driver
 // ---------------------------------------------------------------------------
-namespace pfft {
-// learned correction: z = P^-1 v + |v| delta(v/|v|); defined in learned.hip
-bool learned_apply(pfft_ctx *c, int R, const double2 *v, double2 *z, hipStream_t st);
-}
-
 struct Fgmres {
   int R, l, m;
   double2 *V, *Z, *H, *cs, *sn, *g, *h1, *h2, *nrm, *yv, *x, *w, *b, *Ax;
+  double2 *Hraw = nullptr;   // optional unrotated Hessenberg [R][m+1][m]
   double *resid;
   int *kr;
   std::vector<void *> al;
@@ -395,8 +382,16 @@ struct Fgmres {
 
 // Solves Z_l(omega_r) x_r = b_r for all r; b is already in F.b.  precond: 0,
 // 1 (P), 2 (P + learned).  Returns per-RHS iterations and true residuals.
+// rec (optional) receives, for the first cycle, each RHS's Krylov length and
+// residual estimates |g_{k+1}| after every step.
+struct FirstCycle {
+  std::vector<int> k;
+  std::vector<std::vector<double>> res;
+  std::vector<double> bnorm;
+};
 static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int maxit, int precond,
-                   std::vector<int> &iters, std::vector<double> &relres, hipStream_t st) {
+                   std::vector<int> &iters, std::vector<double> &relres, hipStream_t st,
+                   FirstCycle *rec = nullptr) {
   const int R = F.R, l = F.l, m = F.m;
   const dim3 gl((l + 255) / 256, R);
   Precond *P = precond ? precond_prepare(c, R, omega, st) : nullptr;
@@ -406,6 +401,12 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
   std::vector<double> bnorm(R), res(R);
   std::vector<uint8_t> done(R, 0);
   std::vector<int> kconv(R, 0);
+  // learned correction judged against the plain preconditioner's convergence
+  // factor per step: a right-hand side whose residual estimate falls more
+  // slowly over two steps is switched back to plain P for the rest of the solve
+  std::vector<uint8_t> use_l(R, precond == 2 ? 1 : 0);
+  const double judge = precond == 2 ? learned_judge_factor(c) : 0.0;
+  std::vector<std::vector<double>> seq(R);
   // |b|
   k_mdot<<<dim3(1, R), 256, 0, st>>>(F.b, F.b, F.nrm, l, 1, 1, 1, nullptr);
   {
@@ -417,7 +418,13 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
   int total = 0;
   // residual r0 = b (x0 = 0) in w
   hip_ok(hipMemcpyAsync(F.w, F.b, (size_t)R * l * sizeof(double2), hipMemcpyDeviceToDevice, st), "r0");
+  if (rec) {
+    rec->k.assign(R, 0);
+    rec->res.assign(R, {});
+    rec->bnorm = bnorm;
+  }
   bool all_done = false;
+  bool first = true;
   while (total < maxit && !all_done) {
     std::vector<uint8_t> done_before = done;
     std::vector<int> kthis(R, 0);   // Krylov length at convergence in this cycle
@@ -431,7 +438,7 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
                               l * sizeof(double2), R, hipMemcpyDeviceToDevice, st),
              "gather v");
       double2 *zk = F.Ax;  // contiguous [R][l]
-      if (precond == 2 && learned_apply(c, R, F.w, zk, st)) {
+      if (precond == 2 && learned_apply(c, R, omega, F.w, zk, use_l.data(), st)) {
       } else if (precond) {
         precond_apply(P->dev, P->d_fidx, F.w, zk, P->d_work, R, st);
       } else {
@@ -449,9 +456,23 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
       k_maxpy<<<gl, 256, 0, st>>>(F.V, F.w, F.h2, l, m + 1, k + 1, m + 1, nullptr);
       k_mdot<<<dim3(1, R), 256, 0, st>>>(F.w, F.w, F.nrm, l, 1, 1, 1, nullptr);
       k_scale<<<gl, 256, 0, st>>>(F.w, F.V + (size_t)(k + 1) * l, F.nrm, l, (m + 1) * l, l);
-      k_givens<<<(R + 63) / 64, 64, 0, st>>>(F.H, F.h1, F.h2, F.nrm, F.cs, F.sn, F.g, F.resid, k, m, R);
+      k_givens<<<(R + 63) / 64, 64, 0, st>>>(F.H, F.h1, F.h2, F.nrm, F.cs, F.sn, F.g, F.resid, k, m, R,
+                                             F.Hraw);
       hip_ok(hipMemcpyAsync(res.data(), F.resid, R * sizeof(double), hipMemcpyDeviceToHost, st), "resid");
       hip_ok(hipStreamSynchronize(st), "resid sync");
+      if (rec && first)
+        for (int r = 0; r < R; ++r)
+          if (!done[r]) rec->res[r].push_back(res[r]);
+      for (int r = 0; r < R; ++r) {
+        if (done[r]) continue;
+        if (k == 0) seq[r].clear();
+        seq[r].push_back(res[r]);
+        const size_t n = seq[r].size();
+        if (use_l[r] && judge > 0 && n >= 3 && !(std::sqrt(seq[r][n - 1] / seq[r][n - 3]) <= judge)) {
+          use_l[r] = 0;
+          learned_judged_off(c, 1);
+        }
+      }
       bool all = true;
       for (int r = 0; r < R; ++r) {
         if (!done[r] && res[r] <= tol * bnorm[r]) {
@@ -470,6 +491,8 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
     // unchanged, otherwise the full cycle
     std::vector<int> kr(R);
     for (int r = 0; r < R; ++r) kr[r] = done_before[r] ? 0 : (kthis[r] > 0 ? kthis[r] : k);
+    if (rec && first) rec->k = kr;
+    first = false;
     hip_ok(hipMemcpyAsync(F.kr, kr.data(), R * sizeof(int), hipMemcpyHostToDevice, st), "kr");
     k_backsolve<<<(R + 63) / 64, 64, 0, st>>>(F.H, F.g, F.yv, F.kr, m, R);
     k_xupdate<<<gl, 256, 0, st>>>(F.x, F.Z, F.yv, F.kr, l, m);
@@ -488,6 +511,51 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
     relres[r] = std::sqrt(std::max(n2[r].x, 0.0)) / (bnorm[r] > 0 ? bnorm[r] : 1.0);
     if (!done[r]) iters[r] = total;
   }
+}
+
+// right-hand sides of the port solves (Sec. V): 1 V on the driven port's
+// source loop, frequency-major
+static void port_rhs(const pfft_ctx *c, int nfreq, const double *freq_hz, std::vector<double> &omega,
+                     std::vector<double2> &bh) {
+  const int p = c->m.p, l = c->m.l, R = nfreq * p;
+  omega.assign(R, 0.0);
+  bh.assign((size_t)R * l, make_double2(0, 0));
+  for (int f = 0; f < nfreq; ++f)
+    for (int k = 0; k < p; ++k) {
+      int r = f * p + k;
+      omega[r] = 2.0 * M_PI * freq_hz[f];
+      bh[(size_t)r * l + c->m.port_loop[k]] = make_double2(1.0, 0.0);
+    }
+}
+
+void pfft::solve_ports_krylov(pfft_ctx *c, int nfreq, const double *freq_hz, double tol, int maxit,
+                              const KrylovFn &done, hipStream_t st) {
+  const int R = nfreq * c->m.p, l = c->m.l, m = maxit;
+  Fgmres F(R, l, m);
+  F.Hraw = (double2 *)F.alloc((size_t)R * (m + 1) * m * sizeof(double2));
+  std::vector<double> omega;
+  std::vector<double2> bh;
+  port_rhs(c, nfreq, freq_hz, omega, bh);
+  hip_ok(hipMemcpyAsync(F.b, bh.data(), bh.size() * sizeof(double2), hipMemcpyHostToDevice, st), "b");
+  std::vector<int> iters;
+  std::vector<double> relres;
+  FirstCycle rec;
+  fgmres(c, F, omega.data(), tol, maxit, 1, iters, relres, st, &rec);
+  KrylovView kv;
+  kv.R = R;
+  kv.l = l;
+  kv.m = m;
+  kv.V = F.V;
+  kv.Z = F.Z;
+  kv.Hraw = F.Hraw;
+  kv.x = F.x;
+  kv.omega = omega.data();
+  kv.k = rec.k;
+  kv.res = rec.res;
+  kv.bnorm = rec.bnorm;
+  kv.relres = relres;
+  done(kv);
+  hip_ok(hipStreamSynchronize(st), "krylov sync");
 }
 
 extern "C" {
@@ -515,14 +583,9 @@ pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, doubl
     const int p = c->m.p, l = c->m.l, R = nfreq * p;
     const int m = std::min(restart, maxit);
     Fgmres F(R, l, m);
-    std::vector<double> omega(R);
-    std::vector<double2> bh((size_t)R * l, make_double2(0, 0));
-    for (int f = 0; f < nfreq; ++f)
-      for (int k = 0; k < p; ++k) {
-        int r = f * p + k;
-        omega[r] = 2.0 * M_PI * freq_hz[f];
-        bh[(size_t)r * l + c->m.port_loop[k]] = make_double2(1.0, 0.0);
-      }
+    std::vector<double> omega;
+    std::vector<double2> bh;
+    port_rhs(c, nfreq, freq_hz, omega, bh);
     hip_ok(hipMemcpyAsync(F.b, bh.data(), bh.size() * sizeof(double2), hipMemcpyHostToDevice, st), "b");
     std::vector<int> iters;
     std::vector<double> relres;

@@ -17,6 +17,8 @@ PFFT_FAR_ONLY = 1
 PFFT_NEAR_ONLY = 2
 PFFT_PRECOND = 4
 PFFT_PRECOND_ONLY = 8
+PFFT_LEARNED_ONLY = 16
+MLP_MAGIC = 0x504D4C50
 
 STATUS = {0: "PFFT_OK", -1: "PFFT_EINVAL", -2: "PFFT_ETOPO", -3: "PFFT_ENOMEM",
           -4: "PFFT_EDEVICE", -5: "PFFT_ENOCONV", -6: "PFFT_EFACTOR"}
@@ -24,7 +26,8 @@ STATUS = {0: "PFFT_OK", -1: "PFFT_EINVAL", -2: "PFFT_ETOPO", -3: "PFFT_ENOMEM",
 EXPORTS = ("pfft_setup", "pfft_sizes", "pfft_matvec", "solve_ports", "extract_RL",
            "pfft_precond_load", "pfft_destroy", "pfft_last_error",
            "pfft_host_setup", "pfft_host_get", "pfft_host_free", "pfft_profile",
-           "pfft_stage_times")
+           "pfft_stage_times", "pfft_precond_save", "pfft_learned_collect", "pfft_learned_train",
+           "pfft_learned_clear", "pfft_learned_stats", "pfft_mlp_grad")
 
 STAGES = ("loop_to_branch", "tri_current", "project", "fft_x", "fft_y", "fft_z_conv", "ifft_y",
           "ifft_x", "interp", "combine", "branch_to_loop", "precond")
@@ -87,6 +90,18 @@ def load():
     lib.pfft_profile.restype = i32
     lib.pfft_stage_times.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     lib.pfft_stage_times.restype = i32
+    lib.pfft_precond_save.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+    lib.pfft_precond_save.restype = i32
+    lib.pfft_learned_collect.argtypes = [vp, i32, vp, dbl, i32, ctypes.POINTER(i64), vp]
+    lib.pfft_learned_collect.restype = i32
+    lib.pfft_learned_train.argtypes = [vp, i32, i32, i32, dbl, ctypes.c_uint64, vp, vp]
+    lib.pfft_learned_train.restype = i32
+    lib.pfft_learned_clear.argtypes = [vp]
+    lib.pfft_learned_clear.restype = i32
+    lib.pfft_learned_stats.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.pfft_learned_stats.restype = i32
+    lib.pfft_mlp_grad.argtypes = [i32, vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]
+    lib.pfft_mlp_grad.restype = i32
     _lib = lib
     return lib
 
@@ -234,9 +249,44 @@ class Context:
         _check(load().pfft_stage_times(self._h, ms, calls))
         return {name: (ms[i], int(calls[i])) for i, name in enumerate(STAGES)}
 
-    def precond_load(self, weights_bf16):
-        w = np.ascontiguousarray(weights_bf16)
+    def precond_load(self, blob):
+        """Load a weight blob (bytes or uint8 array, layout in pfft.h)."""
+        w = np.frombuffer(bytes(blob), np.uint8).copy()
         _check(load().pfft_precond_load(self._h, _ptr(w), w.nbytes))
+
+    def precond_save(self):
+        """Current weight blob as bytes."""
+        n = ctypes.c_int64()
+        _check(load().pfft_precond_save(self._h, None, 0, ctypes.byref(n)))
+        buf = np.zeros(n.value, np.uint8)
+        _check(load().pfft_precond_save(self._h, _ptr(buf), n.value, ctypes.byref(n)))
+        return buf.tobytes()
+
+    def learned_collect(self, freqs_hz, tol=1e-8, maxit=60, stream=None):
+        """Append (Krylov vector, exact error) training pairs from one-cycle
+        plain-P solves; returns the training-set size in rows."""
+        f = np.ascontiguousarray(np.asarray(freqs_hz, np.float64).reshape(-1))
+        rows = ctypes.c_int64()
+        _check(load().pfft_learned_collect(self._h, f.size, _ptr(f), tol, maxit,
+                                           ctypes.byref(rows), _stream_handle(stream)))
+        return rows.value
+
+    def learned_train(self, steps, batch=8192, hidden=256, lr=1e-3, seed=0, stream=None):
+        """Adam steps on the collected set; returns the per-step minibatch loss."""
+        loss = np.zeros(max(steps, 1), np.float32)
+        _check(load().pfft_learned_train(self._h, steps, batch, hidden, lr, seed, _ptr(loss),
+                                         _stream_handle(stream)))
+        return loss[:steps]
+
+    def learned_clear(self):
+        _check(load().pfft_learned_clear(self._h))
+
+    def learned_stats(self):
+        """(applications, numeric fallbacks to P^-1, right-hand sides switched
+        back to plain P by the convergence judge)."""
+        out = (ctypes.c_int64 * 3)()
+        _check(load().pfft_learned_stats(self._h, out))
+        return int(out[0]), int(out[1]), int(out[2])
 
     def close(self):
         if getattr(self, "_h", None):
@@ -248,6 +298,68 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def _to_bf16_bits(a):
+    """float -> bfloat16 bit patterns (round to nearest even)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def mlp_blob(params):
+    """Weight blob (pfft.h layout) from {W1 [H,F], W2 [H,H], W3 [O,H], b1, b2, b3}."""
+    W1, W2, W3 = (np.asarray(params[k], np.float64) for k in ("W1", "W2", "W3"))
+    H, F = W1.shape
+    O = W3.shape[0]
+    w = _to_bf16_bits(np.concatenate([W1.ravel(), W2.ravel(), W3.ravel()]))
+    if w.size % 2:
+        w = np.concatenate([w, np.zeros(1, np.uint16)])
+    b = np.concatenate([np.asarray(params[k], np.float32).ravel() for k in ("b1", "b2", "b3")])
+    head = np.array([MLP_MAGIC, F, H, O], np.uint32).view(np.int32)
+    return head.tobytes() + w.tobytes() + b.astype(np.float32).tobytes()
+
+
+def mlp_params(blob):
+    """Inverse of mlp_blob (weights as the float64 values of their bf16)."""
+    raw = bytes(blob)
+    magic, F, H, O = np.frombuffer(raw[:16], np.int32)
+    if np.uint32(magic) != MLP_MAGIC:
+        raise ValueError("not a weight blob")
+    nw = H * F + H * H + O * H
+    w = np.frombuffer(raw[16:16 + 2 * nw], np.uint16).astype(np.uint32) << 16
+    w = w.view(np.float32).astype(np.float64)
+    off = 16 + 4 * ((nw + 1) // 2)
+    b = np.frombuffer(raw[off:], np.float32).astype(np.float64)
+    return dict(W1=w[:H * F].reshape(H, F), W2=w[H * F:H * F + H * H].reshape(H, H),
+                W3=w[H * F + H * H:].reshape(O, H), b1=b[:H], b2=b[H:2 * H], b3=b[2 * H:])
+
+
+def mlp_grad(blob, X_bf16, T, w, stream=None):
+    """Network output, loss sum_i w_i |y_i - t_i|^2 and parameter gradients
+    on the device (pfft_mlp_grad).  X_bf16: CUDA int16/uint16 tensor [rows, F]
+    of bf16 bit patterns (or torch.bfloat16); T: float32 [rows, 2]; w: float32
+    [rows].  Returns (Y [rows, 2] float32 tensor, gradient dict, loss)."""
+    import torch
+    raw = np.frombuffer(bytes(blob), np.uint8).copy()
+    _, F, H, O = np.frombuffer(raw[:16].tobytes(), np.int32)
+    rows = X_bf16.shape[0]
+    Y = torch.empty((rows, 2), dtype=torch.float32, device=X_bf16.device)
+    npar = H * F + H * H + 2 * H + 2 * H + 2
+    g = torch.empty(npar, dtype=torch.float32, device=X_bf16.device)
+    loss = ctypes.c_double()
+    X_bf16, T, w = X_bf16.contiguous(), T.contiguous(), w.contiguous()
+    _check(load().pfft_mlp_grad(rows, _ptr(raw), raw.nbytes, ctypes.c_void_p(X_bf16.data_ptr()),
+                                ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                ctypes.byref(loss), _stream_handle(stream)))
+    gc = g.cpu().numpy().astype(np.float64)
+    sizes = [("W1", (H, F)), ("W2", (H, H)), ("W3", (2, H)), ("b1", (H,)), ("b2", (H,)), ("b3", (2,))]
+    out, o = {}, 0
+    for k, shp in sizes:
+        n = int(np.prod(shp))
+        out[k] = gc[o:o + n].reshape(shp)
+        o += n
+    return Y, out, loss.value
 
 
 def extract_RL(freqs_hz, Y):

@@ -1,0 +1,246 @@
+"""GPU checks of the learned preconditioner correction.
+
+* Network forward and gradients (matrix-core GEMMs with bf16 weights, FP32
+  accumulation, FP32 activations fed as bf16 hi + lo pairs) against the FP64
+  reference with the same bf16 weights and inputs: within 1e-3 (norm-wise,
+  per tensor; tighter than the 1e-2 a bf16 path needs); an integer case
+  exactly.
+* The correction applied to loop vectors against the oracle's dense P^-1,
+  features and network.
+* Fallback: NaN or oversized corrections leave P^-1 untouched.
+* Training on residual/error pairs from the solver itself, and what the
+  trained correction gains over plain P (printed, asserted not to hurt).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+
+def _bf16_tensor(Xd):
+    """float64 values that are bf16-representable -> CUDA int16 bit patterns."""
+    bits = (np.ascontiguousarray(Xd, np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    return torch.from_numpy(bits.view(np.int16)).cuda()
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _rounded(p):
+    q = dict(p)
+    for k in ("W1", "W2", "W3"):
+        q[k] = mlp.bf16_round(p[k])
+    for k in ("b1", "b2", "b3"):
+        q[k] = np.asarray(p[k], np.float32).astype(np.float64)
+    return q
+
+
+@gpu
+@pytest.mark.parametrize("rows,F,H,seed", [(1000, 8, 64, 0), (333, 8, 256, 1), (77, 5, 40, 2)])
+def test_mlp_gradients_match_oracle(rows, F, H, seed):
+    import paper_2210_04891_amd as P
+    rng = np.random.default_rng(seed)
+    p = mlp.init(F, H, 2, seed=seed)
+    p["W3"] = p["W3"] * 10.0
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.standard_normal(p[k].shape) * 0.1
+    q = _rounded(p)
+    X = mlp.bf16_round(rng.standard_normal((rows, F)))
+    T = rng.standard_normal((rows, 2)).astype(np.float32).astype(np.float64)
+    group = rng.integers(0, 7, rows)
+    w = mlp.group_weights(T, group).astype(np.float32).astype(np.float64)
+    L, g, y = mlp.loss_and_grad(q, X, T, w)
+    Yd, gd, Ld = P.mlp_grad(P.mlp_blob(q), _bf16_tensor(X), torch.from_numpy(T.astype(np.float32)).cuda(),
+                            torch.from_numpy(w.astype(np.float32)).cuda())
+    assert _relerr(Yd.cpu().numpy().astype(np.float64), y) <= 1e-3
+    assert Ld == pytest.approx(L, rel=1e-3)
+    for k in g:
+        assert _relerr(gd[k], g[k]) <= 1e-3, k
+
+
+@gpu
+def test_mlp_forward_exact_on_integers():
+    """Small-integer weights and inputs: every product and partial sum is an
+    exact FP32 (and bf16) integer, so the matrix-core result must be exact;
+    checks the tile layout of both operands and the accumulator."""
+    import paper_2210_04891_amd as P
+    rng = np.random.default_rng(4)
+    F, H, rows = 8, 96, 200
+    W1 = rng.integers(-1, 2, (H, F)).astype(float)
+    W2 = np.zeros((H, H))
+    for i in range(H):
+        W2[i, rng.choice(H, 4, replace=False)] = rng.choice([-1.0, 1.0], 4)
+    W3 = rng.integers(-2, 3, (2, H)).astype(float)
+    p = dict(W1=W1, W2=W2, W3=W3, b1=rng.integers(-2, 3, H).astype(float),
+             b2=rng.integers(-2, 3, H).astype(float), b3=np.array([0.5, -1.0]))
+    X = rng.integers(-2, 3, (rows, F)).astype(float)
+    y, _ = mlp.forward(p, X)
+    T = np.zeros((rows, 2))
+    Yd, _, _ = P.mlp_grad(P.mlp_blob(p), _bf16_tensor(X), torch.from_numpy(T.astype(np.float32)).cuda(),
+                          torch.ones(rows, dtype=torch.float32, device="cuda"))
+    assert np.array_equal(Yd.cpu().numpy().astype(np.float64), y)
+
+
+@pytest.fixture(scope="module")
+def bar():
+    from oracle.mesh import RWGMesh, gram_matrix
+    from oracle.circuit import Circuit
+    from oracle import integrals as I, solve as S
+    s = W.paper_bar_e1()
+    m = RWGMesh(s.V, s.T)
+    c = Circuit(m, s.ports)
+    K = I.kernel_dense(m)
+    A = c.loop_matrix().toarray()
+    G = gram_matrix(m, weight=S.triangle_impedance(m, c, 1.0).real).toarray()
+    return dict(s=s, m=m, c=c, K=K, A=A, G=G)
+
+
+def _oracle_features(bar, v, z, omega):
+    """Features of pfft.h for one right-hand side, from oracle data."""
+    from oracle import solve as S
+    m, c, K, G = bar["m"], bar["c"], bar["K"], bar["G"]
+    l = v.size
+    sv, sz = np.sqrt(l) / np.linalg.norm(v), np.sqrt(l) / np.linalg.norm(z)
+    zs = S.surface_impedance(omega, 5.8e7)
+    X = np.zeros((l, 8))
+    X[:, 0], X[:, 1] = v.real * sv, v.imag * sv
+    X[:, 2], X[:, 3] = z.real * sz, z.imag * sz
+    X[:, 4] = (np.log10(omega / (2 * np.pi)) - 8) / 2
+    for i, e in enumerate(c.links):
+        if e >= m.nedge:
+            X[i, 5] = 1.0
+            continue
+        X[i, 6] = 1.0 if c.branch_u[e] == c.branch_v[e] else 0.0
+        D = zs * G[e, e] + 1j * omega * S.MU0 / (4 * np.pi) * K[e, e]
+        X[i, 7] = D.real / abs(D)
+    return X, sz
+
+
+def _dense_precond(bar, omega):
+    from oracle import solve as S
+    m, c, K, A, G = bar["m"], bar["c"], bar["K"], bar["A"], bar["G"]
+    zs = S.surface_impedance(omega, 5.8e7)
+    d = np.zeros(m.nedge + c.nport, complex)
+    d[:m.nedge] = zs * np.diag(G) + 1j * omega * S.MU0 / (4 * np.pi) * np.diag(K)
+    return A @ np.diag(d) @ A.T
+
+
+def _small_net(seed, H=64, scale=1.0):
+    p = mlp.init(8, H, 2, seed=seed)
+    p["W3"] = p["W3"] * scale
+    return _rounded(p)
+
+
+@gpu
+def test_learned_apply_matches_oracle(bar):
+    import paper_2210_04891_amd as P
+    ctx = P.Context(bar["s"], (32, 8, 8), near_kappa=1.5, grid_fp64=True)
+    q = _small_net(3, scale=10.0)
+    ctx.precond_load(P.mlp_blob(q))
+    om = 2 * np.pi * np.array([1e9, 2e10, 1e11])
+    V = W.complex_normal(11, (3, bar["c"].nloop))
+    zd = ctx.matvec(torch.from_numpy(V).cuda(), omega=om, flags=P.PFFT_LEARNED_ONLY).cpu().numpy()
+    for r in range(3):
+        z0 = np.linalg.solve(_dense_precond(bar, om[r]), V[r])
+        X, sz = _oracle_features(bar, V[r], z0, om[r])
+        y, _ = mlp.forward(q, mlp.bf16_round(X))
+        zexp = z0 + (y[:, 0] + 1j * y[:, 1]) / sz
+        assert np.linalg.norm(zexp - z0) > 1e-3 * np.linalg.norm(z0)   # the correction is not negligible
+        assert np.linalg.norm(zd[r] - zexp) <= 2e-2 * np.linalg.norm(zexp - z0) + 1e-6 * np.linalg.norm(z0)
+    assert ctx.learned_stats() == (3, 0, 0)
+
+
+@gpu
+def test_zero_network_is_plain_precond(bar):
+    import paper_2210_04891_amd as P
+    ctx = P.Context(bar["s"], (32, 8, 8), near_kappa=1.5, grid_fp64=True)
+    q = _small_net(5)
+    q["W3"][:] = 0
+    q["b3"][:] = 0
+    ctx.precond_load(P.mlp_blob(q))
+    om = 2 * np.pi * np.array([5e9, 5e10])
+    V = torch.from_numpy(W.complex_normal(12, (2, bar["c"].nloop))).cuda()
+    a = ctx.matvec(V, omega=om, flags=P.PFFT_LEARNED_ONLY).cpu().numpy()
+    b = ctx.matvec(V, omega=om, flags=P.PFFT_PRECOND_ONLY).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+@gpu
+@pytest.mark.parametrize("poison", ["nan", "oversized"])
+def test_misbehaving_network_falls_back(bar, poison):
+    import paper_2210_04891_amd as P
+    ctx = P.Context(bar["s"], (32, 8, 8), near_kappa=1.5, grid_fp64=True)
+    q = _small_net(6)
+    if poison == "nan":
+        q["W2"][7, 3] = np.nan
+    else:
+        q["b3"][:] = 100.0
+    ctx.precond_load(P.mlp_blob(q))
+    om = 2 * np.pi * np.array([5e9, 5e10])
+    V = torch.from_numpy(W.complex_normal(13, (2, bar["c"].nloop))).cuda()
+    a = ctx.matvec(V, omega=om, flags=P.PFFT_LEARNED_ONLY).cpu().numpy()
+    b = ctx.matvec(V, omega=om, flags=P.PFFT_PRECOND_ONLY).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert ctx.learned_stats() == (2, 2, 0)
+    f = np.array([3e10, 9e10])
+    Y1, it1, _, c1 = ctx.solve_ports(f, tol=1e-7, maxit=200, restart=40, precond=1)
+    Y2, it2, _, c2 = ctx.solve_ports(f, tol=1e-7, maxit=200, restart=40, precond=2)
+    assert c1 == 0 and c2 == 0
+    assert np.array_equal(it1, it2) and np.array_equal(Y1, Y2)
+
+
+@gpu
+def test_weights_roundtrip_and_bad_blob(bar):
+    import paper_2210_04891_amd as P
+    ctx = P.Context(bar["s"], (32, 8, 8), near_kappa=1.5, grid_fp64=True)
+    with pytest.raises(P.PfftError):
+        ctx.precond_save()          # nothing loaded yet
+    blob = P.mlp_blob(_small_net(7))
+    ctx.precond_load(blob)
+    assert ctx.precond_save() == blob
+    with pytest.raises(P.PfftError):
+        ctx.precond_load(blob[:-4])
+    bad = bytearray(blob)
+    bad[0] ^= 1
+    with pytest.raises(P.PfftError):
+        ctx.precond_load(bytes(bad))
+
+
+@gpu
+def test_train_on_solver_pairs_and_gain():
+    """Exact (Krylov vector, error) pairs from one-cycle plain-P solves of a
+    two-wire array at 8 training frequencies; Adam on the device; evaluation
+    at 4 other frequencies.  The measured gain is printed; the convergence
+    judge bounds what a poor correction can cost."""
+    import paper_2210_04891_amd as P
+    s = W.bond_wires(nwire=2, nseg=48, span=0.8e-3, height=120e-6)
+    ctx = P.Context(s, (64, 16, 16), near_kappa=1.5, grid_fp64=False)
+    f_train = 10.0 ** np.linspace(7.1, 10.1, 8)
+    f_eval = 10.0 ** np.array([7.5, 8.4, 9.3, 9.9])
+    rows = ctx.learned_collect(f_train, tol=1e-9, maxit=80)
+    assert rows > 0 and rows % ctx.sizes["l"] == 0
+    loss = ctx.learned_train(600, batch=4096, hidden=256, lr=1e-3, seed=0)
+    assert np.all(np.isfinite(loss))
+    assert loss[-50:].mean() < 0.9 * loss[:10].mean()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Y1, it1, rr1, c1 = ctx.solve_ports(f_eval, tol=1e-6, maxit=300, restart=60, precond=1)
+    t1 = time.perf_counter()
+    Y2, it2, rr2, c2 = ctx.solve_ports(f_eval, tol=1e-6, maxit=300, restart=60, precond=2)
+    t2 = time.perf_counter()
+    assert c1 == 0 and c2 == 0 and np.all(rr2 <= 1e-6)
+    n_apply, n_fall, n_off = ctx.learned_stats()
+    assert n_apply > 0 and n_fall == 0
+    assert np.abs(Y2 - Y1).max() <= 1e-4 * np.abs(Y1).max()
+    print("\nlearned-correction gain (%d training rows): loss %.3f -> %.3f; iterations plain %s learned %s "
+          "(judge switched %d of %d RHS back); time plain %.3f s learned %.3f s"
+          % (rows, loss[:10].mean(), loss[-50:].mean(), it1.ravel().tolist(), it2.ravel().tolist(), n_off,
+             it1.size, t1 - t0, t2 - t1))
+    assert np.all(it2 <= it1 + 6)
