@@ -142,10 +142,13 @@ def test_kernel_symmetric_and_positive(c1):
 
 
 def test_kernel_rows_match_dense(c1):
+    """kernel_rows integrates each pair with the row triangle outermost;
+    kernel_dense averages both orders, so the two differ by at most half the
+    quadrature asymmetry bounded above (1e-7 of the largest entry)."""
     m, K = c1["mesh"], c1["K"]
     rows = np.array([0, 17, 1499, 2999])
     R = I.kernel_rows(m, rows)
-    assert np.allclose(R, K[rows], rtol=1e-12, atol=1e-12 * np.abs(K).max())
+    assert np.abs(R - K[rows]).max() <= 0.5e-7 * np.abs(K).max()
 
 
 def test_singular_rule_converged():
