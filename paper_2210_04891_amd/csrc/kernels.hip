@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <string>
 
 #include "kernels.h"
 
@@ -504,6 +506,363 @@ __global__ void __launch_bounds__(256) k_fft_yz(YZArgs a, V2<T> *data, const T *
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant of the fused plane kernel (FP32).  A zero-padded
+// length-2N transform of N inputs splits into two N-point transforms: the
+// even outputs are FFT_N(x), the odd ones FFT_N(x_n W_2N^n); a cropped
+// length-2N inverse is the sum of the two N-point inverses, the odd one
+// multiplied by conj(W_2N^n).  Each thread owns one N-point line in
+// registers (decimation in frequency forward, in time inverse, so no
+// reordering), the two halves of a line live in a lane pair and are summed
+// with a lane exchange, and the plane crosses LDS twice (rows -> columns ->
+// rows).  Twiddles are compile-time constants.
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846;
+constexpr double taylor_sin(double x) {
+  double t = x, s = x;
+  for (int i = 1; i < 12; ++i) {
+    t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+    s += t;
+  }
+  return s;
+}
+constexpr double taylor_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int i = 1; i < 12; ++i) {
+    t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+    s += t;
+  }
+  return s;
+}
+// W_n^k = exp(-2 pi i k / n) by quadrant reduction to [0, pi/2]
+struct TwTable {
+  static constexpr int N = 1024;
+  float c[N], s[N];
+  constexpr TwTable() : c(), s() {
+    for (int k = 0; k < N; ++k) {
+      const int q = (4 * k) / N, r = 4 * k - q * N;
+      const double a = kPi / 2 * r / N, ca = taylor_cos(a), sa = taylor_sin(a);
+      const double cc = q == 0 ? ca : q == 1 ? -sa : q == 2 ? -ca : sa;
+      const double ss = q == 0 ? sa : q == 1 ? ca : q == 2 ? -sa : -ca;
+      c[k] = (float)cc;
+      s[k] = (float)-ss;
+    }
+  }
+};
+constexpr TwTable kTw{};
+
+// W_n^k (SIGN -1) or its conjugate (SIGN +1); n divides 1024
+template <int SIGN>
+__device__ __forceinline__ float2 tw(int k, int n) {
+  // n is a power of two up to TwTable::N (all call sites use compile-time n)
+  const int i = (k * (TwTable::N / n)) & (TwTable::N - 1);
+  return make_float2(kTw.c[i], SIGN < 0 ? kTw.s[i] : -kTw.s[i]);
+}
+
+constexpr int clog2(int n) { return n <= 1 ? 0 : 1 + clog2(n / 2); }
+constexpr int brev(int k, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((k >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// decimation in frequency: natural order in, bit-reversed order out
+template <int N, int SIGN, int S = 0>
+__device__ __forceinline__ void fft_dif(float2 (&v)[N]) {
+  if constexpr ((1 << S) < N) {
+    constexpr int half = N >> (S + 1);
+#pragma unroll
+    for (int b = 0; b < (1 << S); ++b)
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const int i0 = b * 2 * half + j, i1 = i0 + half;
+        const float2 a = v[i0], c = v[i1];
+        v[i0] = make_float2(a.x + c.x, a.y + c.y);
+        const float2 d = make_float2(a.x - c.x, a.y - c.y);
+        if (j == 0) {
+          v[i1] = d;
+        } else {
+          const float2 w = tw<SIGN>(j, 2 * half);
+          v[i1] = make_float2(d.x * w.x - d.y * w.y, d.x * w.y + d.y * w.x);
+        }
+      }
+    fft_dif<N, SIGN, S + 1>(v);
+  }
+}
+
+// decimation in time: bit-reversed order in, natural order out
+template <int N, int SIGN, int S = 0>
+__device__ __forceinline__ void fft_dit(float2 (&v)[N]) {
+  if constexpr ((1 << S) < N) {
+    constexpr int half = 1 << S;
+#pragma unroll
+    for (int b = 0; b < N / (2 * half); ++b)
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const int i0 = b * 2 * half + j, i1 = i0 + half;
+        const float2 a = v[i0];
+        float2 c = v[i1];
+        if (j != 0) {
+          const float2 w = tw<SIGN>(j, 2 * half);
+          c = make_float2(c.x * w.x - c.y * w.y, c.x * w.y + c.y * w.x);
+        }
+        v[i0] = make_float2(a.x + c.x, a.y + c.y);
+        v[i1] = make_float2(a.x - c.x, a.y - c.y);
+      }
+    fft_dit<N, SIGN, S + 1>(v);
+  }
+}
+
+// Lane-quad exchange (DPP quad_perm): lane q of each quad of 4 receives the
+// value of lane q ^ 1, q ^ 2 or q ^ 3.
+template <int CTRL>
+__device__ __forceinline__ float qperm(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ float2 qperm2(float2 v) {
+  return make_float2(qperm<CTRL>(v.x), qperm<CTRL>(v.y));
+}
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Per-lane constants of the radix-4 step across a quad (lane q keeps output
+// q): rot[d] = W_4^{(q ^ d) q} for the value received from lane q ^ d, and
+// one-hot weights for twiddles W^{q k}.  Everything lane-dependent is
+// arithmetic (no branches, so loads are not serialised).
+struct QuadLane {
+  float2 rot[4];
+  float f[4];
+};
+template <int SIGN>
+__device__ __forceinline__ QuadLane quad_lane(int q) {
+  QuadLane L;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int e = ((q ^ d) * q) & 3;     // W_4^e, W_4 = exp(SIGN 2 pi i / 4)
+    const float re = e == 0 ? 1.f : e == 2 ? -1.f : 0.f;
+    const float im = e == 1 ? (float)SIGN : e == 3 ? (float)-SIGN : 0.f;
+    L.rot[d] = make_float2(re, im);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) L.f[j] = q == j ? 1.f : 0.f;
+  return L;
+}
+template <int SIGN>
+__device__ __forceinline__ float2 quad_dft(float2 v, const QuadLane &L) {
+  const float2 v1 = qperm2<0xB1>(v), v2 = qperm2<0x4E>(v), v3 = qperm2<0x1B>(v);
+  const float2 a = cmulf(v, L.rot[0]), b = cmulf(v1, L.rot[1]), c = cmulf(v2, L.rot[2]), d = cmulf(v3, L.rot[3]);
+  return make_float2((a.x + b.x) + (c.x + d.x), (a.y + b.y) + (c.y + d.y));
+}
+// W_n^{q k} for the lane's q (one-hot blend of compile-time constants)
+template <int SIGN>
+__device__ __forceinline__ float2 tw_q(const QuadLane &L, int k, int n) {
+  const float2 w1 = tw<SIGN>(k, n), w2 = tw<SIGN>(2 * k, n), w3 = tw<SIGN>(3 * k, n);
+  return make_float2(L.f[0] + L.f[1] * w1.x + L.f[2] * w2.x + L.f[3] * w3.x,
+                     L.f[1] * w1.y + L.f[2] * w2.y + L.f[3] * w3.y);
+}
+// exact branch-free select: a where mask is all ones, b where it is zero
+__device__ __forceinline__ float selb(int mask, float a, float b) {
+  return __int_as_float((__float_as_int(a) & mask) | (__float_as_int(b) & ~mask));
+}
+__device__ __forceinline__ float2 selb2(int mask, float2 a, float2 b) {
+  return make_float2(selb(mask, a.x, b.x), selb(mask, a.y, b.y));
+}
+// w on the odd half (hmask all ones), 1 on the even half
+__device__ __forceinline__ float2 half_tw(int hmask, float2 w) {
+  return selb2(hmask, w, make_float2(1.f, 0.f));
+}
+
+// X passes of the convolution (FP32), lines of NX = 4 M points along x with
+// stride C between points; a zero-padded length-2 NX transform splits into
+// even/odd halves h, each an NX-point transform done as M-point register
+// FFTs over x = 4m + q (one per lane q of a quad) and a radix-4 step across
+// the quad.  Lanes: 8 columns per wave, lane = 8 col + 4 h + q.
+//   forward: in [ch][NX][C] -> out [ch][2NX][C]
+//   inverse: in [ch][2NX][C] -> out [ch][NX][C] (crop, times scale)
+typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t(), 0, 0, 0)) b64_t;
+
+// Buffer access with a per-lane byte offset (VGPR) and a uniform one (SGPR):
+// no per-element 64-bit addresses, and the hardware drops accesses beyond
+// the buffer's size.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_load2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store2(float2 v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64_t, v), r, voff, soff, 0);
+}
+
+template <int NX, int SIGN>
+__global__ void __launch_bounds__(256) k_fft_x_reg(const float2 *in, float2 *out, int C, int ncol, float scale) {
+  constexpr int M = NX / 4, LM = clog2(M);
+  const int lane = threadIdx.x & 63, q = lane & 3, h = (lane >> 2) & 1;
+  const int hm = -h;   // all ones on the odd half
+  // the launch covers ncol (a multiple of 32) columns exactly
+  const int col = blockIdx.x * 32 + (threadIdx.x >> 6) * 8 + (lane >> 3);
+  const int chn = col / C, c = col - chn * C;
+  const unsigned nin = (unsigned)ncol * (SIGN < 0 ? NX : 2 * NX) * 8u;
+  const unsigned nout = (unsigned)ncol * (SIGN < 0 ? 2 * NX : NX) * 8u;
+  const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in, nin), rout = buf_rsrc(out, nout);
+  const unsigned C8 = (unsigned)C * 8u;
+  const QuadLane L = quad_lane<SIGN>(q);
+  float2 v[M];
+  if (SIGN < 0) {
+    const unsigned vo = ((unsigned)chn * NX * C + c + q * C) * 8u;
+    // x = 4 m + q, times W_{2NX}^x on the odd half
+    const float2 wq = half_tw(hm, tw_q<-1>(L, 1, 2 * NX));
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = buf_load2(rin, vo, 4u * m * C8);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = cmulf(cmulf(v[m], half_tw(hm, tw<-1>(4 * m, 2 * NX))), wq);
+    fft_dif<M, -1>(v);                       // position p holds k = brev(p)
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+      const int k = brev(p, LM);
+      v[p] = quad_dft<-1>(cmulf(v[p], tw_q<-1>(L, k, NX)), L);
+      __builtin_amdgcn_sched_barrier(0);   // one exchange at a time (register pressure)
+    }
+    // lane q now holds X_h[k + M q]; frequency kx = 2 (k + M q) + h
+    const unsigned oo = ((unsigned)chn * 2 * NX * C + c + (2 * M * q + h) * C) * 8u;
+#pragma unroll
+    for (int p = 0; p < M; ++p) buf_store2(v[p], rout, oo, 2u * brev(p, LM) * C8);
+  } else {
+    const unsigned vo = ((unsigned)chn * 2 * NX * C + c + (2 * M * q + h) * C) * 8u;
+#pragma unroll
+    for (int p = 0; p < M; ++p) v[p] = buf_load2(rin, vo, 2u * brev(p, LM) * C8);
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+      const int k = brev(p, LM);
+      v[p] = cmulf(quad_dft<+1>(v[p], L), tw_q<+1>(L, k, NX));
+    }
+    fft_dit<M, +1>(v);                       // natural order: v[m] = U_h[4 m + q]
+    const float2 wq = half_tw(hm, tw_q<+1>(L, 1, 2 * NX));
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = cmulf(cmulf(v[m], half_tw(hm, tw<+1>(4 * m, 2 * NX))), wq);
+    // sum the halves (lanes 4 apart); lane h keeps m in [h M/2, (h+1) M/2)
+    const unsigned oo = ((unsigned)chn * NX * C + c + (4 * h * (M / 2) + q) * C) * 8u;
+#pragma unroll
+    for (int j = 0; j < M / 2; ++j) {
+      const float2 lo = v[j], hi = v[j + M / 2];
+      const float2 send = selb2(hm, lo, hi), keep = selb2(hm, hi, lo);
+      const float2 r = make_float2(__shfl_xor(send.x, 4), __shfl_xor(send.y, 4));
+      buf_store2(make_float2((keep.x + r.x) * scale, (keep.y + r.y) * scale), rout, oo, 4u * j * C8);
+    }
+  }
+}
+
+// One (channel, kx) plane per workgroup of 2 NY threads (NY = 2 NZ).  Block
+// b works on kx = b / ch, channel = b % ch, so consecutive workgroups share
+// the spectrum slice of one kx in L2.
+template <int NY, int NZ>
+__global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, const float *ghat, long ch) {
+  static_assert(NY == 2 * NZ, "one thread per (row, half) and per (column, half)");
+  constexpr int PT = NY + 1;                 // T[kz][y] pitch
+  constexpr int P0 = NZ + 1;                 // staging [y][z] pitch
+  constexpr int LZ = 2 * NZ, LY = 2 * NY;
+  __shared__ float2 sm[LZ * PT];
+  const int t = threadIdx.x, half = t & 1, line = t >> 1;
+  const long kx = blockIdx.x / ch, chan = blockIdx.x - kx * ch;
+  float2 *io = data + (chan * a.two_nx + kx) * (long)(NY * NZ);
+  // stage 0: coalesced load of the NY x NZ plane
+#pragma unroll
+  for (int q = 0; q < NZ / 2; ++q) {
+    const int idx = t + q * 2 * NY, y = idx / NZ, z = idx - y * NZ;
+    sm[y * P0 + z] = io[idx];
+  }
+  __syncthreads();
+  // stage A: forward z half `half` of row `line`
+  {
+    float2 v[NZ];
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) {
+      float2 x = sm[line * P0 + z];
+      if (half) {
+        const float2 w = tw<-1>(z, LZ);
+        x = make_float2(x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x);
+      }
+      v[z] = x;
+    }
+    fft_dif<NZ, -1>(v);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) sm[(2 * k + half) * PT + line] = v[brev(k, clog2(NZ))];
+  }
+  __syncthreads();
+  // stage C: column kz = line, y half `half`: forward, spectrum, inverse
+  {
+    const int kz = line;
+    float2 v[NY];
+#pragma unroll
+    for (int y = 0; y < NY; ++y) {
+      float2 x = sm[kz * PT + y];
+      if (half) {
+        const float2 w = tw<-1>(y, LY);
+        x = make_float2(x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x);
+      }
+      v[y] = x;
+    }
+    fft_dif<NY, -1>(v);
+    const int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
+    const int fz = kz <= NZ ? kz : LZ - kz;
+    const float *gx = ghat + (long)fx * (NY + 1) * (NZ + 1) + fz;
+#pragma unroll
+    for (int p = 0; p < NY; ++p) {
+      const int ky = 2 * brev(p, clog2(NY)) + half;
+      const int fy = ky <= NY ? ky : LY - ky;
+      const float g = gx[fy * (NZ + 1)];
+      v[p] = make_float2(v[p].x * g, v[p].y * g);
+    }
+    fft_dit<NY, +1>(v);
+    if (half) {
+#pragma unroll
+      for (int n = 0; n < NY; ++n) {
+        const float2 w = tw<+1>(n, LY);
+        v[n] = make_float2(v[n].x * w.x - v[n].y * w.y, v[n].x * w.y + v[n].y * w.x);
+      }
+    }
+    // lane pair sum; lane `half` keeps n in [half NY/2, (half+1) NY/2)
+    float2 out[NY / 2];
+#pragma unroll
+    for (int j = 0; j < NY / 2; ++j) {
+      const float2 lo = v[j], hi = v[j + NY / 2];
+      const float2 send = half ? lo : hi, keep = half ? hi : lo;
+      const float2 r = qperm2<0xB1>(send);   // lane ^ 1
+      out[j] = make_float2(keep.x + r.x, keep.y + r.y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NY / 2; ++j) sm[kz * PT + half * (NY / 2) + j] = out[j];
+  }
+  __syncthreads();
+  // stage D: row n = line, z half `half`: inverse, crop, store
+  {
+    float2 v[NZ];
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) v[k] = sm[(2 * k + half) * PT + line];
+    fft_dif<NZ, +1>(v);                     // position p holds z = brev(p)
+    if (half) {
+#pragma unroll
+      for (int p = 0; p < NZ; ++p) {
+        const float2 w = tw<+1>(brev(p, clog2(NZ)), LZ);
+        v[p] = make_float2(v[p].x * w.x - v[p].y * w.y, v[p].x * w.y + v[p].y * w.x);
+      }
+    }
+    const float sc = a.scale;
+    float2 *row = io + (long)line * NZ + half * (NZ / 2);
+#pragma unroll
+    for (int j = 0; j < NZ / 2; ++j) {
+      const float2 lo = v[brev(j, clog2(NZ))], hi = v[brev(j + NZ / 2, clog2(NZ))];
+      const float2 send = half ? lo : hi, keep = half ? hi : lo;
+      const float2 r = qperm2<0xB1>(send);   // lane ^ 1
+      row[j] = make_float2((keep.x + r.x) * sc, (keep.y + r.y) * sc);
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fft_axis(FftArgs a, const V2<T> *in, V2<T> *out, const T *ghat) {
   extern __shared__ unsigned char smraw[];
@@ -643,16 +1002,84 @@ static void fft_axis(const V2<T> *in, V2<T> *out, long A, long C, int n_in, int 
   k_fft_axis<T><<<cdiv(lines, lb), 256, shm, st>>>(a, in, out, ghat);
 }
 
+// Plane-kernel choice: the register variant exists for (N_y, N_z) =
+// (64, 32), (32, 16), (16, 8) in FP32; PFFT_FFT_PLAN=lds forces the LDS
+// Stockham variant (both are exact transforms; the choice is a tuning knob).
+static bool plan_lds_forced() {
+  const char *e = getenv("PFFT_FFT_PLAN");
+  return e && std::string(e) == "lds";
+}
+
+template <typename T>
+static bool reg_plane_ok(int Ny, int Nz) {
+  if (sizeof(T) != 4 || plan_lds_forced()) return false;
+  return (Ny == 64 && Nz == 32) || (Ny == 32 && Nz == 16) || (Ny == 16 && Nz == 8);
+}
+
+static void launch_yz_reg(float2 *data, const float *ghat, const YZArgs &y, long ch, hipStream_t st) {
+  const unsigned nb = (unsigned)(ch * y.two_nx);
+  if (y.ny == 64) k_fft_yz_reg<64, 32><<<nb, 128, 0, st>>>(y, data, ghat, ch);
+  else if (y.ny == 32) k_fft_yz_reg<32, 16><<<nb, 64, 0, st>>>(y, data, ghat, ch);
+  else k_fft_yz_reg<16, 8><<<nb, 32, 0, st>>>(y, data, ghat, ch);
+}
+
+// Register X passes: FP32, N_x in {32, 64, 128, 256}, N_y N_z a multiple of
+// 32, element offsets of the padded grid below 2^32.
+template <typename T>
+static bool reg_x_ok(int Nx, long C, long ch) {
+  if (sizeof(T) != 4 || plan_lds_forced()) return false;
+  if ((double)ch * 2.0 * Nx * (double)C >= 4294967295.0) return false;
+  return (Nx == 256 || Nx == 128 || Nx == 64 || Nx == 32) && C % 32 == 0;
+}
+
+static void launch_x_reg(const float2 *in, float2 *out, int Nx, long C, long ch, int sign, float scale,
+                         hipStream_t st) {
+  const int ncol = (int)(ch * C), Ci = (int)C;
+  const unsigned nb = (unsigned)(ncol / 32);   // C % 32 == 0 (reg_x_ok)
+  if (sign < 0) {
+    if (Nx == 256) k_fft_x_reg<256, -1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+    else if (Nx == 128) k_fft_x_reg<128, -1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+    else if (Nx == 64) k_fft_x_reg<64, -1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+    else k_fft_x_reg<32, -1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+  } else {
+    if (Nx == 256) k_fft_x_reg<256, 1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+    else if (Nx == 128) k_fft_x_reg<128, 1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+    else if (Nx == 64) k_fft_x_reg<64, 1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+    else k_fft_x_reg<32, 1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+  }
+}
+
 template <typename T>
 void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStream_t st, PassHook *hook) {
   const int Nx = g.dims[0], Ny = g.dims[1], Nz = g.dims[2];
   long ch = 3L * R;
+  const bool xreg = reg_x_ok<T>(Nx, (long)Ny * Nz, ch);
   // X forward: [ch][Nx][Ny*Nz] -> [ch][2Nx][Ny*Nz]
   if (hook) hook->pass(0, st);
-  fft_axis<T>(Q, T1, ch, (long)Ny * Nz, Nx, 2 * Nx, 2 * Nx, -1, 1.0f, nullptr, nullptr, st);
+  if (xreg)
+    launch_x_reg((const float2 *)Q, (float2 *)T1, Nx, (long)Ny * Nz, ch, -1, 1.0f, st);
+  else
+    fft_axis<T>(Q, T1, ch, (long)Ny * Nz, Nx, 2 * Nx, 2 * Nx, -1, 1.0f, nullptr, nullptr, st);
   const int vs = (int)sizeof(V2<T>);
   const int pitch = 2 * Nz + 1;
   const size_t yz_lds = (size_t)(2 * Ny + 2 * Nz + 2 * Ny * pitch) * vs;
+  if (reg_plane_ok<T>(Ny, Nz)) {
+    if (hook) hook->pass(1, st);
+    YZArgs y{};
+    y.ny = Ny;
+    y.nz = Nz;
+    y.nx = Nx;
+    y.two_nx = 2 * Nx;
+    y.scale = 1.0f / (4.0f * Ny * Nz);
+    launch_yz_reg((float2 *)T1, (const float *)g.ghat, y, ch, st);
+    if (hook) hook->pass(4, st);
+    if (xreg)
+      launch_x_reg((const float2 *)T1, (float2 *)Q, Nx, (long)Ny * Nz, ch, +1, 1.0f / (2.0f * Nx), st);
+    else
+      fft_axis<T>(T1, Q, ch, (long)Ny * Nz, 2 * Nx, Nx, 2 * Nx, +1, 1.0f / (2.0f * Nx), nullptr, nullptr, st);
+    if (hook) hook->done(st);
+    return;
+  }
   if (4L * Ny * Nz <= 8192 && allow_lds((const void *)k_fft_yz<T>, (int)yz_lds)) {
     // fused Y, Z(+ spectrum), inverse Z, inverse Y on each (channel, kx) plane
     if (hook) hook->pass(1, st);

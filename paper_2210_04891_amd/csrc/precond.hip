@@ -356,6 +356,16 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+typedef decltype(__builtin_amdgcn_raw_buffer_load_b128(__amdgpu_buffer_rsrc_t(), 0, 0, 0)) b128_t;
+
+// Band factor rows are read with buffer loads (per-lane VGPR offset, uniform
+// SGPR row offset): they count only against vmcnt, so waiting on the LDS
+// window never waits on the prefetch of the next rows (flat loads would), and
+// the hardware returns zero beyond the factor's size.
+__device__ __forceinline__ double2 band_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 template <int WP>
 __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx, double2 *work) {
   __shared__ double2 win[WP];
@@ -370,18 +380,26 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
   const double2 *dg = d.diag + (size_t)f * d.nu;
   double2 *x = work + (size_t)r * d.nu;
   const double2 zero = make_double2(0, 0);
+  const unsigned row_bytes = (unsigned)d.nu * (unsigned)W * 16u, col_bytes = (unsigned)d.nu * (unsigned)Wc * 16u;
+  const __amdgpu_buffer_rsrc_t rrow = __builtin_amdgcn_make_buffer_rsrc((void *)rowp, (short)0, (int)row_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rcol = __builtin_amdgcn_make_buffer_rsrc((void *)colp, (short)0, (int)col_bytes, 0x00020000);
+  const unsigned lane16 = (unsigned)lane * 16u;
   double2 cur[PF], nxt[PF];
   // ---- forward, band rows
   if (lo < mid) {
     int loaded_hi = lo;
 #pragma unroll
-    for (int q = 0; q < PF; ++q) cur[q] = (lo + q < mid && lane < Wc) ? colp[(size_t)(lo + q) * Wc + lane] : zero;
+    for (int q = 0; q < PF; ++q) {
+      const double2 v = band_load(rcol, lane16, (unsigned)(lo + q) * (unsigned)Wc * 16u);
+      cur[q] = (lo + q < mid && lane < Wc) ? v : zero;
+    }
     for (int i0 = lo; i0 < mid; i0 += PF) {
       const int nb = min(PF, mid - i0);
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
-        int i = i0 + PF + q;
-        nxt[q] = (i < mid && lane < Wc) ? colp[(size_t)i * Wc + lane] : zero;
+        const int i = i0 + PF + q;
+        const double2 v = band_load(rcol, lane16, (unsigned)i * (unsigned)Wc * 16u);
+        nxt[q] = (i < mid && lane < Wc) ? v : zero;
       }
       const int need = min(mid, i0 + nb + Wc);
       while (loaded_hi < need) {
@@ -457,15 +475,17 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
     int loaded = mid;  // window holds z_j for j in [loaded, mid)
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
-      int i = mid - 1 - q;
-      cur[q] = (i >= lo && lane < W) ? rowp[(size_t)i * W + lane] : zero;
+      const int i = mid - 1 - q;
+      const double2 v = band_load(rrow, lane16, (unsigned)max(i, 0) * (unsigned)W * 16u);
+      cur[q] = (i >= lo && lane < W) ? v : zero;
     }
     for (int i0 = mid - 1; i0 >= lo; i0 -= PF) {
       const int nb = min(PF, i0 - lo + 1);
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
-        int i = i0 - PF - q;
-        nxt[q] = (i >= lo && lane < W) ? rowp[(size_t)i * W + lane] : zero;
+        const int i = i0 - PF - q;
+        const double2 v = band_load(rrow, lane16, (unsigned)max(i, 0) * (unsigned)W * 16u);
+        nxt[q] = (i >= lo && lane < W) ? v : zero;
       }
       const int target = max(lo, i0 - (nb - 1) - W);
       while (loaded > target) {
@@ -546,6 +566,8 @@ void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, doubl
   // still pending
   dim3 g(d.ncomp, R);
   const int span = std::max(d.W, d.Wc) + PF;
+  if ((double)d.nu * std::max(std::max(d.W, d.Wc), 1) * 16.0 >= 2147483647.0)
+    throw SetupError{-1, "preconditioner band larger than 2 GB per frequency"};
   if (span < 128)
     k_ldl_solve<128><<<g, 64, 0, st>>>(d, fidx, work);
   else if (span < 512)
