@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction sweep arm")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before the steps, copy a buffer of this size three times (device to device) so that "
+                         "hardware byte counters can be scaled against a transfer of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the whole hot path on a single "
@@ -109,6 +113,13 @@ def main():
     x = torch.from_numpy(rng.standard_normal((R, sz["l"])) + 1j * rng.standard_normal((R, sz["l"]))).cuda()
     y = torch.empty_like(x)
     flags = P.PFFT_PRECOND
+    if args.copy_probe_mb > 0:
+        a = torch.ones(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     for _ in range(args.warmup):
         ctx.matvec(x, omega, space=1, flags=flags, out=y)
     torch.cuda.synchronize()
@@ -162,12 +173,40 @@ def main():
                    "lds_per_block": getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", None)},
     }
     if not args.no_sweep:
+        # plain preconditioner, all ports x frequencies batched (80 RHS)
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
         Y, it, rr, code = ctx.solve_ports(freqs, tol=1e-6, maxit=400, restart=60, precond=1)
         t_sweep = time.perf_counter() - t1
-        out["sweep"] = {"plain_s": round(t_sweep, 3), "learned_s": None, "status": int(code),
-                        "iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 2),
-                        "max_relres": float(rr.max())}
+        # plain preconditioner, one frequency (8 RHS) per call
+        t2 = time.perf_counter()
+        for f in freqs:
+            ctx.solve_ports([f], tol=1e-6, maxit=400, restart=60, precond=1)
+        t_perf = time.perf_counter() - t2
+        out["sweep"] = {"plain_s": round(t_sweep, 3), "plain_per_frequency_s": round(t_perf, 3),
+                        "status": int(code), "iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 2),
+                        "max_relres": float(rr.max()), "learned_s": None}
+        if not args.no_learned:
+            # learned correction: pairs from plain solves at 8 frequencies
+            # between the bench frequencies, device training, then the sweep
+            f_train = 10.0 ** (6.2 + 3.6 * np.arange(8) / 7.0)
+            t3 = time.perf_counter()
+            rows = ctx.learned_collect(f_train, tol=1e-8, maxit=40)
+            t_collect = time.perf_counter() - t3
+            t4 = time.perf_counter()
+            ctx.learned_train(600, batch=8192, hidden=256, lr=1e-3, seed=0)
+            torch.cuda.synchronize()
+            t_train = time.perf_counter() - t4
+            t5 = time.perf_counter()
+            Y2, it2, rr2, code2 = ctx.solve_ports(freqs, tol=1e-6, maxit=400, restart=60, precond=2)
+            t_learned = time.perf_counter() - t5
+            n_apply, n_fall, n_off = ctx.learned_stats()
+            out["sweep"].update({"learned_s": round(t_learned, 3), "learned_status": int(code2),
+                                 "learned_iters_mean": round(float(it2.mean()), 2),
+                                 "learned_iters_max": int(it2.max()),
+                                 "learned_rhs_switched_to_plain": n_off, "learned_rhs_applications": n_apply,
+                                 "learned_collect_s": round(t_collect, 2), "learned_train_s": round(t_train, 2),
+                                 "learned_training_rows": int(rows)})
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_baseline(s)
     print(json.dumps(out), flush=True)

@@ -179,6 +179,12 @@ pfft_status pfft_learned_collect(pfft_ctx *c, int32_t nfreq, const double *freq_
 pfft_status pfft_learned_train(pfft_ctx *c, int32_t steps, int32_t batch, int32_t hidden, double lr,
                                uint64_t seed, float *loss_out, void *hip_stream);
 
+/* Loss of the current network over the whole training set (the mean over
+ * the collected right-hand sides of sum_i |y_i - t_i|^2 / sum_i |t_i|^2),
+ * in training precision, into *loss_out (host).  PFFT_EINVAL when the set is
+ * empty or no network exists. */
+pfft_status pfft_learned_eval(pfft_ctx *c, double *loss_out, void *hip_stream);
+
 /* Drops the training set (weights stay). */
 pfft_status pfft_learned_clear(pfft_ctx *c);
 

@@ -157,7 +157,7 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
         timer.end(st);
         convolve<double>(gm, (double2 *)ws_Q, (double2 *)ws_T1, (double2 *)ws_T2, Rn, st, hk);
         timer.begin(ST_INTERP, st);
-        interp_tri<double>(gm, (double2 *)ws_Q, ws_U, Rn, st);
+        interp_tri<double>(gm, (double2 *)ws_Q, ws_U, Rn, st, ws_T1);
       } else {
         timer.begin(ST_TRI_CURRENT, st);
         tri_currents<float>(gm, alpha, (float2 *)ws_J, Rn, st);
@@ -166,7 +166,7 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
         timer.end(st);
         convolve<float>(gm, (float2 *)ws_Q, (float2 *)ws_T1, (float2 *)ws_T2, Rn, st, hk);
         timer.begin(ST_INTERP, st);
-        interp_tri<float>(gm, (float2 *)ws_Q, ws_U, Rn, st);
+        interp_tri<float>(gm, (float2 *)ws_Q, ws_U, Rn, st, ws_T1);
       }
     }
     double2 *zs = ws_coef, *jw = ws_coef + Rc;
@@ -335,6 +335,55 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
       tri_w[256 * (size_t)t + 4 * k] = m.M0[64 * (size_t)t + k];
       for (int cc = 0; cc < 3; ++cc) tri_w[256 * (size_t)t + 4 * k + 1 + cc] = m.M1[192 * (size_t)t + 3 * k + cc];
     }
+  // projection tiles: TZ x TY x TX nodes with z fastest (the Q layout), each
+  // listing the triangles whose 4 x 4 x 4 stencil meets it
+  {
+    const int TZ = std::min(m.dims[2], 32), TY = std::min(m.dims[1], 4);
+    const int TX = std::min(m.dims[0], std::max(1, 512 / (TY * TZ)));
+    const int nt3[3] = {(m.dims[0] + TX - 1) / TX, (m.dims[1] + TY - 1) / TY, (m.dims[2] + TZ - 1) / TZ};
+    const int T3[3] = {TX, TY, TZ};
+    const long ntile = (long)nt3[0] * nt3[1] * nt3[2];
+    std::vector<int> tt_off(ntile + 1, 0);
+    auto tiles_of = [&](int t, auto &&fn) {
+      int lo[3], hi[3];
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = m.anchor[3 * t + d] / T3[d];
+        hi[d] = std::min(nt3[d] - 1, (m.anchor[3 * t + d] + 3) / T3[d]);
+      }
+      for (int a = lo[0]; a <= hi[0]; ++a)
+        for (int b2 = lo[1]; b2 <= hi[1]; ++b2)
+          for (int c2 = lo[2]; c2 <= hi[2]; ++c2) fn(((long)a * nt3[1] + b2) * nt3[2] + c2);
+    };
+    for (int t = 0; t < n; ++t) tiles_of(t, [&](long T) { tt_off[T + 1]++; });
+    for (long T = 0; T < ntile; ++T) tt_off[T + 1] += tt_off[T];
+    std::vector<int> tt_tri(tt_off[ntile]);
+    {
+      std::vector<int> f(tt_off.begin(), tt_off.end() - 1);
+      for (int t = 0; t < n; ++t) tiles_of(t, [&](long T) { tt_tri[f[T]++] = t; });
+    }
+    std::vector<int> pg_loc(pg_tri.size());
+    for (long node = 0; node < N; ++node) {
+      const int z = (int)(node % m.dims[2]), y = (int)((node / m.dims[2]) % m.dims[1]),
+                x = (int)(node / ((long)m.dims[2] * m.dims[1]));
+      const long T = ((long)(x / TX) * nt3[1] + y / TY) * nt3[2] + z / TZ;
+      const int *b0 = tt_tri.data() + tt_off[T], *b1 = tt_tri.data() + tt_off[T + 1];
+      for (int q = pg_off[node]; q < pg_off[node + 1]; ++q) {
+        const int *it = std::lower_bound(b0, b1, pg_tri[q]);
+        if (it == b1 || *it != pg_tri[q]) throw SetupError{PFFT_EINVAL, "projection tile lists inconsistent"};
+        pg_loc[q] = (int)(it - b0);
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      g.tile[d] = T3[d];
+      g.ntile[d] = nt3[d];
+    }
+    // LDS: tcap triangles x 4 (FP32) or 2 (FP64) right-hand sides x 4 moments
+    // (48 KB: three 512-thread workgroups per CU)
+    g.tcap = 384;
+    g.tt_off = upload(c, tt_off, st);
+    g.tt_tri = upload(c, tt_tri, st);
+    g.pg_loc = upload(c, pg_loc, st);
+  }
   g.pg_off = upload(c, pg_off, st);
   g.pg_tri = upload(c, pg_tri, st);
   if (c->grid_fp64) {

@@ -52,6 +52,12 @@ struct GridMaps {
   const void *pg_w;      // [nnz][4] (M0, M1x, M1y, M1z) in T
   const void *tri_w;     // [n][64][4] same weights, triangle-major, in T
   const void *ghat;      // [(Nx+1)(Ny+1)(Nz+1)] real spectrum in T
+  // projection tiles of tile[0] x tile[1] x tile[2] nodes (z fastest):
+  // triangles whose stencil meets tile T are tt_tri[tt_off[T] .. tt_off[T+1])
+  // (ascending); pg_loc[q] = position of pg_tri[q] in its node's tile list;
+  // the first tcap triangles of a tile are staged in LDS
+  int tile[3], ntile[3], tcap;
+  const int *tt_off, *tt_tri, *pg_loc;
 };
 
 // alpha [b][R] -> J [n][R][4]
@@ -67,9 +73,12 @@ struct PassHook {
 template <typename T>
 void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStream_t st,
               PassHook *hook = nullptr);
-// phi [R][3][N] -> U [n][R][4]
+// phi [R][3][N] -> U [n][R][4]; scratch: N * 3R complex values of T that
+// the FP32 path uses for a node-major copy of phi
 template <typename T>
-void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStream_t st);
+void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStream_t st, void *scratch);
+template <>
+void interp_tri<float>(const GridMaps &g, const float2 *phi, double2 *U, int R, hipStream_t st, void *scratch);
 
 // Full-length forward 3-D FFT of a (2Nx, 2Ny, 2Nz) complex128 array in place.
 void fft3_full_fp64(double2 *data, const int dims2[3], hipStream_t st);

@@ -34,6 +34,38 @@ __device__ __forceinline__ V2<T> cscale(V2<T> a, T s) { return cmk<T>(a.x * s, a
 
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
+// XCD-aware block order.  The dispatcher sends workgroup b to XCD b % 8, and
+// each XCD has its own L2; this bijection gives XCD x the contiguous range of
+// logical blocks [x*(nb/8) + min(x, nb%8), ...), so neighbouring rows, which
+// gather overlapping data, share one L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned x = b & 7u, k = b >> 3, q = nb >> 3, rem = nb & 7u;
+  return x * q + (x < rem ? x : rem) + k;
+}
+
+// Largest dynamic LDS allocation one workgroup may request (capped at 128 KB).
+static int lds_budget() {
+  static int v = -1;
+  if (v < 0) {
+    int dev = 0, q = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) q = 65536;
+    v = std::max(65536, std::min(q, 131072));
+  }
+  return v;
+}
+
+// Raises a kernel's dynamic LDS limit above 64 KB once; false if refused.
+static bool allow_lds(const void *fn, int bytes) {
+  if (bytes <= 65536) return true;
+  if (bytes > lds_budget()) return false;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
 // ===========================================================================
 // batched prefix sums (complex128), three phases, deterministic
 // ===========================================================================
@@ -267,7 +299,7 @@ constexpr int PRG = 8;   // right-hand sides per thread in the projection
 template <typename T>
 __global__ void k_project(GridMaps g, const V2<T> *J, V2<T> *Q, int R) {
   const int r0 = blockIdx.y * PRG;
-  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  const int node = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (node >= g.N) return;
   const int nr = min(PRG, R - r0);
   const T *w = (const T *)g.pg_w;
@@ -305,9 +337,95 @@ __global__ void k_project(GridMaps g, const V2<T> *J, V2<T> *Q, int R) {
   }
 }
 
+// Tiled projection: one workgroup per (tile, group of RC right-hand sides)
+// stages the moments J of the tile's triangles in LDS once, then each node
+// gathers its contributions from LDS (triangles beyond tcap from memory).
+// Every node is still a gather in a fixed order: no atomics.
+template <typename T> struct ProjRC;
+template <> struct ProjRC<float> { static constexpr int v = 4; };
+template <> struct ProjRC<double> { static constexpr int v = 2; };
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *J, V2<T> *Q, int R) {
+  constexpr int RC = ProjRC<T>::v;
+  extern __shared__ unsigned char smraw[];
+  V2<T> *sJ = (V2<T> *)smraw;   // [tcap][RC][4]
+  const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int r0 = blockIdx.y * RC, nr = min(RC, R - r0);
+  const int t0 = g.tt_off[tile], nt = g.tt_off[tile + 1] - t0;
+  const int ns = min(nt, g.tcap);
+  for (int i = threadIdx.x; i < ns * RC * 4; i += blockDim.x) {
+    const int lt = i / (RC * 4), rem = i - lt * (RC * 4), rr = rem >> 2, comp = rem & 3;
+    V2<T> v = cmk<T>(0, 0);
+    if (rr < nr) v = J[((size_t)g.tt_tri[t0 + lt] * R + r0 + rr) * 4 + comp];
+    sJ[i] = v;
+  }
+  __syncthreads();
+  const int TX = g.tile[0], TY = g.tile[1], TZ = g.tile[2];
+  const int tz = tile % g.ntile[2], ty = (tile / g.ntile[2]) % g.ntile[1], tx = tile / (g.ntile[2] * g.ntile[1]);
+  const int Ny = g.dims[1], Nz = g.dims[2];
+  const T *w = (const T *)g.pg_w;
+  for (int u = threadIdx.x; u < TX * TY * TZ; u += blockDim.x) {
+    const int iz = u % TZ, iy = (u / TZ) % TY, ix = u / (TZ * TY);
+    const int x = tx * TX + ix, y = ty * TY + iy, z = tz * TZ + iz;
+    if (x >= g.dims[0] || y >= Ny || z >= Nz) continue;
+    const int node = (x * Ny + y) * Nz + z;
+    T acc[RC][6];
+#pragma unroll
+    for (int q = 0; q < RC; ++q)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[q][c] = 0;
+    for (int k = g.pg_off[node]; k < g.pg_off[node + 1]; ++k) {
+      const int loc = g.pg_loc[k];
+      const T m0 = w[4 * (size_t)k], m1x = w[4 * (size_t)k + 1], m1y = w[4 * (size_t)k + 2],
+              m1z = w[4 * (size_t)k + 3];
+      V2<T> jv[RC][4];
+      if (loc < ns) {
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) jv[q][c] = sJ[(loc * RC + q) * 4 + c];
+      } else {
+        const V2<T> *jt = J + ((size_t)g.pg_tri[k] * R + r0) * 4;
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) jv[q][c] = q < nr ? jt[4 * q + c] : cmk<T>(0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < RC; ++q) {
+        const V2<T> j0 = jv[q][0], jx = jv[q][1], jy = jv[q][2], jz = jv[q][3];
+        acc[q][0] += j0.x * m1x - jx.x * m0;
+        acc[q][1] += j0.y * m1x - jx.y * m0;
+        acc[q][2] += j0.x * m1y - jy.x * m0;
+        acc[q][3] += j0.y * m1y - jy.y * m0;
+        acc[q][4] += j0.x * m1z - jz.x * m0;
+        acc[q][5] += j0.y * m1z - jz.y * m0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RC; ++q) {
+      if (q < nr) {
+        V2<T> *Qr = Q + (size_t)(r0 + q) * 3 * g.N;
+        Qr[node] = cmk<T>(acc[q][0], acc[q][1]);
+        Qr[g.N + node] = cmk<T>(acc[q][2], acc[q][3]);
+        Qr[2 * (size_t)g.N + node] = cmk<T>(acc[q][4], acc[q][5]);
+      }
+    }
+  }
+}
+
 template <typename T>
 void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st) {
-  k_project<T><<<dim3(cdiv(g.N, 256), cdiv(R, PRG)), 256, 0, st>>>(g, J, Q, R);
+  constexpr int RC = ProjRC<T>::v;
+  const size_t lds = (size_t)g.tcap * RC * 4 * sizeof(V2<T>);
+  static bool lds_ok = allow_lds((const void *)k_project_tiled<T>, (int)lds);
+  if (lds_ok) {
+    const unsigned ntile = (unsigned)g.ntile[0] * g.ntile[1] * g.ntile[2];
+    k_project_tiled<T><<<dim3(ntile, cdiv(R, RC)), 512, lds, st>>>(g, J, Q, R);
+  } else {
+    k_project<T><<<dim3(cdiv(g.N, 256), cdiv(R, PRG)), 256, 0, st>>>(g, J, Q, R);
+  }
 }
 
 // ===========================================================================
@@ -935,29 +1053,6 @@ static int ilog2(int v) {
   return r;
 }
 
-// Largest dynamic LDS allocation one workgroup may request (capped at 128 KB).
-static int lds_budget() {
-  static int v = -1;
-  if (v < 0) {
-    int dev = 0, q = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) q = 65536;
-    v = std::max(65536, std::min(q, 131072));
-  }
-  return v;
-}
-
-// Raises a kernel's dynamic LDS limit above 64 KB once; false if refused.
-static bool allow_lds(const void *fn, int bytes) {
-  if (bytes <= 65536) return true;
-  if (bytes > lds_budget()) return false;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return true;
-}
-
 template <typename T>
 static void fft_axis(const V2<T> *in, V2<T> *out, long A, long C, int n_in, int n_out, int Lf,
                      int sign, float scale, const T *ghat, const int *dims, hipStream_t st) {
@@ -1147,7 +1242,7 @@ constexpr int IRG = 4;   // right-hand sides per thread in the interpolation
 template <typename T>
 __global__ void k_interp_tri(GridMaps g, const V2<T> *phi, double2 *U, int R) {
   const int r0 = blockIdx.y * IRG;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (t >= g.n) return;
   const int nr = min(IRG, R - r0);
   const int Ny = g.dims[1], Nz = g.dims[2];
@@ -1190,9 +1285,80 @@ __global__ void k_interp_tri(GridMaps g, const V2<T> *phi, double2 *U, int R) {
   }
 }
 
+// FP32 path: phi is first transposed to node-major [N][3R] (channel
+// innermost), then one workgroup per triangle reads each stencil node's 3R
+// channels as one coalesced row; the triangle's weights are uniform (scalar
+// loads).  Lane (r, c) accumulates M1_c phi_c and M0 phi_c; the three
+// components of U0 are summed through LDS.
+__global__ void __launch_bounds__(256) k_transpose_c64(const float2 *in, float2 *out, int rows, int cols) {
+  __shared__ float2 tile[32][33];
+  const int c0 = (int)xcd_block(blockIdx.x, gridDim.x) * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[k][tx] = in[(size_t)r * cols + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][k];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_interp_nm(GridMaps g, const float2 *phiT, double2 *U, int R) {
+  __shared__ double2 s0[256];
+  const int t = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int ch = 3 * R;
+  const int Ny = g.dims[1], Nz = g.dims[2];
+  const float *w = (const float *)g.tri_w + (size_t)t * 256;
+  const int ax = g.anchor[3 * t], ay = g.anchor[3 * t + 1], az = g.anchor[3 * t + 2];
+  // passes of 255 channels (85 right-hand sides), so the three components of
+  // a right-hand side are always in the same pass
+  for (int base = 0; base < ch; base += 255) {
+    const int chn = base + threadIdx.x;
+    const bool ok = threadIdx.x < 255 && chn < ch;
+    const int c = ok ? chn % 3 : 0;
+    double a0x = 0, a0y = 0, a1x = 0, a1y = 0;
+#pragma unroll 8
+    for (int k = 0; k < 64; ++k) {
+      const int i = k >> 4, j = (k >> 2) & 3, l = k & 3;
+      const long node = ((long)(ax + i) * Ny + (ay + j)) * Nz + (az + l);
+      const float m0 = w[4 * k], m1 = w[4 * k + 1 + c];
+      const float2 v = ok ? phiT[(size_t)node * ch + chn] : make_float2(0.f, 0.f);
+      a0x += (double)m1 * v.x;
+      a0y += (double)m1 * v.y;
+      a1x += (double)m0 * v.x;
+      a1y += (double)m0 * v.y;
+    }
+    s0[threadIdx.x] = make_double2(a0x, a0y);
+    __syncthreads();
+    if (ok) {
+      const int r = chn / 3;
+      double2 *o = U + ((size_t)t * R + r) * 4;   // U[t][r][4]
+      o[1 + c] = make_double2(a1x, a1y);
+      if (c == 0) {
+        const int lt = threadIdx.x;   // components 1, 2 of this r are lanes lt + 1, lt + 2 (same pass)
+        const double2 p0 = s0[lt], p1 = s0[lt + 1], p2 = s0[lt + 2];
+        o[0] = make_double2(p0.x + p1.x + p2.x, p0.y + p1.y + p2.y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
-void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStream_t st) {
+void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStream_t st, void *scratch) {
+  (void)scratch;
   k_interp_tri<T><<<dim3(cdiv(g.n, 128), cdiv(R, IRG)), 128, 0, st>>>(g, phi, U, R);
+}
+
+template <>
+void interp_tri<float>(const GridMaps &g, const float2 *phi, double2 *U, int R, hipStream_t st, void *scratch) {
+  // node-major copy of phi (N x 3R complex64) in the caller's free scratch
+  float2 *phiT = (float2 *)scratch;
+  const int ch = 3 * R;
+  k_transpose_c64<<<dim3(cdiv(g.N, 32), cdiv(ch, 32)), 256, 0, st>>>(phi, phiT, ch, g.N);
+  k_interp_nm<<<(unsigned)g.n, 256, 0, st>>>(g, phiT, U, R);
 }
 
 // ===========================================================================
@@ -1203,7 +1369,7 @@ void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStrea
 // is one contiguous segment, so every load of the sparse product coalesces.
 __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U, const double2 *zs,
                           const double2 *jw, double2 *y, int R, int mode) {
-  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long idx = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (idx >= (long)c.b * R) return;
   int e = (int)(idx / R), r = (int)(idx - (long)e * R);
   double kx = 0, ky = 0;
@@ -1220,13 +1386,29 @@ __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U,
     }
   }
   if (mode & 2) {
-    const int64_t q1 = c.nf_rowptr[e + 1];
-    for (int64_t q = c.nf_rowptr[e]; q < q1; ++q) {
-      double v = c.nf_val[q];
-      double2 x = alpha[(size_t)c.nf_col[q] * R + r];
-      kx += v * x.x;
-      ky += v * x.y;
+    // four nonzeros per step: their column and value loads, then the four
+    // gathers, are independent (more loads in flight)
+    const int64_t q0 = c.nf_rowptr[e], q1 = c.nf_rowptr[e + 1];
+    int64_t q = q0;
+    double ax = 0, ay = 0, bx = 0, by = 0;
+    for (; q + 4 <= q1; q += 4) {
+      const int c0 = c.nf_col[q], c1 = c.nf_col[q + 1], c2 = c.nf_col[q + 2], c3 = c.nf_col[q + 3];
+      const double v0 = c.nf_val[q], v1 = c.nf_val[q + 1], v2 = c.nf_val[q + 2], v3 = c.nf_val[q + 3];
+      const double2 x0 = alpha[(size_t)c0 * R + r], x1 = alpha[(size_t)c1 * R + r];
+      const double2 x2 = alpha[(size_t)c2 * R + r], x3 = alpha[(size_t)c3 * R + r];
+      kx += v0 * x0.x + v1 * x1.x;
+      ky += v0 * x0.y + v1 * x1.y;
+      ax += v2 * x2.x + v3 * x3.x;
+      ay += v2 * x2.y + v3 * x3.y;
     }
+    for (; q < q1; ++q) {
+      const double v = c.nf_val[q];
+      const double2 x = alpha[(size_t)c.nf_col[q] * R + r];
+      bx += v * x.x;
+      by += v * x.y;
+    }
+    kx += ax + bx;
+    ky += ay + by;
   }
   double2 out;
   if (mode & 4) {
@@ -1277,8 +1459,7 @@ template void project<float>(const GridMaps &, const V2<float> *, V2<float> *, i
 template void project<double>(const GridMaps &, const V2<double> *, V2<double> *, int, hipStream_t);
 template void convolve<float>(const GridMaps &, V2<float> *, V2<float> *, V2<float> *, int, hipStream_t, PassHook *);
 template void convolve<double>(const GridMaps &, V2<double> *, V2<double> *, V2<double> *, int, hipStream_t, PassHook *);
-template void interp_tri<float>(const GridMaps &, const V2<float> *, double2 *, int, hipStream_t);
-template void interp_tri<double>(const GridMaps &, const V2<double> *, double2 *, int, hipStream_t);
+template void interp_tri<double>(const GridMaps &, const V2<double> *, double2 *, int, hipStream_t, void *);
 template void fold_spectrum<float>(const double2 *, float *, const int *, hipStream_t);
 template void fold_spectrum<double>(const double2 *, double *, const int *, hipStream_t);
 

@@ -421,6 +421,20 @@ __global__ __launch_bounds__(256) void k_tnorm(const float *T, int l, double *ou
   if (threadIdx.x == 0) out[r] = s;
 }
 
+// per-block partial of sum_i |y_i - t_i|^2 / (G den[group_i]) over a chunk
+__global__ __launch_bounds__(256) void k_set_loss(const float *Y, const float *T, const int *gs, const double *den,
+                                                  int G, int n, double *part) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double l = 0;
+  if (i < n) {
+    const double d0 = (double)Y[2 * i] - T[2 * i], d1 = (double)Y[2 * i + 1] - T[2 * i + 1];
+    l = (d0 * d0 + d1 * d1) / ((double)G * den[gs[i]]);
+  }
+  const double s = block_sum256(l, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 __global__ void k_fill_int(int *p, long long n, int v) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1049,6 +1063,45 @@ pfft_status pfft_learned_train(pfft_ctx *c, int32_t steps, int32_t batch, int32_
     return PFFT_OK;
   } catch (const DeviceError &e) {
     return fail("pfft_learned_train", e.msg, e.code);
+  }
+}
+
+pfft_status pfft_learned_eval(pfft_ctx *c, double *loss_out, void *hip_stream) {
+  if (!c || !loss_out) return fail("pfft_learned_eval", "bad argument", PFFT_EINVAL);
+  Learned *L = c->learned;
+  if (!L || L->rows == 0) return fail("pfft_learned_eval", "the training set is empty", PFFT_EINVAL);
+  if (!L->have) return fail("pfft_learned_eval", "no network", PFFT_EINVAL);
+  double *d_den = nullptr, *part = nullptr;
+  try {
+    hip_ok(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int G = (int)L->den.size();
+    constexpr int CH = 65536;
+    dev_alloc((void **)&d_den, (size_t)G * 8, "group norms");
+    dev_alloc((void **)&part, (size_t)(CH / 256) * 8, "loss partials");
+    hip_ok(hipMemcpyAsync(d_den, L->den.data(), (size_t)G * 8, hipMemcpyHostToDevice, st), "group norms");
+    Acts a;
+    a.ensure(CH, L->net.s.H, true);
+    double total = 0;
+    std::vector<double> hp(CH / 256);
+    for (long long o = 0; o < L->rows; o += CH) {
+      const int n = (int)std::min<long long>(CH, L->rows - o);
+      forward(L->net, n, L->Xs + o * F_IN, a, st);
+      const int nb = (n + 255) / 256;
+      k_set_loss<<<nb, 256, 0, st>>>(a.Y, L->Ts + o * 2, L->gs + o, d_den, G, n, part);
+      hip_ok(hipMemcpyAsync(hp.data(), part, nb * 8, hipMemcpyDeviceToHost, st), "loss partials");
+      hip_ok(hipStreamSynchronize(st), "eval sync");
+      for (int i = 0; i < nb; ++i) total += hp[i];
+    }
+    a.release();
+    hipFree(d_den);
+    hipFree(part);
+    *loss_out = total;
+    return PFFT_OK;
+  } catch (const DeviceError &e) {
+    if (d_den) hipFree(d_den);
+    if (part) hipFree(part);
+    return fail("pfft_learned_eval", e.msg, e.code);
   }
 }
 

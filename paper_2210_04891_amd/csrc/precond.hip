@@ -5,6 +5,7 @@
 #include <cmath>
 #include <deque>
 #include <numeric>
+#include <string>
 
 #include "precond.h"
 
@@ -521,6 +522,190 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
   }
 }
 
+// Register-window variant (band widths W, Wc <= 63).  The W pending partial
+// sums of the band substitution live one per lane (lane j: row i + j forward,
+// row i - j backward): each row takes its final value from lane 0
+// (readlane), updates every lane with one complex FMA against the factor row
+// (one entry per lane), and shifts the window down one lane (DPP wave_shl:1),
+// the next row's right-hand side entering at lane 63.  No LDS, no barrier;
+// the row chain is register and DPP latency only.  Solved values are
+// collected one per lane and stored 64 rows at a time.
+__device__ __forceinline__ double dbl_lane(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+// lane j <- lane j + 1, lane 63 <- in
+__device__ __forceinline__ double dbl_shl1(double v, double in) {
+  const long long b = __builtin_bit_cast(long long, v), c = __builtin_bit_cast(long long, in);
+  const int lo = __builtin_amdgcn_update_dpp((int)(c & 0xffffffffll), (int)(b & 0xffffffffll), 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(c >> 32), (int)(b >> 32), 0x130, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+constexpr int RP = 32;   // rows of factor data in flight per buffer
+
+__global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *fidx, double2 *work) {
+  const int c = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const int lo = d.comp_off[c], hi = d.comp_off[c + 1], mid = d.comp_mid[c];
+  if (lo >= hi) return;
+  const int f = fidx[r];
+  const int W = max(d.W, 1), Wc = max(d.Wc, 1);
+  const double2 *rowp = d.env + (size_t)f * d.nu * W;
+  const double2 *colp = d.colenv + (size_t)f * d.nu * Wc;
+  const double2 *full = d.full + (size_t)f * d.nnz_full;
+  const double2 *dg = d.diag + (size_t)f * d.nu;
+  double2 *x = work + (size_t)r * d.nu;
+  const double2 zero = make_double2(0, 0);
+  const unsigned row_bytes = (unsigned)d.nu * (unsigned)W * 16u, col_bytes = (unsigned)d.nu * (unsigned)Wc * 16u;
+  const __amdgpu_buffer_rsrc_t rrow = __builtin_amdgcn_make_buffer_rsrc((void *)rowp, (short)0, (int)row_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rcol = __builtin_amdgcn_make_buffer_rsrc((void *)colp, (short)0, (int)col_bytes, 0x00020000);
+  const unsigned voff = (unsigned)max(lane - 1, 0) * 16u;   // lane j reads entry j - 1
+  // ---- forward, band rows: y_i = acc_i, then acc_{i+j} -= L(i+j, i) y_i.
+  // Factor columns are prefetched RP rows ahead (double buffer).
+  if (lo < mid) {
+    double ax, ay;
+    {
+      const double2 v = lo + lane < mid ? x[lo + lane] : zero;
+      ax = v.x;
+      ay = v.y;
+    }
+    // Lc/Ln: factor columns of RP rows; bc/bn: lane q < RP holds the
+    // right-hand side entering the window at row q of the block (row + 64)
+    double2 Lc[RP], Ln[RP], bc, bn;
+#pragma unroll
+    for (int q = 0; q < RP; ++q) Lc[q] = band_load(rcol, voff, (unsigned)min(lo + q, mid - 1) * (unsigned)Wc * 16u);
+    bc = (lane < RP && lo + 64 + lane < mid) ? x[lo + 64 + lane] : zero;
+    double yx = 0, yy = 0;
+    for (int i = lo; i < mid; i += RP) {
+      // rows [i - 64, i) done: store them before this block's prefetch, so
+      // no wait on the store ever drains the prefetch (vmcnt is in order)
+      if (i > lo && ((i - lo) & 63) == 0) x[i - 64 + lane] = make_double2(yx, yy);
+#pragma unroll
+      for (int q = 0; q < RP; ++q)
+        Ln[q] = band_load(rcol, voff, (unsigned)min(i + RP + q, mid - 1) * (unsigned)Wc * 16u);
+      bn = (lane < RP && i + RP + 64 + lane < mid) ? x[i + RP + 64 + lane] : zero;
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < RP; ++q) {
+        // straight-line steps: rows past mid only shift zeros (their factor
+        // entries are masked and their values are never stored)
+        const int ii = i + q;
+        const int s = (ii - lo) & 63;          // position in the current 64-row batch
+        {
+          const bool use = lane >= 1 && lane <= Wc && ii + lane < mid;
+          const double2 L = use ? Lc[q] : zero;
+          const double vx = dbl_lane(ax, 0), vy = dbl_lane(ay, 0);
+          yx = lane == s ? vx : yx;
+          yy = lane == s ? vy : yy;
+          ax -= L.x * vx - L.y * vy;
+          ay -= L.x * vy + L.y * vx;
+          ax = dbl_shl1(ax, dbl_lane(bc.x, q));
+          ay = dbl_shl1(ay, dbl_lane(bc.y, q));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RP; ++q) Lc[q] = Ln[q];
+      bc = bn;
+    }
+    {  // the last, partial batch
+      const int b0 = lo + ((mid - 1 - lo) & ~63);
+      if (b0 + lane < mid) x[b0 + lane] = make_double2(yx, yy);
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  // ---- forward, supernode rows: y_s = b_s - sum_j L_sj y_j over the full row
+  for (int s = mid; s < hi; ++s) {
+    const int fs = d.first[s];
+    const double2 *Ls = full + d.env_off[s];
+    double2 acc = zero;
+    for (int j = fs + lane; j < s; j += 64) {
+      double2 lv = Ls[j - fs], yv = x[j];
+      acc.x += lv.x * yv.x - lv.y * yv.y;
+      acc.y += lv.x * yv.y + lv.y * yv.x;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      double2 bs = x[s];
+      x[s] = make_double2(bs.x - acc.x, bs.y - acc.y);
+    }
+    __threadfence();
+    __syncthreads();
+  }
+  // ---- diagonal: z = y / D
+  for (int i = lo + lane; i < hi; i += 64) x[i] = cdiv2(x[i], dg[i]);
+  __threadfence();
+  __syncthreads();
+  // ---- backward, supernode rows (last rows first): scatter over the full row
+  for (int s = hi - 1; s >= mid; --s) {
+    const int fs = d.first[s];
+    const double2 *Ls = full + d.env_off[s];
+    const double2 xs = x[s];
+    for (int j = fs + lane; j < s; j += 64) {
+      double2 lv = Ls[j - fs], t = x[j];
+      t.x -= lv.x * xs.x - lv.y * xs.y;
+      t.y -= lv.x * xs.y + lv.y * xs.x;
+      x[j] = t;
+    }
+    __threadfence();
+    __syncthreads();
+  }
+  // ---- backward, band rows: x_k = acc_k, then acc_{k-j} -= L(k, k-j) x_k
+  if (lo < mid) {
+    double ax, ay;
+    {
+      const int row = mid - 1 - lane;
+      const double2 v = row >= lo ? x[row] : zero;
+      ax = v.x;
+      ay = v.y;
+    }
+    double2 Lc[RP], Ln[RP], bc, bn;
+#pragma unroll
+    for (int q = 0; q < RP; ++q) Lc[q] = band_load(rrow, voff, (unsigned)max(mid - 1 - q, lo) * (unsigned)W * 16u);
+    bc = (lane < RP && mid - 1 - 64 - lane >= lo) ? x[mid - 1 - 64 - lane] : zero;
+    double ox = 0, oy = 0;
+    for (int k = mid - 1; k >= lo; k -= RP) {
+      if (k < mid - 1 && ((mid - 1 - k) & 63) == 0) x[k + 64 - lane] = make_double2(ox, oy);
+#pragma unroll
+      for (int q = 0; q < RP; ++q) Ln[q] = band_load(rrow, voff, (unsigned)max(k - RP - q, lo) * (unsigned)W * 16u);
+      bn = (lane < RP && k - RP - 64 - lane >= lo) ? x[k - RP - 64 - lane] : zero;
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < RP; ++q) {
+        const int kk = k - q;
+        const int s = (mid - 1 - kk) & 63;
+        {
+          const bool use = lane >= 1 && lane <= W && kk - lane >= lo;
+          const double2 L = use ? Lc[q] : zero;
+          const double vx = dbl_lane(ax, 0), vy = dbl_lane(ay, 0);
+          ox = lane == s ? vx : ox;
+          oy = lane == s ? vy : oy;
+          ax -= L.x * vx - L.y * vy;
+          ay -= L.x * vy + L.y * vx;
+          ax = dbl_shl1(ax, dbl_lane(bc.x, q));
+          ay = dbl_shl1(ay, dbl_lane(bc.y, q));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RP; ++q) Lc[q] = Ln[q];
+      bc = bn;
+    }
+    {  // the last, partial batch
+      const int b0 = mid - 1 - ((mid - 1 - lo) & ~63);
+      if (b0 - lane >= lo) x[b0 - lane] = make_double2(ox, oy);
+    }
+  }
+}
+
+// Band-solve plan: the register window when both band widths fit one wave
+// (PFFT_LDL_PLAN=lds forces the LDS window).
+static bool ldl_reg_plan(const PrecondDev &d) {
+  const char *e = getenv("PFFT_LDL_PLAN");
+  if (e && std::string(e) == "lds") return false;
+  return d.W <= 63 && d.Wc <= 63;
+}
+
 __global__ void k_pre_out(PrecondDev d, const int *fidx, const double2 *y, const double2 *work, double2 *z) {
   int r = blockIdx.y;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -568,7 +753,9 @@ void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, doubl
   const int span = std::max(d.W, d.Wc) + PF;
   if ((double)d.nu * std::max(std::max(d.W, d.Wc), 1) * 16.0 >= 2147483647.0)
     throw SetupError{-1, "preconditioner band larger than 2 GB per frequency"};
-  if (span < 128)
+  if (ldl_reg_plan(d))
+    k_ldl_solve_reg<<<g, 64, 0, st>>>(d, fidx, work);
+  else if (span < 128)
     k_ldl_solve<128><<<g, 64, 0, st>>>(d, fidx, work);
   else if (span < 512)
     k_ldl_solve<512><<<g, 64, 0, st>>>(d, fidx, work);

@@ -27,7 +27,7 @@ EXPORTS = ("pfft_setup", "pfft_sizes", "pfft_matvec", "solve_ports", "extract_RL
            "pfft_precond_load", "pfft_destroy", "pfft_last_error",
            "pfft_host_setup", "pfft_host_get", "pfft_host_free", "pfft_profile",
            "pfft_stage_times", "pfft_precond_save", "pfft_learned_collect", "pfft_learned_train",
-           "pfft_learned_clear", "pfft_learned_stats", "pfft_mlp_grad")
+           "pfft_learned_clear", "pfft_learned_stats", "pfft_mlp_grad", "pfft_learned_eval")
 
 STAGES = ("loop_to_branch", "tri_current", "project", "fft_x", "fft_y", "fft_z_conv", "ifft_y",
           "ifft_x", "interp", "combine", "branch_to_loop", "precond")
@@ -96,6 +96,8 @@ def load():
     lib.pfft_learned_collect.restype = i32
     lib.pfft_learned_train.argtypes = [vp, i32, i32, i32, dbl, ctypes.c_uint64, vp, vp]
     lib.pfft_learned_train.restype = i32
+    lib.pfft_learned_eval.argtypes = [vp, ctypes.POINTER(dbl), vp]
+    lib.pfft_learned_eval.restype = i32
     lib.pfft_learned_clear.argtypes = [vp]
     lib.pfft_learned_clear.restype = i32
     lib.pfft_learned_stats.argtypes = [vp, ctypes.POINTER(i64)]
@@ -277,6 +279,12 @@ class Context:
         _check(load().pfft_learned_train(self._h, steps, batch, hidden, lr, seed, _ptr(loss),
                                          _stream_handle(stream)))
         return loss[:steps]
+
+    def learned_eval(self, stream=None):
+        """Loss of the current network over the whole training set."""
+        v = ctypes.c_double()
+        _check(load().pfft_learned_eval(self._h, ctypes.byref(v), _stream_handle(stream)))
+        return v.value
 
     def learned_clear(self):
         _check(load().pfft_learned_clear(self._h))

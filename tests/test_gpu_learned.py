@@ -226,9 +226,13 @@ def test_train_on_solver_pairs_and_gain():
     f_eval = 10.0 ** np.array([7.5, 8.4, 9.3, 9.9])
     rows = ctx.learned_collect(f_train, tol=1e-9, maxit=80)
     assert rows > 0 and rows % ctx.sizes["l"] == 0
-    loss = ctx.learned_train(600, batch=4096, hidden=256, lr=1e-3, seed=0)
+    loss = ctx.learned_train(1, batch=4096, hidden=256, lr=1e-6, seed=0)
+    before = ctx.learned_eval()
+    loss = np.concatenate([loss, ctx.learned_train(600, batch=4096, hidden=256, lr=1e-3, seed=0)])
+    after = ctx.learned_eval()
     assert np.all(np.isfinite(loss))
-    assert loss[-50:].mean() < loss[:10].mean()
+    # the whole-set loss falls (the minibatch losses are too noisy to compare)
+    assert after < before
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Y1, it1, rr1, c1 = ctx.solve_ports(f_eval, tol=1e-6, maxit=300, restart=60, precond=1)
@@ -239,8 +243,8 @@ def test_train_on_solver_pairs_and_gain():
     n_apply, n_fall, n_off = ctx.learned_stats()
     assert n_apply > 0 and n_fall == 0
     assert np.abs(Y2 - Y1).max() <= 1e-4 * np.abs(Y1).max()
-    print("\nlearned-correction gain (%d training rows): loss %.3f -> %.3f; iterations plain %s learned %s "
+    print("\nlearned-correction gain (%d training rows): set loss %.4f -> %.4f; iterations plain %s learned %s "
           "(judge switched %d of %d RHS back); time plain %.3f s learned %.3f s"
-          % (rows, loss[:10].mean(), loss[-50:].mean(), it1.ravel().tolist(), it2.ravel().tolist(), n_off,
+          % (rows, before, after, it1.ravel().tolist(), it2.ravel().tolist(), n_off,
              it1.size, t1 - t0, t2 - t1))
     assert np.all(it2 <= it1 + 6)
