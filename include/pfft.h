@@ -206,6 +206,31 @@ pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const 
                           const float *T_dev, const float *w_dev, float *Y_dev, float *grad_dev,
                           double *loss_out, void *hip_stream);
 
+/* ---- Plans, graphs and the autotuner (batched execution of Sec. IV) ----
+ * Options of a context (all 0 or 1; the results of every plan are the same
+ * transform up to rounding):
+ *   "fft_plan"     0 register-resident FFT passes where the grid shape allows
+ *                    (FP32), 1 LDS Stockham passes
+ *   "ldl_plan"     0 register-window band solve when both band widths are at
+ *                    most 63, 1 LDS-window band solve
+ *   "project_plan" 0 tiled projection (tile moments staged in LDS),
+ *                  1 node-major gather
+ *   "graphs"       1 solve_ports replays the product and P^-1 of each FGMRES
+ *                    iteration as HIP graphs (after one eager iteration),
+ *                  0 eager launches
+ * PFFT_EINVAL for an unknown name or value. */
+pfft_status pfft_set_option(pfft_ctx *c, const char *name, int64_t value);
+pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *value);
+
+/* Times the preconditioned product P^-1 Z_l x (one FGMRES step) for nrhs
+ * right-hand sides at omega[nrhs] (host, rad/s) for each value of fft_plan,
+ * ldl_plan and project_plan in turn (median of reps runs after one warm-up),
+ * keeps the fastest value of each and writes a JSON report of the timings
+ * (milliseconds) and choices into report[cap] (host, NUL-terminated, may be
+ * NULL).  Allocates two nrhs x l complex128 device vectors for the run. */
+pfft_status pfft_autotune(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t reps, char *report,
+                          int64_t cap, void *hip_stream);
+
 void pfft_destroy(pfft_ctx *c);
 const char *pfft_last_error(void);
 

@@ -64,6 +64,14 @@ struct pfft_ctx {
           *ws_yb = nullptr, *ws_coef = nullptr;
   void *ws_J = nullptr, *ws_Q = nullptr, *ws_T1 = nullptr, *ws_T2 = nullptr;
   std::vector<double2> host_coef;
+  std::vector<double2> coef_on_device;   // what ws_coef holds (single-chunk calls), empty if unknown
+  // plan options (pfft_set_option, pfft_autotune)
+  struct Plans {
+    int fft = 0;      // 0 register-resident FFT passes where the shape allows, 1 LDS Stockham
+    int ldl = 0;      // 0 register-window band solve when the band fits a wave, 1 LDS window
+    int proj = 0;     // 0 tiled projection, 1 node-major gather
+    int graphs = 1;   // 1 FGMRES replays the product and P^-1 as HIP graphs
+  } plans;
   pfft::StageTimer timer;
   // solver state
   pfft::Precond *pre = nullptr;

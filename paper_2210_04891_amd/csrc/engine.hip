@@ -121,6 +121,7 @@ void pfft_ctx::ensure_workspace(int R) {
   ws_T1 = al(vs * (size_t)R * 6 * N);
   ws_T2 = al(vs * (size_t)R * 12 * N);
   ws_R = R;
+  coef_on_device.clear();
 }
 
 void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const double2 *x, double2 *y,
@@ -178,8 +179,15 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
         host_coef[Rc + r] = make_double2(0.0, om * MU0 * mu_r / (4.0 * M_PI));
       }
       timer.end(st);
-      hip_ok(hipMemcpyAsync(ws_coef, host_coef.data(), sizeof(double2) * 2 * Rc, hipMemcpyHostToDevice, st),
-             "coef upload");
+      // per-RHS coefficients: uploaded only when they change, so a product
+      // captured in a graph holds no host-to-device copy
+      const bool single = Rn == R;
+      if (!single || coef_on_device != host_coef) {
+        hip_ok(hipMemcpyAsync(ws_coef, host_coef.data(), sizeof(double2) * 2 * Rc, hipMemcpyHostToDevice, st),
+               "coef upload");
+        if (single) coef_on_device = host_coef;
+        else coef_on_device.clear();
+      }
       timer.begin(ST_COMBINE, st);
       combine(cm, alpha, ws_U, zs, jw, ws_yb, Rn, mode, st);
       timer.begin(ST_BRANCH_TO_LOOP, st);
@@ -380,6 +388,8 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
     // LDS: tcap triangles x 4 (FP32) or 2 (FP64) right-hand sides x 4 moments
     // (48 KB: three 512-thread workgroups per CU)
     g.tcap = 384;
+    g.fft_plan = c->plans.fft;
+    g.proj_plan = c->plans.proj;
     g.tt_off = upload(c, tt_off, st);
     g.tt_tri = upload(c, tt_tri, st);
     g.pg_loc = upload(c, pg_loc, st);
@@ -656,6 +666,134 @@ pfft_status extract_RL(int32_t nfreq, int32_t nport, const double *freq_hz, cons
 }  // extern "C"
 
 void pfft_ctx_free(pfft_ctx *c);
+
+namespace {
+int *option_slot(pfft_ctx *c, const std::string &name) {
+  if (name == "fft_plan") return &c->plans.fft;
+  if (name == "ldl_plan") return &c->plans.ldl;
+  if (name == "project_plan") return &c->plans.proj;
+  if (name == "graphs") return &c->plans.graphs;
+  return nullptr;
+}
+void sync_plans(pfft_ctx *c) {
+  c->gm.fft_plan = c->plans.fft;
+  c->gm.proj_plan = c->plans.proj;
+}
+}  // namespace
+
+extern "C" pfft_status pfft_set_option(pfft_ctx *c, const char *name, int64_t value) {
+  if (!c || !name) {
+    set_error("pfft_set_option: bad argument");
+    return PFFT_EINVAL;
+  }
+  int *slot = option_slot(c, name);
+  if (!slot || value < 0 || value > 1) {
+    set_error(std::string("pfft_set_option: unknown option or value: ") + name);
+    return PFFT_EINVAL;
+  }
+  *slot = (int)value;
+  sync_plans(c);
+  return PFFT_OK;
+}
+
+extern "C" pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *value) {
+  if (!c || !name || !value) {
+    set_error("pfft_get_option: bad argument");
+    return PFFT_EINVAL;
+  }
+  int *slot = option_slot(c, name);
+  if (!slot) {
+    set_error(std::string("pfft_get_option: unknown option: ") + name);
+    return PFFT_EINVAL;
+  }
+  *value = *slot;
+  return PFFT_OK;
+}
+
+// Times the preconditioned loop-space product (the FGMRES step) for each
+// value of each plan option in turn on device-resident synthetic vectors,
+// keeps the fastest value of each, and writes a JSON report.
+extern "C" pfft_status pfft_autotune(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t reps,
+                                     char *report, int64_t cap, void *hip_stream) {
+  if (!c || nrhs <= 0 || !omega || reps <= 0) {
+    set_error("pfft_autotune: bad argument");
+    return PFFT_EINVAL;
+  }
+  double2 *x = nullptr, *y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  try {
+    hip_ok(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t n = (size_t)nrhs * c->m.l;
+    hip_ok(hipMalloc(&x, n * sizeof(double2)), "hipMalloc autotune x");
+    hip_ok(hipMalloc(&y, n * sizeof(double2)), "hipMalloc autotune y");
+    {  // deterministic non-trivial input (x_i = (sin i, cos 2i))
+      std::vector<double2> h(n);
+      for (size_t i = 0; i < n; ++i) h[i] = make_double2(std::sin(0.37 * (double)i), std::cos(0.71 * (double)i));
+      hip_ok(hipMemcpy(x, h.data(), n * sizeof(double2), hipMemcpyHostToDevice), "autotune x");
+    }
+    hip_ok(hipEventCreate(&e0), "event");
+    hip_ok(hipEventCreate(&e1), "event");
+    auto time_step = [&]() {
+      pfft_status s0 = pfft_internal_precond_matvec(c, nrhs, omega, PFFT_PRECOND, x, y, st);
+      if (s0 != PFFT_OK) throw DeviceError{s0, "autotune product"};
+      std::vector<float> t(reps);
+      for (int k = 0; k < reps; ++k) {
+        hip_ok(hipEventRecord(e0, st), "event");
+        pfft_internal_precond_matvec(c, nrhs, omega, PFFT_PRECOND, x, y, st);
+        hip_ok(hipEventRecord(e1, st), "event");
+        hip_ok(hipEventSynchronize(e1), "event sync");
+        hip_ok(hipEventElapsedTime(&t[k], e0, e1), "event time");
+      }
+      std::sort(t.begin(), t.end());
+      return (double)t[reps / 2];
+    };
+    std::string js = "{";
+    const char *names[3] = {"fft_plan", "ldl_plan", "project_plan"};
+    for (int o = 0; o < 3; ++o) {
+      int *slot = option_slot(c, names[o]);
+      double best = 1e300;
+      int arg = *slot;
+      js += std::string(o ? ", " : "") + "\"" + names[o] + "\": {";
+      for (int v = 0; v <= 1; ++v) {
+        *slot = v;
+        sync_plans(c);
+        const double ms = time_step();
+        js += (v ? ", " : "") + std::string("\"") + std::to_string(v) + "\": " + std::to_string(ms);
+        if (ms < best) {
+          best = ms;
+          arg = v;
+        }
+      }
+      *slot = arg;
+      sync_plans(c);
+      js += ", \"chosen\": " + std::to_string(arg) + "}";
+    }
+    js += "}";
+    if (report && cap > 0) {
+      const size_t k = std::min<size_t>((size_t)cap - 1, js.size());
+      memcpy(report, js.data(), k);
+      report[k] = 0;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(x);
+    hipFree(y);
+    return PFFT_OK;
+  } catch (const DeviceError &e) {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (x) hipFree(x);
+    if (y) hipFree(y);
+    set_error("pfft_autotune: " + e.msg);
+    return (pfft_status)e.code;
+  } catch (const SetupError &e) {
+    if (x) hipFree(x);
+    if (y) hipFree(y);
+    set_error("pfft_autotune: " + e.msg);
+    return (pfft_status)e.code;
+  }
+}
 
 extern "C" void pfft_destroy(pfft_ctx *c) {
   if (!c) return;

@@ -58,6 +58,10 @@ struct GridMaps {
   // the first tcap triangles of a tile are staged in LDS
   int tile[3], ntile[3], tcap;
   const int *tt_off, *tt_tri, *pg_loc;
+  // plan choices (set by the context's options or the autotuner):
+  // fft_plan 0 register-resident passes where the shape allows, 1 LDS
+  // Stockham passes; proj_plan 0 tiled (LDS-staged), 1 node-major gather
+  int fft_plan, proj_plan;
 };
 
 // alpha [b][R] -> J [n][R][4]

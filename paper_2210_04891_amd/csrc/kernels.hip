@@ -420,7 +420,7 @@ void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st)
   constexpr int RC = ProjRC<T>::v;
   const size_t lds = (size_t)g.tcap * RC * 4 * sizeof(V2<T>);
   static bool lds_ok = allow_lds((const void *)k_project_tiled<T>, (int)lds);
-  if (lds_ok) {
+  if (lds_ok && g.proj_plan == 0) {
     const unsigned ntile = (unsigned)g.ntile[0] * g.ntile[1] * g.ntile[2];
     k_project_tiled<T><<<dim3(ntile, cdiv(R, RC)), 512, lds, st>>>(g, J, Q, R);
   } else {
@@ -1098,16 +1098,11 @@ static void fft_axis(const V2<T> *in, V2<T> *out, long A, long C, int n_in, int 
 }
 
 // Plane-kernel choice: the register variant exists for (N_y, N_z) =
-// (64, 32), (32, 16), (16, 8) in FP32; PFFT_FFT_PLAN=lds forces the LDS
-// Stockham variant (both are exact transforms; the choice is a tuning knob).
-static bool plan_lds_forced() {
-  const char *e = getenv("PFFT_FFT_PLAN");
-  return e && std::string(e) == "lds";
-}
-
+// (64, 32), (32, 16), (16, 8) in FP32; fft_plan 1 selects the LDS Stockham
+// variant (both are exact transforms; the choice is a tuning knob).
 template <typename T>
-static bool reg_plane_ok(int Ny, int Nz) {
-  if (sizeof(T) != 4 || plan_lds_forced()) return false;
+static bool reg_plane_ok(const GridMaps &g, int Ny, int Nz) {
+  if (sizeof(T) != 4 || g.fft_plan == 1) return false;
   return (Ny == 64 && Nz == 32) || (Ny == 32 && Nz == 16) || (Ny == 16 && Nz == 8);
 }
 
@@ -1121,8 +1116,8 @@ static void launch_yz_reg(float2 *data, const float *ghat, const YZArgs &y, long
 // Register X passes: FP32, N_x in {32, 64, 128, 256}, N_y N_z a multiple of
 // 32, element offsets of the padded grid below 2^32.
 template <typename T>
-static bool reg_x_ok(int Nx, long C, long ch) {
-  if (sizeof(T) != 4 || plan_lds_forced()) return false;
+static bool reg_x_ok(const GridMaps &g, int Nx, long C, long ch) {
+  if (sizeof(T) != 4 || g.fft_plan == 1) return false;
   if ((double)ch * 2.0 * Nx * (double)C >= 4294967295.0) return false;
   return (Nx == 256 || Nx == 128 || Nx == 64 || Nx == 32) && C % 32 == 0;
 }
@@ -1148,7 +1143,7 @@ template <typename T>
 void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStream_t st, PassHook *hook) {
   const int Nx = g.dims[0], Ny = g.dims[1], Nz = g.dims[2];
   long ch = 3L * R;
-  const bool xreg = reg_x_ok<T>(Nx, (long)Ny * Nz, ch);
+  const bool xreg = reg_x_ok<T>(g, Nx, (long)Ny * Nz, ch);
   // X forward: [ch][Nx][Ny*Nz] -> [ch][2Nx][Ny*Nz]
   if (hook) hook->pass(0, st);
   if (xreg)
@@ -1158,7 +1153,7 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
   const int vs = (int)sizeof(V2<T>);
   const int pitch = 2 * Nz + 1;
   const size_t yz_lds = (size_t)(2 * Ny + 2 * Nz + 2 * Ny * pitch) * vs;
-  if (reg_plane_ok<T>(Ny, Nz)) {
+  if (reg_plane_ok<T>(g, Ny, Nz)) {
     if (hook) hook->pass(1, st);
     YZArgs y{};
     y.ny = Ny;

@@ -79,6 +79,7 @@ struct PrecondDev {
   const int8_t *src_sg;
   const int *link_kind, *port_loop;
   int64_t nnz_env;
+  int ldl_plan;          // 0 register window when W, Wc <= 63; 1 LDS window
 };
 
 // z = P^-1 y for R right-hand sides; fidx[r] selects the factor of RHS r

@@ -699,12 +699,8 @@ __global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *f
 }
 
 // Band-solve plan: the register window when both band widths fit one wave
-// (PFFT_LDL_PLAN=lds forces the LDS window).
-static bool ldl_reg_plan(const PrecondDev &d) {
-  const char *e = getenv("PFFT_LDL_PLAN");
-  if (e && std::string(e) == "lds") return false;
-  return d.W <= 63 && d.Wc <= 63;
-}
+// (ldl_plan 1 selects the LDS window).
+static bool ldl_reg_plan(const PrecondDev &d) { return d.ldl_plan == 0 && d.W <= 63 && d.Wc <= 63; }
 
 __global__ void k_pre_out(PrecondDev d, const int *fidx, const double2 *y, const double2 *work, double2 *z) {
   int r = blockIdx.y;

@@ -161,6 +161,7 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
     P->cap_R = R;
     P->fidx_host.clear();
   }
+  P->dev.ldl_plan = c->plans.ldl;
   std::vector<int> fidx(R);
   for (int r = 0; r < R; ++r)
     fidx[r] = (int)(std::lower_bound(P->omegas.begin(), P->omegas.end(), om[r]) - P->omegas.begin());
@@ -407,6 +408,37 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
   std::vector<uint8_t> use_l(R, precond == 2 ? 1 : 0);
   const double judge = precond == 2 ? learned_judge_factor(c) : 0.0;
   std::vector<std::vector<double>> seq(R);
+  // The preconditioner apply (F.w -> F.Ax) and the product (F.Ax -> F.w) use
+  // fixed buffers in every iteration: after one eager iteration (which sets
+  // up workspaces and uploads the per-RHS coefficients) they are captured as
+  // HIP graphs on a private stream and replayed on st.
+  hipStream_t cs = nullptr;
+  hipGraphExec_t g_pre = nullptr, g_mv = nullptr;
+  bool want_graphs = c->plans.graphs && !c->timer.on && c->chunk_for(R) >= R;
+  auto run_pre = [&](hipStream_t s2) { precond_apply(P->dev, P->d_fidx, F.w, F.Ax, P->d_work, R, s2); };
+  auto run_mv = [&](hipStream_t s2) { c->matvec(R, omega, 1, 0, F.Ax, F.w, s2); };
+  auto capture = [&](auto &&fn, hipGraphExec_t &exec) {
+    hipGraph_t gr = nullptr;
+    hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      fn(cs);
+    } catch (...) {
+      hipStreamEndCapture(cs, &gr);
+      if (gr) hipGraphDestroy(gr);
+      throw;
+    }
+    hip_ok(hipStreamEndCapture(cs, &gr), "end capture");
+    const hipError_t e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+    hipGraphDestroy(gr);
+    hip_ok(e, "graph instantiate");
+  };
+  auto release_graphs = [&]() {
+    if (g_pre) hipGraphExecDestroy(g_pre);
+    if (g_mv) hipGraphExecDestroy(g_mv);
+    if (cs) hipStreamDestroy(cs);
+    g_pre = g_mv = nullptr;
+    cs = nullptr;
+  };
   // |b|
   k_mdot<<<dim3(1, R), 256, 0, st>>>(F.b, F.b, F.nrm, l, 1, 1, 1, nullptr);
   {
@@ -440,7 +472,10 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
       double2 *zk = F.Ax;  // contiguous [R][l]
       if (precond == 2 && learned_apply(c, R, omega, F.w, zk, use_l.data(), st)) {
       } else if (precond) {
-        precond_apply(P->dev, P->d_fidx, F.w, zk, P->d_work, R, st);
+        if (g_pre)
+          hip_ok(hipGraphLaunch(g_pre, st), "graph launch");
+        else
+          run_pre(st);
       } else {
         hip_ok(hipMemcpyAsync(zk, F.w, (size_t)R * l * sizeof(double2), hipMemcpyDeviceToDevice, st), "noprec");
       }
@@ -448,7 +483,22 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
                               l * sizeof(double2), R, hipMemcpyDeviceToDevice, st),
              "store z");
       // w = Z_l z_k
-      c->matvec(R, omega, 1, 0, zk, F.w, st);
+      if (g_mv)
+        hip_ok(hipGraphLaunch(g_mv, st), "graph launch");
+      else
+        run_mv(st);
+      if (want_graphs && !g_mv) {
+        want_graphs = false;
+        try {
+          hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+          hip_ok(hipStreamSynchronize(st), "pre-capture sync");
+          capture(run_mv, g_mv);
+          if (precond == 1) capture(run_pre, g_pre);
+        } catch (const DeviceError &) {
+          (void)hipGetLastError();   // graphs are an optimisation: stay eager
+          release_graphs();
+        }
+      }
       // classical Gram-Schmidt, twice
       k_mdot<<<dim3(k + 1, R), 256, 0, st>>>(F.V, F.w, F.h1, l, m + 1, k + 1, m + 1, nullptr);
       k_maxpy<<<gl, 256, 0, st>>>(F.V, F.w, F.h1, l, m + 1, k + 1, m + 1, nullptr);
@@ -519,6 +569,7 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
   std::vector<double2> n2(R);
   hip_ok(hipMemcpyAsync(n2.data(), F.nrm, R * sizeof(double2), hipMemcpyDeviceToHost, st), "final norm");
   hip_ok(hipStreamSynchronize(st), "final sync");
+  release_graphs();
   for (int r = 0; r < R; ++r) {
     relres[r] = std::sqrt(std::max(n2[r].x, 0.0)) / (bnorm[r] > 0 ? bnorm[r] : 1.0);
     if (!done[r]) iters[r] = total;

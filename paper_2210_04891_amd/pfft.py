@@ -27,7 +27,8 @@ EXPORTS = ("pfft_setup", "pfft_sizes", "pfft_matvec", "solve_ports", "extract_RL
            "pfft_precond_load", "pfft_destroy", "pfft_last_error",
            "pfft_host_setup", "pfft_host_get", "pfft_host_free", "pfft_profile",
            "pfft_stage_times", "pfft_precond_save", "pfft_learned_collect", "pfft_learned_train",
-           "pfft_learned_clear", "pfft_learned_stats", "pfft_mlp_grad", "pfft_learned_eval")
+           "pfft_learned_clear", "pfft_learned_stats", "pfft_mlp_grad", "pfft_learned_eval",
+           "pfft_set_option", "pfft_get_option", "pfft_autotune")
 
 STAGES = ("loop_to_branch", "tri_current", "project", "fft_x", "fft_y", "fft_z_conv", "ifft_y",
           "ifft_x", "interp", "combine", "branch_to_loop", "precond")
@@ -96,6 +97,12 @@ def load():
     lib.pfft_learned_collect.restype = i32
     lib.pfft_learned_train.argtypes = [vp, i32, i32, i32, dbl, ctypes.c_uint64, vp, vp]
     lib.pfft_learned_train.restype = i32
+    lib.pfft_set_option.argtypes = [vp, ctypes.c_char_p, i64]
+    lib.pfft_set_option.restype = i32
+    lib.pfft_get_option.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64)]
+    lib.pfft_get_option.restype = i32
+    lib.pfft_autotune.argtypes = [vp, i32, vp, i32, ctypes.c_char_p, i64, vp]
+    lib.pfft_autotune.restype = i32
     lib.pfft_learned_eval.argtypes = [vp, ctypes.POINTER(dbl), vp]
     lib.pfft_learned_eval.restype = i32
     lib.pfft_learned_clear.argtypes = [vp]
@@ -240,6 +247,24 @@ class Context:
                                          _ptr(Y), _ptr(it), _ptr(rr), _stream_handle(stream)),
                       allow=(-5,))
         return Y, it, rr, code
+
+    def set_option(self, name, value):
+        """Plan options: fft_plan, ldl_plan, project_plan, graphs (0 or 1)."""
+        _check(load().pfft_set_option(self._h, name.encode(), int(value)))
+
+    def get_option(self, name):
+        v = ctypes.c_int64()
+        _check(load().pfft_get_option(self._h, name.encode(), ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, omega, reps=3, stream=None):
+        """Time each plan on the preconditioned product for len(omega)
+        right-hand sides, keep the fastest; returns the report (dict)."""
+        import json
+        om = np.ascontiguousarray(np.asarray(omega, np.float64).reshape(-1))
+        buf = ctypes.create_string_buffer(4096)
+        _check(load().pfft_autotune(self._h, om.size, _ptr(om), reps, buf, len(buf), _stream_handle(stream)))
+        return json.loads(buf.value.decode())
 
     def profile(self, enable=True):
         _check(load().pfft_profile(self._h, 1 if enable else 0))

@@ -2,13 +2,11 @@
 
 The plane stage (Y, Z with the spectrum, inverse Z, inverse Y) has two
 implementations: register-resident lines with even/odd half transforms, and
-LDS Stockham passes on the padded plane (PFFT_FFT_PLAN=lds).  Both must
+LDS Stockham passes on the padded plane (option fft_plan = 1).  Both must
 reproduce the oracle's explicit B^T (H * (B alpha)) to FP32 accuracy, on a
 small grid and on the bench grid (256 x 64 x 32, 39,936 triangles), and
 agree with each other.
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -20,16 +18,8 @@ gpu = pytest.mark.gpu
 
 def _far(ctx, X, plan):
     import paper_2210_04891_amd as P
-    old = os.environ.get("PFFT_FFT_PLAN")
-    os.environ["PFFT_FFT_PLAN"] = plan
-    try:
-        y = ctx.matvec(torch.from_numpy(X).cuda(), space=0, flags=P.PFFT_FAR_ONLY).cpu().numpy()
-    finally:
-        if old is None:
-            del os.environ["PFFT_FFT_PLAN"]
-        else:
-            os.environ["PFFT_FFT_PLAN"] = old
-    return y
+    ctx.set_option("fft_plan", 1 if plan == "lds" else 0)
+    return ctx.matvec(torch.from_numpy(X).cuda(), space=0, flags=P.PFFT_FAR_ONLY).cpu().numpy()
 
 
 def _rel(a, b):

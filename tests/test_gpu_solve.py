@@ -54,14 +54,14 @@ def e1_bar():
 @gpu
 @pytest.mark.parametrize("plan", ["register", "lds"])
 @pytest.mark.parametrize("which", ["e1_bar", "two_wires"])
-def test_precond_matches_dense_inverse(which, plan, request, monkeypatch):
+def test_precond_matches_dense_inverse(which, plan, request):
     """Both band-solve plans (register window, LDS window) against the
     oracle's dense inverse."""
     import paper_2210_04891_amd as P
-    monkeypatch.setenv("PFFT_LDL_PLAN", plan)
     s, m, c, K, A, Zb = request.getfixturevalue(which)
     grid = (32, 8, 8) if which == "e1_bar" else (32, 16, 16)
     ctx = P.Context(s, grid, near_kappa=1.5, grid_fp64=True)
+    ctx.set_option("ldl_plan", 1 if plan == "lds" else 0)
     om = 2 * np.pi * np.array([1e9, 1e10, 3e10])
     Y = W.complex_normal(7, (3, c.nloop))
     z = ctx.matvec(_dev(Y), omega=om, space=1, flags=P.PFFT_PRECOND_ONLY).cpu().numpy()
