@@ -375,32 +375,47 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
     for (int q = 0; q < RC; ++q)
 #pragma unroll
       for (int c = 0; c < 6; ++c) acc[q][c] = 0;
-    for (int k = g.pg_off[node]; k < g.pg_off[node + 1]; ++k) {
-      const int loc = g.pg_loc[k];
-      const T m0 = w[4 * (size_t)k], m1x = w[4 * (size_t)k + 1], m1y = w[4 * (size_t)k + 2],
-              m1z = w[4 * (size_t)k + 3];
-      V2<T> jv[RC][4];
-      if (loc < ns) {
+    // contributions in groups of 4: their index and weight loads are
+    // independent, so several are in flight; the sum keeps the list order
+    const int k0 = g.pg_off[node], k1 = g.pg_off[node + 1];
+    for (int kb = k0; kb < k1; kb += 4) {
+      int locs[4];
+      T wv[4][4];
 #pragma unroll
-        for (int q = 0; q < RC; ++q)
+      for (int u2 = 0; u2 < 4; ++u2) {
+        const int k = min(kb + u2, k1 - 1);
+        locs[u2] = g.pg_loc[k];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) jv[q][c] = sJ[(loc * RC + q) * 4 + c];
-      } else {
-        const V2<T> *jt = J + ((size_t)g.pg_tri[k] * R + r0) * 4;
-#pragma unroll
-        for (int q = 0; q < RC; ++q)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) jv[q][c] = q < nr ? jt[4 * q + c] : cmk<T>(0, 0);
+        for (int c = 0; c < 4; ++c) wv[u2][c] = w[4 * (size_t)k + c];
       }
 #pragma unroll
-      for (int q = 0; q < RC; ++q) {
-        const V2<T> j0 = jv[q][0], jx = jv[q][1], jy = jv[q][2], jz = jv[q][3];
-        acc[q][0] += j0.x * m1x - jx.x * m0;
-        acc[q][1] += j0.y * m1x - jx.y * m0;
-        acc[q][2] += j0.x * m1y - jy.x * m0;
-        acc[q][3] += j0.y * m1y - jy.y * m0;
-        acc[q][4] += j0.x * m1z - jz.x * m0;
-        acc[q][5] += j0.y * m1z - jz.y * m0;
+      for (int u2 = 0; u2 < 4; ++u2) {
+        if (kb + u2 >= k1) break;
+        const int loc = locs[u2];
+        const T m0 = wv[u2][0], m1x = wv[u2][1], m1y = wv[u2][2], m1z = wv[u2][3];
+        V2<T> jv[RC][4];
+        if (loc < ns) {
+#pragma unroll
+          for (int q = 0; q < RC; ++q)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) jv[q][c] = sJ[(loc * RC + q) * 4 + c];
+        } else {
+          const V2<T> *jt = J + ((size_t)g.pg_tri[kb + u2] * R + r0) * 4;
+#pragma unroll
+          for (int q = 0; q < RC; ++q)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) jv[q][c] = q < nr ? jt[4 * q + c] : cmk<T>(0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+          const V2<T> j0 = jv[q][0], jx = jv[q][1], jy = jv[q][2], jz = jv[q][3];
+          acc[q][0] += j0.x * m1x - jx.x * m0;
+          acc[q][1] += j0.y * m1x - jx.y * m0;
+          acc[q][2] += j0.x * m1y - jy.x * m0;
+          acc[q][3] += j0.y * m1y - jy.y * m0;
+          acc[q][4] += j0.x * m1z - jz.x * m0;
+          acc[q][5] += j0.y * m1z - jz.y * m0;
+        }
       }
     }
 #pragma unroll
@@ -942,18 +957,16 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
         v[n] = make_float2(v[n].x * w.x - v[n].y * w.y, v[n].x * w.y + v[n].y * w.x);
       }
     }
-    // lane pair sum; lane `half` keeps n in [half NY/2, (half+1) NY/2)
-    float2 out[NY / 2];
+    // lane pair sum; lane `half` keeps n in [half NY/2, (half+1) NY/2).
+    // Column kz was read only by this lane pair (one wave, whose LDS
+    // accesses complete in order), so it is overwritten without a barrier.
 #pragma unroll
     for (int j = 0; j < NY / 2; ++j) {
       const float2 lo = v[j], hi = v[j + NY / 2];
       const float2 send = half ? lo : hi, keep = half ? hi : lo;
       const float2 r = qperm2<0xB1>(send);   // lane ^ 1
-      out[j] = make_float2(keep.x + r.x, keep.y + r.y);
+      sm[kz * PT + half * (NY / 2) + j] = make_float2(keep.x + r.x, keep.y + r.y);
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NY / 2; ++j) sm[kz * PT + half * (NY / 2) + j] = out[j];
   }
   __syncthreads();
   // stage D: row n = line, z half `half`: inverse, crop, store
