@@ -55,6 +55,27 @@ def stage_bytes(sz, R, vbytes=8):
     }
 
 
+def measured_traffic(stage):
+    """HBM bytes per launch of a stage from the committed counter runs
+    (profiles/bond_wires80_traffic.json: rocprofv3 FETCH_SIZE and WRITE_SIZE,
+    each scaled by a 1 GiB copy), or None when the table has no entry or the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "bond_wires80_traffic.json")
+    try:
+        tab = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    for rel, sha in tab.get("sources_sha256", {}).items():
+        try:
+            if hashlib.sha256(open(os.path.join(HERE, rel), "rb").read()).hexdigest() != sha:
+                return None
+        except OSError:
+            return None
+    ent = tab.get("stages", {}).get(stage)
+    return None if ent is None else int(ent["read_bytes"] + ent["write_bytes"])
+
+
 def cpu_oracle_baseline(structure, budget_s=12.0):
     """The oracle's dense kernel matvec, rows computed exactly on the fly
     (closed-form inner / graded outer quadrature), timed on a bounded sample
@@ -145,7 +166,7 @@ def main():
     if dom in nbytes:
         achieved = nbytes[dom] / avg_s / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                 "avg_launch_ms": round(ms / calls, 4), "bytes_per_launch": int(nbytes[dom])}
     else:
         roof = {"kernel": dom, "bound": "latency", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
