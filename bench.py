@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction sweep arm")
+    ap.add_argument("--no-split", action="store_true",
+                    help="run every product on one stream (the per-kernel profile runs use this so that kernel "
+                         "durations are not shared with a concurrent stream)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before the steps, copy a buffer of this size three times (device to device) so that "
                          "hardware byte counters can be scaled against a transfer of known size")
@@ -141,19 +144,28 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.no_split:
+        ctx.set_option("stream_split", 0)
     for _ in range(args.warmup):
         ctx.matvec(x, omega, space=1, flags=flags, out=y)
     torch.cuda.synchronize()
-    ctx.profile(True)
-    torch.cuda.synchronize()
+    # timed region: the steps as they run in the solver (right-hand sides
+    # split over two streams unless --no-split)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.matvec(x, omega, space=1, flags=flags, out=y)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    value = R * args.steps / dt
+    # per-stage HIP-event timing (one stream, so each kernel's duration is its
+    # own): the roofline of the dominant kernel
+    psteps = max(1, min(args.steps, 5))
+    ctx.profile(True)
+    for _ in range(psteps):
+        ctx.matvec(x, omega, space=1, flags=flags, out=y)
+    torch.cuda.synchronize()
     stages = ctx.stage_times()
     ctx.profile(False)
-    value = R * args.steps / dt
     # roofline of the dominant kernel (by total time inside the timed region)
     nbytes = stage_bytes(sz, R)
     if stages.get("fft_z_conv", (0, 0))[1] == 0 and stages.get("fft_y", (0, 0))[1] > 0:
@@ -189,7 +201,8 @@ def main():
                    "triangles": sz["n"], "loops": sz["l"], "rhs": R, "grid": list(grid),
                    "near_nnz": sz["nnz_near"], "setup_s": round(t_setup, 2)},
         "roofline": roof,
-        "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]},
+        "stages_ms_per_step": {k: round(v[0] / psteps, 4) for k, v in stages.items() if v[1]},
+        "stage_sum_ms": round(sum(v[0] for v in stages.values()) / psteps, 3),
         "device": {"name": torch.cuda.get_device_name(0),
                    "lds_per_block": getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", None)},
     }

@@ -44,6 +44,16 @@ struct StageTimer {
 struct Precond;   // nodal-route preconditioner factors (one per frequency)
 struct Learned;   // learned correction network
 
+// Per-product workspace for up to R right-hand sides (one per stream lane).
+struct Workspace {
+  int R = 0;
+  std::vector<void *> allocs;
+  double2 *alpha = nullptr, *scan = nullptr, *part = nullptr, *U = nullptr, *yb = nullptr, *coef = nullptr;
+  void *J = nullptr, *Q = nullptr, *T1 = nullptr, *T2 = nullptr;
+  std::vector<double2> host_coef;
+  std::vector<double2> coef_on_device;   // what coef holds (single-chunk ranges), empty if unknown
+};
+
 }  // namespace pfft
 
 struct pfft_ctx {
@@ -57,20 +67,18 @@ struct pfft_ctx {
   pfft::LoopMaps lm{};
   pfft::GridMaps gm{};
   pfft::CombineMaps cm{};
-  // per-matvec workspace, sized for ws_R right-hand sides
-  int ws_R = 0;
-  std::vector<void *> ws_allocs;
-  double2 *ws_alpha = nullptr, *ws_scan = nullptr, *ws_part = nullptr, *ws_U = nullptr,
-          *ws_yb = nullptr, *ws_coef = nullptr;
-  void *ws_J = nullptr, *ws_Q = nullptr, *ws_T1 = nullptr, *ws_T2 = nullptr;
-  std::vector<double2> host_coef;
-  std::vector<double2> coef_on_device;   // what ws_coef holds (single-chunk calls), empty if unknown
+  // per-product workspaces and the two stream lanes the right-hand sides
+  // are split over (fork/join by events on the caller's stream)
+  pfft::Workspace ws[2];
+  hipStream_t lane[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   // plan options (pfft_set_option, pfft_autotune)
   struct Plans {
     int fft = 0;      // 0 register-resident FFT passes where the shape allows, 1 LDS Stockham
     int ldl = 0;      // 0 register-window band solve when the band fits a wave, 1 LDS window
     int proj = 0;     // 0 tiled projection, 1 node-major gather
     int graphs = 1;   // 1 FGMRES replays the product and P^-1 as HIP graphs
+    int stream_split = 0;  // 1: the right-hand sides of a product are split over two streams
   } plans;
   pfft::StageTimer timer;
   // solver state
@@ -80,11 +88,41 @@ struct pfft_ctx {
   void *dalloc(size_t bytes);
   size_t per_rhs_bytes() const;
   int chunk_for(int R) const;
-  void ensure_workspace(int R);
+  void ensure_workspace(pfft::Workspace &w, int R);
   // y = op(x) for R right-hand sides already resident on the device
   void matvec(int R, const double *omega, int space, int flags, const double2 *x, double2 *y,
               hipStream_t st);
+  // op for right-hand sides [0, R) of x/y/omega on stream st with workspace w
+  void matvec_range(pfft::Workspace &w, int R, const double *omega, int space, int flags, const double2 *x,
+                    double2 *y, hipStream_t st);
+  // Runs fn(r0, rn, stream, workspace) for the right-hand sides [0, R),
+  // split over the two stream lanes when enabled (not while profiling).
+  template <typename Fn> void run_split(int R, hipStream_t st, Fn &&fn);
+  bool split_ok(int R) const { return plans.stream_split == 1 && !timer.on && R >= 8; }
 };
+
+template <typename Fn>
+void pfft_ctx::run_split(int R, hipStream_t st, Fn &&fn) {
+  if (!split_ok(R)) {
+    fn(0, R, st, ws[0]);
+    return;
+  }
+  for (int i = 0; i < 2; ++i)
+    if (!lane[i]) {
+      pfft::hip_ok(hipStreamCreateWithFlags(&lane[i], hipStreamNonBlocking), "lane stream");
+      pfft::hip_ok(hipEventCreateWithFlags(&ev_join[i], hipEventDisableTiming), "lane event");
+    }
+  if (!ev_fork) pfft::hip_ok(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "fork event");
+  pfft::hip_ok(hipEventRecord(ev_fork, st), "fork");
+  const int half = (R + 1) / 2;
+  for (int i = 0; i < 2; ++i) {
+    pfft::hip_ok(hipStreamWaitEvent(lane[i], ev_fork, 0), "fork wait");
+    const int r0 = i ? half : 0, rn = i ? R - half : half;
+    fn(r0, rn, lane[i], ws[i]);
+    pfft::hip_ok(hipEventRecord(ev_join[i], lane[i]), "join");
+    pfft::hip_ok(hipStreamWaitEvent(st, ev_join[i], 0), "join wait");
+  }
+}
 
 // P^-1 (Z_l x) or P^-1 x in loop space (defined with the solver)
 pfft_status pfft_internal_precond_matvec(pfft_ctx *c, int R, const double *omega, int flags,

@@ -98,42 +98,50 @@ int pfft_ctx::chunk_for(int R) const {
   return std::max(1, std::min(R, cap));
 }
 
-void pfft_ctx::ensure_workspace(int R) {
-  if (R <= ws_R) return;
-  for (void *p : ws_allocs) hipFree(p);
-  ws_allocs.clear();
+void pfft_ctx::ensure_workspace(Workspace &w, int R) {
+  if (R <= w.R) return;
+  for (void *p : w.allocs) hipFree(p);
+  w.allocs.clear();
   auto al = [&](size_t bytes) {
     void *p = nullptr;
     hip_ok(hipMalloc(&p, bytes ? bytes : 16), "hipMalloc workspace");
-    ws_allocs.push_back(p);
+    w.allocs.push_back(p);
     return p;
   };
   size_t vs = grid_fp64 ? sizeof(double2) : sizeof(float2);
   size_t N = (size_t)m.dims[0] * m.dims[1] * m.dims[2];
-  ws_alpha = (double2 *)al(sizeof(double2) * (size_t)R * m.b);
-  ws_yb = (double2 *)al(sizeof(double2) * (size_t)R * m.b);
-  ws_scan = (double2 *)al(sizeof(double2) * (size_t)R * (m.nn + 1));
-  ws_part = (double2 *)al(sizeof(double2) * scan_partials_size(m.nn + 1, R));
-  ws_U = (double2 *)al(sizeof(double2) * (size_t)R * m.n * 4);
-  ws_coef = (double2 *)al(sizeof(double2) * 2 * (size_t)R);
-  ws_J = al(vs * (size_t)R * m.n * 4);
-  ws_Q = al(vs * (size_t)R * 3 * N);
-  ws_T1 = al(vs * (size_t)R * 6 * N);
-  ws_T2 = al(vs * (size_t)R * 12 * N);
-  ws_R = R;
-  coef_on_device.clear();
+  w.alpha = (double2 *)al(sizeof(double2) * (size_t)R * m.b);
+  w.yb = (double2 *)al(sizeof(double2) * (size_t)R * m.b);
+  w.scan = (double2 *)al(sizeof(double2) * (size_t)R * (m.nn + 1));
+  w.part = (double2 *)al(sizeof(double2) * scan_partials_size(m.nn + 1, R));
+  w.U = (double2 *)al(sizeof(double2) * (size_t)R * m.n * 4);
+  w.coef = (double2 *)al(sizeof(double2) * 2 * (size_t)R);
+  w.J = al(vs * (size_t)R * m.n * 4);
+  w.Q = al(vs * (size_t)R * 3 * N);
+  w.T1 = al(vs * (size_t)R * 6 * N);
+  w.T2 = al(vs * (size_t)R * 12 * N);
+  w.R = R;
+  w.coef_on_device.clear();
 }
 
 void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const double2 *x, double2 *y,
                       hipStream_t st) {
   const int dim = space == 1 ? m.l : m.b;
+  run_split(R, st, [&](int r0, int rn, hipStream_t s2, Workspace &w) {
+    matvec_range(w, rn, omega ? omega + r0 : nullptr, space, flags, x + (size_t)r0 * dim, y + (size_t)r0 * dim, s2);
+  });
+}
+
+void pfft_ctx::matvec_range(Workspace &w, int R, const double *omega, int space, int flags, const double2 *x,
+                            double2 *y, hipStream_t st) {
+  const int dim = space == 1 ? m.l : m.b;
   const int Rc = chunk_for(R);
-  ensure_workspace(Rc);
+  ensure_workspace(w, Rc);
   int mode = 0;
   if (!(flags & PFFT_NEAR_ONLY)) mode |= 1;
   if (!(flags & PFFT_FAR_ONLY)) mode |= 2;
   if (space == 1) mode |= 4;
-  host_coef.resize(2 * (size_t)Rc);
+  w.host_coef.resize(2 * (size_t)Rc);
   for (int r0 = 0; r0 < R; r0 += Rc) {
     int Rn = std::min(Rc, R - r0);
     const double2 *xc = x + (size_t)r0 * dim;
@@ -143,60 +151,60 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
     PassHook *hk = timer.on ? &hook : nullptr;
     if (space == 1) {
       timer.begin(ST_LOOP_TO_BRANCH, st);
-      loop_to_branch(lm, xc, ws_alpha, ws_scan, ws_part, Rn, st);
+      loop_to_branch(lm, xc, w.alpha, w.scan, w.part, Rn, st);
     } else {
       timer.begin(ST_LOOP_TO_BRANCH, st);
-      transpose(xc, ws_alpha, Rn, m.b, st);
+      transpose(xc, w.alpha, Rn, m.b, st);
     }
-    alpha = ws_alpha;
+    alpha = w.alpha;
     if (mode & 1) {
       if (grid_fp64) {
         timer.begin(ST_TRI_CURRENT, st);
-        tri_currents<double>(gm, alpha, (double2 *)ws_J, Rn, st);
+        tri_currents<double>(gm, alpha, (double2 *)w.J, Rn, st);
         timer.begin(ST_PROJECT, st);
-        project<double>(gm, (double2 *)ws_J, (double2 *)ws_Q, Rn, st);
+        project<double>(gm, (double2 *)w.J, (double2 *)w.Q, Rn, st);
         timer.end(st);
-        convolve<double>(gm, (double2 *)ws_Q, (double2 *)ws_T1, (double2 *)ws_T2, Rn, st, hk);
+        convolve<double>(gm, (double2 *)w.Q, (double2 *)w.T1, (double2 *)w.T2, Rn, st, hk);
         timer.begin(ST_INTERP, st);
-        interp_tri<double>(gm, (double2 *)ws_Q, ws_U, Rn, st, ws_T1);
+        interp_tri<double>(gm, (double2 *)w.Q, w.U, Rn, st, w.T1);
       } else {
         timer.begin(ST_TRI_CURRENT, st);
-        tri_currents<float>(gm, alpha, (float2 *)ws_J, Rn, st);
+        tri_currents<float>(gm, alpha, (float2 *)w.J, Rn, st);
         timer.begin(ST_PROJECT, st);
-        project<float>(gm, (float2 *)ws_J, (float2 *)ws_Q, Rn, st);
+        project<float>(gm, (float2 *)w.J, (float2 *)w.Q, Rn, st);
         timer.end(st);
-        convolve<float>(gm, (float2 *)ws_Q, (float2 *)ws_T1, (float2 *)ws_T2, Rn, st, hk);
+        convolve<float>(gm, (float2 *)w.Q, (float2 *)w.T1, (float2 *)w.T2, Rn, st, hk);
         timer.begin(ST_INTERP, st);
-        interp_tri<float>(gm, (float2 *)ws_Q, ws_U, Rn, st, ws_T1);
+        interp_tri<float>(gm, (float2 *)w.Q, w.U, Rn, st, w.T1);
       }
     }
-    double2 *zs = ws_coef, *jw = ws_coef + Rc;
+    double2 *zs = w.coef, *jw = w.coef + Rc;
     if (space == 1) {
       for (int r = 0; r < Rn; ++r) {
         double om = omega[r0 + r];
         double a = std::sqrt(om * MU0 * mu_r / (2.0 * sigma));
-        host_coef[r] = make_double2(a, a);
-        host_coef[Rc + r] = make_double2(0.0, om * MU0 * mu_r / (4.0 * M_PI));
+        w.host_coef[r] = make_double2(a, a);
+        w.host_coef[Rc + r] = make_double2(0.0, om * MU0 * mu_r / (4.0 * M_PI));
       }
       timer.end(st);
       // per-RHS coefficients: uploaded only when they change, so a product
       // captured in a graph holds no host-to-device copy
       const bool single = Rn == R;
-      if (!single || coef_on_device != host_coef) {
-        hip_ok(hipMemcpyAsync(ws_coef, host_coef.data(), sizeof(double2) * 2 * Rc, hipMemcpyHostToDevice, st),
+      if (!single || w.coef_on_device != w.host_coef) {
+        hip_ok(hipMemcpyAsync(w.coef, w.host_coef.data(), sizeof(double2) * 2 * Rc, hipMemcpyHostToDevice, st),
                "coef upload");
-        if (single) coef_on_device = host_coef;
-        else coef_on_device.clear();
+        if (single) w.coef_on_device = w.host_coef;
+        else w.coef_on_device.clear();
       }
       timer.begin(ST_COMBINE, st);
-      combine(cm, alpha, ws_U, zs, jw, ws_yb, Rn, mode, st);
+      combine(cm, alpha, w.U, zs, jw, w.yb, Rn, mode, st);
       timer.begin(ST_BRANCH_TO_LOOP, st);
-      branch_to_loop(lm, ws_yb, yc, ws_scan, ws_part, Rn, st);
+      branch_to_loop(lm, w.yb, yc, w.scan, w.part, Rn, st);
     } else {
       timer.begin(ST_COMBINE, st);
-      combine(cm, alpha, ws_U, zs, jw, ws_yb, Rn, mode, st);
+      combine(cm, alpha, w.U, zs, jw, w.yb, Rn, mode, st);
       timer.begin(ST_BRANCH_TO_LOOP, st);
-      transpose(ws_yb, yc, m.b, Rn, st);
+      transpose(w.yb, yc, m.b, Rn, st);
     }
     timer.end(st);
   }
@@ -673,6 +681,7 @@ int *option_slot(pfft_ctx *c, const std::string &name) {
   if (name == "ldl_plan") return &c->plans.ldl;
   if (name == "project_plan") return &c->plans.proj;
   if (name == "graphs") return &c->plans.graphs;
+  if (name == "stream_split") return &c->plans.stream_split;
   return nullptr;
 }
 void sync_plans(pfft_ctx *c) {
@@ -749,8 +758,8 @@ extern "C" pfft_status pfft_autotune(pfft_ctx *c, int32_t nrhs, const double *om
       return (double)t[reps / 2];
     };
     std::string js = "{";
-    const char *names[3] = {"fft_plan", "ldl_plan", "project_plan"};
-    for (int o = 0; o < 3; ++o) {
+    const char *names[4] = {"fft_plan", "ldl_plan", "project_plan", "stream_split"};
+    for (int o = 0; o < 4; ++o) {
       int *slot = option_slot(c, names[o]);
       double best = 1e300;
       int arg = *slot;

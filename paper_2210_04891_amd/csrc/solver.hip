@@ -47,7 +47,13 @@ static void precond_free(Precond *p) {
 void pfft_ctx_free(pfft_ctx *c) {
   precond_free(c->pre);
   learned_free(c);
-  for (void *p : c->ws_allocs) hipFree(p);
+  for (auto &w : c->ws)
+    for (void *p : w.allocs) hipFree(p);
+  for (int i = 0; i < 2; ++i) {
+    if (c->lane[i]) hipStreamDestroy(c->lane[i]);
+    if (c->ev_join[i]) hipEventDestroy(c->ev_join[i]);
+  }
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
   for (void *p : c->allocs) hipFree(p);
   delete c;
 }
@@ -173,23 +179,35 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
   return P;
 }
 
+// P^-1 y for right-hand sides [0, R), split over the stream lanes
+static void precond_split(pfft_ctx *c, Precond *P, int R, const double2 *y, double2 *z, hipStream_t st) {
+  const size_t l = c->m.l, nu = P->ps.nu;
+  c->run_split(R, st, [&](int r0, int rn, hipStream_t s2, Workspace &) {
+    precond_apply(P->dev, P->d_fidx + r0, y + r0 * l, z + r0 * l, P->d_work + r0 * nu, rn, s2);
+  });
+}
+
 pfft_status pfft_internal_precond_matvec(pfft_ctx *c, int R, const double *omega, int flags, const double2 *x,
                                          double2 *y, hipStream_t st) {
   Precond *P = precond_prepare(c, R, omega, st);
+  const size_t l = c->m.l, nu = P->ps.nu;
   if (flags & PFFT_LEARNED_ONLY) {
     c->timer.begin(ST_PRECOND, st);
     if (!learned_apply(c, R, omega, x, y, nullptr, st)) precond_apply(P->dev, P->d_fidx, x, y, P->d_work, R, st);
     c->timer.end(st);
   } else if (flags & PFFT_PRECOND_ONLY) {
     c->timer.begin(ST_PRECOND, st);
-    precond_apply(P->dev, P->d_fidx, x, y, P->d_work, R, st);
+    precond_split(c, P, R, x, y, st);
     c->timer.end(st);
   } else {
-    // Z_l x into y, then P^-1 through the preconditioner scratch
-    c->matvec(R, omega, 1, flags & (PFFT_FAR_ONLY | PFFT_NEAR_ONLY), x, P->d_tmp, st);
-    c->timer.begin(ST_PRECOND, st);
-    precond_apply(P->dev, P->d_fidx, P->d_tmp, y, P->d_work, R, st);
-    c->timer.end(st);
+    // Z_l x into the preconditioner scratch, then P^-1, per stream lane
+    const int mf = flags & (PFFT_FAR_ONLY | PFFT_NEAR_ONLY);
+    c->run_split(R, st, [&](int r0, int rn, hipStream_t s2, Workspace &w) {
+      c->matvec_range(w, rn, omega + r0, 1, mf, x + r0 * l, P->d_tmp + r0 * l, s2);
+      c->timer.begin(ST_PRECOND, s2);
+      precond_apply(P->dev, P->d_fidx + r0, P->d_tmp + r0 * l, y + r0 * l, P->d_work + r0 * nu, rn, s2);
+      c->timer.end(s2);
+    });
   }
   hip_ok(hipGetLastError(), "precond launch");
   return PFFT_OK;
@@ -415,7 +433,7 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
   hipStream_t cs = nullptr;
   hipGraphExec_t g_pre = nullptr, g_mv = nullptr;
   bool want_graphs = c->plans.graphs && !c->timer.on && c->chunk_for(R) >= R;
-  auto run_pre = [&](hipStream_t s2) { precond_apply(P->dev, P->d_fidx, F.w, F.Ax, P->d_work, R, s2); };
+  auto run_pre = [&](hipStream_t s2) { precond_split(c, P, R, F.w, F.Ax, s2); };
   auto run_mv = [&](hipStream_t s2) { c->matvec(R, omega, 1, 0, F.Ax, F.w, s2); };
   auto capture = [&](auto &&fn, hipGraphExec_t &exec) {
     hipGraph_t gr = nullptr;

@@ -64,18 +64,40 @@ def test_plans_agree_and_autotune(wires):
     om = 2 * np.pi * np.array([1e9, 1e10])
     x = torch.from_numpy(W.complex_normal(31, (2, l))).cuda()
     ref = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
-    for name in ("fft_plan", "ldl_plan", "project_plan"):
-        ctx.set_option(name, 1)
+    for name in ("fft_plan", "ldl_plan", "project_plan", "stream_split"):
+        ctx.set_option(name, 1 - ctx.get_option(name))
         y = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
-        ctx.set_option(name, 0)
+        ctx.set_option(name, 1 - ctx.get_option(name))
         assert np.linalg.norm(y - ref) <= 2e-6 * np.linalg.norm(ref), name
     rep = ctx.autotune(om, reps=2)
-    for name in ("fft_plan", "ldl_plan", "project_plan"):
+    for name in ("fft_plan", "ldl_plan", "project_plan", "stream_split"):
         assert rep[name]["chosen"] in (0, 1)
         assert ctx.get_option(name) == rep[name]["chosen"]
         assert rep[name]["0"] > 0 and rep[name]["1"] > 0
     y = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
     assert np.linalg.norm(y - ref) <= 2e-6 * np.linalg.norm(ref)
+
+
+@gpu
+def test_stream_split_matches_one_stream(wires):
+    """The right-hand sides of a product split over two streams give the same
+    result bit for bit (every kernel treats right-hand sides independently)."""
+    import paper_2210_04891_amd as P
+    ctx = _ctx(wires)
+    l = ctx.sizes["l"]
+    om = 2 * np.pi * np.repeat(np.array([1e8, 1e9, 1e10, 3e10]), 3)
+    x = torch.from_numpy(W.complex_normal(41, (om.size, l))).cuda()
+    assert ctx.get_option("stream_split") == 0
+    ctx.set_option("stream_split", 1)
+    a = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
+    ctx.set_option("stream_split", 0)
+    b = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
+    assert np.array_equal(a, b)
+    f = np.array([2e9, 2e10])
+    Y0, it0, _, _ = ctx.solve_ports(f, tol=1e-7, maxit=200, restart=60)
+    ctx.set_option("stream_split", 1)
+    Y1, it1, _, _ = ctx.solve_ports(f, tol=1e-7, maxit=200, restart=60)
+    assert np.array_equal(Y0, Y1) and np.array_equal(it0, it1)
 
 
 @gpu
