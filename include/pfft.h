@@ -218,12 +218,12 @@ pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const 
  *   "graphs"       1 solve_ports replays the product and P^-1 of each FGMRES
  *                    iteration as HIP graphs (after one eager iteration),
  *                  0 eager launches
- *   "stream_split" 1 (default) the right-hand sides of a product (and of
- *                    P^-1) are split into two halves run on two streams of
- *                    the context, forked from and joined to the caller's
- *                    stream with events, so latency-bound kernels of one half
- *                    overlap bandwidth-bound kernels of the other (not while
- *                    profiling); 0 (default) one stream
+ *   "stream_split" 1 the right-hand sides of a product (and of P^-1) are
+ *                    split into two halves run on two streams of the
+ *                    context, forked from and joined to the caller's stream
+ *                    with events, so kernels of one half can overlap those
+ *                    of the other (not while profiling); 0 (default) one
+ *                    stream
  * PFFT_EINVAL for an unknown name or value. */
 pfft_status pfft_set_option(pfft_ctx *c, const char *name, int64_t value);
 pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *value);
