@@ -119,6 +119,19 @@ pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, doubl
                         int32_t maxit, int32_t restart, int32_t precond, void *Y_out,
                         int32_t *iters_out, double *relres_out, void *hip_stream);
 
+/* The solver form of Sec. IV-A (Eq. LoopWithP): GMRES on the left-preconditioned
+ * system P^-1 A Z_b A^T I_l = P^-1 V_l for every (frequency, port), restart
+ * `restart`, x0 = 0.  tol applies to the preconditioned relative residual
+ * |P^-1 (V_l - Z_l I_l)| / |P^-1 V_l| (the quantity left-preconditioned GMRES
+ * minimises; Sec. V reports iteration counts at 1e-3), and relres_out
+ * receives that quantity.  precond: 0 none (plain GMRES, the same iteration
+ * as solve_ports with precond 0), 1 the paper's P; the learned correction
+ * (2) is rejected with PFFT_EINVAL, since a left preconditioner must be a
+ * fixed operator.  Arguments, layouts and errors otherwise as solve_ports. */
+pfft_status solve_ports_lgmres(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol,
+                               int32_t maxit, int32_t restart, int32_t precond, void *Y_out,
+                               int32_t *iters_out, double *relres_out, void *hip_stream);
+
 /* Z = Y^-1, R = Re Z, L = Im Z / omega per frequency (Sec. V).  Y: host
  * complex128 [nfreq][nport][nport]; R_out, L_out: host [nfreq][nport][nport].
  * Pure host function; no context.  PFFT_EINVAL if some Y is singular. */

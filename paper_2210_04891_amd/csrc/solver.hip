@@ -401,6 +401,10 @@ struct Fgmres {
 
 // Solves Z_l(omega_r) x_r = b_r for all r; b is already in F.b.  precond: 0,
 // 1 (P), 2 (P + learned).  Returns per-RHS iterations and true residuals.
+// left: GMRES on P^-1 Z_l x = P^-1 b (precond 0 or 1): the basis vectors are
+// the update directions (Z holds copies of V), every Arnoldi step is a product
+// followed by P^-1, and the residual that is estimated, tested and reported
+// is the preconditioned one, relative to |P^-1 b|.
 // rec (optional) receives, for the first cycle, each RHS's Krylov length and
 // residual estimates |g_{k+1}| after every step.
 struct FirstCycle {
@@ -410,9 +414,10 @@ struct FirstCycle {
 };
 static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int maxit, int precond,
                    std::vector<int> &iters, std::vector<double> &relres, hipStream_t st,
-                   FirstCycle *rec = nullptr) {
+                   FirstCycle *rec = nullptr, bool left = false) {
   const int R = F.R, l = F.l, m = F.m;
   const dim3 gl((l + 255) / 256, R);
+  if (precond != 1) left = false;   // without P both forms are plain GMRES
   Precond *P = precond ? precond_prepare(c, R, omega, st) : nullptr;
   hip_ok(hipMemsetAsync(F.x, 0, (size_t)R * l * sizeof(double2), st), "x0");
   iters.assign(R, 0);
@@ -433,8 +438,29 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
   hipStream_t cs = nullptr;
   hipGraphExec_t g_pre = nullptr, g_mv = nullptr;
   bool want_graphs = c->plans.graphs && !c->timer.on && c->chunk_for(R) >= R;
-  auto run_pre = [&](hipStream_t s2) { precond_split(c, P, R, F.w, F.Ax, s2); };
-  auto run_mv = [&](hipStream_t s2) { c->matvec(R, omega, 1, 0, F.Ax, F.w, s2); };
+  // right: w -> P^-1 -> Ax -> Z_l -> w;  left: w -> Z_l -> Ax -> P^-1 -> w
+  auto run_pre = [&](hipStream_t s2) {
+    if (left)
+      precond_split(c, P, R, F.Ax, F.w, s2);
+    else
+      precond_split(c, P, R, F.w, F.Ax, s2);
+  };
+  auto run_mv = [&](hipStream_t s2) {
+    if (left)
+      c->matvec(R, omega, 1, 0, F.w, F.Ax, s2);
+    else
+      c->matvec(R, omega, 1, 0, F.Ax, F.w, s2);
+  };
+  const size_t vbytes = (size_t)R * l * sizeof(double2);
+  // left: P^-1 applied to a residual in w (through Ax, back into w)
+  auto left_precond_w = [&]() {
+    if (!precond) return;
+    hip_ok(hipMemcpyAsync(F.Ax, F.w, vbytes, hipMemcpyDeviceToDevice, st), "left residual");
+    if (g_pre)
+      hip_ok(hipGraphLaunch(g_pre, st), "graph launch");
+    else
+      run_pre(st);
+  };
   auto capture = [&](auto &&fn, hipGraphExec_t &exec) {
     hipGraph_t gr = nullptr;
     hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -457,8 +483,11 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
     g_pre = g_mv = nullptr;
     cs = nullptr;
   };
-  // |b|
-  k_mdot<<<dim3(1, R), 256, 0, st>>>(F.b, F.b, F.nrm, l, 1, 1, 1, nullptr);
+  // residual r0 = b (x0 = 0) in w; left: P^-1 b
+  hip_ok(hipMemcpyAsync(F.w, F.b, vbytes, hipMemcpyDeviceToDevice, st), "r0");
+  if (left) left_precond_w();
+  // |b| (left: |P^-1 b|)
+  k_mdot<<<dim3(1, R), 256, 0, st>>>(F.w, F.w, F.nrm, l, 1, 1, 1, nullptr);
   {
     std::vector<double2> n2(R);
     hip_ok(hipMemcpyAsync(n2.data(), F.nrm, R * sizeof(double2), hipMemcpyDeviceToHost, st), "bnorm");
@@ -466,8 +495,6 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
     for (int r = 0; r < R; ++r) bnorm[r] = std::sqrt(std::max(n2[r].x, 0.0));
   }
   int total = 0;
-  // residual r0 = b (x0 = 0) in w
-  hip_ok(hipMemcpyAsync(F.w, F.b, (size_t)R * l * sizeof(double2), hipMemcpyDeviceToDevice, st), "r0");
   if (rec) {
     rec->k.assign(R, 0);
     rec->res.assign(R, {});
@@ -488,7 +515,9 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
                               l * sizeof(double2), R, hipMemcpyDeviceToDevice, st),
              "gather v");
       double2 *zk = F.Ax;  // contiguous [R][l]
-      if (precond == 2 && learned_apply(c, R, omega, F.w, zk, use_l.data(), st)) {
+      if (left) {
+        zk = F.w;          // the update direction is v_k itself
+      } else if (precond == 2 && learned_apply(c, R, omega, F.w, zk, use_l.data(), st)) {
       } else if (precond) {
         if (g_pre)
           hip_ok(hipGraphLaunch(g_pre, st), "graph launch");
@@ -500,11 +529,17 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
       hip_ok(hipMemcpy2DAsync(F.Z + (size_t)k * l, m * l * sizeof(double2), zk, l * sizeof(double2),
                               l * sizeof(double2), R, hipMemcpyDeviceToDevice, st),
              "store z");
-      // w = Z_l z_k
+      // w = Z_l z_k  (left: w = P^-1 Z_l v_k)
       if (g_mv)
         hip_ok(hipGraphLaunch(g_mv, st), "graph launch");
       else
         run_mv(st);
+      if (left && precond) {
+        if (g_pre)
+          hip_ok(hipGraphLaunch(g_pre, st), "graph launch");
+        else
+          run_pre(st);
+      }
       if (want_graphs && !g_mv) {
         want_graphs = false;
         try {
@@ -570,6 +605,7 @@ static void fgmres(pfft_ctx *c, Fgmres &F, const double *omega, double tol, int 
     // true residual: restart vector, convergence test and the reported residual
     c->matvec(R, omega, 1, 0, F.x, F.Ax, st);
     k_residual<<<(unsigned)(((size_t)R * l + 255) / 256), 256, 0, st>>>(F.b, F.Ax, F.w, R * l);
+    if (left) left_precond_w();
     k_mdot<<<dim3(1, R), 256, 0, st>>>(F.w, F.w, F.nrm, l, 1, 1, 1, nullptr);
     {
       std::vector<double2> t2(R);
@@ -639,23 +675,23 @@ void pfft::solve_ports_krylov(pfft_ctx *c, int nfreq, const double *freq_hz, dou
   hip_ok(hipStreamSynchronize(st), "krylov sync");
 }
 
-extern "C" {
-
-pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol, int32_t maxit,
-                        int32_t restart, int32_t precond, void *Y_out, int32_t *iters_out, double *relres_out,
-                        void *hip_stream) {
+static pfft_status solve_ports_any(const char *name, bool left, pfft_ctx *c, int32_t nfreq,
+                                   const double *freq_hz, double tol, int32_t maxit, int32_t restart,
+                                   int32_t precond, void *Y_out, int32_t *iters_out, double *relres_out,
+                                   void *hip_stream) {
+  const std::string who = std::string(name) + ": ";
   if (!c || nfreq <= 0 || !freq_hz || !Y_out || !(tol > 0) || maxit <= 0 || restart <= 0 || precond < 0 ||
-      precond > 2) {
-    set_error("solve_ports: bad argument");
+      precond > (left ? 1 : 2)) {
+    set_error(who + "bad argument");
     return PFFT_EINVAL;
   }
   if (c->m.p == 0) {
-    set_error("solve_ports: the problem has no ports");
+    set_error(who + "the problem has no ports");
     return PFFT_EINVAL;
   }
   for (int f = 0; f < nfreq; ++f)
     if (!(freq_hz[f] > 0)) {
-      set_error("solve_ports: frequencies must be positive");
+      set_error(who + "frequencies must be positive");
       return PFFT_EINVAL;
     }
   try {
@@ -670,7 +706,7 @@ pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, doubl
     hip_ok(hipMemcpyAsync(F.b, bh.data(), bh.size() * sizeof(double2), hipMemcpyHostToDevice, st), "b");
     std::vector<int> iters;
     std::vector<double> relres;
-    fgmres(c, F, omega.data(), tol, maxit, precond, iters, relres, st);
+    fgmres(c, F, omega.data(), tol, maxit, precond, iters, relres, st, nullptr, left);
     std::vector<double2> xh((size_t)R * l);
     hip_ok(hipMemcpyAsync(xh.data(), F.x, xh.size() * sizeof(double2), hipMemcpyDeviceToHost, st), "x");
     hip_ok(hipStreamSynchronize(st), "x sync");
@@ -685,17 +721,33 @@ pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, doubl
         ok = ok && relres[r] <= tol * 1.0001 + 1e-15;
       }
     if (!ok) {
-      set_error("solve_ports: some right-hand sides did not reach the tolerance");
+      set_error(who + "some right-hand sides did not reach the tolerance");
       return PFFT_ENOCONV;
     }
     return PFFT_OK;
   } catch (const DeviceError &e) {
-    set_error("solve_ports: " + e.msg);
+    set_error(who + e.msg);
     return (pfft_status)e.code;
   } catch (const SetupError &e) {
-    set_error("solve_ports: " + e.msg);
+    set_error(who + e.msg);
     return (pfft_status)e.code;
   }
+}
+
+extern "C" {
+
+pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol, int32_t maxit,
+                        int32_t restart, int32_t precond, void *Y_out, int32_t *iters_out, double *relres_out,
+                        void *hip_stream) {
+  return solve_ports_any("solve_ports", false, c, nfreq, freq_hz, tol, maxit, restart, precond, Y_out, iters_out,
+                         relres_out, hip_stream);
+}
+
+pfft_status solve_ports_lgmres(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol, int32_t maxit,
+                               int32_t restart, int32_t precond, void *Y_out, int32_t *iters_out,
+                               double *relres_out, void *hip_stream) {
+  return solve_ports_any("solve_ports_lgmres", true, c, nfreq, freq_hz, tol, maxit, restart, precond, Y_out,
+                         iters_out, relres_out, hip_stream);
 }
 
 }  // extern "C"

@@ -28,7 +28,7 @@ EXPORTS = ("pfft_setup", "pfft_sizes", "pfft_matvec", "solve_ports", "extract_RL
            "pfft_host_setup", "pfft_host_get", "pfft_host_free", "pfft_profile",
            "pfft_stage_times", "pfft_precond_save", "pfft_learned_collect", "pfft_learned_train",
            "pfft_learned_clear", "pfft_learned_stats", "pfft_mlp_grad", "pfft_learned_eval",
-           "pfft_set_option", "pfft_get_option", "pfft_autotune")
+           "pfft_set_option", "pfft_get_option", "pfft_autotune", "solve_ports_lgmres")
 
 STAGES = ("loop_to_branch", "tri_current", "project", "fft_x", "fft_y", "fft_z_conv", "ifft_y",
           "ifft_x", "interp", "combine", "branch_to_loop", "precond")
@@ -73,6 +73,8 @@ def load():
     lib.pfft_matvec.restype = i32
     lib.solve_ports.argtypes = [vp, i32, vp, dbl, i32, i32, i32, vp, vp, vp, vp]
     lib.solve_ports.restype = i32
+    lib.solve_ports_lgmres.argtypes = [vp, i32, vp, dbl, i32, i32, i32, vp, vp, vp, vp]
+    lib.solve_ports_lgmres.restype = i32
     lib.extract_RL.argtypes = [i32, i32, vp, vp, vp, vp]
     lib.extract_RL.restype = i32
     lib.pfft_precond_load.argtypes = [vp, vp, i64]
@@ -237,14 +239,23 @@ class Context:
         return y
 
     def solve_ports(self, freqs_hz, tol=1e-6, maxit=500, restart=60, precond=1, stream=None):
-        """Returns (Y [nf, p, p] complex128, iterations [nf, p], relres [nf, p], status)."""
+        """Right-preconditioned FGMRES.  Returns (Y [nf, p, p] complex128,
+        iterations [nf, p], relres [nf, p], status)."""
+        return self._solve(load().solve_ports, freqs_hz, tol, maxit, restart, precond, stream)
+
+    def solve_ports_lgmres(self, freqs_hz, tol=1e-3, maxit=500, restart=60, precond=1, stream=None):
+        """Left-preconditioned GMRES (relres is the preconditioned residual).
+        Returns as solve_ports."""
+        return self._solve(load().solve_ports_lgmres, freqs_hz, tol, maxit, restart, precond, stream)
+
+    def _solve(self, fn, freqs_hz, tol, maxit, restart, precond, stream):
         f = np.ascontiguousarray(np.asarray(freqs_hz, np.float64).reshape(-1))
         nf, p = f.size, self.nport
         Y = np.zeros((nf, p, p), np.complex128)
         it = np.zeros((nf, p), np.int32)
         rr = np.zeros((nf, p), np.float64)
-        code = _check(load().solve_ports(self._h, nf, _ptr(f), tol, maxit, restart, precond,
-                                         _ptr(Y), _ptr(it), _ptr(rr), _stream_handle(stream)),
+        code = _check(fn(self._h, nf, _ptr(f), tol, maxit, restart, precond,
+                         _ptr(Y), _ptr(it), _ptr(rr), _stream_handle(stream)),
                       allow=(-5,))
         return Y, it, rr, code
 

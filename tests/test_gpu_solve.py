@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from systems import oracle_system
 
 torch = pytest.importorskip("torch")
 gpu = pytest.mark.gpu
@@ -20,35 +21,16 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
 
 
-def _oracle_system(s, K=None):
-    from oracle.mesh import RWGMesh, gram_matrix
-    from oracle.circuit import Circuit
-    from oracle import integrals as I, solve as S
-    m = RWGMesh(s.V, s.T)
-    c = Circuit(m, s.ports)
-    if K is None:
-        K = I.kernel_dense(m)
-    A = c.loop_matrix().toarray()
-    G = gram_matrix(m, weight=S.triangle_impedance(m, c, 1.0).real).toarray()
-
-    def Zb(omega):
-        zs = S.surface_impedance(omega, 5.8e7)
-        Z = np.zeros((m.nedge + c.nport,) * 2, complex)
-        Z[:m.nedge, :m.nedge] = zs * G + 1j * omega * S.MU0 / (4 * np.pi) * K
-        return Z
-    return m, c, K, A, Zb
-
-
 @pytest.fixture(scope="module")
 def two_wires():
     s = W.bond_wires(nwire=2, nseg=24, span=0.4e-3, height=80e-6)
-    return (s,) + _oracle_system(s)
+    return (s,) + oracle_system(s)
 
 
 @pytest.fixture(scope="module")
 def e1_bar():
     s = W.paper_bar_e1()
-    return (s,) + _oracle_system(s)
+    return (s,) + oracle_system(s)
 
 
 @gpu
@@ -93,7 +75,7 @@ def test_solve_ports_config1_matches_oracle(c1):
     import paper_2210_04891_amd as P
     from oracle import solve as S
     s, m, c, K = c1["s"], c1["mesh"], c1["circ"], c1["K"]
-    _, _, _, A, Zb = _oracle_system(s, K)
+    _, _, _, A, Zb = oracle_system(s, K)
     f = np.array([1e9])
     ctx = P.Context(s, (64, 8, 8), near_kappa=1.5, grid_fp64=True)
     Y, it, rr, code = ctx.solve_ports(f, tol=1e-6, maxit=200, restart=60, precond=1)
@@ -117,7 +99,7 @@ def test_solve_ports_matches_oracle_pfft_operator(e1_bar):
     grid = (32, 8, 8)
     op = PF.PFFTOperator(m, grid, 4, 1.5)
     Kp = np.stack([op.apply(col) for col in np.eye(m.nedge)], axis=1).real
-    _, _, _, _, Zbp = _oracle_system(s, Kp)
+    _, _, _, _, Zbp = oracle_system(s, Kp)
     f = np.array([2e10, 1e11])
     ctx = P.Context(s, grid, near_kappa=1.5, grid_fp64=True)
     Y, it, rr, code = ctx.solve_ports(f, tol=1e-7, maxit=300, restart=50, precond=1)

@@ -129,3 +129,39 @@ def test_surface_impedance_principal_root():
     zs = S.surface_impedance(om, SIGMA)
     assert zs * zs == pytest.approx(1j * om * S.MU0 / SIGMA, rel=1e-14)
     assert zs.real > 0 and zs.imag == pytest.approx(zs.real)
+
+
+@pytest.mark.parametrize("right", [True, False])
+def test_gmres_terminates_on_distinct_eigenvalues(right):
+    """A diagonalisable matrix with k distinct eigenvalues has a minimal
+    polynomial of degree k, so (full) GMRES reaches the exact solution in k
+    steps whatever b is; the residual history never increases."""
+    rng = np.random.default_rng(3)
+    n, k = 40, 5
+    lam = np.array([1.0, 2.0 + 1j, -3.0, 0.5j, 4.0 - 2j])
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))
+    D = lam[np.arange(n) % k]
+    Am = (Q * D) @ Q.conj().T
+    b = rng.normal(size=n) + 1j * rng.normal(size=n)
+    x, it, hist = S.gmres(lambda v: Am @ v, b, None, tol=1e-12, restart=n, right=right)
+    assert it == k
+    assert np.all(np.diff(hist) <= 1e-14)
+    assert np.linalg.norm(Am @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_left_gmres_monitors_preconditioned_residual():
+    """Left preconditioning (Eq. LoopWithP): the stopping quantity is
+    |M (b - A x)| / |M b|, recomputed here from the returned iterate; with M
+    the exact inverse the first step solves the system."""
+    rng = np.random.default_rng(5)
+    n = 30
+    Am = np.eye(n) * 4 + rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    Md = np.diag(1.0 / np.diag(Am))
+    b = rng.normal(size=n) + 0j
+    x, it, hist = S.gmres(lambda v: Am @ v, b, lambda v: Md @ v, tol=1e-3, restart=n, right=False)
+    pres = np.linalg.norm(Md @ (b - Am @ x)) / np.linalg.norm(Md @ b)
+    assert hist[-1] <= 1e-3 and pres == pytest.approx(hist[-1], rel=1e-8)
+    assert len(hist) == it and (it == 1 or hist[-2] > 1e-3)
+    Ainv = np.linalg.inv(Am)
+    x1, it1, _ = S.gmres(lambda v: Am @ v, b, lambda v: Ainv @ v, tol=1e-10, restart=n, right=False)
+    assert it1 == 1 and np.linalg.norm(x1 - Ainv @ b) <= 1e-10 * np.linalg.norm(x1)
