@@ -132,6 +132,36 @@ pfft_status solve_ports_lgmres(pfft_ctx *c, int32_t nfreq, const double *freq_hz
                                int32_t maxit, int32_t restart, int32_t precond, void *Y_out,
                                int32_t *iters_out, double *relres_out, void *hip_stream);
 
+/* solve_ports that also keeps the solution: Il_dev (device, caller-owned)
+ * receives the loop currents I_l, complex128 [nfreq][nport][l] (row f*nport + k
+ * is frequency f with port k driven at 1 V), for pfft_postprocess. */
+pfft_status solve_ports_loops(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol,
+                              int32_t maxit, int32_t restart, int32_t precond, void *Y_out,
+                              int32_t *iters_out, double *relres_out, void *Il_dev, void *hip_stream);
+
+/* Post-processing of loop currents (Sec. V-A) for nrhs right-hand sides at
+ * omega[nrhs] (host, rad/s).  Il_dev: device complex128 [nrhs][l] loop
+ * currents.  Outputs (device, caller-owned, complex128, RHS-major; each may be
+ * NULL):
+ *   Vl_dev  [nrhs][l]    loop voltages Z_l I_l (Eq. LoopVandI; equal to the
+ *                        excitation up to the solve's residual)
+ *   Ib_dev  [nrhs][b+p]  branch currents A^T I_l (Eq. CurT): mesh edges in
+ *                        edge order, then port k's source branch (sink face
+ *                        to source face)
+ *   Vb_dev  [nrhs][b]    mesh-branch voltages Z_b I_b (Eq. BranchVandI), the
+ *                        T+ potential minus the T- potential (Eq. Vb)
+ *   J_dev   [nrhs][n][3] surface current density at each triangle's centroid
+ *                        (A/m), sum of I_e f_e (Eqs. ExpandJ, RWG)
+ *   phi_dev [nrhs][n]    panel potentials (V): each conductor's reference
+ *                        node (the sink face of its lowest-numbered port,
+ *                        else its lowest triangle's node) at 0 V, every other
+ *                        node by summing branch voltages along the spanning
+ *                        tree; a contact face is one node.
+ * Uses the same pFFT product as pfft_matvec (and its workspace). */
+pfft_status pfft_postprocess(pfft_ctx *c, int32_t nrhs, const double *omega, const void *Il_dev,
+                             void *Vl_dev, void *Ib_dev, void *Vb_dev, void *J_dev, void *phi_dev,
+                             void *hip_stream);
+
 /* Z = Y^-1, R = Re Z, L = Im Z / omega per frequency (Sec. V).  Y: host
  * complex128 [nfreq][nport][nport]; R_out, L_out: host [nfreq][nport][nport].
  * Pure host function; no context.  PFFT_EINVAL if some Y is singular. */
@@ -237,13 +267,22 @@ pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const 
  *                    with events, so kernels of one half can overlap those
  *                    of the other (not while profiling); 0 (default) one
  *                    stream
+ *   "combine_plan" 0 near-field product over row tiles with the tile's
+ *                    columns of x staged in LDS (when every tile's column list
+ *                    fits), 1 per-nonzero gathers from memory
+ *   "factor_plan"  0 (default) the LDL^T factors of the nodal matrix of P
+ *                    (one per distinct frequency) are computed on the device,
+ *                    one workgroup per conductor and frequency, when no
+ *                    conductor carries more than 4 ports; 1 on the host
+ *                    (OpenMP over frequencies).  Changing it refactors at the
+ *                    next use of P.
  * PFFT_EINVAL for an unknown name or value. */
 pfft_status pfft_set_option(pfft_ctx *c, const char *name, int64_t value);
 pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *value);
 
 /* Times the preconditioned product P^-1 Z_l x (one FGMRES step) for nrhs
  * right-hand sides at omega[nrhs] (host, rad/s) for each value of fft_plan,
- * ldl_plan, project_plan and stream_split in turn (median of reps runs after one warm-up),
+ * ldl_plan, project_plan, combine_plan and stream_split in turn (median of reps runs after one warm-up),
  * keeps the fastest value of each and writes a JSON report of the timings
  * (milliseconds) and choices into report[cap] (host, NUL-terminated, may be
  * NULL).  Allocates two nrhs x l complex128 device vectors for the run. */

@@ -79,6 +79,8 @@ struct pfft_ctx {
     int proj = 0;     // 0 tiled projection, 1 node-major gather
     int graphs = 1;   // 1 FGMRES replays the product and P^-1 as HIP graphs
     int stream_split = 0;  // 1: the right-hand sides of a product are split over two streams
+    int factor = 0;   // 0 preconditioner factored on the device, 1 on the host
+    int comb = 0;     // 0 LDS-tiled near-field product when the tiles fit, 1 gather
   } plans;
   pfft::StageTimer timer;
   // solver state
@@ -93,8 +95,12 @@ struct pfft_ctx {
   void matvec(int R, const double *omega, int space, int flags, const double2 *x, double2 *y,
               hipStream_t st);
   // op for right-hand sides [0, R) of x/y/omega on stream st with workspace w
+  // post (loop space only, optional): also writes the post-processing
+  // outputs of x taken as loop currents (rows offset by the chunk)
   void matvec_range(pfft::Workspace &w, int R, const double *omega, int space, int flags, const double2 *x,
-                    double2 *y, hipStream_t st);
+                    double2 *y, hipStream_t st, const pfft::PostOut *post = nullptr);
+  // device maps of the post-processing (built on first use)
+  int *d_tri_pos = nullptr, *d_tri_ref = nullptr, *d_port_loop = nullptr;
   // Runs fn(r0, rn, stream, workspace) for the right-hand sides [0, R),
   // split over the two stream lanes when enabled (not while profiling).
   template <typename Fn> void run_split(int R, hipStream_t st, Fn &&fn);

@@ -133,7 +133,7 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
 }
 
 void pfft_ctx::matvec_range(Workspace &w, int R, const double *omega, int space, int flags, const double2 *x,
-                            double2 *y, hipStream_t st) {
+                            double2 *y, hipStream_t st, const PostOut *post) {
   const int dim = space == 1 ? m.l : m.b;
   const int Rc = chunk_for(R);
   ensure_workspace(w, Rc);
@@ -200,6 +200,14 @@ void pfft_ctx::matvec_range(Workspace &w, int R, const double *omega, int space,
       combine(cm, alpha, w.U, zs, jw, w.yb, Rn, mode, st);
       timer.begin(ST_BRANCH_TO_LOOP, st);
       branch_to_loop(lm, w.yb, yc, w.scan, w.part, Rn, st);
+      if (post) {
+        PostOut o = *post;
+        if (o.Ib) o.Ib += (size_t)r0 * (m.b + m.p);
+        if (o.Vb) o.Vb += (size_t)r0 * m.b;
+        if (o.J) o.J += (size_t)r0 * m.n * 3;
+        if (o.phi) o.phi += (size_t)r0 * m.n;
+        post_outputs(gm, lm, o, xc, alpha, w.yb, w.scan, Rn, st);
+      }
     } else {
       timer.begin(ST_COMBINE, st);
       combine(cm, alpha, w.U, zs, jw, w.yb, Rn, mode, st);
@@ -389,13 +397,86 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
         pg_loc[q] = (int)(it - b0);
       }
     }
+    // nodes of each tile by descending gather length (ties by local index)
+    const int TN = TX * TY * TZ;
+    std::vector<uint16_t> tn_perm((size_t)ntile * TN);
+    {
+      std::vector<std::pair<int, int>> key(TN);
+      for (long T = 0; T < ntile; ++T) {
+        const int tz = (int)(T % nt3[2]), ty = (int)((T / nt3[2]) % nt3[1]), tx = (int)(T / ((long)nt3[2] * nt3[1]));
+        for (int u = 0; u < TN; ++u) {
+          const int iz = u % TZ, iy = (u / TZ) % TY, ix = u / (TZ * TY);
+          const int x = tx * TX + ix, y = ty * TY + iy, z = tz * TZ + iz;
+          int len = -1;
+          if (x < m.dims[0] && y < m.dims[1] && z < m.dims[2]) {
+            const long node = ((long)x * m.dims[1] + y) * m.dims[2] + z;
+            len = pg_off[node + 1] - pg_off[node];
+          }
+          key[u] = {-len, u};
+        }
+        std::sort(key.begin(), key.end());
+        for (int u = 0; u < TN; ++u) tn_perm[(size_t)T * TN + u] = (uint16_t)key[u].second;
+      }
+    }
     for (int d = 0; d < 3; ++d) {
       g.tile[d] = T3[d];
       g.ntile[d] = nt3[d];
     }
+    g.tn_perm = upload(c, tn_perm, st);
     // LDS: tcap triangles x 4 (FP32) or 2 (FP64) right-hand sides x 4 moments
-    // (48 KB: three 512-thread workgroups per CU)
-    g.tcap = 384;
+    // at a 144-byte pitch (53 KB: three 512-thread workgroups per CU)
+    g.tcap = 376;
+    // sliced gather lists in the tile's node order
+    {
+      const int nwave = (TN + 63) / 64;
+      const size_t ns_ = (size_t)ntile * nwave;
+      std::vector<int> ps_off(ns_ + 1, 0), ps_k(ns_, 0);
+      auto node_at = [&](long T, int u) -> long {
+        const int tz = (int)(T % nt3[2]), ty = (int)((T / nt3[2]) % nt3[1]), tx = (int)(T / ((long)nt3[2] * nt3[1]));
+        const int v = tn_perm[(size_t)T * TN + u];
+        const int iz = v % TZ, iy = (v / TZ) % TY, ix = v / (TZ * TY);
+        const int x = tx * TX + ix, y = ty * TY + iy, z = tz * TZ + iz;
+        if (x >= m.dims[0] || y >= m.dims[1] || z >= m.dims[2]) return -1;
+        return ((long)x * m.dims[1] + y) * m.dims[2] + z;
+      };
+      for (long T = 0; T < ntile; ++T)
+        for (int w = 0; w < nwave; ++w) {
+          int K = 0;
+          for (int ln = 0; ln < 64 && w * 64 + ln < TN; ++ln) {
+            const long node = node_at(T, w * 64 + ln);
+            if (node >= 0) K = std::max(K, pg_off[node + 1] - pg_off[node]);
+          }
+          const size_t sidx = (size_t)T * nwave + w;
+          ps_k[sidx] = K;
+          ps_off[sidx + 1] = ps_off[sidx] + 64 * K;
+        }
+      std::vector<int> ps_ent(ps_off[ns_], 0);
+      std::vector<double> ps_w(4 * (size_t)ps_off[ns_], 0.0);
+      for (long T = 0; T < ntile; ++T)
+        for (int w = 0; w < nwave; ++w) {
+          const size_t sidx = (size_t)T * nwave + w;
+          for (int ln = 0; ln < 64 && w * 64 + ln < TN; ++ln) {
+            const long node = node_at(T, w * 64 + ln);
+            if (node < 0) continue;
+            for (int k = 0; k < pg_off[node + 1] - pg_off[node]; ++k) {
+              const int q = pg_off[node] + k;
+              const size_t at = (size_t)ps_off[sidx] + 64 * (size_t)k + ln;
+              ps_ent[at] = pg_loc[q] < g.tcap ? pg_loc[q] : -1 - pg_tri[q];
+              for (int cc = 0; cc < 4; ++cc) ps_w[4 * at + cc] = pg_w[4 * (size_t)q + cc];
+            }
+          }
+        }
+      g.nwave = nwave;
+      g.ps_off = upload(c, ps_off, st);
+      g.ps_k = upload(c, ps_k, st);
+      g.ps_ent = upload(c, ps_ent, st);
+      if (c->grid_fp64) {
+        g.ps_w = upload(c, ps_w, st);
+      } else {
+        std::vector<float> a(ps_w.begin(), ps_w.end());
+        g.ps_w = upload(c, a, st);
+      }
+    }
     g.fft_plan = c->plans.fft;
     g.proj_plan = c->plans.proj;
     g.tt_off = upload(c, tt_off, st);
@@ -472,6 +553,53 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
   cm.nf_val = upload(c, m.nf_val, st);
   cm.gram_col = upload(c, m.gram_col, st);
   cm.gram_val = upload(c, m.gram_val, st);
+  // near-field row tiles: the widest tile (rows a power of two, at most 32)
+  // whose column lists all fit the LDS staging area of the tiled product
+  cm.ctile = 0;
+  cm.ctr = 0;
+  cm.cmax = 0;
+  cm.comb_plan = c->plans.comb;
+  cm.crc = 16;
+  for (int trial = 0; trial < 12 && cm.ctile == 0 && b > 0; ++trial) {
+    // 16 right-hand sides per workgroup with rows 32, 16, .. 1; then 8
+    const int rc = trial < 6 ? 16 : 8, tr = 32 >> (trial % 6);
+    const int ucap = combine_tile_cap(rc);
+    const int nt = (b + tr - 1) / tr;
+    std::vector<int> ct_off(nt + 1, 0);
+    std::vector<std::vector<int>> cols(nt);
+    bool fits = true;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int T = 0; T < nt; ++T) {
+      const int64_t q0 = m.nf_rowptr[(size_t)T * tr], q1 = m.nf_rowptr[std::min(b, (T + 1) * tr)];
+      std::vector<int> u(m.nf_col.begin() + q0, m.nf_col.begin() + q1);
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+      cols[T] = std::move(u);
+    }
+    int umax = 0;
+    for (int T = 0; T < nt; ++T) {
+      umax = std::max(umax, (int)cols[T].size());
+      ct_off[T + 1] = ct_off[T] + (int)cols[T].size();
+    }
+    if (umax > ucap) fits = false;
+    if (!fits) continue;
+    cm.crc = rc;
+    std::vector<int> ct_col(ct_off[nt]);
+    std::vector<uint16_t> slot(m.nf_col.size());
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int T = 0; T < nt; ++T) {
+      std::copy(cols[T].begin(), cols[T].end(), ct_col.begin() + ct_off[T]);
+      for (int e = T * tr; e < std::min(b, (T + 1) * tr); ++e)
+        for (int64_t q = m.nf_rowptr[e]; q < m.nf_rowptr[e + 1]; ++q)
+          slot[q] = (uint16_t)(std::lower_bound(cols[T].begin(), cols[T].end(), m.nf_col[q]) - cols[T].begin());
+    }
+    cm.ctr = tr;
+    cm.ctile = nt;
+    cm.cmax = umax;
+    cm.ct_off = upload(c, ct_off, st);
+    cm.ct_col = upload(c, ct_col, st);
+    cm.nf_slot = upload(c, slot, st);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -582,6 +710,69 @@ pfft_status pfft_matvec(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t 
   }
 }
 
+pfft_status pfft_postprocess(pfft_ctx *c, int32_t nrhs, const double *omega, const void *Il_dev, void *Vl_dev,
+                             void *Ib_dev, void *Vb_dev, void *J_dev, void *phi_dev, void *hip_stream) {
+  if (!c || nrhs < 0 || (nrhs > 0 && (!omega || !Il_dev))) {
+    set_error("pfft_postprocess: bad argument");
+    return PFFT_EINVAL;
+  }
+  if (nrhs == 0) return PFFT_OK;
+  double2 *scratch = nullptr;
+  try {
+    hip_ok(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const HostModel &m = c->m;
+    if (!c->d_tri_pos) {
+      // reference node of each conductor: the sink of its lowest-numbered
+      // port, else its root (lowest node)
+      std::vector<int> root(m.nn);
+      for (int k = 0; k < m.nn; ++k) {
+        const int z = m.order[k];   // preorder: a parent precedes its children
+        root[z] = m.parent[z] < 0 ? z : root[m.parent[z]];
+      }
+      std::vector<int> ref(m.nn, -1);
+      for (int k = m.p - 1; k >= 0; --k) ref[root[m.bu[m.b + k]]] = m.bu[m.b + k];
+      std::vector<int> tpos(m.n), tref(m.n);
+      for (int t = 0; t < m.n; ++t) {
+        const int z = m.node_of_tri[t], r = root[z];
+        tpos[t] = m.pre[z];
+        tref[t] = m.pre[ref[r] >= 0 ? ref[r] : r];
+      }
+      c->d_tri_pos = upload(c, tpos, st);
+      c->d_tri_ref = upload(c, tref, st);
+      c->d_port_loop = upload(c, m.port_loop, st);
+    }
+    PostOut o;
+    o.Ib = (double2 *)Ib_dev;
+    o.Vb = (double2 *)Vb_dev;
+    o.J = (double2 *)J_dev;
+    o.phi = (double2 *)phi_dev;
+    o.p = m.p;
+    o.port_loop = c->d_port_loop;
+    o.tri_pos = c->d_tri_pos;
+    o.tri_ref = c->d_tri_ref;
+    double2 *vl = (double2 *)Vl_dev;
+    if (!vl) {
+      hip_ok(hipMalloc(&scratch, (size_t)nrhs * m.l * sizeof(double2)), "hipMalloc post scratch");
+      vl = scratch;
+    }
+    c->matvec_range(c->ws[0], nrhs, omega, 1, 0, (const double2 *)Il_dev, vl, st, &o);
+    if (scratch) {
+      hip_ok(hipStreamSynchronize(st), "post sync");
+      hipFree(scratch);
+    }
+    return PFFT_OK;
+  } catch (const DeviceError &e) {
+    if (scratch) hipFree(scratch);
+    set_error("pfft_postprocess: " + e.msg);
+    return (pfft_status)e.code;
+  } catch (const SetupError &e) {
+    if (scratch) hipFree(scratch);
+    set_error("pfft_postprocess: " + e.msg);
+    return (pfft_status)e.code;
+  }
+}
+
 pfft_status pfft_profile(pfft_ctx *c, int32_t enable) {
   if (!c) {
     set_error("pfft_profile: null context");
@@ -682,11 +873,14 @@ int *option_slot(pfft_ctx *c, const std::string &name) {
   if (name == "project_plan") return &c->plans.proj;
   if (name == "graphs") return &c->plans.graphs;
   if (name == "stream_split") return &c->plans.stream_split;
+  if (name == "factor_plan") return &c->plans.factor;
+  if (name == "combine_plan") return &c->plans.comb;
   return nullptr;
 }
 void sync_plans(pfft_ctx *c) {
   c->gm.fft_plan = c->plans.fft;
   c->gm.proj_plan = c->plans.proj;
+  c->cm.comb_plan = c->plans.comb;
 }
 }  // namespace
 
@@ -758,8 +952,8 @@ extern "C" pfft_status pfft_autotune(pfft_ctx *c, int32_t nrhs, const double *om
       return (double)t[reps / 2];
     };
     std::string js = "{";
-    const char *names[4] = {"fft_plan", "ldl_plan", "project_plan", "stream_split"};
-    for (int o = 0; o < 4; ++o) {
+    const char *names[5] = {"fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split"};
+    for (int o = 0; o < 5; ++o) {
       int *slot = option_slot(c, names[o]);
       double best = 1e300;
       int arg = *slot;

@@ -40,6 +40,7 @@ void branch_to_loop(const LoopMaps &mp, const double2 *yb, double2 *yl, double2 
 // out[c][r] = in[r][c] (complex128)
 void transpose(const double2 *in, double2 *out, int rows, int cols, hipStream_t st);
 
+
 struct GridMaps {
   int n, b, N, dims[3];
   const int *tri_edge;
@@ -58,6 +59,18 @@ struct GridMaps {
   // the first tcap triangles of a tile are staged in LDS
   int tile[3], ntile[3], tcap;
   const int *tt_off, *tt_tri, *pg_loc;
+  // per tile, its local node indices with the most contributions first, so
+  // the nodes of one wavefront have similar gather lengths
+  const uint16_t *tn_perm;
+  // the same gathers sliced per (tile, wavefront of that order): slice s
+  // holds ps_k[s] entries per lane stored k-major from ps_off[s] (entry
+  // ps_off[s] + 64 k + lane), so a wavefront's index and weight loads are
+  // contiguous.  An entry is the triangle's LDS slot (>= 0) or -1 - triangle
+  // (beyond tcap, read from memory); shorter lists are padded with slot 0
+  // and zero weights.
+  int nwave;
+  const int *ps_off, *ps_k, *ps_ent;
+  const void *ps_w;      // [entries][4] (M0, M1x, M1y, M1z) in T
   // plan choices (set by the context's options or the autotuner):
   // fft_plan 0 register-resident passes where the shape allows, 1 LDS
   // Stockham passes; proj_plan 0 tiled (LDS-staged), 1 node-major gather
@@ -99,6 +112,14 @@ struct CombineMaps {
   const double *nf_val;
   const int *gram_col;      // [b][5]
   const double *gram_val;
+  // Row tiles of the near-field matrix for the LDS-staged product: rows
+  // [T ctr, (T+1) ctr) read only the columns ct_col[ct_off[T] .. ct_off[T+1])
+  // (ascending), nf_slot[q] is nf_col[q]'s position in its tile's list and
+  // no list is longer than cmax.  ctile = 0: no tiles (gather only).
+  int ctr, ctile, cmax, crc;   // crc: right-hand sides per workgroup (8 or 16)
+  const int *ct_off, *ct_col;
+  const uint16_t *nf_slot;
+  int comb_plan;            // 0 tiled product when available, 1 gather
 };
 
 // y[e][r] = zs[r] * (G a)[e] + jw[r] * (far[e] + (L_d a)[e]); far from U;
@@ -107,5 +128,24 @@ struct CombineMaps {
 // and kscale = 1: y = far + near).
 void combine(const CombineMaps &c, const double2 *alpha, const double2 *U, const double2 *zs,
              const double2 *jw, double2 *y, int R, int mode, hipStream_t st);
+// Longest column list of a near-field row tile that the tiled product can
+// stage in LDS with rc (8 or 16) right-hand sides per workgroup.
+int combine_tile_cap(int rc);
+
+// Post-processing outputs of solved loop currents (any pointer may be null),
+// RHS-major: Ib [R][b+p] branch currents (mesh branches, then the port
+// source branches), Vb [R][b] branch voltages, J [R][n][3] surface current
+// density at the triangle centroids, phi [R][n] panel potentials.
+struct PostOut {
+  double2 *Ib, *Vb, *J, *phi;
+  int p;
+  const int *port_loop;   // [p] loop of each port's source branch
+  const int *tri_pos;     // [n] preorder position of the triangle's node
+  const int *tri_ref;     // [n] preorder position of its conductor's reference node
+};
+// x: loop currents [R][l]; alpha, yb: [b][R]; pot: [R][nn+1] node potentials
+// (prefix scan of the twig drops, any constant per conductor)
+void post_outputs(const GridMaps &g, const LoopMaps &lm, const PostOut &o, const double2 *x, const double2 *alpha,
+                  const double2 *yb, const double2 *pot, int R, hipStream_t st);
 
 }  // namespace pfft

@@ -340,32 +340,53 @@ __global__ void k_project(GridMaps g, const V2<T> *J, V2<T> *Q, int R) {
 // Tiled projection: one workgroup per (tile, group of RC right-hand sides)
 // stages the moments J of the tile's triangles in LDS once, then each node
 // gathers its contributions from LDS (triangles beyond tcap from memory).
-// Every node is still a gather in a fixed order: no atomics.
+// Threads take the tile's nodes heaviest first, so a wavefront's lanes loop
+// about equally long (most grid nodes have no contribution at all).  Every
+// node is still a gather in a fixed order: no atomics.
 template <typename T> struct ProjRC;
 template <> struct ProjRC<float> { static constexpr int v = 4; };
 template <> struct ProjRC<double> { static constexpr int v = 2; };
+// LDS pitch of one staged triangle: its RC x 4 moments (128 bytes) plus 16
+// bytes, so that the 16-byte reads of lanes gathering different triangles
+// spread over the banks (a 128-byte pitch maps them to two bank groups)
+template <typename T> constexpr int proj_pitch() { return ProjRC<T>::v * 4 + 16 / (int)sizeof(V2<T>); }
 
 template <typename T>
 __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *J, V2<T> *Q, int R) {
   constexpr int RC = ProjRC<T>::v;
   extern __shared__ unsigned char smraw[];
-  V2<T> *sJ = (V2<T> *)smraw;   // [tcap][RC][4]
+  constexpr int PS = proj_pitch<T>();
+  V2<T> *sJ = (V2<T> *)smraw;   // [tcap][PS]: (rr, comp) at rr * 4 + comp
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int r0 = blockIdx.y * RC, nr = min(RC, R - r0);
   const int t0 = g.tt_off[tile], nt = g.tt_off[tile + 1] - t0;
   const int ns = min(nt, g.tcap);
-  for (int i = threadIdx.x; i < ns * RC * 4; i += blockDim.x) {
-    const int lt = i / (RC * 4), rem = i - lt * (RC * 4), rr = rem >> 2, comp = rem & 3;
-    V2<T> v = cmk<T>(0, 0);
-    if (rr < nr) v = J[((size_t)g.tt_tri[t0 + lt] * R + r0 + rr) * 4 + comp];
-    sJ[i] = v;
+  // staging, four loads in flight per thread
+  const int tot = ns * RC * 4;
+  for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * blockDim.x) {
+    V2<T> v[4];
+#pragma unroll
+    for (int u2 = 0; u2 < 4; ++u2) {
+      const int i = min(i0 + u2 * (int)blockDim.x, tot - 1);
+      const int lt = i / (RC * 4), rem = i - lt * (RC * 4), rr = rem >> 2, comp = rem & 3;
+      v[u2] = rr < nr ? J[((size_t)g.tt_tri[t0 + lt] * R + r0 + rr) * 4 + comp] : cmk<T>(0, 0);
+    }
+#pragma unroll
+    for (int u2 = 0; u2 < 4; ++u2) {
+      const int i = i0 + u2 * (int)blockDim.x;
+      if (i < tot) {
+        const int lt = i / (RC * 4), rem = i - lt * (RC * 4);
+        sJ[lt * PS + rem] = v[u2];
+      }
+    }
   }
   __syncthreads();
   const int TX = g.tile[0], TY = g.tile[1], TZ = g.tile[2];
   const int tz = tile % g.ntile[2], ty = (tile / g.ntile[2]) % g.ntile[1], tx = tile / (g.ntile[2] * g.ntile[1]);
   const int Ny = g.dims[1], Nz = g.dims[2];
-  const T *w = (const T *)g.pg_w;
-  for (int u = threadIdx.x; u < TX * TY * TZ; u += blockDim.x) {
+  const int TN = TX * TY * TZ;
+  for (int uu = threadIdx.x; uu < TN; uu += blockDim.x) {
+    const int u = g.tn_perm[(size_t)tile * TN + uu];
     const int iz = u % TZ, iy = (u / TZ) % TY, ix = u / (TZ * TY);
     const int x = tx * TX + ix, y = ty * TY + iy, z = tz * TZ + iz;
     if (x >= g.dims[0] || y >= Ny || z >= Nz) continue;
@@ -375,32 +396,35 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
     for (int q = 0; q < RC; ++q)
 #pragma unroll
       for (int c = 0; c < 6; ++c) acc[q][c] = 0;
-    // contributions in groups of 4: their index and weight loads are
-    // independent, so several are in flight; the sum keeps the list order
-    const int k0 = g.pg_off[node], k1 = g.pg_off[node + 1];
-    for (int kb = k0; kb < k1; kb += 4) {
+    // the wavefront's sliced list: entry k of this lane at 64 k + lane, in
+    // groups of 4 so that several loads are in flight; pads add zero
+    const int sidx = tile * g.nwave + (uu >> 6), lane = uu & 63;
+    const int off = g.ps_off[sidx], K = g.ps_k[sidx];
+    const int *ent = g.ps_ent + off + lane;
+    const T *wl = (const T *)g.ps_w + 4 * ((size_t)off + lane);
+    for (int kb = 0; kb < K; kb += 4) {
       int locs[4];
       T wv[4][4];
 #pragma unroll
       for (int u2 = 0; u2 < 4; ++u2) {
-        const int k = min(kb + u2, k1 - 1);
-        locs[u2] = g.pg_loc[k];
+        const int k = min(kb + u2, K - 1);
+        locs[u2] = ent[64 * (size_t)k];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) wv[u2][c] = w[4 * (size_t)k + c];
+        for (int c = 0; c < 4; ++c) wv[u2][c] = wl[256 * (size_t)k + c];
       }
 #pragma unroll
       for (int u2 = 0; u2 < 4; ++u2) {
-        if (kb + u2 >= k1) break;
+        if (kb + u2 >= K) break;
         const int loc = locs[u2];
         const T m0 = wv[u2][0], m1x = wv[u2][1], m1y = wv[u2][2], m1z = wv[u2][3];
         V2<T> jv[RC][4];
-        if (loc < ns) {
+        if (loc >= 0) {
 #pragma unroll
           for (int q = 0; q < RC; ++q)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) jv[q][c] = sJ[(loc * RC + q) * 4 + c];
+            for (int c = 0; c < 4; ++c) jv[q][c] = sJ[loc * PS + q * 4 + c];
         } else {
-          const V2<T> *jt = J + ((size_t)g.pg_tri[kb + u2] * R + r0) * 4;
+          const V2<T> *jt = J + ((size_t)(-1 - loc) * R + r0) * 4;
 #pragma unroll
           for (int q = 0; q < RC; ++q)
 #pragma unroll
@@ -433,7 +457,7 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
 template <typename T>
 void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st) {
   constexpr int RC = ProjRC<T>::v;
-  const size_t lds = (size_t)g.tcap * RC * 4 * sizeof(V2<T>);
+  const size_t lds = (size_t)g.tcap * proj_pitch<T>() * sizeof(V2<T>);
   static bool lds_ok = allow_lds((const void *)k_project_tiled<T>, (int)lds);
   if (lds_ok && g.proj_plan == 0) {
     const unsigned ntile = (unsigned)g.ntile[0] * g.ntile[1] * g.ntile[2];
@@ -692,6 +716,22 @@ __device__ __forceinline__ float2 tw(int k, int n) {
   return make_float2(kTw.c[i], SIGN < 0 ? kTw.s[i] : -kTw.s[i]);
 }
 
+// x W_n^k (SIGN -1) or x conj(W_n^k) (SIGN +1).  k and n are constants after
+// unrolling; quarter turns become exact swaps and negations (no multiply).
+template <int SIGN>
+__device__ __forceinline__ float2 twmul(float2 x, int k, int n) {
+  if ((4 * k) % n == 0) {
+    const int e = ((4 * k) / n) & 3;
+    const int r = SIGN < 0 ? e : (4 - e) & 3;   // rotation by (-i)^r
+    if (r == 0) return x;
+    if (r == 1) return make_float2(x.y, -x.x);
+    if (r == 2) return make_float2(-x.x, -x.y);
+    return make_float2(-x.y, x.x);
+  }
+  const float2 w = tw<SIGN>(k, n);
+  return make_float2(x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x);
+}
+
 constexpr int clog2(int n) { return n <= 1 ? 0 : 1 + clog2(n / 2); }
 constexpr int brev(int k, int bits) {
   int r = 0;
@@ -711,13 +751,7 @@ __device__ __forceinline__ void fft_dif(float2 (&v)[N]) {
         const int i0 = b * 2 * half + j, i1 = i0 + half;
         const float2 a = v[i0], c = v[i1];
         v[i0] = make_float2(a.x + c.x, a.y + c.y);
-        const float2 d = make_float2(a.x - c.x, a.y - c.y);
-        if (j == 0) {
-          v[i1] = d;
-        } else {
-          const float2 w = tw<SIGN>(j, 2 * half);
-          v[i1] = make_float2(d.x * w.x - d.y * w.y, d.x * w.y + d.y * w.x);
-        }
+        v[i1] = twmul<SIGN>(make_float2(a.x - c.x, a.y - c.y), j, 2 * half);
       }
     fft_dif<N, SIGN, S + 1>(v);
   }
@@ -734,11 +768,7 @@ __device__ __forceinline__ void fft_dit(float2 (&v)[N]) {
       for (int j = 0; j < half; ++j) {
         const int i0 = b * 2 * half + j, i1 = i0 + half;
         const float2 a = v[i0];
-        float2 c = v[i1];
-        if (j != 0) {
-          const float2 w = tw<SIGN>(j, 2 * half);
-          c = make_float2(c.x * w.x - c.y * w.y, c.x * w.y + c.y * w.x);
-        }
+        const float2 c = twmul<SIGN>(v[i1], j, 2 * half);
         v[i0] = make_float2(a.x + c.x, a.y + c.y);
         v[i1] = make_float2(a.x - c.x, a.y - c.y);
       }
@@ -912,12 +942,8 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
     float2 v[NZ];
 #pragma unroll
     for (int z = 0; z < NZ; ++z) {
-      float2 x = sm[line * P0 + z];
-      if (half) {
-        const float2 w = tw<-1>(z, LZ);
-        x = make_float2(x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x);
-      }
-      v[z] = x;
+      const float2 x = sm[line * P0 + z];
+      v[z] = half ? twmul<-1>(x, z, LZ) : x;
     }
     fft_dif<NZ, -1>(v);
     __syncthreads();
@@ -931,12 +957,8 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
     float2 v[NY];
 #pragma unroll
     for (int y = 0; y < NY; ++y) {
-      float2 x = sm[kz * PT + y];
-      if (half) {
-        const float2 w = tw<-1>(y, LY);
-        x = make_float2(x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x);
-      }
-      v[y] = x;
+      const float2 x = sm[kz * PT + y];
+      v[y] = half ? twmul<-1>(x, y, LY) : x;
     }
     fft_dif<NY, -1>(v);
     const int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
@@ -952,10 +974,7 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
     fft_dit<NY, +1>(v);
     if (half) {
 #pragma unroll
-      for (int n = 0; n < NY; ++n) {
-        const float2 w = tw<+1>(n, LY);
-        v[n] = make_float2(v[n].x * w.x - v[n].y * w.y, v[n].x * w.y + v[n].y * w.x);
-      }
+      for (int n = 0; n < NY; ++n) v[n] = twmul<+1>(v[n], n, LY);
     }
     // lane pair sum; lane `half` keeps n in [half NY/2, (half+1) NY/2).
     // Column kz was read only by this lane pair (one wave, whose LDS
@@ -977,10 +996,7 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
     fft_dif<NZ, +1>(v);                     // position p holds z = brev(p)
     if (half) {
 #pragma unroll
-      for (int p = 0; p < NZ; ++p) {
-        const float2 w = tw<+1>(brev(p, clog2(NZ)), LZ);
-        v[p] = make_float2(v[p].x * w.x - v[p].y * w.y, v[p].x * w.y + v[p].y * w.x);
-      }
+      for (int p = 0; p < NZ; ++p) v[p] = twmul<+1>(v[p], brev(p, clog2(NZ)), LZ);
     }
     const float sc = a.scale;
     float2 *row = io + (long)line * NZ + half * (NZ / 2);
@@ -1395,28 +1411,40 @@ __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U,
   }
   if (mode & 2) {
     // four nonzeros per step: their column and value loads, then the four
-    // gathers, are independent (more loads in flight)
+    // gathers, are independent (more loads in flight).  Summation order, the
+    // same in every near-field kernel: nonzero j of the row goes to the even
+    // (far part included) or odd partial sum by its parity, in order; then
+    // even += odd.
     const int64_t q0 = c.nf_rowptr[e], q1 = c.nf_rowptr[e + 1];
     int64_t q = q0;
-    double ax = 0, ay = 0, bx = 0, by = 0;
+    double ax = 0, ay = 0;
     for (; q + 4 <= q1; q += 4) {
       const int c0 = c.nf_col[q], c1 = c.nf_col[q + 1], c2 = c.nf_col[q + 2], c3 = c.nf_col[q + 3];
       const double v0 = c.nf_val[q], v1 = c.nf_val[q + 1], v2 = c.nf_val[q + 2], v3 = c.nf_val[q + 3];
       const double2 x0 = alpha[(size_t)c0 * R + r], x1 = alpha[(size_t)c1 * R + r];
       const double2 x2 = alpha[(size_t)c2 * R + r], x3 = alpha[(size_t)c3 * R + r];
-      kx += v0 * x0.x + v1 * x1.x;
-      ky += v0 * x0.y + v1 * x1.y;
-      ax += v2 * x2.x + v3 * x3.x;
-      ay += v2 * x2.y + v3 * x3.y;
+      kx += v0 * x0.x;
+      ky += v0 * x0.y;
+      ax += v1 * x1.x;
+      ay += v1 * x1.y;
+      kx += v2 * x2.x;
+      ky += v2 * x2.y;
+      ax += v3 * x3.x;
+      ay += v3 * x3.y;
     }
     for (; q < q1; ++q) {
       const double v = c.nf_val[q];
       const double2 x = alpha[(size_t)c.nf_col[q] * R + r];
-      bx += v * x.x;
-      by += v * x.y;
+      if ((q - q0) & 1) {
+        ax += v * x.x;
+        ay += v * x.y;
+      } else {
+        kx += v * x.x;
+        ky += v * x.y;
+      }
     }
-    kx += ax + bx;
-    ky += ay + by;
+    kx += ax;
+    ky += ay;
   }
   double2 out;
   if (mode & 4) {
@@ -1436,9 +1464,152 @@ __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U,
   y[idx] = out;
 }
 
+// Tiled near-field product: one workgroup per (row tile, group of CRC
+// right-hand sides).  The tile's rows touch few distinct columns (geometric
+// neighbours share most of their near lists), so alpha of those columns is
+// staged in LDS once and every nonzero reads it from there; the CSR values
+// and slots are shared by the CRC lanes of a row.  The chunks of one tile
+// are consecutive on one XCD, so its CSR rows are read from HBM once.
+constexpr int CLDS = 120 * 1024;   // staging bytes
+
+int combine_tile_cap(int rc) { return std::min(CLDS / (rc * 16), 65535); }
+
+template <int CRC>
+__global__ void __launch_bounds__(512) k_combine_tiled(CombineMaps c, const double2 *alpha, const double2 *U,
+                                                       const double2 *zs, const double2 *jw, double2 *y, int R,
+                                                       int mode) {
+  extern __shared__ double2 sA[];   // [column slot][CRC]
+  const int nch = (R + CRC - 1) / CRC;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int tile = lb / nch, r0 = (lb - tile * nch) * CRC;
+  const int u0 = c.ct_off[tile], nu = c.ct_off[tile + 1] - u0;
+  for (int i = threadIdx.x; i < nu * CRC; i += blockDim.x) {
+    const int sl = i / CRC, rr = i - sl * CRC;
+    sA[i] = r0 + rr < R ? alpha[(size_t)c.ct_col[u0 + sl] * R + r0 + rr] : make_double2(0, 0);
+  }
+  __syncthreads();
+  // every lane stays to the end (the rows' nonzeros are shared across lanes);
+  // lanes past the last row or right-hand side read clamped indices and
+  // store nothing
+  const int rr = threadIdx.x % CRC, e0 = tile * c.ctr + threadIdx.x / CRC, r0c = r0 + rr;
+  const bool live = e0 < c.b && r0c < R;
+  const int e = min(e0, c.b - 1), r = min(r0c, R - 1);
+  double kx = 0, ky = 0;
+  if (mode & 1) {
+    for (int side = 0; side < 2; ++side) {
+      const int t = c.efar_t[2 * e + side];
+      const double sg = c.efar_s[2 * e + side];
+      const double *p = c.efar_pl + 6 * (size_t)e + 3 * side;
+      const double2 *u = U + ((size_t)t * R + r) * 4;
+      const double vx = u[0].x - (p[0] * u[1].x + p[1] * u[2].x + p[2] * u[3].x);
+      const double vy = u[0].y - (p[0] * u[1].y + p[1] * u[2].y + p[2] * u[3].y);
+      kx += sg * vx;
+      ky += sg * vy;
+    }
+  }
+  if ((mode & 2) && CRC == 16) {
+    // the 16 lanes of a row (one DPP row) load 16 nonzeros at a time, one
+    // each, and broadcast them in turn (row_newbcast); the next 16 are
+    // fetched while these are used.  Lanes past their row's end carry zeros.
+    const int64_t q0 = c.nf_rowptr[e], q1 = e0 < c.b ? c.nf_rowptr[e + 1] : q0;
+    int64_t qb = q0;
+    double vn = qb + rr < q1 ? c.nf_val[qb + rr] : 0.0;
+    int sn = qb + rr < q1 ? (int)c.nf_slot[qb + rr] : 0;
+    double ax = 0, ay = 0;
+    while (__any(qb < q1)) {
+      const double vc = vn;
+      const int sc = sn;
+      const int64_t qn = qb + 16 + rr;
+      vn = qn < q1 ? c.nf_val[qn] : 0.0;
+      sn = qn < q1 ? (int)c.nf_slot[qn] : 0;
+      const int vlo = __double2loint(vc), vhi = __double2hiint(vc);
+#define PFFT_NZ(K)                                                                                  \
+  {                                                                                                 \
+    const double v = __hiloint2double(__builtin_amdgcn_update_dpp(0, vhi, 0x150 + K, 0xF, 0xF, false), \
+                                      __builtin_amdgcn_update_dpp(0, vlo, 0x150 + K, 0xF, 0xF, false)); \
+    const int sl = __builtin_amdgcn_update_dpp(0, sc, 0x150 + K, 0xF, 0xF, false);                  \
+    const double2 xv = sA[sl * CRC + rr];                                                           \
+    if (K & 1) {                                                                                    \
+      ax += v * xv.x;                                                                               \
+      ay += v * xv.y;                                                                               \
+    } else {                                                                                        \
+      kx += v * xv.x;                                                                               \
+      ky += v * xv.y;                                                                               \
+    }                                                                                               \
+  }
+      PFFT_NZ(0) PFFT_NZ(1) PFFT_NZ(2) PFFT_NZ(3) PFFT_NZ(4) PFFT_NZ(5) PFFT_NZ(6) PFFT_NZ(7)
+      PFFT_NZ(8) PFFT_NZ(9) PFFT_NZ(10) PFFT_NZ(11) PFFT_NZ(12) PFFT_NZ(13) PFFT_NZ(14) PFFT_NZ(15)
+#undef PFFT_NZ
+      qb += 16;
+    }
+    kx += ax;
+    ky += ay;
+  } else if (mode & 2) {
+    const int64_t q0 = c.nf_rowptr[e], q1 = e0 < c.b ? c.nf_rowptr[e + 1] : q0;
+    int64_t q = q0;
+    double ax = 0, ay = 0;
+    for (; q + 4 <= q1; q += 4) {
+      const int s0 = c.nf_slot[q], s1 = c.nf_slot[q + 1], s2 = c.nf_slot[q + 2], s3 = c.nf_slot[q + 3];
+      const double v0 = c.nf_val[q], v1 = c.nf_val[q + 1], v2 = c.nf_val[q + 2], v3 = c.nf_val[q + 3];
+      const double2 x0 = sA[s0 * CRC + rr], x1 = sA[s1 * CRC + rr];
+      const double2 x2 = sA[s2 * CRC + rr], x3 = sA[s3 * CRC + rr];
+      kx += v0 * x0.x;
+      ky += v0 * x0.y;
+      ax += v1 * x1.x;
+      ay += v1 * x1.y;
+      kx += v2 * x2.x;
+      ky += v2 * x2.y;
+      ax += v3 * x3.x;
+      ay += v3 * x3.y;
+    }
+    for (; q < q1; ++q) {
+      const double v = c.nf_val[q];
+      const double2 x = sA[c.nf_slot[q] * CRC + rr];
+      if ((q - q0) & 1) {
+        ax += v * x.x;
+        ay += v * x.y;
+      } else {
+        kx += v * x.x;
+        ky += v * x.y;
+      }
+    }
+    kx += ax;
+    ky += ay;
+  }
+  double2 out;
+  if (mode & 4) {
+    double gx = 0, gy = 0;
+    for (int q = 0; q < 5; ++q) {
+      const double v = c.gram_val[5 * e + q];
+      const double2 x = alpha[(size_t)c.gram_col[5 * e + q] * R + r];
+      gx += v * x.x;
+      gy += v * x.y;
+    }
+    const double2 z = zs[r], j = jw[r];
+    out.x = z.x * gx - z.y * gy + j.x * kx - j.y * ky;
+    out.y = z.x * gy + z.y * gx + j.x * ky + j.y * kx;
+  } else {
+    out = make_double2(kx, ky);
+  }
+  if (live) y[(size_t)e * R + r] = out;
+}
+
 void combine(const CombineMaps &c, const double2 *alpha, const double2 *U, const double2 *zs,
              const double2 *jw, double2 *y, int R, int mode, hipStream_t st) {
-  k_combine<<<cdiv((long)c.b * R, 256), 256, 0, st>>>(c, alpha, U, zs, jw, y, R, mode);
+  static const bool lds16 = allow_lds((const void *)k_combine_tiled<16>, CLDS);
+  static const bool lds8 = allow_lds((const void *)k_combine_tiled<8>, CLDS);
+  // the choice does not depend on R, so a product gives the same result
+  // however its right-hand sides are split
+  if (c.ctile > 0 && c.comb_plan == 0 && (mode & 2) && (c.crc == 16 ? lds16 : lds8)) {
+    const unsigned nb = (unsigned)c.ctile * (unsigned)cdiv(R, c.crc);
+    const size_t lds = (size_t)c.cmax * c.crc * sizeof(double2);
+    if (c.crc == 16)
+      k_combine_tiled<16><<<nb, c.ctr * 16, lds, st>>>(c, alpha, U, zs, jw, y, R, mode);
+    else
+      k_combine_tiled<8><<<nb, c.ctr * 8, lds, st>>>(c, alpha, U, zs, jw, y, R, mode);
+  } else {
+    k_combine<<<cdiv((long)c.b * R, 256), 256, 0, st>>>(c, alpha, U, zs, jw, y, R, mode);
+  }
 }
 
 // out[c][r] = in[r][c] for a rows x cols complex128 matrix, 32 x 32 LDS tiles
@@ -1458,6 +1629,54 @@ __global__ void k_transpose(const double2 *in, double2 *out, int rows, int cols)
 
 void transpose(const double2 *in, double2 *out, int rows, int cols, hipStream_t st) {
   k_transpose<<<dim3(cdiv(cols, 32), cdiv(rows, 32)), dim3(32, 8), 0, st>>>(in, out, rows, cols);
+}
+
+// ===========================================================================
+// post-processing (branch currents, voltages, centroid current, potentials)
+// ===========================================================================
+__global__ void k_post_branch(LoopMaps lm, PostOut o, const double2 *x, const double2 *alpha, const double2 *yb,
+                              int R) {
+  const int r = blockIdx.y, e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = lm.b;
+  if (e < b) {
+    if (o.Ib) o.Ib[(size_t)r * (b + o.p) + e] = alpha[(size_t)e * R + r];
+    if (o.Vb) o.Vb[(size_t)r * b + e] = yb[(size_t)e * R + r];
+  } else if (e < b + o.p) {
+    // a source branch is a link: its current is its own loop current
+    if (o.Ib) o.Ib[(size_t)r * (b + o.p) + e] = x[(size_t)r * lm.l + o.port_loop[e - b]];
+  }
+}
+
+// J(centroid) = sum_e s_e I_e (c - v_e) / (2A) = -sum_e s_e I_e (v_e - c) / (2A)
+__global__ void k_post_tri(GridMaps g, PostOut o, const double2 *alpha, const double2 *pot, int nn, int R) {
+  const int r = blockIdx.y, t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n) return;
+  if (o.J) {
+    double dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i) {
+      const double2 v = alpha[(size_t)g.tri_edge[3 * t + i] * R + r];
+      const double s = g.tri_sign[3 * t + i];
+      for (int c = 0; c < 3; ++c) {
+        const double p = g.pl[9 * t + 3 * i + c];
+        dx[c] += s * v.x * p;
+        dy[c] += s * v.y * p;
+      }
+    }
+    const double f = -g.inv2A[t];
+    double2 *out = o.J + ((size_t)r * g.n + t) * 3;
+    for (int c = 0; c < 3; ++c) out[c] = make_double2(dx[c] * f, dy[c] * f);
+  }
+  if (o.phi) {
+    const double2 *D = pot + (size_t)r * (nn + 1);
+    const double2 a = D[o.tri_pos[t]], z = D[o.tri_ref[t]];
+    o.phi[(size_t)r * g.n + t] = make_double2(a.x - z.x, a.y - z.y);
+  }
+}
+
+void post_outputs(const GridMaps &g, const LoopMaps &lm, const PostOut &o, const double2 *x, const double2 *alpha,
+                  const double2 *yb, const double2 *pot, int R, hipStream_t st) {
+  if (o.Ib || o.Vb) k_post_branch<<<dim3(cdiv(lm.b + o.p, 256), R), 256, 0, st>>>(lm, o, x, alpha, yb, R);
+  if (o.J || o.phi) k_post_tri<<<dim3(cdiv(g.n, 256), R), 256, 0, st>>>(g, o, alpha, pot, lm.nn, R);
 }
 
 // explicit instantiations

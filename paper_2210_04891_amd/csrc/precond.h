@@ -5,9 +5,10 @@
 // with the nodal matrix L_w = N D^-1 N^T replaces the factorization of P.  A
 // port's zero-impedance source branch ties its sink node to its source node
 // (supernode with a known potential offset); one node per conductor is
-// grounded.  L_w is factored on the host (reverse Cuthill-McKee order per
-// conductor, envelope LDL^T without pivoting: Re L_w is positive definite)
-// and solved on the device.
+// grounded.  L_w is ordered on the host (reverse Cuthill-McKee per
+// conductor, supernodes last), factored per frequency (LDL^T without
+// pivoting: Re L_w is positive definite) on the device, or on the host, and
+// solved on the device.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -61,6 +62,30 @@ bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, d
                     std::vector<std::complex<double>> &yinv, std::vector<std::complex<double>> &colpad,
                     std::vector<std::complex<double>> &full);
 
+// Device factorization: the same factor, in the same layouts, as
+// factor_precond, for nf frequencies at once (one workgroup per conductor and
+// frequency, right-looking over the band with the active (W+1) x (W+1)
+// window in LDS, or in global scratch when it does not fit).  The branch
+// admittances 1/D_e are formed on the device from the Gram and kernel
+// diagonals.  FACT_NS bounds the supernode rows of a conductor.
+constexpr int FACT_NS = 4;
+struct FactorArgs {
+  int nu, b, W, Wc, ncomp, nf;       // W, Wc: layout widths max(W, 1), max(Wc, 1)
+  const int *comp_off, *comp_mid, *first, *inc_off, *inc_br, *br_ru, *br_rv;
+  const int64_t *env_off;
+  int64_t nnz_full;
+  const double *gdiag, *kdiag;       // [b] Gram and kernel diagonals
+  const double *omega;               // [nf] rad/s (device)
+  double sigma, mu_r;
+  double2 *env, *colenv, *full, *diag, *yinv;
+  double2 *gwin;                     // [nf][ncomp][(W+1)^2 + FACT_NS (W+1)] or null (LDS window)
+  int *status;                       // [nf * ncomp + nf]: nonzero on a zero pivot / impedance
+};
+// Bytes of global window scratch the factorization needs (0: LDS suffices),
+// or -1 when the structure does not suit the device kernel.
+int64_t factor_device_scratch(const PrecondStruct &ps, int nf);
+void factor_precond_device(const FactorArgs &a, hipStream_t st);
+
 struct PrecondDev {
   int nu, ncomp, W, Wc, b, l, p, nf;
   const int *comp_off, *comp_mid, *first, *clast;
@@ -100,6 +125,13 @@ struct Precond {
   double2 *d_env = nullptr, *d_diag = nullptr, *d_yinv = nullptr, *d_work = nullptr, *d_tmp = nullptr,
           *d_colenv = nullptr, *d_full = nullptr;
   int *d_fidx = nullptr;
+  // device factorization inputs and scratch
+  double *d_gdiag = nullptr, *d_kdiag = nullptr, *d_om = nullptr;
+  int *d_status = nullptr;
+  double2 *d_gwin = nullptr;
+  int cap_om = 0;
+  int64_t cap_gwin = 0;
+  int factor_plan = -1;                  // plan the current factors were made with
 };
 
 }  // namespace pfft

@@ -11,6 +11,8 @@
 
 namespace pfft {
 
+void hip_ok(hipError_t e, const char *what);   // throws DeviceError
+
 typedef std::complex<double> cd;
 static constexpr double MU0 = 4e-7 * M_PI;
 
@@ -367,6 +369,84 @@ __device__ __forceinline__ double2 band_load(__amdgpu_buffer_rsrc_t r, unsigned 
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
+// Between the two band sweeps (one wavefront): forward over the supernode
+// rows, y_s = b_s - sum_j L_sj y_j over each full row; z = y / D; then the
+// transposed scatter of the supernode rows, last row first.  Each lane loads
+// SB entries before using any, so that several loads are in flight.
+constexpr int SB = 8;
+__device__ void ldl_middle(const PrecondDev &d, int f, double2 *x, int lo, int mid, int hi, int lane) {
+  const double2 *full = d.full + (size_t)f * d.nnz_full;
+  const double2 *dg = d.diag + (size_t)f * d.nu;
+  const double2 zero = make_double2(0, 0);
+  for (int s = mid; s < hi; ++s) {
+    const int fs = d.first[s];
+    const double2 *Ls = full + d.env_off[s];
+    double2 acc = zero;
+    for (int j0 = fs; j0 < s; j0 += 64 * SB) {
+      double2 lv[SB], yv[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        const int j = j0 + q * 64 + lane;
+        lv[q] = j < s ? Ls[j - fs] : zero;
+        yv[q] = j < s ? x[j] : zero;
+      }
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        acc.x += lv[q].x * yv[q].x - lv[q].y * yv[q].y;
+        acc.y += lv[q].x * yv[q].y + lv[q].y * yv[q].x;
+      }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const double2 bs = x[s];
+      x[s] = make_double2(bs.x - acc.x, bs.y - acc.y);
+    }
+    __threadfence();
+    __syncthreads();
+  }
+  for (int i0 = lo; i0 < hi; i0 += 64 * SB) {
+    double2 xv[SB], dv[SB];
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int i = i0 + q * 64 + lane;
+      xv[q] = i < hi ? x[i] : zero;
+      dv[q] = i < hi ? dg[i] : make_double2(1, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int i = i0 + q * 64 + lane;
+      if (i < hi) x[i] = cdiv2(xv[q], dv[q]);
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  for (int s = hi - 1; s >= mid; --s) {
+    const int fs = d.first[s];
+    const double2 *Ls = full + d.env_off[s];
+    const double2 xs = x[s];
+    for (int j0 = fs; j0 < s; j0 += 64 * SB) {
+      double2 lv[SB], t[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        const int j = j0 + q * 64 + lane;
+        lv[q] = j < s ? Ls[j - fs] : zero;
+        t[q] = j < s ? x[j] : zero;
+      }
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        const int j = j0 + q * 64 + lane;
+        if (j < s) {
+          t[q].x -= lv[q].x * xs.x - lv[q].y * xs.y;
+          t[q].y -= lv[q].x * xs.y + lv[q].y * xs.x;
+          x[j] = t[q];
+        }
+      }
+    }
+    __threadfence();
+    __syncthreads();
+  }
+}
+
 template <int WP>
 __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx, double2 *work) {
   __shared__ double2 win[WP];
@@ -435,42 +515,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
   }
   __threadfence();
   __syncthreads();
-  // ---- forward, supernode rows: y_s = b_s - sum_j L_sj y_j over the full row
-  for (int s = mid; s < hi; ++s) {
-    const int fs = d.first[s];
-    const double2 *Ls = full + d.env_off[s];
-    double2 acc = zero;
-    for (int j = fs + lane; j < s; j += 64) {
-      double2 lv = Ls[j - fs], yv = x[j];
-      acc.x += lv.x * yv.x - lv.y * yv.y;
-      acc.y += lv.x * yv.y + lv.y * yv.x;
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) {
-      double2 bs = x[s];
-      x[s] = make_double2(bs.x - acc.x, bs.y - acc.y);
-    }
-    __threadfence();
-    __syncthreads();
-  }
-  // ---- diagonal: z = y / D
-  for (int i = lo + lane; i < hi; i += 64) x[i] = cdiv2(x[i], dg[i]);
-  __threadfence();
-  __syncthreads();
-  // ---- backward, supernode rows (last rows first): scatter over the full row
-  for (int s = hi - 1; s >= mid; --s) {
-    const int fs = d.first[s];
-    const double2 *Ls = full + d.env_off[s];
-    const double2 xs = x[s];
-    for (int j = fs + lane; j < s; j += 64) {
-      double2 lv = Ls[j - fs], t = x[j];
-      t.x -= lv.x * xs.x - lv.y * xs.y;
-      t.y -= lv.x * xs.y + lv.y * xs.x;
-      x[j] = t;
-    }
-    __threadfence();
-    __syncthreads();
-  }
+  ldl_middle(d, f, x, lo, mid, hi, lane);
   // ---- backward, band rows
   if (lo < mid) {
     int loaded = mid;  // window holds z_j for j in [loaded, mid)
@@ -615,42 +660,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *f
   }
   __threadfence();
   __syncthreads();
-  // ---- forward, supernode rows: y_s = b_s - sum_j L_sj y_j over the full row
-  for (int s = mid; s < hi; ++s) {
-    const int fs = d.first[s];
-    const double2 *Ls = full + d.env_off[s];
-    double2 acc = zero;
-    for (int j = fs + lane; j < s; j += 64) {
-      double2 lv = Ls[j - fs], yv = x[j];
-      acc.x += lv.x * yv.x - lv.y * yv.y;
-      acc.y += lv.x * yv.y + lv.y * yv.x;
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) {
-      double2 bs = x[s];
-      x[s] = make_double2(bs.x - acc.x, bs.y - acc.y);
-    }
-    __threadfence();
-    __syncthreads();
-  }
-  // ---- diagonal: z = y / D
-  for (int i = lo + lane; i < hi; i += 64) x[i] = cdiv2(x[i], dg[i]);
-  __threadfence();
-  __syncthreads();
-  // ---- backward, supernode rows (last rows first): scatter over the full row
-  for (int s = hi - 1; s >= mid; --s) {
-    const int fs = d.first[s];
-    const double2 *Ls = full + d.env_off[s];
-    const double2 xs = x[s];
-    for (int j = fs + lane; j < s; j += 64) {
-      double2 lv = Ls[j - fs], t = x[j];
-      t.x -= lv.x * xs.x - lv.y * xs.y;
-      t.y -= lv.x * xs.y + lv.y * xs.x;
-      x[j] = t;
-    }
-    __threadfence();
-    __syncthreads();
-  }
+  ldl_middle(d, f, x, lo, mid, hi, lane);
   // ---- backward, band rows: x_k = acc_k, then acc_{k-j} -= L(k, k-j) x_k
   if (lo < mid) {
     double ax, ay;
@@ -760,6 +770,284 @@ void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, doubl
   else
     k_ldl_solve<4096><<<g, 64, 0, st>>>(d, fidx, work);
   k_pre_out<<<dim3((d.l + 255) / 256, R), 256, 0, st>>>(d, fidx, y, work, z);
+}
+
+
+// ---------------------------------------------------------------------------
+// device factorization of L_w, one workgroup per (conductor, frequency)
+// ---------------------------------------------------------------------------
+constexpr int FACT_T = 256;
+
+// 1/D_e with D_e = Z_s G_ee + (j omega mu / 4 pi) K_ee (Eq. Zb's diagonal)
+__global__ void k_fac_yinv(FactorArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x, f = blockIdx.y;
+  if (e >= a.b) return;
+  const double om = a.omega[f];
+  const double zr = sqrt(om * MU0 * a.mu_r / (2.0 * a.sigma));   // Z_s = zr (1 + j)
+  const double jw = om * MU0 * a.mu_r / (4.0 * M_PI);
+  const double g = a.gdiag[e];
+  const double2 D = make_double2(zr * g, zr * g + jw * a.kdiag[e]);
+  double2 y = make_double2(0, 0);
+  if (D.x == 0.0 && D.y == 0.0)
+    a.status[a.nf * a.ncomp + f] = 1;
+  else
+    y = cdiv2(make_double2(1, 0), D);
+  a.yinv[(size_t)f * a.b + e] = y;
+}
+
+// Row i of L_w = N D^-1 N^T: band rows into the padded row layout, supernode
+// rows into their envelope; the diagonal separately.  One thread per row
+// gathers its incident branches (no atomics); the padded column layout is
+// cleared for the factorization to fill.
+__global__ void k_fac_assemble(FactorArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, f = blockIdx.y;
+  if (i >= a.nu) return;
+  int lo = 0, hi = a.ncomp;            // conductor of row i
+  while (hi - lo > 1) {
+    const int m = (lo + hi) >> 1;
+    if (a.comp_off[m] <= i) lo = m; else hi = m;
+  }
+  const bool super = i >= a.comp_mid[lo];
+  const double2 *yi = a.yinv + (size_t)f * a.b;
+  double2 *rowp = a.env + ((size_t)f * a.nu + i) * a.W;
+  double2 *colp = a.colenv + ((size_t)f * a.nu + i) * a.Wc;
+  double2 *fr = a.full + (size_t)f * a.nnz_full + a.env_off[i];
+  const int fi = a.first[i];
+  const double2 zero = make_double2(0, 0);
+  for (int t = 0; t < a.W; ++t) rowp[t] = zero;
+  for (int t = 0; t < a.Wc; ++t) colp[t] = zero;
+  if (super)
+    for (int k = 0; k < i - fi; ++k) fr[k] = zero;
+  double2 dsum = zero;
+  for (int q = a.inc_off[i]; q < a.inc_off[i + 1]; ++q) {
+    const int e = a.inc_br[q];
+    const double2 y = yi[e];
+    dsum.x += y.x;
+    dsum.y += y.y;
+    const int o = a.br_ru[e] == i ? a.br_rv[e] : a.br_ru[e];
+    if (o >= 0 && o < i) {
+      double2 &t = super ? fr[o - fi] : rowp[i - 1 - o];
+      t.x -= y.x;
+      t.y -= y.y;
+    }
+  }
+  a.diag[(size_t)f * a.nu + i] = dsum;
+}
+
+__device__ __forceinline__ bool bad_pivot(double2 d) {
+  return !(isfinite(d.x) && isfinite(d.y)) || (d.x == 0.0 && d.y == 0.0);
+}
+
+// Right-looking LDL^T over the band rows [lo, mid) of one conductor: step j
+// takes d_j and column j of L (l_ij = a_ij / d_j, i = j+1 .. j+W) and applies
+// the rank-one update a_ik -= l_ij (d_j l_kj) to the (W x W) trailing window.
+// The window holds rows j .. j+W (circular slots, row slot x offset i - k);
+// after step j, row j+W+1 enters row j's slot (it receives no update before
+// step j+1).  Each supernode row s keeps a circular window of its entries in
+// columns j .. j+W and is updated the same way; the supernode block itself is
+// factored last.  L is written in place over the assembled values: row i's
+// assembled entries are read when it enters the window, before any of its L
+// entries is stored.
+template <bool LW>
+__global__ void __launch_bounds__(FACT_T) k_ldl_factor(FactorArgs a) {
+  extern __shared__ double2 fsm[];
+  const int c = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
+  const int lo = a.comp_off[c], mid = a.comp_mid[c], hi = a.comp_off[c + 1];
+  const int ns = hi - mid;
+  const int W = a.W, Wp = a.W + 1, Wc = a.Wc;
+  double2 *env = a.env + (size_t)f * a.nu * W;
+  double2 *col = a.colenv + (size_t)f * a.nu * Wc;
+  double2 *full = a.full + (size_t)f * a.nnz_full;
+  double2 *dg = a.diag + (size_t)f * a.nu;
+  double2 *lcol = fsm, *ucol = fsm + Wp, *lsn = ucol + Wp, *usn = lsn + FACT_NS, *S = usn + FACT_NS;
+  double2 *win, *swin;
+  if (LW) {
+    win = S + FACT_NS * FACT_NS;
+    swin = win + Wp * Wp;
+  } else {
+    win = a.gwin + ((size_t)f * a.ncomp + c) * ((size_t)Wp * Wp + FACT_NS * Wp);
+    swin = win + (size_t)Wp * Wp;
+  }
+  const double2 zero = make_double2(0, 0);
+  // window rows lo .. lo+W (slot = row - lo)
+  for (int idx = tid; idx < Wp * Wp; idx += FACT_T) {
+    const int q = idx / Wp, o = idx - q * Wp, i = lo + q;
+    double2 v = zero;
+    if (i < mid) v = o == 0 ? dg[i] : env[(size_t)i * W + (o - 1)];
+    win[idx] = v;
+  }
+  for (int idx = tid; idx < ns * Wp; idx += FACT_T) {
+    const int s = idx / Wp, q = idx - s * Wp, k = lo + q, row = mid + s, fs = a.first[row];
+    swin[idx] = (k < mid && k >= fs) ? full[a.env_off[row] + (k - fs)] : zero;
+  }
+  for (int idx = tid; idx < ns * ns; idx += FACT_T) {
+    const int s = idx / ns, s2 = idx - s * ns, row = mid + s, k = mid + s2, fs = a.first[row];
+    double2 v = zero;
+    if (s2 == s)
+      v = dg[row];
+    else if (s2 < s && k >= fs)
+      v = full[a.env_off[row] + (k - fs)];
+    S[s * FACT_NS + s2] = v;
+  }
+  __syncthreads();
+  const int npair = W * (W + 1) / 2;
+  int sj = 0;
+  bool bad = false;
+  for (int j = lo; j < mid; ++j) {
+    const double2 d = win[sj * Wp];
+    if (bad_pivot(d)) {     // uniform: every thread read the same value
+      bad = true;
+      break;
+    }
+    // column j of L, and of the supernode rows
+    for (int t = tid; t <= W + ns; t += FACT_T) {
+      if (t == 0) {
+        dg[j] = d;
+      } else if (t <= W) {
+        const int i = j + t;
+        double2 u = zero, l = zero;
+        if (i < mid) {
+          int si = sj + t;
+          if (si >= Wp) si -= Wp;
+          u = win[si * Wp + t];
+          l = cdiv2(u, d);
+          env[(size_t)i * W + (t - 1)] = l;
+        }
+        ucol[t] = u;
+        lcol[t] = l;
+        if (t <= Wc) col[(size_t)j * Wc + (t - 1)] = l;
+      } else {
+        const int s = t - W - 1, row = mid + s, fs = a.first[row];
+        const double2 u = swin[s * Wp + sj], l = cdiv2(u, d);
+        usn[s] = u;
+        lsn[s] = l;
+        if (j >= fs) full[a.env_off[row] + (j - fs)] = l;
+      }
+    }
+    __syncthreads();
+    // trailing update: pair (t, t2), 1 <= t2 <= t <= W, is entry (j+t, j+t2)
+    for (int p = tid; p < npair; p += FACT_T) {
+      int r0 = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+      while ((r0 + 1) * (r0 + 2) / 2 <= p) ++r0;
+      while (r0 * (r0 + 1) / 2 > p) --r0;
+      const int t = r0 + 1, t2 = p - r0 * (r0 + 1) / 2 + 1;
+      if (j + t < mid) {
+        int si = sj + t;
+        if (si >= Wp) si -= Wp;
+        double2 &w = win[si * Wp + (t - t2)];
+        const double2 l = lcol[t], u = ucol[t2];
+        w.x -= l.x * u.x - l.y * u.y;
+        w.y -= l.x * u.y + l.y * u.x;
+      }
+    }
+    for (int p = tid; p < ns * W; p += FACT_T) {
+      const int s = p / W, t = p - s * W + 1;
+      if (j + t < mid) {
+        int sk = sj + t;
+        if (sk >= Wp) sk -= Wp;
+        double2 &w = swin[s * Wp + sk];
+        const double2 l = lsn[s], u = ucol[t];
+        w.x -= l.x * u.x - l.y * u.y;
+        w.y -= l.x * u.y + l.y * u.x;
+      }
+    }
+    for (int p = tid; p < ns * ns; p += FACT_T) {
+      const int s = p / ns, s2 = p - s * ns;
+      if (s2 <= s) {
+        double2 &w = S[s * FACT_NS + s2];
+        const double2 l = lsn[s], u = usn[s2];
+        w.x -= l.x * u.x - l.y * u.y;
+        w.y -= l.x * u.y + l.y * u.x;
+      }
+    }
+    // row j+W+1 (and the supernode entries of column j+W+1) into slot sj
+    const int inew = j + Wp;
+    for (int o = tid; o < Wp; o += FACT_T) {
+      double2 v = zero;
+      if (inew < mid) v = o == 0 ? dg[inew] : env[(size_t)inew * W + (o - 1)];
+      win[sj * Wp + o] = v;
+    }
+    for (int s = tid; s < ns; s += FACT_T) {
+      const int row = mid + s, fs = a.first[row];
+      swin[s * Wp + sj] = (inew < mid && inew >= fs) ? full[a.env_off[row] + (inew - fs)] : zero;
+    }
+    __syncthreads();
+    if (++sj == Wp) sj = 0;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  // supernode block: dense right-looking LDL^T (u values stay in S)
+  for (int s = 0; s < ns && !bad; ++s) {
+    const double2 d = S[s * FACT_NS + s];
+    if (bad_pivot(d)) {
+      bad = true;
+      break;
+    }
+    dg[mid + s] = d;
+    for (int s2 = s + 1; s2 < ns; ++s2) {
+      const double2 u = S[s2 * FACT_NS + s], l = cdiv2(u, d);
+      const int row = mid + s2, k = mid + s, fs = a.first[row];
+      if (k >= fs) full[a.env_off[row] + (k - fs)] = l;
+      for (int s3 = s + 1; s3 <= s2; ++s3) {
+        double2 &w = S[s2 * FACT_NS + s3];
+        const double2 v = S[s3 * FACT_NS + s];
+        w.x -= l.x * v.x - l.y * v.y;
+        w.y -= l.x * v.y + l.y * v.x;
+      }
+    }
+  }
+  if (bad) a.status[f * a.ncomp + c] = 2;
+}
+
+__global__ void k_fill_int(int *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static size_t factor_lds_bytes(int W, bool lw) {
+  const size_t Wp = (size_t)W + 1;
+  size_t n = 2 * Wp + 2 * FACT_NS + FACT_NS * FACT_NS;
+  if (lw) n += Wp * Wp + FACT_NS * Wp;
+  return n * sizeof(double2);
+}
+
+static bool factor_allow_lds(const void *fn, size_t bytes) {
+  if (bytes <= 65536) return true;
+  int dev = 0, q = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) q = 65536;
+  if (bytes > (size_t)std::min(q, 131072)) return false;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+int64_t factor_device_scratch(const PrecondStruct &ps, int nf) {
+  for (int c = 0; c < ps.ncomp; ++c)
+    if (ps.comp_off[c + 1] - ps.comp_mid[c] > FACT_NS) return -1;
+  const int W = std::max(ps.W, 1);
+  if (factor_lds_bytes(W, false) > 131072) return -1;
+  if (factor_allow_lds((const void *)k_ldl_factor<true>, factor_lds_bytes(W, true))) return 0;
+  const int64_t Wp = W + 1;
+  return (int64_t)nf * ps.ncomp * (Wp * Wp + FACT_NS * Wp) * (int64_t)sizeof(double2);
+}
+
+void factor_precond_device(const FactorArgs &a, hipStream_t st) {
+  const int nst = a.nf * a.ncomp + a.nf;
+  k_fill_int<<<(nst + 255) / 256, 256, 0, st>>>(a.status, nst, 0);
+  k_fac_yinv<<<dim3((a.b + 255) / 256, a.nf), 256, 0, st>>>(a);
+  k_fac_assemble<<<dim3((a.nu + 255) / 256, a.nf), 256, 0, st>>>(a);
+  const dim3 g(a.ncomp, a.nf);
+  if (a.gwin) {
+    if (!factor_allow_lds((const void *)k_ldl_factor<false>, factor_lds_bytes(a.W, false)))
+      throw SetupError{-1, "preconditioner factorization: LDS request refused"};
+    k_ldl_factor<false><<<g, FACT_T, factor_lds_bytes(a.W, false), st>>>(a);
+  } else {
+    k_ldl_factor<true><<<g, FACT_T, factor_lds_bytes(a.W, true), st>>>(a);
+  }
+  hip_ok(hipGetLastError(), "factor launch");
 }
 
 }  // namespace pfft

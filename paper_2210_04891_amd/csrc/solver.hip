@@ -41,6 +41,9 @@ static void precond_free(Precond *p) {
   if (p->d_tmp) hipFree(p->d_tmp);
   if (p->d_colenv) hipFree(p->d_colenv);
   if (p->d_full) hipFree(p->d_full);
+  if (p->d_om) hipFree(p->d_om);
+  if (p->d_status) hipFree(p->d_status);
+  if (p->d_gwin) hipFree(p->d_gwin);
   delete p;
 }
 
@@ -99,6 +102,13 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
     d.src_sg = pre_upload(P, ps.src_sg);
     d.link_kind = pre_upload(P, ps.link_kind);
     d.port_loop = pre_upload(P, ps.port_loop);
+    // diagonals for the device factorization
+    std::vector<double> gd(m.b, 0.0);
+    for (int e = 0; e < m.b; ++e)
+      for (int q = 0; q < 5; ++q)
+        if (m.gram_col[5 * e + q] == e) gd[e] += m.gram_val[5 * e + q];
+    P->d_gdiag = pre_upload(P, gd);
+    P->d_kdiag = pre_upload(P, m.kdiag);
     P->built = true;
   }
   // distinct frequencies of this batch
@@ -106,47 +116,109 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
   std::vector<double> uniq = om;
   std::sort(uniq.begin(), uniq.end());
   uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-  if (uniq != P->omegas) {
+  if (uniq != P->omegas || P->factor_plan != c->plans.factor) {
     const int nf = (int)uniq.size();
     const size_t ne = (size_t)P->ps.nu * std::max(P->ps.W, 1), nc = (size_t)P->ps.nu * std::max(P->ps.Wc, 1);
     const size_t nfull = P->ps.env_off[P->ps.nu];
-    std::vector<std::complex<double>> env(nf * ne), dg((size_t)nf * P->ps.nu), yi((size_t)nf * m.b),
-        ce((size_t)nf * nc), fe((size_t)nf * nfull);
-    int bad = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
-    for (int f = 0; f < nf; ++f) {
-      std::vector<std::complex<double>> e1, d1, y1, c1, f1;
-      if (!factor_precond(m, P->ps, uniq[f], c->sigma, c->mu_r, e1, d1, y1, c1, f1)) {
-        ++bad;
-        continue;
-      }
-      std::copy(e1.begin(), e1.end(), env.begin() + (size_t)f * ne);
-      std::copy(d1.begin(), d1.end(), dg.begin() + (size_t)f * P->ps.nu);
-      std::copy(y1.begin(), y1.end(), yi.begin() + (size_t)f * m.b);
-      std::copy(c1.begin(), c1.end(), ce.begin() + (size_t)f * nc);
-      std::copy(f1.begin(), f1.end(), fe.begin() + (size_t)f * nfull);
-    }
-    if (bad) throw SetupError{PFFT_EFACTOR, "zero pivot in the nodal factorization"};
     if (nf > P->cap_f) {
+      hip_ok(hipStreamSynchronize(st), "precond realloc sync");
       if (P->d_env) hipFree(P->d_env);
       if (P->d_diag) hipFree(P->d_diag);
       if (P->d_yinv) hipFree(P->d_yinv);
       if (P->d_colenv) hipFree(P->d_colenv);
       if (P->d_full) hipFree(P->d_full);
+      if (P->d_om) hipFree(P->d_om);
+      if (P->d_status) hipFree(P->d_status);
+      P->d_env = P->d_diag = P->d_yinv = P->d_colenv = P->d_full = nullptr;
+      P->d_om = nullptr;
+      P->d_status = nullptr;
+      P->cap_f = 0;
       hip_ok(hipMalloc(&P->d_full, std::max<size_t>(16, nfull * nf * sizeof(double2))), "hipMalloc full");
       hip_ok(hipMalloc(&P->d_env, std::max<size_t>(16, ne * nf * sizeof(double2))), "hipMalloc env");
       hip_ok(hipMalloc(&P->d_colenv, std::max<size_t>(16, nc * nf * sizeof(double2))), "hipMalloc colenv");
       hip_ok(hipMalloc(&P->d_diag, std::max<size_t>(16, (size_t)P->ps.nu * nf * sizeof(double2))), "hipMalloc diag");
       hip_ok(hipMalloc(&P->d_yinv, (size_t)m.b * nf * sizeof(double2)), "hipMalloc yinv");
+      hip_ok(hipMalloc(&P->d_om, (size_t)nf * sizeof(double)), "hipMalloc omegas");
+      hip_ok(hipMalloc(&P->d_status, (size_t)nf * (P->ps.ncomp + 1) * sizeof(int)), "hipMalloc status");
       P->cap_f = nf;
     }
-    hip_ok(hipStreamSynchronize(st), "precond sync");
-    if (ne) hip_ok(hipMemcpy(P->d_env, env.data(), ne * nf * sizeof(double2), hipMemcpyHostToDevice), "env");
-    if (P->ps.nu)
-      hip_ok(hipMemcpy(P->d_diag, dg.data(), (size_t)P->ps.nu * nf * sizeof(double2), hipMemcpyHostToDevice), "diag");
-    hip_ok(hipMemcpy(P->d_yinv, yi.data(), (size_t)m.b * nf * sizeof(double2), hipMemcpyHostToDevice), "yinv");
-    if (nc) hip_ok(hipMemcpy(P->d_colenv, ce.data(), nc * nf * sizeof(double2), hipMemcpyHostToDevice), "colenv");
-    if (nfull) hip_ok(hipMemcpy(P->d_full, fe.data(), nfull * nf * sizeof(double2), hipMemcpyHostToDevice), "full");
+    const int64_t scratch = c->plans.factor == 0 ? factor_device_scratch(P->ps, nf) : -1;
+    if (scratch >= 0) {
+      // device factorization, ordered after earlier work on st that reads the old factors
+      if (scratch > P->cap_gwin) {
+        hip_ok(hipStreamSynchronize(st), "factor scratch sync");
+        if (P->d_gwin) hipFree(P->d_gwin);
+        P->d_gwin = nullptr;
+        P->cap_gwin = 0;
+        hip_ok(hipMalloc(&P->d_gwin, (size_t)scratch), "hipMalloc factor window");
+        P->cap_gwin = scratch;
+      }
+      hip_ok(hipMemcpyAsync(P->d_om, uniq.data(), nf * sizeof(double), hipMemcpyHostToDevice, st), "omegas");
+      FactorArgs fa;
+      fa.nu = P->ps.nu;
+      fa.b = m.b;
+      fa.W = std::max(P->ps.W, 1);
+      fa.Wc = std::max(P->ps.Wc, 1);
+      fa.ncomp = P->ps.ncomp;
+      fa.nf = nf;
+      fa.comp_off = P->dev.comp_off;
+      fa.comp_mid = P->dev.comp_mid;
+      fa.first = P->dev.first;
+      fa.inc_off = P->dev.inc_off;
+      fa.inc_br = P->dev.inc_br;
+      fa.br_ru = P->dev.br_ru;
+      fa.br_rv = P->dev.br_rv;
+      fa.env_off = P->dev.env_off;
+      fa.nnz_full = (int64_t)nfull;
+      fa.gdiag = P->d_gdiag;
+      fa.kdiag = P->d_kdiag;
+      fa.omega = P->d_om;
+      fa.sigma = c->sigma;
+      fa.mu_r = c->mu_r;
+      fa.env = P->d_env;
+      fa.colenv = P->d_colenv;
+      fa.full = P->d_full;
+      fa.diag = P->d_diag;
+      fa.yinv = P->d_yinv;
+      fa.gwin = scratch > 0 ? P->d_gwin : nullptr;
+      fa.status = P->d_status;
+      factor_precond_device(fa, st);
+      std::vector<int> stat((size_t)nf * (P->ps.ncomp + 1));
+      hip_ok(hipMemcpyAsync(stat.data(), P->d_status, stat.size() * sizeof(int), hipMemcpyDeviceToHost, st),
+             "factor status");
+      hip_ok(hipStreamSynchronize(st), "factor sync");
+      P->omegas.clear();   // no valid factors until the check passes
+      for (int v : stat)
+        if (v) throw SetupError{PFFT_EFACTOR, "zero pivot in the nodal factorization"};
+    } else {
+      std::vector<std::complex<double>> env(nf * ne), dg((size_t)nf * P->ps.nu), yi((size_t)nf * m.b),
+          ce((size_t)nf * nc), fe((size_t)nf * nfull);
+      int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+      for (int f = 0; f < nf; ++f) {
+        std::vector<std::complex<double>> e1, d1, y1, c1, f1;
+        if (!factor_precond(m, P->ps, uniq[f], c->sigma, c->mu_r, e1, d1, y1, c1, f1)) {
+          ++bad;
+          continue;
+        }
+        std::copy(e1.begin(), e1.end(), env.begin() + (size_t)f * ne);
+        std::copy(d1.begin(), d1.end(), dg.begin() + (size_t)f * P->ps.nu);
+        std::copy(y1.begin(), y1.end(), yi.begin() + (size_t)f * m.b);
+        std::copy(c1.begin(), c1.end(), ce.begin() + (size_t)f * nc);
+        std::copy(f1.begin(), f1.end(), fe.begin() + (size_t)f * nfull);
+      }
+      if (bad) throw SetupError{PFFT_EFACTOR, "zero pivot in the nodal factorization"};
+      hip_ok(hipStreamSynchronize(st), "precond sync");
+      P->omegas.clear();
+      if (ne) hip_ok(hipMemcpy(P->d_env, env.data(), ne * nf * sizeof(double2), hipMemcpyHostToDevice), "env");
+      if (P->ps.nu)
+        hip_ok(hipMemcpy(P->d_diag, dg.data(), (size_t)P->ps.nu * nf * sizeof(double2), hipMemcpyHostToDevice),
+               "diag");
+      hip_ok(hipMemcpy(P->d_yinv, yi.data(), (size_t)m.b * nf * sizeof(double2), hipMemcpyHostToDevice), "yinv");
+      if (nc) hip_ok(hipMemcpy(P->d_colenv, ce.data(), nc * nf * sizeof(double2), hipMemcpyHostToDevice), "colenv");
+      if (nfull) hip_ok(hipMemcpy(P->d_full, fe.data(), nfull * nf * sizeof(double2), hipMemcpyHostToDevice), "full");
+    }
+    P->factor_plan = c->plans.factor;
     P->omegas = uniq;
     P->fidx_host.clear();
     P->dev.env = P->d_env;
@@ -678,7 +750,7 @@ void pfft::solve_ports_krylov(pfft_ctx *c, int nfreq, const double *freq_hz, dou
 static pfft_status solve_ports_any(const char *name, bool left, pfft_ctx *c, int32_t nfreq,
                                    const double *freq_hz, double tol, int32_t maxit, int32_t restart,
                                    int32_t precond, void *Y_out, int32_t *iters_out, double *relres_out,
-                                   void *hip_stream) {
+                                   void *hip_stream, void *Il_dev = nullptr) {
   const std::string who = std::string(name) + ": ";
   if (!c || nfreq <= 0 || !freq_hz || !Y_out || !(tol > 0) || maxit <= 0 || restart <= 0 || precond < 0 ||
       precond > (left ? 1 : 2)) {
@@ -708,6 +780,8 @@ static pfft_status solve_ports_any(const char *name, bool left, pfft_ctx *c, int
     std::vector<double> relres;
     fgmres(c, F, omega.data(), tol, maxit, precond, iters, relres, st, nullptr, left);
     std::vector<double2> xh((size_t)R * l);
+    if (Il_dev)
+      hip_ok(hipMemcpyAsync(Il_dev, F.x, xh.size() * sizeof(double2), hipMemcpyDeviceToDevice, st), "loop currents");
     hip_ok(hipMemcpyAsync(xh.data(), F.x, xh.size() * sizeof(double2), hipMemcpyDeviceToHost, st), "x");
     hip_ok(hipStreamSynchronize(st), "x sync");
     double2 *Y = (double2 *)Y_out;
@@ -741,6 +815,17 @@ pfft_status solve_ports(pfft_ctx *c, int32_t nfreq, const double *freq_hz, doubl
                         void *hip_stream) {
   return solve_ports_any("solve_ports", false, c, nfreq, freq_hz, tol, maxit, restart, precond, Y_out, iters_out,
                          relres_out, hip_stream);
+}
+
+pfft_status solve_ports_loops(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol, int32_t maxit,
+                              int32_t restart, int32_t precond, void *Y_out, int32_t *iters_out, double *relres_out,
+                              void *Il_dev, void *hip_stream) {
+  if (!Il_dev) {
+    set_error("solve_ports_loops: null loop-current buffer");
+    return PFFT_EINVAL;
+  }
+  return solve_ports_any("solve_ports_loops", false, c, nfreq, freq_hz, tol, maxit, restart, precond, Y_out,
+                         iters_out, relres_out, hip_stream, Il_dev);
 }
 
 pfft_status solve_ports_lgmres(pfft_ctx *c, int32_t nfreq, const double *freq_hz, double tol, int32_t maxit,

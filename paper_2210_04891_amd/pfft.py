@@ -28,7 +28,8 @@ EXPORTS = ("pfft_setup", "pfft_sizes", "pfft_matvec", "solve_ports", "extract_RL
            "pfft_host_setup", "pfft_host_get", "pfft_host_free", "pfft_profile",
            "pfft_stage_times", "pfft_precond_save", "pfft_learned_collect", "pfft_learned_train",
            "pfft_learned_clear", "pfft_learned_stats", "pfft_mlp_grad", "pfft_learned_eval",
-           "pfft_set_option", "pfft_get_option", "pfft_autotune", "solve_ports_lgmres")
+           "pfft_set_option", "pfft_get_option", "pfft_autotune", "solve_ports_lgmres",
+           "solve_ports_loops", "pfft_postprocess")
 
 STAGES = ("loop_to_branch", "tri_current", "project", "fft_x", "fft_y", "fft_z_conv", "ifft_y",
           "ifft_x", "interp", "combine", "branch_to_loop", "precond")
@@ -75,6 +76,10 @@ def load():
     lib.solve_ports.restype = i32
     lib.solve_ports_lgmres.argtypes = [vp, i32, vp, dbl, i32, i32, i32, vp, vp, vp, vp]
     lib.solve_ports_lgmres.restype = i32
+    lib.solve_ports_loops.argtypes = [vp, i32, vp, dbl, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.solve_ports_loops.restype = i32
+    lib.pfft_postprocess.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pfft_postprocess.restype = i32
     lib.extract_RL.argtypes = [i32, i32, vp, vp, vp, vp]
     lib.extract_RL.restype = i32
     lib.pfft_precond_load.argtypes = [vp, vp, i64]
@@ -247,6 +252,45 @@ class Context:
         """Left-preconditioned GMRES (relres is the preconditioned residual).
         Returns as solve_ports."""
         return self._solve(load().solve_ports_lgmres, freqs_hz, tol, maxit, restart, precond, stream)
+
+    def solve_ports_loops(self, freqs_hz, tol=1e-6, maxit=500, restart=60, precond=1, stream=None):
+        """solve_ports that also returns the loop currents, a device complex128
+        tensor [nf * p, l] (row f * p + k: port k driven at frequency f).
+        Returns (Y, iterations, relres, status, I_l)."""
+        import torch
+        f = np.ascontiguousarray(np.asarray(freqs_hz, np.float64).reshape(-1))
+        Il = torch.empty((f.size * self.nport, self.sizes["l"]), dtype=torch.complex128, device="cuda")
+        lib = load()
+
+        def fn(h, nf, fp, tol_, maxit_, restart_, pre, Yp, itp, rrp, st):
+            return lib.solve_ports_loops(h, nf, fp, tol_, maxit_, restart_, pre, Yp, itp, rrp,
+                                         ctypes.c_void_p(Il.data_ptr()), st)
+        Y, it, rr, code = self._solve(fn, f, tol, maxit, restart, precond, stream)
+        return Y, it, rr, code, Il
+
+    def postprocess(self, Il, omega, stream=None):
+        """Sec. V-A outputs of loop currents Il (device complex128 [R, l]) at
+        omega [R] (rad/s): dict of device tensors Vl [R, l], Ib [R, b + p],
+        Vb [R, b], J [R, n, 3], phi [R, n]."""
+        import torch
+        assert Il.dtype == torch.complex128 and Il.is_cuda and Il.dim() == 2
+        if Il.shape[1] != self.sizes["l"]:
+            raise ValueError("Il has %d columns, expected %d" % (Il.shape[1], self.sizes["l"]))
+        Il = Il.contiguous()
+        R = Il.shape[0]
+        om = np.ascontiguousarray(np.asarray(omega, np.float64).reshape(-1))
+        if om.size != R:
+            raise ValueError("omega must have one value per row of Il")
+        n, b, l, p = self.sizes["n"], self.sizes["b"], self.sizes["l"], self.nport
+        kw = dict(dtype=torch.complex128, device=Il.device)
+        out = dict(Vl=torch.empty((R, l), **kw), Ib=torch.empty((R, b + p), **kw), Vb=torch.empty((R, b), **kw),
+                   J=torch.empty((R, n, 3), **kw), phi=torch.empty((R, n), **kw))
+        vp_ = ctypes.c_void_p
+        _check(load().pfft_postprocess(self._h, R, _ptr(om), vp_(Il.data_ptr()), vp_(out["Vl"].data_ptr()),
+                                       vp_(out["Ib"].data_ptr()), vp_(out["Vb"].data_ptr()),
+                                       vp_(out["J"].data_ptr()), vp_(out["phi"].data_ptr()),
+                                       _stream_handle(stream)))
+        return out
 
     def _solve(self, fn, freqs_hz, tol, maxit, restart, precond, stream):
         f = np.ascontiguousarray(np.asarray(freqs_hz, np.float64).reshape(-1))

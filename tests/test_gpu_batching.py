@@ -61,16 +61,18 @@ def test_plans_agree_and_autotune(wires):
     import paper_2210_04891_amd as P
     ctx = _ctx(wires)
     l = ctx.sizes["l"]
-    om = 2 * np.pi * np.array([1e9, 1e10])
-    x = torch.from_numpy(W.complex_normal(31, (2, l))).cuda()
+    # 20 right-hand sides: the tiled near-field product runs (two chunks,
+    # the second ragged)
+    om = 2 * np.pi * np.repeat(np.array([1e9, 1e10]), 10)
+    x = torch.from_numpy(W.complex_normal(31, (om.size, l))).cuda()
     ref = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
-    for name in ("fft_plan", "ldl_plan", "project_plan", "stream_split"):
+    for name in ("fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split"):
         ctx.set_option(name, 1 - ctx.get_option(name))
         y = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
         ctx.set_option(name, 1 - ctx.get_option(name))
         assert np.linalg.norm(y - ref) <= 2e-6 * np.linalg.norm(ref), name
     rep = ctx.autotune(om, reps=2)
-    for name in ("fft_plan", "ldl_plan", "project_plan", "stream_split"):
+    for name in ("fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split"):
         assert rep[name]["chosen"] in (0, 1)
         assert ctx.get_option(name) == rep[name]["chosen"]
         assert rep[name]["0"] > 0 and rep[name]["1"] > 0

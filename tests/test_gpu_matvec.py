@@ -120,6 +120,50 @@ def test_loop_space_product(c1_oracle):
 
 
 @gpu
+def test_tiled_near_field_product(c1_oracle):
+    """The LDS-tiled near-field product gives the gather product's result to
+    rounding and the oracle's loop-space product to the near-field
+    quadrature agreement.  The bar's tiles stage 8 right-hand sides per
+    workgroup (here 8 + 8 + 4)."""
+    ctx = _ctx(c1_oracle["s"])
+    c = c1_oracle["circ"]
+    om = 2 * np.pi * np.geomspace(1e7, 3e10, 20)
+    X = W.complex_normal(9, (20, c.nloop))
+    assert ctx.get_option("combine_plan") == 0
+    yt = ctx.matvec(_dev(X), omega=om, space=1).cpu().numpy()
+    ctx.set_option("combine_plan", 1)
+    yg = ctx.matvec(_dev(X), omega=om, space=1).cpu().numpy()
+    for r in range(20):
+        assert _rel(yt[r], yg[r]) < 1e-13
+    for r in (0, 7, 19):
+        ref_p = _oracle_loop(c1_oracle, c1_oracle["op"].apply, om[r], X[r])
+        assert _rel(yt[r], ref_p) < 1e-6
+
+
+@gpu
+@pytest.mark.parametrize("nrhs", [16, 20, 37])
+def test_tiled_near_field_product_16(nrhs):
+    """Wire array whose tiles stage 16 right-hand sides per workgroup (rows
+    share their nonzeros through lane broadcasts): tiled against gather, with
+    a ragged last group, in the branch space (K only) and the loop space.
+    Both sum a row's nonzeros in the same order; the compiled FMA sequences
+    differ, so the results agree to rounding, not bit for bit."""
+    import paper_2210_04891_amd as P
+    s = W.bond_wires(nwire=2, nseg=24, span=0.4e-3, height=80e-6)
+    ctx = P.Context(s, (32, 32, 16), stencil=4, near_kappa=1.5, grid_fp64=True)
+    b, l = ctx.sizes["b"], ctx.sizes["l"]
+    om = 2 * np.pi * np.geomspace(1e7, 3e10, nrhs)
+    for space, dim in ((0, b), (1, l)):
+        X = _dev(W.complex_normal(11 + space, (nrhs, dim)))
+        ctx.set_option("combine_plan", 0)
+        yt = ctx.matvec(X, omega=om, space=space).cpu().numpy()
+        ctx.set_option("combine_plan", 1)
+        yg = ctx.matvec(X, omega=om, space=space).cpu().numpy()
+        for r in range(nrhs):
+            assert _rel(yt[r], yg[r]) < 1e-13, (space, r)
+
+
+@gpu
 def test_loop_transforms_alone(c1_oracle):
     """With the grid term only, compare A^T/A against the explicit loop
     matrix at FP64 rounding: y = A (j w/4pi K_far + Zs G) A^T x."""

@@ -33,17 +33,31 @@ def e1_bar():
     return (s,) + oracle_system(s)
 
 
+@pytest.fixture(scope="module")
+def bar3():
+    """One bar with three ports (x, y and z face pairs): three supernodes in
+    one conductor."""
+    from workloads.geometry import box_bar
+    s = box_bar(np.linspace(0.0, 100e-6, 13), np.linspace(0.0, 6e-6, 3), np.linspace(0.0, 4e-6, 3))
+    fo = s.params["face_of"]
+    s.ports = [(np.nonzero(fo == a)[0].astype(np.int32), np.nonzero(fo == b)[0].astype(np.int32))
+               for a, b in (("x0", "x1"), ("y0", "y1"), ("z0", "z1"))]
+    return (s,) + oracle_system(s)
+
+
 @gpu
+@pytest.mark.parametrize("factor", ["device", "host"])
 @pytest.mark.parametrize("plan", ["register", "lds"])
-@pytest.mark.parametrize("which", ["e1_bar", "two_wires"])
-def test_precond_matches_dense_inverse(which, plan, request):
-    """Both band-solve plans (register window, LDS window) against the
-    oracle's dense inverse."""
+@pytest.mark.parametrize("which", ["e1_bar", "two_wires", "bar3"])
+def test_precond_matches_dense_inverse(which, plan, factor, request):
+    """Both band-solve plans (register window, LDS window) and both
+    factorizations (device, host) against the oracle's dense inverse."""
     import paper_2210_04891_amd as P
     s, m, c, K, A, Zb = request.getfixturevalue(which)
-    grid = (32, 8, 8) if which == "e1_bar" else (32, 16, 16)
+    grid = (32, 16, 16) if which == "two_wires" else (32, 8, 8)
     ctx = P.Context(s, grid, near_kappa=1.5, grid_fp64=True)
     ctx.set_option("ldl_plan", 1 if plan == "lds" else 0)
+    ctx.set_option("factor_plan", 1 if factor == "host" else 0)
     om = 2 * np.pi * np.array([1e9, 1e10, 3e10])
     Y = W.complex_normal(7, (3, c.nloop))
     z = ctx.matvec(_dev(Y), omega=om, space=1, flags=P.PFFT_PRECOND_ONLY).cpu().numpy()
@@ -52,6 +66,27 @@ def test_precond_matches_dense_inverse(which, plan, request):
         Pd = A @ D @ A.T
         ref = np.linalg.solve(Pd, Y[r])
         assert np.linalg.norm(z[r] - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+@gpu
+def test_device_and_host_factors_agree():
+    """The device factorization reproduces the host one (same ordering, same
+    arithmetic up to rounding) on a four-wire array over a sweep, and a
+    changed plan refactors."""
+    import paper_2210_04891_amd as P
+    s = W.bond_wires(nwire=4, nseg=40, span=0.6e-3, height=100e-6)
+    ctx = P.Context(s, (64, 16, 16), near_kappa=1.5, grid_fp64=False)
+    l = ctx.sizes["l"]
+    om = 2 * np.pi * np.repeat(np.logspace(6, 10.5, 6), 2)
+    Y = _dev(W.complex_normal(11, (om.size, l)))
+    zd = ctx.matvec(Y, omega=om, space=1, flags=P.PFFT_PRECOND_ONLY).cpu().numpy()
+    ctx.set_option("factor_plan", 1)
+    zh = ctx.matvec(Y, omega=om, space=1, flags=P.PFFT_PRECOND_ONLY).cpu().numpy()
+    ctx.set_option("factor_plan", 0)
+    zd2 = ctx.matvec(Y, omega=om, space=1, flags=P.PFFT_PRECOND_ONLY).cpu().numpy()
+    for r in range(om.size):
+        assert np.linalg.norm(zd[r] - zh[r]) <= 1e-12 * np.linalg.norm(zh[r])
+    assert np.array_equal(zd, zd2)
 
 
 @gpu
