@@ -273,9 +273,10 @@ pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const 
  *   "factor_plan"  0 (default) the LDL^T factors of the nodal matrix of P
  *                    (one per distinct frequency) are computed on the device,
  *                    one workgroup per conductor and frequency, when no
- *                    conductor carries more than 4 ports; 1 on the host
- *                    (OpenMP over frequencies).  Changing it refactors at the
- *                    next use of P.
+ *                    conductor carries more than 4 ports and the band window
+ *                    fits in LDS (band width up to about 85), else on the
+ *                    host; 1 always on the host (OpenMP over frequencies).
+ *                    Changing it refactors at the next use of P.
  * PFFT_EINVAL for an unknown name or value. */
 pfft_status pfft_set_option(pfft_ctx *c, const char *name, int64_t value);
 pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *value);

@@ -483,6 +483,17 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
     g.tt_tri = upload(c, tt_tri, st);
     g.pg_loc = upload(c, pg_loc, st);
   }
+  {
+    std::vector<int> act, act_of(N, -1);
+    for (long node = 0; node < N; ++node)
+      if (pg_off[node + 1] > pg_off[node]) {
+        act_of[node] = (int)act.size();
+        act.push_back((int)node);
+      }
+    g.nact = (int)act.size();
+    g.act = upload(c, act, st);
+    g.act_of = upload(c, act_of, st);
+  }
   g.pg_off = upload(c, pg_off, st);
   g.pg_tri = upload(c, pg_tri, st);
   if (c->grid_fp64) {

@@ -68,6 +68,10 @@ struct GridMaps {
   // contiguous.  An entry is the triangle's LDS slot (>= 0) or -1 - triangle
   // (beyond tcap, read from memory); shorter lists are padded with slot 0
   // and zero weights.
+  // active nodes (touched by some triangle's stencil): act[a] is the a-th in
+  // ascending order, act_of[node] its position (-1 for the others)
+  int nact;
+  const int *act, *act_of;
   int nwave;
   const int *ps_off, *ps_k, *ps_ent;
   const void *ps_w;      // [entries][4] (M0, M1x, M1y, M1z) in T

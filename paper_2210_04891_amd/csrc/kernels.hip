@@ -1309,23 +1309,28 @@ __global__ void k_interp_tri(GridMaps g, const V2<T> *phi, double2 *U, int R) {
   }
 }
 
-// FP32 path: phi is first transposed to node-major [N][3R] (channel
-// innermost), then one workgroup per triangle reads each stencil node's 3R
-// channels as one coalesced row; the triangle's weights are uniform (scalar
-// loads).  Lane (r, c) accumulates M1_c phi_c and M0 phi_c; the three
-// components of U0 are summed through LDS.
-__global__ void __launch_bounds__(256) k_transpose_c64(const float2 *in, float2 *out, int rows, int cols) {
+// FP32 path: phi is first transposed to node-major [N_a][3R] (channel
+// innermost) over the N_a active nodes only (those some triangle's stencil
+// touches; every other node is never read), then one workgroup per triangle
+// reads each stencil node's 3R channels as one coalesced row; the triangle's
+// weights and the nodes' compact indices are uniform (scalar loads).  Lane
+// (r, c) accumulates M1_c phi_c and M0 phi_c; the three components of U0 are
+// summed through LDS.
+// out[a][r] = in[r][act[a]] for the na active nodes (in: rows x N, out: na x rows)
+__global__ void __launch_bounds__(256) k_transpose_c64(const float2 *in, float2 *out, int rows, int N, int na,
+                                                       const int *act) {
   __shared__ float2 tile[32][33];
-  const int c0 = (int)xcd_block(blockIdx.x, gridDim.x) * 32, r0 = blockIdx.y * 32;
+  const int a0 = (int)xcd_block(blockIdx.x, gridDim.x) * 32, r0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const int node = a0 + tx < na ? act[a0 + tx] : 0;
   for (int k = ty; k < 32; k += 8) {
-    const int r = r0 + k, c = c0 + tx;
-    if (r < rows && c < cols) tile[k][tx] = in[(size_t)r * cols + c];
+    const int r = r0 + k;
+    if (r < rows && a0 + tx < na) tile[k][tx] = in[(size_t)r * N + node];
   }
   __syncthreads();
   for (int k = ty; k < 32; k += 8) {
-    const int c = c0 + k, r = r0 + tx;
-    if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[tx][k];
+    const int a = a0 + k, r = r0 + tx;
+    if (r < rows && a < na) out[(size_t)a * rows + r] = tile[tx][k];
   }
 }
 
@@ -1347,8 +1352,9 @@ __global__ void __launch_bounds__(256) k_interp_nm(GridMaps g, const float2 *phi
     for (int k = 0; k < 64; ++k) {
       const int i = k >> 4, j = (k >> 2) & 3, l = k & 3;
       const long node = ((long)(ax + i) * Ny + (ay + j)) * Nz + (az + l);
+      const int an = g.act_of[node];
       const float m0 = w[4 * k], m1 = w[4 * k + 1 + c];
-      const float2 v = ok ? phiT[(size_t)node * ch + chn] : make_float2(0.f, 0.f);
+      const float2 v = ok ? phiT[(size_t)an * ch + chn] : make_float2(0.f, 0.f);
       a0x += (double)m1 * v.x;
       a0y += (double)m1 * v.y;
       a1x += (double)m0 * v.x;
@@ -1381,7 +1387,7 @@ void interp_tri<float>(const GridMaps &g, const float2 *phi, double2 *U, int R, 
   // node-major copy of phi (N x 3R complex64) in the caller's free scratch
   float2 *phiT = (float2 *)scratch;
   const int ch = 3 * R;
-  k_transpose_c64<<<dim3(cdiv(g.N, 32), cdiv(ch, 32)), 256, 0, st>>>(phi, phiT, ch, g.N);
+  k_transpose_c64<<<dim3(cdiv(g.nact, 32), cdiv(ch, 32)), 256, 0, st>>>(phi, phiT, ch, g.N, g.nact, g.act);
   k_interp_nm<<<(unsigned)g.n, 256, 0, st>>>(g, phiT, U, R);
 }
 

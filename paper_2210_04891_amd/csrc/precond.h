@@ -65,7 +65,7 @@ bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, d
 // Device factorization: the same factor, in the same layouts, as
 // factor_precond, for nf frequencies at once (one workgroup per conductor and
 // frequency, right-looking over the band with the active (W+1) x (W+1)
-// window in LDS, or in global scratch when it does not fit).  The branch
+// window in LDS).  The branch
 // admittances 1/D_e are formed on the device from the Gram and kernel
 // diagonals.  FACT_NS bounds the supernode rows of a conductor.
 constexpr int FACT_NS = 4;
@@ -78,12 +78,11 @@ struct FactorArgs {
   const double *omega;               // [nf] rad/s (device)
   double sigma, mu_r;
   double2 *env, *colenv, *full, *diag, *yinv;
-  double2 *gwin;                     // [nf][ncomp][(W+1)^2 + FACT_NS (W+1)] or null (LDS window)
   int *status;                       // [nf * ncomp + nf]: nonzero on a zero pivot / impedance
 };
-// Bytes of global window scratch the factorization needs (0: LDS suffices),
-// or -1 when the structure does not suit the device kernel.
-int64_t factor_device_scratch(const PrecondStruct &ps, int nf);
+// Whether the device factorization applies: every conductor carries at most
+// FACT_NS supernode rows and the band window fits in LDS (W up to about 85).
+bool factor_device_ok(const PrecondStruct &ps);
 void factor_precond_device(const FactorArgs &a, hipStream_t st);
 
 struct PrecondDev {
@@ -128,9 +127,6 @@ struct Precond {
   // device factorization inputs and scratch
   double *d_gdiag = nullptr, *d_kdiag = nullptr, *d_om = nullptr;
   int *d_status = nullptr;
-  double2 *d_gwin = nullptr;
-  int cap_om = 0;
-  int64_t cap_gwin = 0;
   int factor_plan = -1;                  // plan the current factors were made with
 };
 

@@ -848,7 +848,6 @@ __device__ __forceinline__ bool bad_pivot(double2 d) {
 // factored last.  L is written in place over the assembled values: row i's
 // assembled entries are read when it enters the window, before any of its L
 // entries is stored.
-template <bool LW>
 __global__ void __launch_bounds__(FACT_T) k_ldl_factor(FactorArgs a) {
   extern __shared__ double2 fsm[];
   const int c = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
@@ -860,14 +859,7 @@ __global__ void __launch_bounds__(FACT_T) k_ldl_factor(FactorArgs a) {
   double2 *full = a.full + (size_t)f * a.nnz_full;
   double2 *dg = a.diag + (size_t)f * a.nu;
   double2 *lcol = fsm, *ucol = fsm + Wp, *lsn = ucol + Wp, *usn = lsn + FACT_NS, *S = usn + FACT_NS;
-  double2 *win, *swin;
-  if (LW) {
-    win = S + FACT_NS * FACT_NS;
-    swin = win + Wp * Wp;
-  } else {
-    win = a.gwin + ((size_t)f * a.ncomp + c) * ((size_t)Wp * Wp + FACT_NS * Wp);
-    swin = win + (size_t)Wp * Wp;
-  }
+  double2 *win = S + FACT_NS * FACT_NS, *swin = win + Wp * Wp;
   const double2 zero = make_double2(0, 0);
   // window rows lo .. lo+W (slot = row - lo)
   for (int idx = tid; idx < Wp * Wp; idx += FACT_T) {
@@ -1004,11 +996,9 @@ __global__ void k_fill_int(int *p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
-static size_t factor_lds_bytes(int W, bool lw) {
+static size_t factor_lds_bytes(int W) {
   const size_t Wp = (size_t)W + 1;
-  size_t n = 2 * Wp + 2 * FACT_NS + FACT_NS * FACT_NS;
-  if (lw) n += Wp * Wp + FACT_NS * Wp;
-  return n * sizeof(double2);
+  return (2 * Wp + 2 * FACT_NS + FACT_NS * FACT_NS + Wp * Wp + FACT_NS * Wp) * sizeof(double2);
 }
 
 static bool factor_allow_lds(const void *fn, size_t bytes) {
@@ -1024,14 +1014,10 @@ static bool factor_allow_lds(const void *fn, size_t bytes) {
   return true;
 }
 
-int64_t factor_device_scratch(const PrecondStruct &ps, int nf) {
+bool factor_device_ok(const PrecondStruct &ps) {
   for (int c = 0; c < ps.ncomp; ++c)
-    if (ps.comp_off[c + 1] - ps.comp_mid[c] > FACT_NS) return -1;
-  const int W = std::max(ps.W, 1);
-  if (factor_lds_bytes(W, false) > 131072) return -1;
-  if (factor_allow_lds((const void *)k_ldl_factor<true>, factor_lds_bytes(W, true))) return 0;
-  const int64_t Wp = W + 1;
-  return (int64_t)nf * ps.ncomp * (Wp * Wp + FACT_NS * Wp) * (int64_t)sizeof(double2);
+    if (ps.comp_off[c + 1] - ps.comp_mid[c] > FACT_NS) return false;
+  return factor_allow_lds((const void *)k_ldl_factor, factor_lds_bytes(std::max(ps.W, 1)));
 }
 
 void factor_precond_device(const FactorArgs &a, hipStream_t st) {
@@ -1039,14 +1025,7 @@ void factor_precond_device(const FactorArgs &a, hipStream_t st) {
   k_fill_int<<<(nst + 255) / 256, 256, 0, st>>>(a.status, nst, 0);
   k_fac_yinv<<<dim3((a.b + 255) / 256, a.nf), 256, 0, st>>>(a);
   k_fac_assemble<<<dim3((a.nu + 255) / 256, a.nf), 256, 0, st>>>(a);
-  const dim3 g(a.ncomp, a.nf);
-  if (a.gwin) {
-    if (!factor_allow_lds((const void *)k_ldl_factor<false>, factor_lds_bytes(a.W, false)))
-      throw SetupError{-1, "preconditioner factorization: LDS request refused"};
-    k_ldl_factor<false><<<g, FACT_T, factor_lds_bytes(a.W, false), st>>>(a);
-  } else {
-    k_ldl_factor<true><<<g, FACT_T, factor_lds_bytes(a.W, true), st>>>(a);
-  }
+  k_ldl_factor<<<dim3(a.ncomp, a.nf), FACT_T, factor_lds_bytes(a.W), st>>>(a);
   hip_ok(hipGetLastError(), "factor launch");
 }
 

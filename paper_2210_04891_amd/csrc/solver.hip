@@ -43,7 +43,6 @@ static void precond_free(Precond *p) {
   if (p->d_full) hipFree(p->d_full);
   if (p->d_om) hipFree(p->d_om);
   if (p->d_status) hipFree(p->d_status);
-  if (p->d_gwin) hipFree(p->d_gwin);
   delete p;
 }
 
@@ -142,17 +141,8 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
       hip_ok(hipMalloc(&P->d_status, (size_t)nf * (P->ps.ncomp + 1) * sizeof(int)), "hipMalloc status");
       P->cap_f = nf;
     }
-    const int64_t scratch = c->plans.factor == 0 ? factor_device_scratch(P->ps, nf) : -1;
-    if (scratch >= 0) {
+    if (c->plans.factor == 0 && factor_device_ok(P->ps)) {
       // device factorization, ordered after earlier work on st that reads the old factors
-      if (scratch > P->cap_gwin) {
-        hip_ok(hipStreamSynchronize(st), "factor scratch sync");
-        if (P->d_gwin) hipFree(P->d_gwin);
-        P->d_gwin = nullptr;
-        P->cap_gwin = 0;
-        hip_ok(hipMalloc(&P->d_gwin, (size_t)scratch), "hipMalloc factor window");
-        P->cap_gwin = scratch;
-      }
       hip_ok(hipMemcpyAsync(P->d_om, uniq.data(), nf * sizeof(double), hipMemcpyHostToDevice, st), "omegas");
       FactorArgs fa;
       fa.nu = P->ps.nu;
@@ -180,7 +170,6 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
       fa.full = P->d_full;
       fa.diag = P->d_diag;
       fa.yinv = P->d_yinv;
-      fa.gwin = scratch > 0 ? P->d_gwin : nullptr;
       fa.status = P->d_status;
       factor_precond_device(fa, st);
       std::vector<int> stat((size_t)nf * (P->ps.ncomp + 1));
