@@ -423,9 +423,13 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
       g.ntile[d] = nt3[d];
     }
     g.tn_perm = upload(c, tn_perm, st);
-    // LDS: tcap triangles x 4 (FP32) or 2 (FP64) right-hand sides x 4 moments
-    // at a 144-byte pitch (53 KB: three 512-thread workgroups per CU)
-    g.tcap = 376;
+    // LDS: tcap triangles x 16 (FP32) or 2 (FP64) right-hand sides x 4
+    // moments at a 528- or 144-byte pitch, at most 120 KB (or 53 KB)
+    {
+      int tmax = 1;
+      for (long T = 0; T < ntile; ++T) tmax = std::max(tmax, tt_off[T + 1] - tt_off[T]);
+      g.tcap = c->grid_fp64 ? 376 : std::min(tmax, 232);
+    }
     // sliced gather lists in the tile's node order
     {
       const int nwave = (TN + 63) / 64;

@@ -346,36 +346,45 @@ __global__ void k_project(GridMaps g, const V2<T> *J, V2<T> *Q, int R) {
 template <typename T> struct ProjRC;
 template <> struct ProjRC<float> { static constexpr int v = 4; };
 template <> struct ProjRC<double> { static constexpr int v = 2; };
-// LDS pitch of one staged triangle: its RC x 4 moments (128 bytes) plus 16
-// bytes, so that the 16-byte reads of lanes gathering different triangles
-// spread over the banks (a 128-byte pitch maps them to two bank groups)
-template <typename T> constexpr int proj_pitch() { return ProjRC<T>::v * 4 + 16 / (int)sizeof(V2<T>); }
+// groups of RC right-hand sides per workgroup: its wavefronts take (node
+// chunk, group) pairs, so a tile's few active node chunks keep all of them
+// busy
+template <typename T> struct ProjRG;
+template <> struct ProjRG<float> { static constexpr int v = 4; };
+template <> struct ProjRG<double> { static constexpr int v = 1; };
+// LDS pitch of one staged triangle: its RG x RC x 4 moments plus 16 bytes, so
+// that the 16-byte reads of lanes gathering different triangles spread over
+// the banks (a pitch that is a multiple of 128 bytes maps them to two bank
+// groups)
+template <typename T> constexpr int proj_pitch() {
+  return ProjRG<T>::v * ProjRC<T>::v * 4 + 16 / (int)sizeof(V2<T>);
+}
 
 template <typename T>
 __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *J, V2<T> *Q, int R) {
-  constexpr int RC = ProjRC<T>::v;
+  constexpr int RC = ProjRC<T>::v, RG = ProjRG<T>::v, RB = RC * RG;
   extern __shared__ unsigned char smraw[];
   constexpr int PS = proj_pitch<T>();
-  V2<T> *sJ = (V2<T> *)smraw;   // [tcap][PS]: (rr, comp) at rr * 4 + comp
+  V2<T> *sJ = (V2<T> *)smraw;   // [tcap][PS]: (rr, comp) at rr * 4 + comp, rr < RB
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = blockIdx.y * RC, nr = min(RC, R - r0);
+  const int rb0 = blockIdx.y * RB, nrb = min(RB, R - rb0);
   const int t0 = g.tt_off[tile], nt = g.tt_off[tile + 1] - t0;
   const int ns = min(nt, g.tcap);
   // staging, four loads in flight per thread
-  const int tot = ns * RC * 4;
+  const int tot = ns * RB * 4;
   for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * blockDim.x) {
     V2<T> v[4];
 #pragma unroll
     for (int u2 = 0; u2 < 4; ++u2) {
       const int i = min(i0 + u2 * (int)blockDim.x, tot - 1);
-      const int lt = i / (RC * 4), rem = i - lt * (RC * 4), rr = rem >> 2, comp = rem & 3;
-      v[u2] = rr < nr ? J[((size_t)g.tt_tri[t0 + lt] * R + r0 + rr) * 4 + comp] : cmk<T>(0, 0);
+      const int lt = i / (RB * 4), rem = i - lt * (RB * 4), rr = rem >> 2, comp = rem & 3;
+      v[u2] = rr < nrb ? J[((size_t)g.tt_tri[t0 + lt] * R + rb0 + rr) * 4 + comp] : cmk<T>(0, 0);
     }
 #pragma unroll
     for (int u2 = 0; u2 < 4; ++u2) {
       const int i = i0 + u2 * (int)blockDim.x;
       if (i < tot) {
-        const int lt = i / (RC * 4), rem = i - lt * (RC * 4);
+        const int lt = i / (RB * 4), rem = i - lt * (RB * 4);
         sJ[lt * PS + rem] = v[u2];
       }
     }
@@ -385,7 +394,12 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
   const int tz = tile % g.ntile[2], ty = (tile / g.ntile[2]) % g.ntile[1], tx = tile / (g.ntile[2] * g.ntile[1]);
   const int Ny = g.dims[1], Nz = g.dims[2];
   const int TN = TX * TY * TZ;
-  for (int uu = threadIdx.x; uu < TN; uu += blockDim.x) {
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int p = threadIdx.x >> 6; p < g.nwave * RG; p += nw) {
+    const int chunk = p / RG, grp = p - chunk * RG;
+    const int uu = chunk * 64 + lane;
+    const int r0 = rb0 + grp * RC, nr = min(RC, R - r0);
+    if (uu >= TN || nr <= 0) continue;
     const int u = g.tn_perm[(size_t)tile * TN + uu];
     const int iz = u % TZ, iy = (u / TZ) % TY, ix = u / (TZ * TY);
     const int x = tx * TX + ix, y = ty * TY + iy, z = tz * TZ + iz;
@@ -396,9 +410,9 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
     for (int q = 0; q < RC; ++q)
 #pragma unroll
       for (int c = 0; c < 6; ++c) acc[q][c] = 0;
-    // the wavefront's sliced list: entry k of this lane at 64 k + lane, in
+    // the chunk's sliced list: entry k of this lane at 64 k + lane, in
     // groups of 4 so that several loads are in flight; pads add zero
-    const int sidx = tile * g.nwave + (uu >> 6), lane = uu & 63;
+    const int sidx = tile * g.nwave + chunk;
     const int off = g.ps_off[sidx], K = g.ps_k[sidx];
     const int *ent = g.ps_ent + off + lane;
     const T *wl = (const T *)g.ps_w + 4 * ((size_t)off + lane);
@@ -422,7 +436,7 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
 #pragma unroll
           for (int q = 0; q < RC; ++q)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) jv[q][c] = sJ[loc * PS + q * 4 + c];
+            for (int c = 0; c < 4; ++c) jv[q][c] = sJ[loc * PS + (grp * RC + q) * 4 + c];
         } else {
           const V2<T> *jt = J + ((size_t)(-1 - loc) * R + r0) * 4;
 #pragma unroll
@@ -457,11 +471,13 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
 template <typename T>
 void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st) {
   constexpr int RC = ProjRC<T>::v;
+  // largest staging any context asks for: 232 (FP32) or 376 (FP64) triangles
+  constexpr int lds_max = (sizeof(T) == 4 ? 232 : 376) * proj_pitch<T>() * (int)sizeof(V2<T>);
+  static const bool lds_ok = allow_lds((const void *)k_project_tiled<T>, lds_max);
   const size_t lds = (size_t)g.tcap * proj_pitch<T>() * sizeof(V2<T>);
-  static bool lds_ok = allow_lds((const void *)k_project_tiled<T>, (int)lds);
-  if (lds_ok && g.proj_plan == 0) {
+  if (lds_ok && g.proj_plan == 0 && lds <= (size_t)lds_max) {
     const unsigned ntile = (unsigned)g.ntile[0] * g.ntile[1] * g.ntile[2];
-    k_project_tiled<T><<<dim3(ntile, cdiv(R, RC)), 512, lds, st>>>(g, J, Q, R);
+    k_project_tiled<T><<<dim3(ntile, cdiv(R, RC * ProjRG<T>::v)), 512, lds, st>>>(g, J, Q, R);
   } else {
     k_project<T><<<dim3(cdiv(g.N, 256), cdiv(R, PRG)), 256, 0, st>>>(g, J, Q, R);
   }
