@@ -34,6 +34,9 @@ struct PrecondStruct {
   // row's envelope starts later)
   int Wc = 0;
   std::vector<int> clast;         // [nu]
+  // pitches of the padded row / column layouts: 64 (zero beyond the band)
+  // when both band widths are at most 63, else max(W, 1) / max(Wc, 1)
+  int pr = 1, pc = 1;
   std::vector<int64_t> col_off;   // [nu+1]
   // branch data (mesh edges)
   std::vector<int> br_ru, br_rv;  // unknown of merged end nodes (-1: ground)
@@ -55,8 +58,8 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps);
 // Factor for one angular frequency: envelope values (unit lower L), diagonal
 // and the branch admittances 1/D_e.  Returns false on a zero pivot.
 // The solve kernel reads L in two padded layouts (no per-row offsets):
-//   rowpad[i][t] = L(i, i-1-t) for t < W   (zero outside row i's envelope)
-//   colpad[j][t] = L(j+1+t, j) for t < Wc  (zero outside column j's profile)
+//   rowpad[i][t] = L(i, i-1-t) for t < pr  (zero outside row i's envelope)
+//   colpad[j][t] = L(j+1+t, j) for t < pc  (zero outside column j's profile)
 bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, double sigma, double mu_r,
                     std::vector<std::complex<double>> &rowpad, std::vector<std::complex<double>> &diag,
                     std::vector<std::complex<double>> &yinv, std::vector<std::complex<double>> &colpad,
@@ -70,7 +73,8 @@ bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, d
 // diagonals.  FACT_NS bounds the supernode rows of a conductor.
 constexpr int FACT_NS = 4;
 struct FactorArgs {
-  int nu, b, W, Wc, ncomp, nf;       // W, Wc: layout widths max(W, 1), max(Wc, 1)
+  int nu, b, W, Wc, ncomp, nf;       // W, Wc: max(W, 1), max(Wc, 1)
+  int pr, pc;                        // layout pitches
   const int *comp_off, *comp_mid, *first, *inc_off, *inc_br, *br_ru, *br_rv;
   const int64_t *env_off;
   int64_t nnz_full;
@@ -87,13 +91,14 @@ void factor_precond_device(const FactorArgs &a, hipStream_t st);
 
 struct PrecondDev {
   int nu, ncomp, W, Wc, b, l, p, nf;
+  int pr, pc;            // pitches of the padded row / column layouts
   const int *comp_off, *comp_mid, *first, *clast;
   int64_t nnz_full;
   const double2 *full;   // [nf][env_off[nu]] row envelopes (used for supernode rows)
   const int64_t *env_off, *col_off;
   int64_t nnz_col;       // nu * Wc
-  const double2 *colenv; // [nf][nu][Wc] padded columns
-  const double2 *env;    // [nf][nu][W] padded rows
+  const double2 *colenv; // [nf][nu][pc] padded columns
+  const double2 *env;    // [nf][nu][pr] padded rows
   const double2 *diag;   // [nf][nu]
   const double2 *yinv;   // [nf][b]
   const int *br_ru, *br_rv, *br_link, *br_offu, *br_offv;

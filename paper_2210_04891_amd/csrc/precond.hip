@@ -170,6 +170,12 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
     ps.col_off[j + 1] = ps.col_off[j] + (ps.clast[j] - j);
     ps.Wc = std::max(ps.Wc, ps.clast[j] - j);
   }
+  if (ps.W <= 63 && ps.Wc <= 63) {
+    ps.pr = ps.pc = 64;
+  } else {
+    ps.pr = std::max(ps.W, 1);
+    ps.pc = std::max(ps.Wc, 1);
+  }
   // branches
   ps.br_ru.resize(b);
   ps.br_rv.resize(b);
@@ -273,9 +279,9 @@ bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, d
     if (std::abs(d) == 0.0 || !std::isfinite(d.real()) || !std::isfinite(d.imag())) return false;
     diag[i] = d;
   }
-  const int W = std::max(ps.W, 1), Wc = std::max(ps.Wc, 1);
-  rowpad.assign((size_t)nu * W, 0.0);
-  colpad.assign((size_t)nu * Wc, 0.0);
+  const int W = std::max(ps.W, 1), pr = ps.pr, pc = ps.pc;
+  rowpad.assign((size_t)nu * pr, 0.0);
+  colpad.assign((size_t)nu * pc, 0.0);
   for (int i = 0; i < nu; ++i) {
     if (i - ps.first[i] > W) continue;             // supernode row: kept in env only
     if (ps.clast[i] < i) continue;
@@ -285,8 +291,8 @@ bool factor_precond(const HostModel &m, const PrecondStruct &ps, double omega, d
     if (!is_band) continue;
     for (int j = ps.first[i]; j < i; ++j) {
       cd v = env[ps.env_off[i] + (j - ps.first[i])];
-      rowpad[(size_t)i * W + (i - 1 - j)] = v;
-      colpad[(size_t)j * Wc + (i - j - 1)] = v;
+      rowpad[(size_t)i * pr + (i - 1 - j)] = v;
+      colpad[(size_t)j * pc + (i - j - 1)] = v;
     }
   }
   return true;
@@ -454,14 +460,12 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
   const int lo = d.comp_off[c], hi = d.comp_off[c + 1], mid = d.comp_mid[c];
   if (lo >= hi) return;
   const int f = fidx[r];
-  const int W = max(d.W, 1), Wc = max(d.Wc, 1);
-  const double2 *rowp = d.env + (size_t)f * d.nu * W;
-  const double2 *colp = d.colenv + (size_t)f * d.nu * Wc;
-  const double2 *full = d.full + (size_t)f * d.nnz_full;
-  const double2 *dg = d.diag + (size_t)f * d.nu;
+  const int W = max(d.W, 1), Wc = max(d.Wc, 1), pr = d.pr, pc = d.pc;
+  const double2 *rowp = d.env + (size_t)f * d.nu * pr;
+  const double2 *colp = d.colenv + (size_t)f * d.nu * pc;
   double2 *x = work + (size_t)r * d.nu;
   const double2 zero = make_double2(0, 0);
-  const unsigned row_bytes = (unsigned)d.nu * (unsigned)W * 16u, col_bytes = (unsigned)d.nu * (unsigned)Wc * 16u;
+  const unsigned row_bytes = (unsigned)d.nu * (unsigned)pr * 16u, col_bytes = (unsigned)d.nu * (unsigned)pc * 16u;
   const __amdgpu_buffer_rsrc_t rrow = __builtin_amdgcn_make_buffer_rsrc((void *)rowp, (short)0, (int)row_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t rcol = __builtin_amdgcn_make_buffer_rsrc((void *)colp, (short)0, (int)col_bytes, 0x00020000);
   const unsigned lane16 = (unsigned)lane * 16u;
@@ -471,7 +475,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
     int loaded_hi = lo;
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
-      const double2 v = band_load(rcol, lane16, (unsigned)(lo + q) * (unsigned)Wc * 16u);
+      const double2 v = band_load(rcol, lane16, (unsigned)(lo + q) * (unsigned)pc * 16u);
       cur[q] = (lo + q < mid && lane < Wc) ? v : zero;
     }
     for (int i0 = lo; i0 < mid; i0 += PF) {
@@ -479,7 +483,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
         const int i = i0 + PF + q;
-        const double2 v = band_load(rcol, lane16, (unsigned)i * (unsigned)Wc * 16u);
+        const double2 v = band_load(rcol, lane16, (unsigned)i * (unsigned)pc * 16u);
         nxt[q] = (i < mid && lane < Wc) ? v : zero;
       }
       const int need = min(mid, i0 + nb + Wc);
@@ -501,7 +505,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
           t.y -= cur[q].x * yi.y + cur[q].y * yi.x;
         }
         for (int t2 = 64 + lane; t2 < Wc && i + 1 + t2 < mid; t2 += 64) {   // columns taller than 64
-          double2 l2 = colp[(size_t)i * Wc + t2];
+          double2 l2 = colp[(size_t)i * pc + t2];
           double2 &t = win[(i + 1 + t2) & (WP - 1)];
           t.x -= l2.x * yi.x - l2.y * yi.y;
           t.y -= l2.x * yi.y + l2.y * yi.x;
@@ -522,7 +526,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       const int i = mid - 1 - q;
-      const double2 v = band_load(rrow, lane16, (unsigned)max(i, 0) * (unsigned)W * 16u);
+      const double2 v = band_load(rrow, lane16, (unsigned)max(i, 0) * (unsigned)pr * 16u);
       cur[q] = (i >= lo && lane < W) ? v : zero;
     }
     for (int i0 = mid - 1; i0 >= lo; i0 -= PF) {
@@ -530,7 +534,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
         const int i = i0 - PF - q;
-        const double2 v = band_load(rrow, lane16, (unsigned)max(i, 0) * (unsigned)W * 16u);
+        const double2 v = band_load(rrow, lane16, (unsigned)max(i, 0) * (unsigned)pr * 16u);
         nxt[q] = (i >= lo && lane < W) ? v : zero;
       }
       const int target = max(lo, i0 - (nb - 1) - W);
@@ -553,7 +557,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
           t.y -= cur[q].x * xi.y + cur[q].y * xi.x;
         }
         for (int t2 = 64 + lane; t2 < W && i - 1 - t2 >= lo; t2 += 64) {
-          double2 l2 = rowp[(size_t)i * W + t2];
+          double2 l2 = rowp[(size_t)i * pr + t2];
           double2 &t = win[(i - 1 - t2) & (WP - 1)];
           t.x -= l2.x * xi.x - l2.y * xi.y;
           t.y -= l2.x * xi.y + l2.y * xi.x;
@@ -567,24 +571,21 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
   }
 }
 
-// Register-window variant (band widths W, Wc <= 63).  The W pending partial
-// sums of the band substitution live one per lane (lane j: row i + j forward,
-// row i - j backward): each row takes its final value from lane 0
-// (readlane), updates every lane with one complex FMA against the factor row
-// (one entry per lane), and shifts the window down one lane (DPP wave_shl:1),
-// the next row's right-hand side entering at lane 63.  No LDS, no barrier;
-// the row chain is register and DPP latency only.  Solved values are
-// collected one per lane and stored 64 rows at a time.
+// Register-window variant (band widths W, Wc <= 63, factor layouts padded to
+// 64 entries).  The pending partial sums of the band substitution live one
+// per lane in a circular window: lane l holds the row whose position
+// (forward: row - lo, backward: mid - 1 - row) is l mod 64.  Step p reads the
+// finished value of position p from lane p mod 64 (readlane with a uniform
+// lane index), subtracts its product with the factor from every lane (one
+// complex FMA; the factor row is loaded rotated by p, so lane l takes the
+// entry of its own row and the zero padding masks everything outside the
+// band), and hands lane p mod 64 the right-hand side of position p + 64.  No
+// LDS, no barrier, no lane shifts; solved values are collected one per lane
+// and stored 64 rows at a time.  Rows past the band read from beyond the
+// factor buffer, which the buffer load returns as zeros.
 __device__ __forceinline__ double dbl_lane(double v, int l) {
   const long long b = __builtin_bit_cast(long long, v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-// lane j <- lane j + 1, lane 63 <- in
-__device__ __forceinline__ double dbl_shl1(double v, double in) {
-  const long long b = __builtin_bit_cast(long long, v), c = __builtin_bit_cast(long long, in);
-  const int lo = __builtin_amdgcn_update_dpp((int)(c & 0xffffffffll), (int)(b & 0xffffffffll), 0x130, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(c >> 32), (int)(b >> 32), 0x130, 0xF, 0xF, false);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -595,74 +596,78 @@ __global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *f
   const int lo = d.comp_off[c], hi = d.comp_off[c + 1], mid = d.comp_mid[c];
   if (lo >= hi) return;
   const int f = fidx[r];
-  const int W = max(d.W, 1), Wc = max(d.Wc, 1);
-  const double2 *rowp = d.env + (size_t)f * d.nu * W;
-  const double2 *colp = d.colenv + (size_t)f * d.nu * Wc;
-  const double2 *full = d.full + (size_t)f * d.nnz_full;
-  const double2 *dg = d.diag + (size_t)f * d.nu;
+  const double2 *rowp = d.env + (size_t)f * d.nu * 64;
+  const double2 *colp = d.colenv + (size_t)f * d.nu * 64;
   double2 *x = work + (size_t)r * d.nu;
   const double2 zero = make_double2(0, 0);
-  const unsigned row_bytes = (unsigned)d.nu * (unsigned)W * 16u, col_bytes = (unsigned)d.nu * (unsigned)Wc * 16u;
-  const __amdgpu_buffer_rsrc_t rrow = __builtin_amdgcn_make_buffer_rsrc((void *)rowp, (short)0, (int)row_bytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rcol = __builtin_amdgcn_make_buffer_rsrc((void *)colp, (short)0, (int)col_bytes, 0x00020000);
-  const unsigned voff = (unsigned)max(lane - 1, 0) * 16u;   // lane j reads entry j - 1
-  // ---- forward, band rows: y_i = acc_i, then acc_{i+j} -= L(i+j, i) y_i.
-  // Factor columns are prefetched RP rows ahead (double buffer).
-  if (lo < mid) {
+  const unsigned bytes = (unsigned)d.nu * 1024u;
+  const __amdgpu_buffer_rsrc_t rrow = __builtin_amdgcn_make_buffer_rsrc((void *)rowp, (short)0, (int)bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rcol = __builtin_amdgcn_make_buffer_rsrc((void *)colp, (short)0, (int)bytes, 0x00020000);
+  const int nb = mid - lo;
+  // ---- forward, band rows: y = L^-1 b, column by column
+  if (nb > 0) {
     double ax, ay;
     {
-      const double2 v = lo + lane < mid ? x[lo + lane] : zero;
+      const double2 v = lane < nb ? x[lo + lane] : zero;
       ax = v.x;
       ay = v.y;
     }
-    // Lc/Ln: factor columns of RP rows; bc/bn: lane q < RP holds the
-    // right-hand side entering the window at row q of the block (row + 64)
+    // right-hand side entering at step p (lane p mod 64) for the RP steps of
+    // the block starting at p0: position p + 64
+    auto bload = [&](int p0) -> double2 {
+      const int pl = (lane - p0) & 63, row = lo + p0 + pl + 64;
+      return (pl < RP && row < mid) ? x[row] : zero;
+    };
     double2 Lc[RP], Ln[RP], bc, bn;
 #pragma unroll
-    for (int q = 0; q < RP; ++q) Lc[q] = band_load(rcol, voff, (unsigned)min(lo + q, mid - 1) * (unsigned)Wc * 16u);
-    bc = (lane < RP && lo + 64 + lane < mid) ? x[lo + 64 + lane] : zero;
+    for (int q = 0; q < RP; ++q)
+      Lc[q] = band_load(rcol, (unsigned)((lane - q - 1) & 63) * 16u, q < nb ? (unsigned)(lo + q) * 1024u : bytes);
+    bc = bload(0);
     double yx = 0, yy = 0;
-    for (int i = lo; i < mid; i += RP) {
-      // rows [i - 64, i) done: store them before this block's prefetch, so
-      // no wait on the store ever drains the prefetch (vmcnt is in order)
-      if (i > lo && ((i - lo) & 63) == 0) x[i - 64 + lane] = make_double2(yx, yy);
-#pragma unroll
-      for (int q = 0; q < RP; ++q)
-        Ln[q] = band_load(rcol, voff, (unsigned)min(i + RP + q, mid - 1) * (unsigned)Wc * 16u);
-      bn = (lane < RP && i + RP + 64 + lane < mid) ? x[i + RP + 64 + lane] : zero;
-      __builtin_amdgcn_sched_barrier(0);
+    // value of the current position, read one step ahead from the updated
+    // window (the hand-over of lane p mod 64 does not touch lane p + 1)
+    double vx = dbl_lane(ax, 0), vy = dbl_lane(ay, 0);
+    for (int p0 = 0; p0 < nb; p0 += RP) {
+      // positions [p0 - 64, p0) done: store them before this block's prefetch,
+      // so no wait on the store drains the prefetch (vmcnt is in order)
+      if (p0 > 0 && (p0 & 63) == 0) x[lo + p0 - 64 + lane] = make_double2(yx, yy);
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
-        // straight-line steps: rows past mid only shift zeros (their factor
-        // entries are masked and their values are never stored)
-        const int ii = i + q;
-        const int s = (ii - lo) & 63;          // position in the current 64-row batch
-        {
-          const bool use = lane >= 1 && lane <= Wc && ii + lane < mid;
-          const double2 L = use ? Lc[q] : zero;
-          const double vx = dbl_lane(ax, 0), vy = dbl_lane(ay, 0);
-          yx = lane == s ? vx : yx;
-          yy = lane == s ? vy : yy;
-          ax -= L.x * vx - L.y * vy;
-          ay -= L.x * vy + L.y * vx;
-          ax = dbl_shl1(ax, dbl_lane(bc.x, q));
-          ay = dbl_shl1(ay, dbl_lane(bc.y, q));
-        }
+        const int p = p0 + RP + q;
+        Ln[q] = band_load(rcol, (unsigned)((lane - p - 1) & 63) * 16u, p < nb ? (unsigned)(lo + p) * 1024u : bytes);
+      }
+      bn = bload(p0 + RP);
+      __builtin_amdgcn_sched_barrier(0);
+      const int sb = p0 & 63;
+#pragma unroll
+      for (int q = 0; q < RP; ++q) {
+        const int s = sb + q;
+        const double2 L = Lc[q];   // zero in lane s (padding)
+        double fx = fma(-L.x, vx, ax), fy = fma(-L.x, vy, ay);
+        fx = fma(L.y, vy, fx);
+        fy = fma(-L.y, vx, fy);
+        vx = dbl_lane(fx, (s + 1) & 63);
+        vy = dbl_lane(fy, (s + 1) & 63);
+        const bool sel = lane == s;
+        yx = sel ? fx : yx;
+        yy = sel ? fy : yy;
+        ax = sel ? bc.x : fx;
+        ay = sel ? bc.y : fy;
       }
 #pragma unroll
       for (int q = 0; q < RP; ++q) Lc[q] = Ln[q];
       bc = bn;
     }
     {  // the last, partial batch
-      const int b0 = lo + ((mid - 1 - lo) & ~63);
-      if (b0 + lane < mid) x[b0 + lane] = make_double2(yx, yy);
+      const int b0 = (nb - 1) & ~63;
+      if (b0 + lane < nb) x[lo + b0 + lane] = make_double2(yx, yy);
     }
   }
   __threadfence();
   __syncthreads();
   ldl_middle(d, f, x, lo, mid, hi, lane);
-  // ---- backward, band rows: x_k = acc_k, then acc_{k-j} -= L(k, k-j) x_k
-  if (lo < mid) {
+  // ---- backward, band rows: x = L^-T z, row by row from the last
+  if (nb > 0) {
     double ax, ay;
     {
       const int row = mid - 1 - lane;
@@ -670,40 +675,49 @@ __global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *f
       ax = v.x;
       ay = v.y;
     }
+    auto bload = [&](int p0) -> double2 {
+      const int pl = (lane - p0) & 63, row = mid - 1 - (p0 + pl + 64);
+      return (pl < RP && row >= lo) ? x[row] : zero;
+    };
     double2 Lc[RP], Ln[RP], bc, bn;
 #pragma unroll
-    for (int q = 0; q < RP; ++q) Lc[q] = band_load(rrow, voff, (unsigned)max(mid - 1 - q, lo) * (unsigned)W * 16u);
-    bc = (lane < RP && mid - 1 - 64 - lane >= lo) ? x[mid - 1 - 64 - lane] : zero;
+    for (int q = 0; q < RP; ++q)
+      Lc[q] = band_load(rrow, (unsigned)((lane - q - 1) & 63) * 16u, q < nb ? (unsigned)(mid - 1 - q) * 1024u : bytes);
+    bc = bload(0);
     double ox = 0, oy = 0;
-    for (int k = mid - 1; k >= lo; k -= RP) {
-      if (k < mid - 1 && ((mid - 1 - k) & 63) == 0) x[k + 64 - lane] = make_double2(ox, oy);
-#pragma unroll
-      for (int q = 0; q < RP; ++q) Ln[q] = band_load(rrow, voff, (unsigned)max(k - RP - q, lo) * (unsigned)W * 16u);
-      bn = (lane < RP && k - RP - 64 - lane >= lo) ? x[k - RP - 64 - lane] : zero;
-      __builtin_amdgcn_sched_barrier(0);
+    double vx = dbl_lane(ax, 0), vy = dbl_lane(ay, 0);
+    for (int p0 = 0; p0 < nb; p0 += RP) {
+      if (p0 > 0 && (p0 & 63) == 0) x[mid - 1 - (p0 - 64 + lane)] = make_double2(ox, oy);
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
-        const int kk = k - q;
-        const int s = (mid - 1 - kk) & 63;
-        {
-          const bool use = lane >= 1 && lane <= W && kk - lane >= lo;
-          const double2 L = use ? Lc[q] : zero;
-          const double vx = dbl_lane(ax, 0), vy = dbl_lane(ay, 0);
-          ox = lane == s ? vx : ox;
-          oy = lane == s ? vy : oy;
-          ax -= L.x * vx - L.y * vy;
-          ay -= L.x * vy + L.y * vx;
-          ax = dbl_shl1(ax, dbl_lane(bc.x, q));
-          ay = dbl_shl1(ay, dbl_lane(bc.y, q));
-        }
+        const int p = p0 + RP + q;
+        Ln[q] = band_load(rrow, (unsigned)((lane - p - 1) & 63) * 16u, p < nb ? (unsigned)(mid - 1 - p) * 1024u : bytes);
+      }
+      bn = bload(p0 + RP);
+      __builtin_amdgcn_sched_barrier(0);
+      const int sb = p0 & 63;
+#pragma unroll
+      for (int q = 0; q < RP; ++q) {
+        const int s = sb + q;
+        const double2 L = Lc[q];   // zero in lane s (padding)
+        double fx = fma(-L.x, vx, ax), fy = fma(-L.x, vy, ay);
+        fx = fma(L.y, vy, fx);
+        fy = fma(-L.y, vx, fy);
+        vx = dbl_lane(fx, (s + 1) & 63);
+        vy = dbl_lane(fy, (s + 1) & 63);
+        const bool sel = lane == s;
+        ox = sel ? fx : ox;
+        oy = sel ? fy : oy;
+        ax = sel ? bc.x : fx;
+        ay = sel ? bc.y : fy;
       }
 #pragma unroll
       for (int q = 0; q < RP; ++q) Lc[q] = Ln[q];
       bc = bn;
     }
     {  // the last, partial batch
-      const int b0 = mid - 1 - ((mid - 1 - lo) & ~63);
-      if (b0 - lane >= lo) x[b0 - lane] = make_double2(ox, oy);
+      const int b0 = (nb - 1) & ~63;
+      if (b0 + lane < nb) x[mid - 1 - (b0 + lane)] = make_double2(ox, oy);
     }
   }
 }
@@ -757,7 +771,7 @@ void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, doubl
   // still pending
   dim3 g(d.ncomp, R);
   const int span = std::max(d.W, d.Wc) + PF;
-  if ((double)d.nu * std::max(std::max(d.W, d.Wc), 1) * 16.0 >= 2147483647.0)
+  if ((double)d.nu * std::max(d.pr, d.pc) * 16.0 + 1024.0 >= 2147483647.0)
     throw SetupError{-1, "preconditioner band larger than 2 GB per frequency"};
   if (ldl_reg_plan(d))
     k_ldl_solve_reg<<<g, 64, 0, st>>>(d, fidx, work);
@@ -809,13 +823,13 @@ __global__ void k_fac_assemble(FactorArgs a) {
   }
   const bool super = i >= a.comp_mid[lo];
   const double2 *yi = a.yinv + (size_t)f * a.b;
-  double2 *rowp = a.env + ((size_t)f * a.nu + i) * a.W;
-  double2 *colp = a.colenv + ((size_t)f * a.nu + i) * a.Wc;
+  double2 *rowp = a.env + ((size_t)f * a.nu + i) * a.pr;
+  double2 *colp = a.colenv + ((size_t)f * a.nu + i) * a.pc;
   double2 *fr = a.full + (size_t)f * a.nnz_full + a.env_off[i];
   const int fi = a.first[i];
   const double2 zero = make_double2(0, 0);
-  for (int t = 0; t < a.W; ++t) rowp[t] = zero;
-  for (int t = 0; t < a.Wc; ++t) colp[t] = zero;
+  for (int t = 0; t < a.pr; ++t) rowp[t] = zero;
+  for (int t = 0; t < a.pc; ++t) colp[t] = zero;
   if (super)
     for (int k = 0; k < i - fi; ++k) fr[k] = zero;
   double2 dsum = zero;
@@ -853,9 +867,9 @@ __global__ void __launch_bounds__(FACT_T) k_ldl_factor(FactorArgs a) {
   const int c = blockIdx.x, f = blockIdx.y, tid = threadIdx.x;
   const int lo = a.comp_off[c], mid = a.comp_mid[c], hi = a.comp_off[c + 1];
   const int ns = hi - mid;
-  const int W = a.W, Wp = a.W + 1, Wc = a.Wc;
-  double2 *env = a.env + (size_t)f * a.nu * W;
-  double2 *col = a.colenv + (size_t)f * a.nu * Wc;
+  const int W = a.W, Wp = a.W + 1, Wc = a.Wc, pr = a.pr, pc = a.pc;
+  double2 *env = a.env + (size_t)f * a.nu * pr;
+  double2 *col = a.colenv + (size_t)f * a.nu * pc;
   double2 *full = a.full + (size_t)f * a.nnz_full;
   double2 *dg = a.diag + (size_t)f * a.nu;
   double2 *lcol = fsm, *ucol = fsm + Wp, *lsn = ucol + Wp, *usn = lsn + FACT_NS, *S = usn + FACT_NS;
@@ -865,7 +879,7 @@ __global__ void __launch_bounds__(FACT_T) k_ldl_factor(FactorArgs a) {
   for (int idx = tid; idx < Wp * Wp; idx += FACT_T) {
     const int q = idx / Wp, o = idx - q * Wp, i = lo + q;
     double2 v = zero;
-    if (i < mid) v = o == 0 ? dg[i] : env[(size_t)i * W + (o - 1)];
+    if (i < mid) v = o == 0 ? dg[i] : env[(size_t)i * pr + (o - 1)];
     win[idx] = v;
   }
   for (int idx = tid; idx < ns * Wp; idx += FACT_T) {
@@ -903,11 +917,11 @@ __global__ void __launch_bounds__(FACT_T) k_ldl_factor(FactorArgs a) {
           if (si >= Wp) si -= Wp;
           u = win[si * Wp + t];
           l = cdiv2(u, d);
-          env[(size_t)i * W + (t - 1)] = l;
+          env[(size_t)i * pr + (t - 1)] = l;
         }
         ucol[t] = u;
         lcol[t] = l;
-        if (t <= Wc) col[(size_t)j * Wc + (t - 1)] = l;
+        if (t <= Wc) col[(size_t)j * pc + (t - 1)] = l;
       } else {
         const int s = t - W - 1, row = mid + s, fs = a.first[row];
         const double2 u = swin[s * Wp + sj], l = cdiv2(u, d);
@@ -956,7 +970,7 @@ __global__ void __launch_bounds__(FACT_T) k_ldl_factor(FactorArgs a) {
     const int inew = j + Wp;
     for (int o = tid; o < Wp; o += FACT_T) {
       double2 v = zero;
-      if (inew < mid) v = o == 0 ? dg[inew] : env[(size_t)inew * W + (o - 1)];
+      if (inew < mid) v = o == 0 ? dg[inew] : env[(size_t)inew * pr + (o - 1)];
       win[sj * Wp + o] = v;
     }
     for (int s = tid; s < ns; s += FACT_T) {

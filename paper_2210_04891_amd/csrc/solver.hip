@@ -76,9 +76,11 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
     d.ncomp = ps.ncomp;
     d.W = ps.W;
     d.Wc = ps.Wc;
+    d.pr = ps.pr;
+    d.pc = ps.pc;
     d.clast = pre_upload(P, ps.clast);
     d.col_off = pre_upload(P, ps.col_off);
-    d.nnz_col = (int64_t)ps.nu * std::max(ps.Wc, 1);
+    d.nnz_col = (int64_t)ps.nu * ps.pc;
     d.b = m.b;
     d.l = m.l;
     d.p = m.p;
@@ -87,7 +89,7 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
     d.nnz_full = ps.env_off[ps.nu];
     d.first = pre_upload(P, ps.first);
     d.env_off = pre_upload(P, ps.env_off);
-    d.nnz_env = (int64_t)ps.nu * std::max(ps.W, 1);
+    d.nnz_env = (int64_t)ps.nu * ps.pr;
     d.br_ru = pre_upload(P, ps.br_ru);
     d.br_rv = pre_upload(P, ps.br_rv);
     d.br_link = pre_upload(P, ps.br_link);
@@ -117,7 +119,7 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
   uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
   if (uniq != P->omegas || P->factor_plan != c->plans.factor) {
     const int nf = (int)uniq.size();
-    const size_t ne = (size_t)P->ps.nu * std::max(P->ps.W, 1), nc = (size_t)P->ps.nu * std::max(P->ps.Wc, 1);
+    const size_t ne = (size_t)P->ps.nu * P->ps.pr, nc = (size_t)P->ps.nu * P->ps.pc;
     const size_t nfull = P->ps.env_off[P->ps.nu];
     if (nf > P->cap_f) {
       hip_ok(hipStreamSynchronize(st), "precond realloc sync");
@@ -149,6 +151,8 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
       fa.b = m.b;
       fa.W = std::max(P->ps.W, 1);
       fa.Wc = std::max(P->ps.Wc, 1);
+      fa.pr = P->ps.pr;
+      fa.pc = P->ps.pc;
       fa.ncomp = P->ps.ncomp;
       fa.nf = nf;
       fa.comp_off = P->dev.comp_off;
