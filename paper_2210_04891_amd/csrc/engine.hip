@@ -498,6 +498,26 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
     g.act = upload(c, act, st);
     g.act_of = upload(c, act_of, st);
   }
+  {
+    // triangles sorted by anchor (then index); runs of one anchor cut into
+    // groups of INTERP_GROUP
+    std::vector<int> ord(n);
+    for (int t = 0; t < n; ++t) ord[t] = t;
+    auto key = [&](int t) {
+      return ((long)m.anchor[3 * t] * m.dims[1] + m.anchor[3 * t + 1]) * m.dims[2] + m.anchor[3 * t + 2];
+    };
+    std::sort(ord.begin(), ord.end(), [&](int a2, int b2) {
+      const long ka = key(a2), kb = key(b2);
+      return ka != kb ? ka < kb : a2 < b2;
+    });
+    std::vector<int> ig_off{0};
+    for (int i = 1; i < n; ++i)
+      if (key(ord[i]) != key(ord[i - 1]) || i - ig_off.back() == INTERP_GROUP) ig_off.push_back(i);
+    ig_off.push_back(n);
+    g.nig = n > 0 ? (int)ig_off.size() - 1 : 0;
+    g.ig_off = upload(c, ig_off, st);
+    g.ig_tri = upload(c, ord, st);
+  }
   g.pg_off = upload(c, pg_off, st);
   g.pg_tri = upload(c, pg_tri, st);
   if (c->grid_fp64) {

@@ -41,6 +41,8 @@ void branch_to_loop(const LoopMaps &mp, const double2 *yb, double2 *yl, double2 
 void transpose(const double2 *in, double2 *out, int rows, int cols, hipStream_t st);
 
 
+constexpr int INTERP_GROUP = 2;
+
 struct GridMaps {
   int n, b, N, dims[3];
   const int *tri_edge;
@@ -72,6 +74,10 @@ struct GridMaps {
   // ascending order, act_of[node] its position (-1 for the others)
   int nact;
   const int *act, *act_of;
+  // interpolation groups: triangles with the same anchor, at most
+  // INTERP_GROUP a group; group q = ig_tri[ig_off[q] .. ig_off[q+1])
+  int nig;
+  const int *ig_off, *ig_tri;
   int nwave;
   const int *ps_off, *ps_k, *ps_ent;
   const void *ps_w;      // [entries][4] (M0, M1x, M1y, M1z) in T

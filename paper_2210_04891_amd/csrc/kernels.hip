@@ -1392,6 +1392,69 @@ __global__ void __launch_bounds__(256) k_interp_nm(GridMaps g, const float2 *phi
   }
 }
 
+// Triangles with the same anchor read the same 64 stencil nodes: a
+// workgroup takes up to INTERP_GROUP of them, and each lane (channel) reads a
+// node's value once for all of them.  Per (triangle, channel) the sums run in
+// the same order as in k_interp_nm.
+__global__ void __launch_bounds__(256) k_interp_grp(GridMaps g, const float2 *phiT, double2 *U, int R) {
+  constexpr int IG = INTERP_GROUP;
+  __shared__ double2 s0[IG][256];
+  const int grp = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int q0 = g.ig_off[grp], gn = g.ig_off[grp + 1] - q0;
+  const int ch = 3 * R;
+  const int Ny = g.dims[1], Nz = g.dims[2];
+  int tq[IG];
+  const float *wq[IG];
+#pragma unroll
+  for (int q = 0; q < IG; ++q) {
+    tq[q] = g.ig_tri[q0 + min(q, gn - 1)];
+    wq[q] = (const float *)g.tri_w + (size_t)tq[q] * 256;
+  }
+  const int ax = g.anchor[3 * tq[0]], ay = g.anchor[3 * tq[0] + 1], az = g.anchor[3 * tq[0] + 2];
+  for (int base = 0; base < ch; base += 255) {
+    const int chn = base + threadIdx.x;
+    const bool ok = threadIdx.x < 255 && chn < ch;
+    const int c = ok ? chn % 3 : 0;
+    double a0x[IG], a0y[IG], a1x[IG], a1y[IG];
+#pragma unroll
+    for (int q = 0; q < IG; ++q) a0x[q] = a0y[q] = a1x[q] = a1y[q] = 0;
+#pragma unroll 8
+    for (int k = 0; k < 64; ++k) {
+      const int i = k >> 4, j = (k >> 2) & 3, l = k & 3;
+      const long node = ((long)(ax + i) * Ny + (ay + j)) * Nz + (az + l);
+      const int an = g.act_of[node];
+      const float2 v = ok ? phiT[(size_t)an * ch + chn] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int q = 0; q < IG; ++q) {
+        const float m0 = wq[q][4 * k], m1 = wq[q][4 * k + 1 + c];
+        a0x[q] += (double)m1 * v.x;
+        a0y[q] += (double)m1 * v.y;
+        a1x[q] += (double)m0 * v.x;
+        a1y[q] += (double)m0 * v.y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < IG; ++q) s0[q][threadIdx.x] = make_double2(a0x[q], a0y[q]);
+    __syncthreads();
+    if (ok) {
+      const int r = chn / 3;
+#pragma unroll
+      for (int q = 0; q < IG; ++q) {
+        if (q < gn) {
+          double2 *o = U + ((size_t)tq[q] * R + r) * 4;   // U[t][r][4]
+          o[1 + c] = make_double2(a1x[q], a1y[q]);
+          if (c == 0) {
+            const int lt = threadIdx.x;
+            const double2 p0 = s0[q][lt], p1 = s0[q][lt + 1], p2 = s0[q][lt + 2];
+            o[0] = make_double2(p0.x + p1.x + p2.x, p0.y + p1.y + p2.y);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStream_t st, void *scratch) {
   (void)scratch;
@@ -1404,7 +1467,7 @@ void interp_tri<float>(const GridMaps &g, const float2 *phi, double2 *U, int R, 
   float2 *phiT = (float2 *)scratch;
   const int ch = 3 * R;
   k_transpose_c64<<<dim3(cdiv(g.nact, 32), cdiv(ch, 32)), 256, 0, st>>>(phi, phiT, ch, g.N, g.nact, g.act);
-  k_interp_nm<<<(unsigned)g.n, 256, 0, st>>>(g, phiT, U, R);
+  if (g.nig > 0) k_interp_grp<<<(unsigned)g.nig, 256, 0, st>>>(g, phiT, U, R);
 }
 
 // ===========================================================================
