@@ -277,6 +277,17 @@ pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const 
  *                    fits in LDS (band width up to about 85), else on the
  *                    host; 1 always on the host (OpenMP over frequencies).
  *                    Changing it refactors at the next use of P.
+ *   "fft_prune"    1 (default) with the register FFT passes, only the grid
+ *                    nodes that some triangle's stencil touches enter and
+ *                    leave the convolution (Eqs. Projection, Interpolation:
+ *                    every other node of B is zero and no row of the
+ *                    interpolation reads it): the X passes skip groups of 32
+ *                    (y, z) grid lines without such a node, the forward X pass
+ *                    reads and the inverse one writes only those nodes, the
+ *                    (y, z) plane kernel reads and writes only the lines
+ *                    that hold one, and the tiled projection does not write
+ *                    node chunks without a contribution; 0 dense passes.
+ *                    The product is the same bit for bit.
  * PFFT_EINVAL for an unknown name or value. */
 pfft_status pfft_set_option(pfft_ctx *c, const char *name, int64_t value);
 pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *value);

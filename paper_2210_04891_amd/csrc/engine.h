@@ -81,6 +81,7 @@ struct pfft_ctx {
     int stream_split = 0;  // 1: the right-hand sides of a product are split over two streams
     int factor = 0;   // 0 preconditioner factored on the device, 1 on the host
     int comb = 0;     // 0 LDS-tiled near-field product when the tiles fit, 1 gather
+    int prune = 1;    // 1 register FFT passes skip grid columns and nodes no stencil touches
   } plans;
   pfft::StageTimer timer;
   // solver state

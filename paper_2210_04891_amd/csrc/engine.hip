@@ -497,6 +497,26 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
     g.nact = (int)act.size();
     g.act = upload(c, act, st);
     g.act_of = upload(c, act_of, st);
+    // masks of the pruned FFT passes
+    const int Nx = m.dims[0], Ny = m.dims[1], Nz = m.dims[2];
+    const long C = (long)Ny * Nz;
+    if (Nx % 32 == 0 && C % 32 == 0 && Ny <= 64) {
+      const int wpc = Nx / 32;
+      std::vector<uint32_t> xm((size_t)C * wpc, 0u);
+      std::vector<uint64_t> zm(Nz, 0u);
+      std::vector<uint8_t> cg((size_t)(C / 32), 0);
+      for (int node : act) {
+        const int z = node % Nz, y = (node / Nz) % Ny, x = node / (Nz * Ny);
+        const long col = (long)y * Nz + z;
+        xm[(size_t)col * wpc + x / 32] |= 1u << (x % 32);
+        zm[z] |= 1ull << y;
+        cg[col / 32] = 1;
+      }
+      g.xmask = upload(c, xm, st);
+      g.zmask = upload(c, zm, st);
+      g.cgrp = upload(c, cg, st);
+    }
+    g.prune = c->plans.prune;
   }
   {
     // triangles sorted by anchor (then index); runs of one anchor cut into
@@ -910,11 +930,13 @@ int *option_slot(pfft_ctx *c, const std::string &name) {
   if (name == "stream_split") return &c->plans.stream_split;
   if (name == "factor_plan") return &c->plans.factor;
   if (name == "combine_plan") return &c->plans.comb;
+  if (name == "fft_prune") return &c->plans.prune;
   return nullptr;
 }
 void sync_plans(pfft_ctx *c) {
   c->gm.fft_plan = c->plans.fft;
   c->gm.proj_plan = c->plans.proj;
+  c->gm.prune = c->plans.prune;
   c->cm.comb_plan = c->plans.comb;
 }
 }  // namespace

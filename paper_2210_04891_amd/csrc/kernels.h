@@ -85,6 +85,19 @@ struct GridMaps {
   // fft_plan 0 register-resident passes where the shape allows, 1 LDS
   // Stockham passes; proj_plan 0 tiled (LDS-staged), 1 node-major gather
   int fft_plan, proj_plan;
+  // Pruned register FFT passes (prune = 1): only the active nodes feed the
+  // convolution and only they are read from it, so the X passes skip every
+  // group of 32 (y, z) columns without an active node, the forward X pass
+  // reads only active nodes, the inverse one writes only those, and the
+  // plane kernel reads only the columns that hold an active node.
+  // xmask[c (Nx / 32) + w] bit b: node (x = 32 w + b, column c = y Nz + z)
+  // active; cgrp[k]: columns [32 k, 32 k + 32) hold an active node;
+  // zmask[z] bit y: column (y, z) holds one (Ny <= 64).  Null where the grid
+  // shape does not allow it.
+  const uint32_t *xmask;
+  const uint64_t *zmask;
+  const uint8_t *cgrp;
+  int prune;
 };
 
 // alpha [b][R] -> J [n][R][4]

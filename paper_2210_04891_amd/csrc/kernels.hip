@@ -360,8 +360,10 @@ template <typename T> constexpr int proj_pitch() {
   return ProjRG<T>::v * ProjRC<T>::v * 4 + 16 / (int)sizeof(V2<T>);
 }
 
+// skip_empty: node chunks without any contribution are not written (the
+// pruned FFT passes never read inactive nodes)
 template <typename T>
-__global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *J, V2<T> *Q, int R) {
+__global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *J, V2<T> *Q, int R, int skip_empty) {
   constexpr int RC = ProjRC<T>::v, RG = ProjRG<T>::v, RB = RC * RG;
   extern __shared__ unsigned char smraw[];
   constexpr int PS = proj_pitch<T>();
@@ -397,6 +399,9 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
   const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int p = threadIdx.x >> 6; p < g.nwave * RG; p += nw) {
     const int chunk = p / RG, grp = p - chunk * RG;
+    const int sidx = tile * g.nwave + chunk;
+    const int off = g.ps_off[sidx], K = g.ps_k[sidx];
+    if (skip_empty && K == 0) continue;
     const int uu = chunk * 64 + lane;
     const int r0 = rb0 + grp * RC, nr = min(RC, R - r0);
     if (uu >= TN || nr <= 0) continue;
@@ -412,8 +417,6 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
       for (int c = 0; c < 6; ++c) acc[q][c] = 0;
     // the chunk's sliced list: entry k of this lane at 64 k + lane, in
     // groups of 4 so that several loads are in flight; pads add zero
-    const int sidx = tile * g.nwave + chunk;
-    const int off = g.ps_off[sidx], K = g.ps_k[sidx];
     const int *ent = g.ps_ent + off + lane;
     const T *wl = (const T *)g.ps_w + 4 * ((size_t)off + lane);
     for (int kb = 0; kb < K; kb += 4) {
@@ -469,6 +472,9 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
 }
 
 template <typename T>
+static bool prune_ok(const GridMaps &g, long ch);
+
+template <typename T>
 void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st) {
   constexpr int RC = ProjRC<T>::v;
   // largest staging any context asks for: 232 (FP32) or 376 (FP64) triangles
@@ -477,7 +483,8 @@ void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st)
   const size_t lds = (size_t)g.tcap * proj_pitch<T>() * sizeof(V2<T>);
   if (lds_ok && g.proj_plan == 0 && lds <= (size_t)lds_max) {
     const unsigned ntile = (unsigned)g.ntile[0] * g.ntile[1] * g.ntile[2];
-    k_project_tiled<T><<<dim3(ntile, cdiv(R, RC * ProjRG<T>::v)), 512, lds, st>>>(g, J, Q, R);
+    k_project_tiled<T><<<dim3(ntile, cdiv(R, RC * ProjRG<T>::v)), 512, lds, st>>>(g, J, Q, R,
+                                                                                 prune_ok<T>(g, 3L * R) ? 1 : 0);
   } else {
     k_project<T><<<dim3(cdiv(g.N, 256), cdiv(R, PRG)), 256, 0, st>>>(g, J, Q, R);
   }
@@ -875,14 +882,28 @@ __device__ __forceinline__ void buf_store2(float2 v, __amdgpu_buffer_rsrc_t r, u
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64_t, v), r, voff, soff, 0);
 }
 
-template <int NX, int SIGN>
-__global__ void __launch_bounds__(256) k_fft_x_reg(const float2 *in, float2 *out, int C, int ncol, float scale) {
-  constexpr int M = NX / 4, LM = clog2(M);
+//   pruned (PR): workgroups whose 32 columns hold no active node exit; the
+//   forward pass reads only active nodes (zero elsewhere), the inverse pass
+//   writes only active nodes.  Skipped accesses take a per-lane byte offset
+//   of 2^31, beyond the buffer of every launch (launch_x_reg keeps those
+//   below 2^31 bytes, and with them every uniform offset), so the hardware's
+//   range check turns the load into zero and drops the store.
+constexpr unsigned X_DROP = 0x80000000u;
+template <int NX, int SIGN, bool PR>
+__global__ void __launch_bounds__(256) k_fft_x_reg(const float2 *in, float2 *out, int C, int ncol, float scale,
+                                                   const uint32_t *xmask, const uint8_t *cgrp) {
+  constexpr int M = NX / 4, LM = clog2(M), WPC = NX / 32;
+  if (PR && !cgrp[(unsigned)(blockIdx.x * 32) % (unsigned)C / 32u]) return;
   const int lane = threadIdx.x & 63, q = lane & 3, h = (lane >> 2) & 1;
   const int hm = -h;   // all ones on the odd half
   // the launch covers ncol (a multiple of 32) columns exactly
   const int col = blockIdx.x * 32 + (threadIdx.x >> 6) * 8 + (lane >> 3);
   const int chn = col / C, c = col - chn * C;
+  uint32_t mw[PR ? WPC : 1];
+  if (PR) {
+#pragma unroll
+    for (int w = 0; w < WPC; ++w) mw[w] = xmask[(size_t)c * WPC + w];
+  }
   const unsigned nin = (unsigned)ncol * (SIGN < 0 ? NX : 2 * NX) * 8u;
   const unsigned nout = (unsigned)ncol * (SIGN < 0 ? 2 * NX : NX) * 8u;
   const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in, nin), rout = buf_rsrc(out, nout);
@@ -894,7 +915,12 @@ __global__ void __launch_bounds__(256) k_fft_x_reg(const float2 *in, float2 *out
     // x = 4 m + q, times W_{2NX}^x on the odd half
     const float2 wq = half_tw(hm, tw_q<-1>(L, 1, 2 * NX));
 #pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = buf_load2(rin, vo, 4u * m * C8);
+    for (int m = 0; m < M; ++m) {
+      // row x = 4 m + q: word m / 8, bit 4 (m % 8) + q; an inactive node's
+      // load goes beyond the buffer's size and so reads zero
+      const unsigned vm = (!PR || ((mw[m / 8] >> (4 * (m % 8) + q)) & 1u)) ? vo : X_DROP;
+      v[m] = buf_load2(rin, vm, 4u * m * C8);
+    }
 #pragma unroll
     for (int m = 0; m < M; ++m) v[m] = cmulf(cmulf(v[m], half_tw(hm, tw<-1>(4 * m, 2 * NX))), wq);
     fft_dif<M, -1>(v);                       // position p holds k = brev(p)
@@ -928,7 +954,17 @@ __global__ void __launch_bounds__(256) k_fft_x_reg(const float2 *in, float2 *out
       const float2 lo = v[j], hi = v[j + M / 2];
       const float2 send = selb2(hm, lo, hi), keep = selb2(hm, hi, lo);
       const float2 r = make_float2(__shfl_xor(send.x, 4), __shfl_xor(send.y, 4));
-      buf_store2(make_float2((keep.x + r.x) * scale, (keep.y + r.y) * scale), rout, oo, 4u * j * C8);
+      const float2 o = make_float2((keep.x + r.x) * scale, (keep.y + r.y) * scale);
+      unsigned om = oo;
+      if (PR) {
+        // row x = 4 (h M / 2 + j) + q; an inactive node's store goes beyond
+        // the buffer's size and is dropped
+        const int r0 = j, r1 = M / 2 + j;
+        const uint32_t wv = h ? mw[r1 / 8] : mw[r0 / 8];
+        const int sh = h ? 4 * (r1 % 8) : 4 * (r0 % 8);
+        om = ((wv >> (sh + q)) & 1u) ? oo : X_DROP;
+      }
+      buf_store2(o, rout, om, 4u * j * C8);
     }
   }
 }
@@ -936,8 +972,12 @@ __global__ void __launch_bounds__(256) k_fft_x_reg(const float2 *in, float2 *out
 // One (channel, kx) plane per workgroup of 2 NY threads (NY = 2 NZ).  Block
 // b works on kx = b / ch, channel = b % ch, so consecutive workgroups share
 // the spectrum slice of one kx in L2.
-template <int NY, int NZ>
-__global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, const float *ghat, long ch) {
+// Pruned (PR): column (y, z) enters as zero unless bit y of zmask[z] is set
+// (it holds no active node, and whatever the buffer holds there is not the
+// forward X pass's output); every column is still written.
+template <int NY, int NZ, bool PR>
+__global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, const float *ghat, long ch,
+                                                       const uint64_t *zmask) {
   static_assert(NY == 2 * NZ, "one thread per (row, half) and per (column, half)");
   constexpr int PT = NY + 1;                 // T[kz][y] pitch
   constexpr int P0 = NZ + 1;                 // staging [y][z] pitch
@@ -946,11 +986,21 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
   const int t = threadIdx.x, half = t & 1, line = t >> 1;
   const long kx = blockIdx.x / ch, chan = blockIdx.x - kx * ch;
   float2 *io = data + (chan * a.two_nx + kx) * (long)(NY * NZ);
-  // stage 0: coalesced load of the NY x NZ plane
+  // stage 0: coalesced load of the NY x NZ plane (2 NY is a multiple of NZ,
+  // so a thread's z is the same for every q).  Pruned: an inactive column's
+  // load takes an offset beyond the plane's buffer and reads zero (no
+  // branch, so all loads are in flight together).
+  const uint64_t zm = PR ? zmask[t % NZ] : 0;
+  const __amdgpu_buffer_rsrc_t rio = buf_rsrc(io, (unsigned)(NY * NZ * 8));
 #pragma unroll
   for (int q = 0; q < NZ / 2; ++q) {
     const int idx = t + q * 2 * NY, y = idx / NZ, z = idx - y * NZ;
-    sm[y * P0 + z] = io[idx];
+    if (PR) {
+      const unsigned off = ((zm >> y) & 1u) ? (unsigned)idx * 8u : X_DROP;
+      sm[y * P0 + z] = buf_load2(rio, off, 0);
+    } else {
+      sm[y * P0 + z] = io[idx];
+    }
   }
   __syncthreads();
   // stage A: forward z half `half` of row `line`
@@ -1151,37 +1201,73 @@ static bool reg_plane_ok(const GridMaps &g, int Ny, int Nz) {
   return (Ny == 64 && Nz == 32) || (Ny == 32 && Nz == 16) || (Ny == 16 && Nz == 8);
 }
 
-static void launch_yz_reg(float2 *data, const float *ghat, const YZArgs &y, long ch, hipStream_t st) {
+template <int NY, int NZ>
+static void launch_yz_reg_n(float2 *data, const float *ghat, const YZArgs &y, long ch, const uint64_t *zmask,
+                            hipStream_t st) {
   const unsigned nb = (unsigned)(ch * y.two_nx);
-  if (y.ny == 64) k_fft_yz_reg<64, 32><<<nb, 128, 0, st>>>(y, data, ghat, ch);
-  else if (y.ny == 32) k_fft_yz_reg<32, 16><<<nb, 64, 0, st>>>(y, data, ghat, ch);
-  else k_fft_yz_reg<16, 8><<<nb, 32, 0, st>>>(y, data, ghat, ch);
+  if (zmask)
+    k_fft_yz_reg<NY, NZ, true><<<nb, 2 * NY, 0, st>>>(y, data, ghat, ch, zmask);
+  else
+    k_fft_yz_reg<NY, NZ, false><<<nb, 2 * NY, 0, st>>>(y, data, ghat, ch, nullptr);
+}
+static void launch_yz_reg(float2 *data, const float *ghat, const YZArgs &y, long ch, const uint64_t *zmask,
+                          hipStream_t st) {
+  if (y.ny == 64) launch_yz_reg_n<64, 32>(data, ghat, y, ch, zmask, st);
+  else if (y.ny == 32) launch_yz_reg_n<32, 16>(data, ghat, y, ch, zmask, st);
+  else launch_yz_reg_n<16, 8>(data, ghat, y, ch, zmask, st);
 }
 
 // Register X passes: FP32, N_x in {32, 64, 128, 256}, N_y N_z a multiple of
-// 32, element offsets of the padded grid below 2^32.
+// 32, one channel of the padded grid below 2^31 bytes.
 template <typename T>
 static bool reg_x_ok(const GridMaps &g, int Nx, long C, long ch) {
+  (void)ch;
   if (sizeof(T) != 4 || g.fft_plan == 1) return false;
-  if ((double)ch * 2.0 * Nx * (double)C >= 4294967295.0) return false;
+  if (2.0 * Nx * (double)C * 8.0 >= 2147483647.0) return false;   // one channel per launch at least
   return (Nx == 256 || Nx == 128 || Nx == 64 || Nx == 32) && C % 32 == 0;
 }
 
+template <int NX, int SIGN>
+static void launch_x_reg_n(const float2 *in, float2 *out, int C, int ncol, float scale, const uint32_t *xmask,
+                           const uint8_t *cgrp, unsigned nb, hipStream_t st) {
+  if (xmask)
+    k_fft_x_reg<NX, SIGN, true><<<nb, 256, 0, st>>>(in, out, C, ncol, scale, xmask, cgrp);
+  else
+    k_fft_x_reg<NX, SIGN, false><<<nb, 256, 0, st>>>(in, out, C, ncol, scale, nullptr, nullptr);
+}
+// xmask / cgrp non-null: pruned passes.  The channels are split over
+// launches so that each addresses less than 2^31 bytes (32-bit byte offsets,
+// and the pruned passes' out-of-range offset stays beyond every buffer).
 static void launch_x_reg(const float2 *in, float2 *out, int Nx, long C, long ch, int sign, float scale,
-                         hipStream_t st) {
+                         const uint32_t *xmask, const uint8_t *cgrp, hipStream_t st) {
+  const long per = 2L * Nx * C * 8;             // bytes of one channel's longer side
+  const long cmax = std::max(1L, 2147483647L / per);
+  if (ch > cmax) {
+    const long in_ch = (sign < 0 ? Nx : 2L * Nx) * C, out_ch = (sign < 0 ? 2L * Nx : Nx) * C;
+    for (long c0 = 0; c0 < ch; c0 += cmax)
+      launch_x_reg(in + c0 * in_ch, out + c0 * out_ch, Nx, C, std::min(cmax, ch - c0), sign, scale, xmask, cgrp, st);
+    return;
+  }
   const int ncol = (int)(ch * C), Ci = (int)C;
   const unsigned nb = (unsigned)(ncol / 32);   // C % 32 == 0 (reg_x_ok)
   if (sign < 0) {
-    if (Nx == 256) k_fft_x_reg<256, -1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
-    else if (Nx == 128) k_fft_x_reg<128, -1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
-    else if (Nx == 64) k_fft_x_reg<64, -1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
-    else k_fft_x_reg<32, -1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+    if (Nx == 256) launch_x_reg_n<256, -1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
+    else if (Nx == 128) launch_x_reg_n<128, -1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
+    else if (Nx == 64) launch_x_reg_n<64, -1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
+    else launch_x_reg_n<32, -1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
   } else {
-    if (Nx == 256) k_fft_x_reg<256, 1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
-    else if (Nx == 128) k_fft_x_reg<128, 1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
-    else if (Nx == 64) k_fft_x_reg<64, 1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
-    else k_fft_x_reg<32, 1><<<nb, 256, 0, st>>>(in, out, Ci, ncol, scale);
+    if (Nx == 256) launch_x_reg_n<256, 1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
+    else if (Nx == 128) launch_x_reg_n<128, 1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
+    else if (Nx == 64) launch_x_reg_n<64, 1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
+    else launch_x_reg_n<32, 1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
   }
+}
+
+// The pruned passes run where both register passes do and the masks exist.
+template <typename T>
+static bool prune_ok(const GridMaps &g, long ch) {
+  const int Nx = g.dims[0], Ny = g.dims[1], Nz = g.dims[2];
+  return g.prune && g.xmask && reg_x_ok<T>(g, Nx, (long)Ny * Nz, ch) && reg_plane_ok<T>(g, Ny, Nz);
 }
 
 template <typename T>
@@ -1189,10 +1275,13 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
   const int Nx = g.dims[0], Ny = g.dims[1], Nz = g.dims[2];
   long ch = 3L * R;
   const bool xreg = reg_x_ok<T>(g, Nx, (long)Ny * Nz, ch);
+  const bool pr = prune_ok<T>(g, ch);
+  const uint32_t *xm = pr ? g.xmask : nullptr;
+  const uint8_t *cg = pr ? g.cgrp : nullptr;
   // X forward: [ch][Nx][Ny*Nz] -> [ch][2Nx][Ny*Nz]
   if (hook) hook->pass(0, st);
   if (xreg)
-    launch_x_reg((const float2 *)Q, (float2 *)T1, Nx, (long)Ny * Nz, ch, -1, 1.0f, st);
+    launch_x_reg((const float2 *)Q, (float2 *)T1, Nx, (long)Ny * Nz, ch, -1, 1.0f, xm, cg, st);
   else
     fft_axis<T>(Q, T1, ch, (long)Ny * Nz, Nx, 2 * Nx, 2 * Nx, -1, 1.0f, nullptr, nullptr, st);
   const int vs = (int)sizeof(V2<T>);
@@ -1206,10 +1295,10 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
     y.nx = Nx;
     y.two_nx = 2 * Nx;
     y.scale = 1.0f / (4.0f * Ny * Nz);
-    launch_yz_reg((float2 *)T1, (const float *)g.ghat, y, ch, st);
+    launch_yz_reg((float2 *)T1, (const float *)g.ghat, y, ch, pr ? g.zmask : nullptr, st);
     if (hook) hook->pass(4, st);
     if (xreg)
-      launch_x_reg((const float2 *)T1, (float2 *)Q, Nx, (long)Ny * Nz, ch, +1, 1.0f / (2.0f * Nx), st);
+      launch_x_reg((const float2 *)T1, (float2 *)Q, Nx, (long)Ny * Nz, ch, +1, 1.0f / (2.0f * Nx), xm, cg, st);
     else
       fft_axis<T>(T1, Q, ch, (long)Ny * Nz, 2 * Nx, Nx, 2 * Nx, +1, 1.0f / (2.0f * Nx), nullptr, nullptr, st);
     if (hook) hook->done(st);
