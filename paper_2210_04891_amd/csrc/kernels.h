@@ -98,6 +98,9 @@ struct GridMaps {
   const uint64_t *zmask;
   const uint8_t *cgrp;
   int prune;
+  // twiddles of the forward register X pass (FP32 grid): xtw[4 h + q][m] =
+  // (-1)^q W_{2Nx}^{(2 k2 + h) m}, k2 the 2-bit reversal of q, m < Nx / 4
+  const float2 *xtw;
 };
 
 // alpha [b][R] -> J [n][R][4]

@@ -969,6 +969,93 @@ __global__ void __launch_bounds__(256) k_fft_x_reg(const float2 *in, float2 *out
   }
 }
 
+// Forward X pass, decimation in frequency across the quad.  With x = m + M q
+// and k = 4 k1 + k2, the NX-point DFT of half h (input times W_{2NX}^{h x})
+// is: a radix-4 DFT over q for each m (after the lane constant W_8^{h q}),
+// the twiddle W_{2NX}^{(2 k2 + h) m}, then an M-point DFT over m in
+// registers; output row kx = 2 k + h = 8 k1 + 2 k2 + h.  The radix-4 step is
+// two radix-2 steps across lanes (DPP, partners q ^ 2 then q ^ 1), whose
+// lane signs and the -i of the second step are folded into the per-lane
+// factors and into the twiddle table xtw[lane & 7][m] (which holds the sign
+// of the second step times W_{2NX}^{(2 k2 + h) m}).  The block's 32 columns
+// of each 64 output rows are staged in LDS, so every store writes whole
+// 256-byte rows (two per wavefront instruction).  Pruned (PR): as in
+// k_fft_x_reg.
+template <int NX, bool PR>
+__global__ void __launch_bounds__(256) k_fft_x_fwd(const float2 *in, float2 *out, int C, int ncol,
+                                                   const float2 *xtw, const uint32_t *xmask, const uint8_t *cgrp) {
+  constexpr int M = NX / 4, LM = clog2(M), WPC = NX / 32;
+  constexpr int TP = M + 1;     // twiddle table pitch: the 8 rows fall in different banks
+  constexpr int LP = 36;        // staging pitch (4 mod 32 slots of 8 bytes: conflict-free)
+  constexpr int NCH = 2 * NX / 64;
+  __shared__ float2 s_tw[8 * TP];
+  __shared__ float2 s_out[2][64 * LP];
+  const unsigned c0 = (unsigned)(blockIdx.x * 32) % (unsigned)C;   // block's first column in its channel
+  if (PR && !cgrp[c0 / 32u]) return;
+  const int t = threadIdx.x, lane = t & 63, q = lane & 3, h = (lane >> 2) & 1, r = lane & 7;
+  const int cl = (t >> 6) * 8 + (lane >> 3);
+  const int col = blockIdx.x * 32 + cl;
+  const int chn = col / C, c = col - chn * C;
+  for (int i = t; i < 8 * M; i += 256) s_tw[(i / M) * TP + i % M] = xtw[i];
+  __syncthreads();
+  const unsigned nin = (unsigned)ncol * NX * 8u, nout = (unsigned)ncol * 2 * NX * 8u;
+  const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in, nin), rout = buf_rsrc(out, nout);
+  const unsigned C8 = (unsigned)C * 8u;
+  float2 v[M];
+  {
+    // rows x = m + M q
+    const unsigned vo = ((unsigned)chn * NX * C + c + (unsigned)(q * M) * C) * 8u;
+    if (PR) {
+      constexpr int NW = M >= 32 ? M / 32 : 1;
+      uint32_t mw[NW];
+#pragma unroll
+      for (int j = 0; j < NW; ++j) mw[j] = xmask[(size_t)c * WPC + (q * M) / 32 + j];
+      const int b0 = (q * M) % 32;   // 0 when M >= 32
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const uint32_t bit = M >= 32 ? (mw[m / 32] >> (m % 32)) & 1u : (mw[0] >> (b0 + m)) & 1u;
+        v[m] = buf_load2(rin, bit ? vo : X_DROP, (unsigned)m * C8);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < M; ++m) v[m] = buf_load2(rin, vo, (unsigned)m * C8);
+    }
+  }
+  // lane constants
+  const QuadLane L = quad_lane<-1>(q);
+  const float2 cq = half_tw(-h, tw_q<-1>(L, M, 2 * NX));   // W_8^{h q}
+  const float sA = q < 2 ? 1.f : -1.f, sB = (q & 1) ? -1.f : 1.f, sk = q == 2 ? -1.f : 1.f;
+  const bool q3 = q == 3;
+  const float2 *tr = s_tw + r * TP;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const float2 w = cmulf(v[m], cq);
+    const float2 pw = qperm2<0x4E>(w);                       // lane q ^ 2
+    const float2 a = make_float2(fmaf(sA, pw.x, w.x), fmaf(sA, pw.y, w.y));
+    const float2 p = make_float2(q3 ? -a.y : sk * a.x, q3 ? a.x : sk * a.y);
+    const float2 pp = qperm2<0xB1>(p);                       // lane q ^ 1
+    const float2 x = make_float2(fmaf(sB, pp.x, p.x), fmaf(sB, pp.y, p.y));
+    v[m] = cmulf(x, tr[m]);
+  }
+  fft_dif<M, -1>(v);                       // position p holds k1 = brev(p)
+  // 64 output rows at a time: rows 64 ch + 8 i + 2 k2 + h hold k1 = 8 ch + i
+  const int k2 = (q >> 1) | ((q & 1) << 1);
+  const int lrow = 2 * k2 + h;
+  const unsigned ob = ((unsigned)chn * 2 * NX * C + c0) * 8u;
+#pragma unroll
+  for (int ck = 0; ck < NCH; ++ck) {
+    float2 *so = s_out[ck & 1];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) so[(8 * i + lrow) * LP + cl] = v[brev(8 * ck + i, LM)];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int rr = (t >> 5) + 8 * i, cc = t & 31;
+      buf_store2(so[rr * LP + cc], rout, ob + ((unsigned)(64 * ck + rr) * C + cc) * 8u, 0);
+    }
+  }
+}
+
 // One (channel, kx) plane per workgroup of 2 NY threads (NY = 2 NZ).  Block
 // b works on kx = b / ch, channel = b % ch, so consecutive workgroups share
 // the spectrum slice of one kx in L2.
@@ -1228,8 +1315,15 @@ static bool reg_x_ok(const GridMaps &g, int Nx, long C, long ch) {
 }
 
 template <int NX, int SIGN>
-static void launch_x_reg_n(const float2 *in, float2 *out, int C, int ncol, float scale, const uint32_t *xmask,
-                           const uint8_t *cgrp, unsigned nb, hipStream_t st) {
+static void launch_x_reg_n(const float2 *in, float2 *out, int C, int ncol, float scale, const float2 *xtw,
+                           const uint32_t *xmask, const uint8_t *cgrp, unsigned nb, hipStream_t st) {
+  if (SIGN < 0 && xtw) {
+    if (xmask)
+      k_fft_x_fwd<NX, true><<<nb, 256, 0, st>>>(in, out, C, ncol, xtw, xmask, cgrp);
+    else
+      k_fft_x_fwd<NX, false><<<nb, 256, 0, st>>>(in, out, C, ncol, xtw, nullptr, nullptr);
+    return;
+  }
   if (xmask)
     k_fft_x_reg<NX, SIGN, true><<<nb, 256, 0, st>>>(in, out, C, ncol, scale, xmask, cgrp);
   else
@@ -1239,27 +1333,28 @@ static void launch_x_reg_n(const float2 *in, float2 *out, int C, int ncol, float
 // launches so that each addresses less than 2^31 bytes (32-bit byte offsets,
 // and the pruned passes' out-of-range offset stays beyond every buffer).
 static void launch_x_reg(const float2 *in, float2 *out, int Nx, long C, long ch, int sign, float scale,
-                         const uint32_t *xmask, const uint8_t *cgrp, hipStream_t st) {
+                         const float2 *xtw, const uint32_t *xmask, const uint8_t *cgrp, hipStream_t st) {
   const long per = 2L * Nx * C * 8;             // bytes of one channel's longer side
   const long cmax = std::max(1L, 2147483647L / per);
   if (ch > cmax) {
     const long in_ch = (sign < 0 ? Nx : 2L * Nx) * C, out_ch = (sign < 0 ? 2L * Nx : Nx) * C;
     for (long c0 = 0; c0 < ch; c0 += cmax)
-      launch_x_reg(in + c0 * in_ch, out + c0 * out_ch, Nx, C, std::min(cmax, ch - c0), sign, scale, xmask, cgrp, st);
+      launch_x_reg(in + c0 * in_ch, out + c0 * out_ch, Nx, C, std::min(cmax, ch - c0), sign, scale, xtw, xmask,
+                   cgrp, st);
     return;
   }
   const int ncol = (int)(ch * C), Ci = (int)C;
   const unsigned nb = (unsigned)(ncol / 32);   // C % 32 == 0 (reg_x_ok)
   if (sign < 0) {
-    if (Nx == 256) launch_x_reg_n<256, -1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
-    else if (Nx == 128) launch_x_reg_n<128, -1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
-    else if (Nx == 64) launch_x_reg_n<64, -1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
-    else launch_x_reg_n<32, -1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
+    if (Nx == 256) launch_x_reg_n<256, -1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
+    else if (Nx == 128) launch_x_reg_n<128, -1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
+    else if (Nx == 64) launch_x_reg_n<64, -1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
+    else launch_x_reg_n<32, -1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
   } else {
-    if (Nx == 256) launch_x_reg_n<256, 1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
-    else if (Nx == 128) launch_x_reg_n<128, 1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
-    else if (Nx == 64) launch_x_reg_n<64, 1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
-    else launch_x_reg_n<32, 1>(in, out, Ci, ncol, scale, xmask, cgrp, nb, st);
+    if (Nx == 256) launch_x_reg_n<256, 1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
+    else if (Nx == 128) launch_x_reg_n<128, 1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
+    else if (Nx == 64) launch_x_reg_n<64, 1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
+    else launch_x_reg_n<32, 1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
   }
 }
 
@@ -1281,7 +1376,7 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
   // X forward: [ch][Nx][Ny*Nz] -> [ch][2Nx][Ny*Nz]
   if (hook) hook->pass(0, st);
   if (xreg)
-    launch_x_reg((const float2 *)Q, (float2 *)T1, Nx, (long)Ny * Nz, ch, -1, 1.0f, xm, cg, st);
+    launch_x_reg((const float2 *)Q, (float2 *)T1, Nx, (long)Ny * Nz, ch, -1, 1.0f, g.xtw, xm, cg, st);
   else
     fft_axis<T>(Q, T1, ch, (long)Ny * Nz, Nx, 2 * Nx, 2 * Nx, -1, 1.0f, nullptr, nullptr, st);
   const int vs = (int)sizeof(V2<T>);
@@ -1298,7 +1393,7 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
     launch_yz_reg((float2 *)T1, (const float *)g.ghat, y, ch, pr ? g.zmask : nullptr, st);
     if (hook) hook->pass(4, st);
     if (xreg)
-      launch_x_reg((const float2 *)T1, (float2 *)Q, Nx, (long)Ny * Nz, ch, +1, 1.0f / (2.0f * Nx), xm, cg, st);
+      launch_x_reg((const float2 *)T1, (float2 *)Q, Nx, (long)Ny * Nz, ch, +1, 1.0f / (2.0f * Nx), g.xtw, xm, cg, st);
     else
       fft_axis<T>(T1, Q, ch, (long)Ny * Nz, 2 * Nx, Nx, 2 * Nx, +1, 1.0f / (2.0f * Nx), nullptr, nullptr, st);
     if (hook) hook->done(st);
