@@ -519,15 +519,18 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
     g.prune = c->plans.prune;
     if (!c->grid_fp64 && (Nx == 32 || Nx == 64 || Nx == 128 || Nx == 256)) {
       const int M = Nx / 4;
-      std::vector<float2> tw(8 * (size_t)M);
+      std::vector<float2> tw(16 * (size_t)M);
       for (int r = 0; r < 8; ++r) {
         const int q = r & 3, h = r >> 2, k2 = (q >> 1) | ((q & 1) << 1);
         const double sg = (q & 1) ? -1.0 : 1.0;
         for (int mm = 0; mm < M; ++mm) {
-          // exact angle reduction: the exponent modulo 2 Nx
-          const long e = ((long)(2 * k2 + h) * mm) % (2 * Nx);
-          const double a = -2.0 * M_PI * (double)e / (2.0 * Nx);
-          tw[(size_t)r * M + mm] = make_float2((float)(sg * std::cos(a)), (float)(sg * std::sin(a)));
+          // exact angle reduction: the exponents modulo 2 Nx
+          const long ef = ((long)(2 * k2 + h) * mm) % (2 * Nx);
+          const long ei = ((long)2 * k2 * mm + (long)h * k2) % (2 * Nx);
+          const double af = -2.0 * M_PI * (double)ef / (2.0 * Nx), ai = 2.0 * M_PI * (double)ei / (2.0 * Nx);
+          const double si = sg / (2.0 * Nx);
+          tw[(size_t)r * M + mm] = make_float2((float)(sg * std::cos(af)), (float)(sg * std::sin(af)));
+          tw[(size_t)(8 + r) * M + mm] = make_float2((float)(si * std::cos(ai)), (float)(si * std::sin(ai)));
         }
       }
       g.xtw = upload(c, tw, st);

@@ -98,8 +98,9 @@ struct GridMaps {
   const uint64_t *zmask;
   const uint8_t *cgrp;
   int prune;
-  // twiddles of the forward register X pass (FP32 grid): xtw[4 h + q][m] =
-  // (-1)^q W_{2Nx}^{(2 k2 + h) m}, k2 the 2-bit reversal of q, m < Nx / 4
+  // twiddles of the register X passes (FP32 grid), k2 the 2-bit reversal of
+  // q, m < Nx / 4: forward xtw[4 h + q][m] = (-1)^q W_{2Nx}^{(2 k2 + h) m};
+  // inverse (from xtw + 2 Nx) (-1)^q W_{2Nx}^{-(2 k2 m + h k2)} / (2 Nx)
   const float2 *xtw;
 };
 

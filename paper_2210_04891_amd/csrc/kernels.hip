@@ -813,33 +813,17 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Per-lane constants of the radix-4 step across a quad (lane q keeps output
-// q): rot[d] = W_4^{(q ^ d) q} for the value received from lane q ^ d, and
-// one-hot weights for twiddles W^{q k}.  Everything lane-dependent is
-// arithmetic (no branches, so loads are not serialised).
+// One-hot weights of a quad lane q for lane-dependent twiddles W^{q k} with
+// compile-time k (arithmetic, no branches).
 struct QuadLane {
-  float2 rot[4];
   float f[4];
 };
 template <int SIGN>
 __device__ __forceinline__ QuadLane quad_lane(int q) {
   QuadLane L;
 #pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    const int e = ((q ^ d) * q) & 3;     // W_4^e, W_4 = exp(SIGN 2 pi i / 4)
-    const float re = e == 0 ? 1.f : e == 2 ? -1.f : 0.f;
-    const float im = e == 1 ? (float)SIGN : e == 3 ? (float)-SIGN : 0.f;
-    L.rot[d] = make_float2(re, im);
-  }
-#pragma unroll
   for (int j = 0; j < 4; ++j) L.f[j] = q == j ? 1.f : 0.f;
   return L;
-}
-template <int SIGN>
-__device__ __forceinline__ float2 quad_dft(float2 v, const QuadLane &L) {
-  const float2 v1 = qperm2<0xB1>(v), v2 = qperm2<0x4E>(v), v3 = qperm2<0x1B>(v);
-  const float2 a = cmulf(v, L.rot[0]), b = cmulf(v1, L.rot[1]), c = cmulf(v2, L.rot[2]), d = cmulf(v3, L.rot[3]);
-  return make_float2((a.x + b.x) + (c.x + d.x), (a.y + b.y) + (c.y + d.y));
 }
 // W_n^{q k} for the lane's q (one-hot blend of compile-time constants)
 template <int SIGN>
@@ -862,11 +846,11 @@ __device__ __forceinline__ float2 half_tw(int hmask, float2 w) {
 
 // X passes of the convolution (FP32), lines of NX = 4 M points along x with
 // stride C between points; a zero-padded length-2 NX transform splits into
-// even/odd halves h, each an NX-point transform done as M-point register
-// FFTs over x = 4m + q (one per lane q of a quad) and a radix-4 step across
-// the quad.  Lanes: 8 columns per wave, lane = 8 col + 4 h + q.
+// even/odd halves h, each an NX-point transform done as a radix-4 step
+// across a lane quad (lane q) and M-point register FFTs.  Lanes: 8 columns
+// per wave, lane = 8 col + 4 h + q.
 //   forward: in [ch][NX][C] -> out [ch][2NX][C]
-//   inverse: in [ch][2NX][C] -> out [ch][NX][C] (crop, times scale)
+//   inverse: in [ch][2NX][C] -> out [ch][NX][C] (crop, times 1 / (2 NX))
 typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t(), 0, 0, 0)) b64_t;
 
 // Buffer access with a per-lane byte offset (VGPR) and a uniform one (SGPR):
@@ -882,92 +866,13 @@ __device__ __forceinline__ void buf_store2(float2 v, __amdgpu_buffer_rsrc_t r, u
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64_t, v), r, voff, soff, 0);
 }
 
-//   pruned (PR): workgroups whose 32 columns hold no active node exit; the
-//   forward pass reads only active nodes (zero elsewhere), the inverse pass
-//   writes only active nodes.  Skipped accesses take a per-lane byte offset
-//   of 2^31, beyond the buffer of every launch (launch_x_reg keeps those
-//   below 2^31 bytes, and with them every uniform offset), so the hardware's
-//   range check turns the load into zero and drops the store.
+// Pruned passes: workgroups whose 32 columns hold no active node exit, the
+// forward pass reads only active nodes (zero elsewhere), the inverse pass
+// writes only active nodes.  Skipped accesses take a per-lane byte offset of
+// 2^31, beyond the buffer of every launch (launch_x_reg keeps those below
+// 2^31 bytes, and with them every uniform offset), so the hardware's range
+// check turns the load into zero and drops the store.
 constexpr unsigned X_DROP = 0x80000000u;
-template <int NX, int SIGN, bool PR>
-__global__ void __launch_bounds__(256) k_fft_x_reg(const float2 *in, float2 *out, int C, int ncol, float scale,
-                                                   const uint32_t *xmask, const uint8_t *cgrp) {
-  constexpr int M = NX / 4, LM = clog2(M), WPC = NX / 32;
-  if (PR && !cgrp[(unsigned)(blockIdx.x * 32) % (unsigned)C / 32u]) return;
-  const int lane = threadIdx.x & 63, q = lane & 3, h = (lane >> 2) & 1;
-  const int hm = -h;   // all ones on the odd half
-  // the launch covers ncol (a multiple of 32) columns exactly
-  const int col = blockIdx.x * 32 + (threadIdx.x >> 6) * 8 + (lane >> 3);
-  const int chn = col / C, c = col - chn * C;
-  uint32_t mw[PR ? WPC : 1];
-  if (PR) {
-#pragma unroll
-    for (int w = 0; w < WPC; ++w) mw[w] = xmask[(size_t)c * WPC + w];
-  }
-  const unsigned nin = (unsigned)ncol * (SIGN < 0 ? NX : 2 * NX) * 8u;
-  const unsigned nout = (unsigned)ncol * (SIGN < 0 ? 2 * NX : NX) * 8u;
-  const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in, nin), rout = buf_rsrc(out, nout);
-  const unsigned C8 = (unsigned)C * 8u;
-  const QuadLane L = quad_lane<SIGN>(q);
-  float2 v[M];
-  if (SIGN < 0) {
-    const unsigned vo = ((unsigned)chn * NX * C + c + q * C) * 8u;
-    // x = 4 m + q, times W_{2NX}^x on the odd half
-    const float2 wq = half_tw(hm, tw_q<-1>(L, 1, 2 * NX));
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      // row x = 4 m + q: word m / 8, bit 4 (m % 8) + q; an inactive node's
-      // load goes beyond the buffer's size and so reads zero
-      const unsigned vm = (!PR || ((mw[m / 8] >> (4 * (m % 8) + q)) & 1u)) ? vo : X_DROP;
-      v[m] = buf_load2(rin, vm, 4u * m * C8);
-    }
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = cmulf(cmulf(v[m], half_tw(hm, tw<-1>(4 * m, 2 * NX))), wq);
-    fft_dif<M, -1>(v);                       // position p holds k = brev(p)
-#pragma unroll
-    for (int p = 0; p < M; ++p) {
-      const int k = brev(p, LM);
-      v[p] = quad_dft<-1>(cmulf(v[p], tw_q<-1>(L, k, NX)), L);
-      __builtin_amdgcn_sched_barrier(0);   // one exchange at a time (register pressure)
-    }
-    // lane q now holds X_h[k + M q]; frequency kx = 2 (k + M q) + h
-    const unsigned oo = ((unsigned)chn * 2 * NX * C + c + (2 * M * q + h) * C) * 8u;
-#pragma unroll
-    for (int p = 0; p < M; ++p) buf_store2(v[p], rout, oo, 2u * brev(p, LM) * C8);
-  } else {
-    const unsigned vo = ((unsigned)chn * 2 * NX * C + c + (2 * M * q + h) * C) * 8u;
-#pragma unroll
-    for (int p = 0; p < M; ++p) v[p] = buf_load2(rin, vo, 2u * brev(p, LM) * C8);
-#pragma unroll
-    for (int p = 0; p < M; ++p) {
-      const int k = brev(p, LM);
-      v[p] = cmulf(quad_dft<+1>(v[p], L), tw_q<+1>(L, k, NX));
-    }
-    fft_dit<M, +1>(v);                       // natural order: v[m] = U_h[4 m + q]
-    const float2 wq = half_tw(hm, tw_q<+1>(L, 1, 2 * NX));
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = cmulf(cmulf(v[m], half_tw(hm, tw<+1>(4 * m, 2 * NX))), wq);
-    // sum the halves (lanes 4 apart); lane h keeps m in [h M/2, (h+1) M/2)
-    const unsigned oo = ((unsigned)chn * NX * C + c + (4 * h * (M / 2) + q) * C) * 8u;
-#pragma unroll
-    for (int j = 0; j < M / 2; ++j) {
-      const float2 lo = v[j], hi = v[j + M / 2];
-      const float2 send = selb2(hm, lo, hi), keep = selb2(hm, hi, lo);
-      const float2 r = make_float2(__shfl_xor(send.x, 4), __shfl_xor(send.y, 4));
-      const float2 o = make_float2((keep.x + r.x) * scale, (keep.y + r.y) * scale);
-      unsigned om = oo;
-      if (PR) {
-        // row x = 4 (h M / 2 + j) + q; an inactive node's store goes beyond
-        // the buffer's size and is dropped
-        const int r0 = j, r1 = M / 2 + j;
-        const uint32_t wv = h ? mw[r1 / 8] : mw[r0 / 8];
-        const int sh = h ? 4 * (r1 % 8) : 4 * (r0 % 8);
-        om = ((wv >> (sh + q)) & 1u) ? oo : X_DROP;
-      }
-      buf_store2(o, rout, om, 4u * j * C8);
-    }
-  }
-}
 
 // Forward X pass, decimation in frequency across the quad.  With x = m + M q
 // and k = 4 k1 + k2, the NX-point DFT of half h (input times W_{2NX}^{h x})
@@ -979,8 +884,8 @@ __global__ void __launch_bounds__(256) k_fft_x_reg(const float2 *in, float2 *out
 // factors and into the twiddle table xtw[lane & 7][m] (which holds the sign
 // of the second step times W_{2NX}^{(2 k2 + h) m}).  The block's 32 columns
 // of each 64 output rows are staged in LDS, so every store writes whole
-// 256-byte rows (two per wavefront instruction).  Pruned (PR): as in
-// k_fft_x_reg.
+// 256-byte rows (two per wavefront instruction).  Pruned (PR): as
+// described above.
 template <int NX, bool PR>
 __global__ void __launch_bounds__(256) k_fft_x_fwd(const float2 *in, float2 *out, int C, int ncol,
                                                    const float2 *xtw, const uint32_t *xmask, const uint8_t *cgrp) {
@@ -1053,6 +958,82 @@ __global__ void __launch_bounds__(256) k_fft_x_fwd(const float2 *in, float2 *out
       const int rr = (t >> 5) + 8 * i, cc = t & 31;
       buf_store2(so[rr * LP + cc], rout, ob + ((unsigned)(64 * ck + rr) * C + cc) * 8u, 0);
     }
+  }
+}
+
+// Inverse X pass in the same form: with k = m + M q and x = 4 k1 + k2 the
+// inverse NX-point DFT of half h (rows kx = 2 k + h) is a radix-4 inverse DFT
+// over q for each m, the twiddle W_{NX}^{-k2 m}, an M-point inverse DFT over
+// m in registers, then the factor W_{2NX}^{-h x} before the two halves are
+// summed (lanes 4 apart).  As in the forward pass the lane signs of the two
+// DPP steps (+i in place of -i), the lane constant W_{2NX}^{-h k2} and the
+// scale are folded into the table itw[lane & 7][m]; the k1-dependent factor
+// W_{2M}^{-h k1} is applied per element.  Pruned (PR): as described above.
+template <int NX, bool PR>
+__global__ void __launch_bounds__(256) k_fft_x_inv(const float2 *in, float2 *out, int C, int ncol,
+                                                   const float2 *itw, const uint32_t *xmask, const uint8_t *cgrp) {
+  constexpr int M = NX / 4, LM = clog2(M), WPC = NX / 32;
+  constexpr int TP = M + 1;
+  __shared__ float2 s_tw[8 * TP];
+  const unsigned c0 = (unsigned)(blockIdx.x * 32) % (unsigned)C;
+  if (PR && !cgrp[c0 / 32u]) return;
+  const int t = threadIdx.x, lane = t & 63, q = lane & 3, h = (lane >> 2) & 1, r = lane & 7;
+  const int hm = -h;
+  const int col = blockIdx.x * 32 + (t >> 6) * 8 + (lane >> 3);
+  const int chn = col / C, c = col - chn * C;
+  for (int i = t; i < 8 * M; i += 256) s_tw[(i / M) * TP + i % M] = itw[i];
+  __syncthreads();
+  const unsigned nin = (unsigned)ncol * 2 * NX * 8u, nout = (unsigned)ncol * NX * 8u;
+  const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in, nin), rout = buf_rsrc(out, nout);
+  const unsigned C8 = (unsigned)C * 8u;
+  float2 v[M];
+  {
+    // rows kx = 2 (m + M q) + h
+    const unsigned vo = ((unsigned)chn * 2 * NX * C + c + (unsigned)(2 * M * q + h) * C) * 8u;
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = buf_load2(rin, vo, 2u * m * C8);
+  }
+  const float sA = q < 2 ? 1.f : -1.f, sB = (q & 1) ? -1.f : 1.f, sk = q == 2 ? -1.f : 1.f;
+  const bool q3 = q == 3;
+  const float2 *tr = s_tw + r * TP;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const float2 w = v[m];
+    const float2 pw = qperm2<0x4E>(w);                       // lane q ^ 2
+    const float2 a = make_float2(fmaf(sA, pw.x, w.x), fmaf(sA, pw.y, w.y));
+    // lane 3 takes +i (the inverse's W_4^{-1}) where the forward pass takes -i
+    const float2 p = make_float2(q3 ? a.y : sk * a.x, q3 ? -a.x : sk * a.y);
+    const float2 pp = qperm2<0xB1>(p);                       // lane q ^ 1
+    const float2 x = make_float2(fmaf(sB, pp.x, p.x), fmaf(sB, pp.y, p.y));
+    v[m] = cmulf(x, tr[m]);
+  }
+  fft_dif<M, +1>(v);                       // position p holds k1 = brev(p)
+  // W_{2M}^{-h k1}, then the halves: lane h keeps positions [h M/2, (h+1) M/2)
+#pragma unroll
+  for (int p = 0; p < M; ++p) v[p] = cmulf(v[p], half_tw(hm, tw<+1>(brev(p, LM), 2 * M)));
+  const int k2 = (q >> 1) | ((q & 1) << 1);
+  uint32_t mw[PR ? WPC : 1];
+  if (PR) {
+#pragma unroll
+    for (int w = 0; w < WPC; ++w) mw[w] = xmask[(size_t)c * WPC + w];
+  }
+  const unsigned ob = ((unsigned)chn * NX * C + c + (unsigned)k2 * C) * 8u;
+#pragma unroll
+  for (int j = 0; j < M / 2; ++j) {
+    const float2 lo = v[j], hi = v[j + M / 2];
+    const float2 send = selb2(hm, lo, hi), keep = selb2(hm, hi, lo);
+    const float2 rv = make_float2(__shfl_xor(send.x, 4), __shfl_xor(send.y, 4));
+    const float2 o = make_float2(keep.x + rv.x, keep.y + rv.y);
+    // row x = 4 k1 + k2, k1 = brev(p), p = j + h M / 2
+    const int k1a = brev(j, LM), k1b = brev(j + M / 2, LM);
+    unsigned om = ob + (unsigned)(h ? 4 * k1b : 4 * k1a) * C8;
+    if (PR) {
+      const int xa = 4 * k1a, xb = 4 * k1b;   // + k2 (< 4, same word)
+      const uint32_t wv = h ? mw[xb / 32] : mw[xa / 32];
+      const int sh = (h ? xb % 32 : xa % 32) + k2;
+      om = ((wv >> sh) & 1u) ? om : X_DROP;
+    }
+    buf_store2(o, rout, om, 0);
   }
 }
 
@@ -1309,52 +1290,53 @@ static void launch_yz_reg(float2 *data, const float *ghat, const YZArgs &y, long
 template <typename T>
 static bool reg_x_ok(const GridMaps &g, int Nx, long C, long ch) {
   (void)ch;
-  if (sizeof(T) != 4 || g.fft_plan == 1) return false;
+  if (sizeof(T) != 4 || g.fft_plan == 1 || !g.xtw) return false;
   if (2.0 * Nx * (double)C * 8.0 >= 2147483647.0) return false;   // one channel per launch at least
   return (Nx == 256 || Nx == 128 || Nx == 64 || Nx == 32) && C % 32 == 0;
 }
 
 template <int NX, int SIGN>
-static void launch_x_reg_n(const float2 *in, float2 *out, int C, int ncol, float scale, const float2 *xtw,
-                           const uint32_t *xmask, const uint8_t *cgrp, unsigned nb, hipStream_t st) {
-  if (SIGN < 0 && xtw) {
+static void launch_x_reg_n(const float2 *in, float2 *out, int C, int ncol, const float2 *xtw, const uint32_t *xmask,
+                           const uint8_t *cgrp, unsigned nb, hipStream_t st) {
+  if (SIGN < 0) {
     if (xmask)
       k_fft_x_fwd<NX, true><<<nb, 256, 0, st>>>(in, out, C, ncol, xtw, xmask, cgrp);
     else
       k_fft_x_fwd<NX, false><<<nb, 256, 0, st>>>(in, out, C, ncol, xtw, nullptr, nullptr);
-    return;
+  } else {
+    const float2 *itw = xtw + 2 * NX;   // the inverse table follows the forward one
+    if (xmask)
+      k_fft_x_inv<NX, true><<<nb, 256, 0, st>>>(in, out, C, ncol, itw, xmask, cgrp);
+    else
+      k_fft_x_inv<NX, false><<<nb, 256, 0, st>>>(in, out, C, ncol, itw, nullptr, nullptr);
   }
-  if (xmask)
-    k_fft_x_reg<NX, SIGN, true><<<nb, 256, 0, st>>>(in, out, C, ncol, scale, xmask, cgrp);
-  else
-    k_fft_x_reg<NX, SIGN, false><<<nb, 256, 0, st>>>(in, out, C, ncol, scale, nullptr, nullptr);
 }
 // xmask / cgrp non-null: pruned passes.  The channels are split over
 // launches so that each addresses less than 2^31 bytes (32-bit byte offsets,
 // and the pruned passes' out-of-range offset stays beyond every buffer).
-static void launch_x_reg(const float2 *in, float2 *out, int Nx, long C, long ch, int sign, float scale,
+static void launch_x_reg(const float2 *in, float2 *out, int Nx, long C, long ch, int sign,
                          const float2 *xtw, const uint32_t *xmask, const uint8_t *cgrp, hipStream_t st) {
   const long per = 2L * Nx * C * 8;             // bytes of one channel's longer side
   const long cmax = std::max(1L, 2147483647L / per);
   if (ch > cmax) {
     const long in_ch = (sign < 0 ? Nx : 2L * Nx) * C, out_ch = (sign < 0 ? 2L * Nx : Nx) * C;
     for (long c0 = 0; c0 < ch; c0 += cmax)
-      launch_x_reg(in + c0 * in_ch, out + c0 * out_ch, Nx, C, std::min(cmax, ch - c0), sign, scale, xtw, xmask,
-                   cgrp, st);
+      launch_x_reg(in + c0 * in_ch, out + c0 * out_ch, Nx, C, std::min(cmax, ch - c0), sign, xtw, xmask, cgrp,
+                   st);
     return;
   }
   const int ncol = (int)(ch * C), Ci = (int)C;
   const unsigned nb = (unsigned)(ncol / 32);   // C % 32 == 0 (reg_x_ok)
   if (sign < 0) {
-    if (Nx == 256) launch_x_reg_n<256, -1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
-    else if (Nx == 128) launch_x_reg_n<128, -1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
-    else if (Nx == 64) launch_x_reg_n<64, -1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
-    else launch_x_reg_n<32, -1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
+    if (Nx == 256) launch_x_reg_n<256, -1>(in, out, Ci, ncol, xtw, xmask, cgrp, nb, st);
+    else if (Nx == 128) launch_x_reg_n<128, -1>(in, out, Ci, ncol, xtw, xmask, cgrp, nb, st);
+    else if (Nx == 64) launch_x_reg_n<64, -1>(in, out, Ci, ncol, xtw, xmask, cgrp, nb, st);
+    else launch_x_reg_n<32, -1>(in, out, Ci, ncol, xtw, xmask, cgrp, nb, st);
   } else {
-    if (Nx == 256) launch_x_reg_n<256, 1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
-    else if (Nx == 128) launch_x_reg_n<128, 1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
-    else if (Nx == 64) launch_x_reg_n<64, 1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
-    else launch_x_reg_n<32, 1>(in, out, Ci, ncol, scale, xtw, xmask, cgrp, nb, st);
+    if (Nx == 256) launch_x_reg_n<256, 1>(in, out, Ci, ncol, xtw, xmask, cgrp, nb, st);
+    else if (Nx == 128) launch_x_reg_n<128, 1>(in, out, Ci, ncol, xtw, xmask, cgrp, nb, st);
+    else if (Nx == 64) launch_x_reg_n<64, 1>(in, out, Ci, ncol, xtw, xmask, cgrp, nb, st);
+    else launch_x_reg_n<32, 1>(in, out, Ci, ncol, xtw, xmask, cgrp, nb, st);
   }
 }
 
@@ -1376,7 +1358,7 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
   // X forward: [ch][Nx][Ny*Nz] -> [ch][2Nx][Ny*Nz]
   if (hook) hook->pass(0, st);
   if (xreg)
-    launch_x_reg((const float2 *)Q, (float2 *)T1, Nx, (long)Ny * Nz, ch, -1, 1.0f, g.xtw, xm, cg, st);
+    launch_x_reg((const float2 *)Q, (float2 *)T1, Nx, (long)Ny * Nz, ch, -1, g.xtw, xm, cg, st);
   else
     fft_axis<T>(Q, T1, ch, (long)Ny * Nz, Nx, 2 * Nx, 2 * Nx, -1, 1.0f, nullptr, nullptr, st);
   const int vs = (int)sizeof(V2<T>);
@@ -1393,7 +1375,7 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
     launch_yz_reg((float2 *)T1, (const float *)g.ghat, y, ch, pr ? g.zmask : nullptr, st);
     if (hook) hook->pass(4, st);
     if (xreg)
-      launch_x_reg((const float2 *)T1, (float2 *)Q, Nx, (long)Ny * Nz, ch, +1, 1.0f / (2.0f * Nx), g.xtw, xm, cg, st);
+      launch_x_reg((const float2 *)T1, (float2 *)Q, Nx, (long)Ny * Nz, ch, +1, g.xtw, xm, cg, st);
     else
       fft_axis<T>(T1, Q, ch, (long)Ny * Nz, 2 * Nx, Nx, 2 * Nx, +1, 1.0f / (2.0f * Nx), nullptr, nullptr, st);
     if (hook) hook->done(st);
