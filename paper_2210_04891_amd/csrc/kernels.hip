@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <string>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -1723,6 +1724,20 @@ __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U,
 // are consecutive on one XCD, so its CSR rows are read from HBM once.
 constexpr int CLDS = 120 * 1024;   // staging bytes
 
+// lane K of each 16-lane row to the whole row (DPP row_newbcast; no old value)
+template <int K>
+__device__ __forceinline__ int row_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xF, 0xF, false);
+}
+// f(integral_constant<int, K>) for K = B .. E - 1
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 int combine_tile_cap(int rc) { return std::min(CLDS / (rc * 16), 65535); }
 
 template <int CRC>
@@ -1734,9 +1749,31 @@ __global__ void __launch_bounds__(512) k_combine_tiled(CombineMaps c, const doub
   const int lb = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tile = lb / nch, r0 = (lb - tile * nch) * CRC;
   const int u0 = c.ct_off[tile], nu = c.ct_off[tile + 1] - u0;
-  for (int i = threadIdx.x; i < nu * CRC; i += blockDim.x) {
-    const int sl = i / CRC, rr = i - sl * CRC;
-    sA[i] = r0 + rr < R ? alpha[(size_t)c.ct_col[u0 + sl] * R + r0 + rr] : make_double2(0, 0);
+  // staging: eight (column index, alpha) load pairs in flight per thread
+  // (each pair is two dependent loads, so one at a time would leave the CU
+  // idle for most of the staging)
+  {
+    constexpr int SU = 8;
+    const int tot = nu * CRC;
+    for (int i0 = threadIdx.x; i0 < tot; i0 += SU * (int)blockDim.x) {
+      int col[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int i = min(i0 + u * (int)blockDim.x, tot - 1);
+        col[u] = c.ct_col[u0 + i / CRC];
+      }
+      double2 v[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int i = min(i0 + u * (int)blockDim.x, tot - 1), rr = i % CRC;
+        v[u] = r0 + rr < R ? alpha[(size_t)col[u] * R + r0 + rr] : make_double2(0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        if (i < tot) sA[i] = v[u];
+      }
+    }
   }
   __syncthreads();
   // every lane stays to the end (the rows' nonzeros are shared across lanes);
@@ -1760,38 +1797,59 @@ __global__ void __launch_bounds__(512) k_combine_tiled(CombineMaps c, const doub
   }
   if ((mode & 2) && CRC == 16) {
     // the 16 lanes of a row (one DPP row) load 16 nonzeros at a time, one
-    // each, and broadcast them in turn (row_newbcast); the next 16 are
-    // fetched while these are used.  Lanes past their row's end carry zeros.
+    // each, and broadcast them in turn (row_newbcast).  Loads run four
+    // batches ahead: the next four batches are loaded (clamped index, no
+    // branch) before the current four are used.  Lanes past their row's end
+    // carry zeros.
     const int64_t q0 = c.nf_rowptr[e], q1 = e0 < c.b ? c.nf_rowptr[e + 1] : q0;
-    int64_t qb = q0;
-    double vn = qb + rr < q1 ? c.nf_val[qb + rr] : 0.0;
-    int sn = qb + rr < q1 ? (int)c.nf_slot[qb + rr] : 0;
+    const int64_t qlast = max(c.nf_rowptr[c.b] - 1, (int64_t)0);   // empty arrays hold 16 bytes
     double ax = 0, ay = 0;
-    while (__any(qb < q1)) {
-      const double vc = vn;
-      const int sc = sn;
-      const int64_t qn = qb + 16 + rr;
-      vn = qn < q1 ? c.nf_val[qn] : 0.0;
-      sn = qn < q1 ? (int)c.nf_slot[qn] : 0;
+    auto batch = [&](double vc, int sc) {
+      double2 xv[16];
+      static_for<0, 16>([&](auto KK) {
+        constexpr int K = decltype(KK)::value;
+        xv[K] = sA[row_bcast<K>(sc) * CRC + rr];
+      });
       const int vlo = __double2loint(vc), vhi = __double2hiint(vc);
-#define PFFT_NZ(K)                                                                                  \
-  {                                                                                                 \
-    const double v = __hiloint2double(__builtin_amdgcn_update_dpp(0, vhi, 0x150 + K, 0xF, 0xF, false), \
-                                      __builtin_amdgcn_update_dpp(0, vlo, 0x150 + K, 0xF, 0xF, false)); \
-    const int sl = __builtin_amdgcn_update_dpp(0, sc, 0x150 + K, 0xF, 0xF, false);                  \
-    const double2 xv = sA[sl * CRC + rr];                                                           \
-    if (K & 1) {                                                                                    \
-      ax += v * xv.x;                                                                               \
-      ay += v * xv.y;                                                                               \
-    } else {                                                                                        \
-      kx += v * xv.x;                                                                               \
-      ky += v * xv.y;                                                                               \
-    }                                                                                               \
-  }
-      PFFT_NZ(0) PFFT_NZ(1) PFFT_NZ(2) PFFT_NZ(3) PFFT_NZ(4) PFFT_NZ(5) PFFT_NZ(6) PFFT_NZ(7)
-      PFFT_NZ(8) PFFT_NZ(9) PFFT_NZ(10) PFFT_NZ(11) PFFT_NZ(12) PFFT_NZ(13) PFFT_NZ(14) PFFT_NZ(15)
-#undef PFFT_NZ
-      qb += 16;
+      static_for<0, 16>([&](auto KK) {
+        constexpr int K = decltype(KK)::value;
+        const double v = __hiloint2double(row_bcast<K>(vhi), row_bcast<K>(vlo));
+        if (K & 1) {
+          ax += v * xv[K].x;
+          ay += v * xv[K].y;
+        } else {
+          kx += v * xv[K].x;
+          ky += v * xv[K].y;
+        }
+      });
+    };
+    constexpr int NB = 4;
+    auto fetch = [&](int64_t q, double &v, int &sl) {
+      const int64_t qc = min(q, qlast);
+      const double vv = c.nf_val[qc];
+      const int ss = (int)c.nf_slot[qc];
+      v = q < q1 ? vv : 0.0;
+      sl = q < q1 ? ss : 0;
+    };
+    double vb[NB];
+    int sb[NB];
+    int64_t qb = q0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) fetch(qb + 16 * j + rr, vb[j], sb[j]);
+    while (__any(qb < q1)) {
+      double vn[NB];
+      int sn[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) fetch(qb + 16 * (NB + j) + rr, vn[j], sn[j]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (__any(qb + 16 * j < q1)) batch(vb[j], sb[j]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        vb[j] = vn[j];
+        sb[j] = sn[j];
+      }
+      qb += 16 * NB;
     }
     kx += ax;
     ky += ay;
