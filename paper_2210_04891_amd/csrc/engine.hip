@@ -555,6 +555,21 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
     g.nig = n > 0 ? (int)ig_off.size() - 1 : 0;
     g.ig_off = upload(c, ig_off, st);
     g.ig_tri = upload(c, ord, st);
+    // the active-node positions of each group's 64 stencil nodes (k = 16 i +
+    // 4 j + l for node anchor + (i, j, l)); every stencil node is active
+    std::vector<int> act_pos(N, -1);
+    for (long node = 0, a = 0; node < N; ++node)
+      if (pg_off[node + 1] > pg_off[node]) act_pos[node] = (int)a++;
+    std::vector<int> ig_act((size_t)g.nig * 64);
+    for (int q = 0; q < g.nig; ++q) {
+      const int t = ord[ig_off[q]];
+      for (int k = 0; k < 64; ++k) {
+        const long node = ((long)(m.anchor[3 * t] + k / 16) * m.dims[1] + (m.anchor[3 * t + 1] + (k / 4) % 4)) *
+                              m.dims[2] + (m.anchor[3 * t + 2] + k % 4);
+        ig_act[(size_t)q * 64 + k] = act_pos[node];
+      }
+    }
+    g.ig_act = upload(c, ig_act, st);
   }
   g.pg_off = upload(c, pg_off, st);
   g.pg_tri = upload(c, pg_tri, st);

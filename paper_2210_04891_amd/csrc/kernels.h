@@ -78,6 +78,7 @@ struct GridMaps {
   // INTERP_GROUP a group; group q = ig_tri[ig_off[q] .. ig_off[q+1])
   int nig;
   const int *ig_off, *ig_tri;
+  const int *ig_act;     // [nig][64] active-node positions of each group's stencil nodes
   int nwave;
   const int *ps_off, *ps_k, *ps_ent;
   const void *ps_w;      // [entries][4] (M0, M1x, M1y, M1z) in T

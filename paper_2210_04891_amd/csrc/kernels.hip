@@ -1561,43 +1561,57 @@ __global__ void __launch_bounds__(256) k_interp_nm(GridMaps g, const float2 *phi
 
 // Triangles with the same anchor read the same 64 stencil nodes: a
 // workgroup takes up to INTERP_GROUP of them, and each lane (channel) reads a
-// node's value once for all of them.  Per (triangle, channel) the sums run in
-// the same order as in k_interp_nm.
+// node's value once for all of them.  The nodes' active positions and the
+// triangles' weights are uniform (scalar loads; a lane picks its component's
+// M1 from the four weights by selection), and a lane's node values are
+// loaded KC at a time before they are used.  Per (triangle, channel) the
+// sums run over k = 0 .. 63 in order, as in k_interp_nm.
+// read-only data addressed uniformly: through the constant address space the
+// compiler may use scalar loads even though the kernel also stores to memory
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *uniform_ro(const T *p) {
+  return (const __attribute__((address_space(4))) T *)p;
+}
+
 __global__ void __launch_bounds__(256) k_interp_grp(GridMaps g, const float2 *phiT, double2 *U, int R) {
   constexpr int IG = INTERP_GROUP;
   __shared__ double2 s0[IG][256];
   const int grp = (int)xcd_block(blockIdx.x, gridDim.x);
   const int q0 = g.ig_off[grp], gn = g.ig_off[grp + 1] - q0;
   const int ch = 3 * R;
-  const int Ny = g.dims[1], Nz = g.dims[2];
   int tq[IG];
-  const float *wq[IG];
+  const __attribute__((address_space(4))) float *wq[IG];
 #pragma unroll
   for (int q = 0; q < IG; ++q) {
     tq[q] = g.ig_tri[q0 + min(q, gn - 1)];
-    wq[q] = (const float *)g.tri_w + (size_t)tq[q] * 256;
+    wq[q] = uniform_ro((const float *)g.tri_w + (size_t)tq[q] * 256);
   }
-  const int ax = g.anchor[3 * tq[0]], ay = g.anchor[3 * tq[0] + 1], az = g.anchor[3 * tq[0] + 2];
+  const __attribute__((address_space(4))) int *ia = uniform_ro(g.ig_act + (size_t)grp * 64);
+  constexpr int KC = 16;   // node values in flight per lane
   for (int base = 0; base < ch; base += 255) {
     const int chn = base + threadIdx.x;
     const bool ok = threadIdx.x < 255 && chn < ch;
     const int c = ok ? chn % 3 : 0;
+    const int cc = min(chn, ch - 1);
     double a0x[IG], a0y[IG], a1x[IG], a1y[IG];
 #pragma unroll
     for (int q = 0; q < IG; ++q) a0x[q] = a0y[q] = a1x[q] = a1y[q] = 0;
-#pragma unroll 8
-    for (int k = 0; k < 64; ++k) {
-      const int i = k >> 4, j = (k >> 2) & 3, l = k & 3;
-      const long node = ((long)(ax + i) * Ny + (ay + j)) * Nz + (az + l);
-      const int an = g.act_of[node];
-      const float2 v = ok ? phiT[(size_t)an * ch + chn] : make_float2(0.f, 0.f);
+    for (int kh = 0; kh < 64; kh += KC) {
+      float2 v[KC];
 #pragma unroll
-      for (int q = 0; q < IG; ++q) {
-        const float m0 = wq[q][4 * k], m1 = wq[q][4 * k + 1 + c];
-        a0x[q] += (double)m1 * v.x;
-        a0y[q] += (double)m1 * v.y;
-        a1x[q] += (double)m0 * v.x;
-        a1y[q] += (double)m0 * v.y;
+      for (int k = 0; k < KC; ++k) v[k] = phiT[(size_t)ia[kh + k] * ch + cc];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const double vx = ok ? (double)v[k].x : 0.0, vy = ok ? (double)v[k].y : 0.0;
+#pragma unroll
+        for (int q = 0; q < IG; ++q) {
+          const auto *w = wq[q] + 4 * (kh + k);   // (M0, M1x, M1y, M1z)
+          const double m0 = (double)w[0], m1 = (double)(c == 0 ? w[1] : c == 1 ? w[2] : w[3]);
+          a0x[q] += m1 * vx;
+          a0y[q] += m1 * vy;
+          a1x[q] += m0 * vx;
+          a1y[q] += m0 * vy;
+        }
       }
     }
 #pragma unroll
