@@ -373,18 +373,26 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
   const int rb0 = blockIdx.y * RB, nrb = min(RB, R - rb0);
   const int t0 = g.tt_off[tile], nt = g.tt_off[tile + 1] - t0;
   const int ns = min(nt, g.tcap);
-  // staging, four loads in flight per thread
+  // staging: SU (triangle index, moment) load pairs in flight per thread,
+  // the index loads of a round issued before its moment loads
+  constexpr int SU = 16;
   const int tot = ns * RB * 4;
-  for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * blockDim.x) {
-    V2<T> v[4];
+  for (int i0 = threadIdx.x; i0 < tot; i0 += SU * blockDim.x) {
+    int tri[SU];
 #pragma unroll
-    for (int u2 = 0; u2 < 4; ++u2) {
+    for (int u2 = 0; u2 < SU; ++u2) {
       const int i = min(i0 + u2 * (int)blockDim.x, tot - 1);
-      const int lt = i / (RB * 4), rem = i - lt * (RB * 4), rr = rem >> 2, comp = rem & 3;
-      v[u2] = rr < nrb ? J[((size_t)g.tt_tri[t0 + lt] * R + rb0 + rr) * 4 + comp] : cmk<T>(0, 0);
+      tri[u2] = g.tt_tri[t0 + i / (RB * 4)];
+    }
+    V2<T> v[SU];
+#pragma unroll
+    for (int u2 = 0; u2 < SU; ++u2) {
+      const int i = min(i0 + u2 * (int)blockDim.x, tot - 1);
+      const int rem = i % (RB * 4), rr = rem >> 2, comp = rem & 3;
+      v[u2] = rr < nrb ? J[((size_t)tri[u2] * R + rb0 + rr) * 4 + comp] : cmk<T>(0, 0);
     }
 #pragma unroll
-    for (int u2 = 0; u2 < 4; ++u2) {
+    for (int u2 = 0; u2 < SU; ++u2) {
       const int i = i0 + u2 * (int)blockDim.x;
       if (i < tot) {
         const int lt = i / (RB * 4), rem = i - lt * (RB * 4);
@@ -420,43 +428,59 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
     // groups of 4 so that several loads are in flight; pads add zero
     const int *ent = g.ps_ent + off + lane;
     const T *wl = (const T *)g.ps_w + 4 * ((size_t)off + lane);
-    for (int kb = 0; kb < K; kb += 4) {
-      int locs[4];
-      T wv[4][4];
+    // entries are fetched one block of PB ahead (the copy at the end of a
+    // trip is where the next block's loads are waited for)
+    constexpr int PB = 8;
+    auto fetch = [&](int k, int &loc, T (&w)[4]) {
+      const int kk = min(k, K - 1);
+      loc = ent[64 * (size_t)kk];
 #pragma unroll
-      for (int u2 = 0; u2 < 4; ++u2) {
-        const int k = min(kb + u2, K - 1);
-        locs[u2] = ent[64 * (size_t)k];
+      for (int c = 0; c < 4; ++c) w[c] = wl[256 * (size_t)kk + c];
+    };
+    auto use = [&](int loc, const T (&w)[4]) {
+      const T m0 = w[0], m1x = w[1], m1y = w[2], m1z = w[3];
+      V2<T> jv[RC][4];
+      if (loc >= 0) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) wv[u2][c] = wl[256 * (size_t)k + c];
+        for (int q = 0; q < RC; ++q)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) jv[q][c] = sJ[loc * PS + (grp * RC + q) * 4 + c];
+      } else {
+        const V2<T> *jt = J + ((size_t)(-1 - loc) * R + r0) * 4;
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) jv[q][c] = q < nr ? jt[4 * q + c] : cmk<T>(0, 0);
       }
 #pragma unroll
-      for (int u2 = 0; u2 < 4; ++u2) {
-        if (kb + u2 >= K) break;
-        const int loc = locs[u2];
-        const T m0 = wv[u2][0], m1x = wv[u2][1], m1y = wv[u2][2], m1z = wv[u2][3];
-        V2<T> jv[RC][4];
-        if (loc >= 0) {
+      for (int q = 0; q < RC; ++q) {
+        const V2<T> j0 = jv[q][0], jx = jv[q][1], jy = jv[q][2], jz = jv[q][3];
+        acc[q][0] += j0.x * m1x - jx.x * m0;
+        acc[q][1] += j0.y * m1x - jx.y * m0;
+        acc[q][2] += j0.x * m1y - jy.x * m0;
+        acc[q][3] += j0.y * m1y - jy.y * m0;
+        acc[q][4] += j0.x * m1z - jz.x * m0;
+        acc[q][5] += j0.y * m1z - jz.y * m0;
+      }
+    };
+    if (K > 0) {
+      int lb[PB];
+      T wb[PB][4];
 #pragma unroll
-          for (int q = 0; q < RC; ++q)
+      for (int u = 0; u < PB; ++u) fetch(u, lb[u], wb[u]);
+      for (int kb = 0; kb < K; kb += PB) {
+        int ln[PB];
+        T wn[PB][4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) jv[q][c] = sJ[loc * PS + (grp * RC + q) * 4 + c];
-        } else {
-          const V2<T> *jt = J + ((size_t)(-1 - loc) * R + r0) * 4;
+        for (int u = 0; u < PB; ++u) fetch(kb + PB + u, ln[u], wn[u]);
 #pragma unroll
-          for (int q = 0; q < RC; ++q)
+        for (int u = 0; u < PB; ++u)
+          if (kb + u < K) use(lb[u], wb[u]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) jv[q][c] = q < nr ? jt[4 * q + c] : cmk<T>(0, 0);
-        }
+        for (int u = 0; u < PB; ++u) {
+          lb[u] = ln[u];
 #pragma unroll
-        for (int q = 0; q < RC; ++q) {
-          const V2<T> j0 = jv[q][0], jx = jv[q][1], jy = jv[q][2], jz = jv[q][3];
-          acc[q][0] += j0.x * m1x - jx.x * m0;
-          acc[q][1] += j0.y * m1x - jx.y * m0;
-          acc[q][2] += j0.x * m1y - jy.x * m0;
-          acc[q][3] += j0.y * m1y - jy.y * m0;
-          acc[q][4] += j0.x * m1z - jz.x * m0;
-          acc[q][5] += j0.y * m1z - jz.y * m0;
+          for (int c = 0; c < 4; ++c) wb[u][c] = wn[u][c];
         }
       }
     }
