@@ -225,10 +225,13 @@ __device__ __forceinline__ double2 twig_drop(const LoopMaps &mp, const double2 *
   return make_double2(sg * v.x, sg * v.y);
 }
 
+// Threads are (position, right-hand side) with 8 right-hand sides fastest: a
+// branch's 8 values are one 128-byte segment of yb[e][r], and each row of
+// the output gets 32 consecutive positions per workgroup.
 __global__ void k_drop_diff(LoopMaps mp, const double2 *yb, double2 *scan, int R) {
-  int r = blockIdx.y;
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= mp.nn) return;
+  const int r = blockIdx.y * 8 + (threadIdx.x & 7);
+  const int k = blockIdx.x * 32 + (threadIdx.x >> 3);
+  if (k >= mp.nn || r >= R) return;
   const double2 *y = yb + r;   // yb[e][r]
   double2 d = twig_drop(mp, y, R, k);
   for (int q = mp.end_off[k]; q < mp.end_off[k + 1]; ++q) {
@@ -239,10 +242,11 @@ __global__ void k_drop_diff(LoopMaps mp, const double2 *yb, double2 *scan, int R
   scan[(size_t)r * (mp.nn + 1) + k] = d;
 }
 
+// threads as in k_drop_diff: (link, right-hand side), 8 right-hand sides fastest
 __global__ void k_link_out(LoopMaps mp, const double2 *yb, const double2 *D, double2 *yl, int R) {
-  int r = blockIdx.y;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= mp.l) return;
+  const int r = blockIdx.y * 8 + (threadIdx.x & 7);
+  const int i = blockIdx.x * 32 + (threadIdx.x >> 3);
+  if (i >= mp.l || r >= R) return;
   int e = mp.link_branch[i];
   double2 v = e < mp.b ? yb[(size_t)e * R + r] : make_double2(0, 0);
   int up = mp.link_upos[i], vp = mp.link_vpos[i];
@@ -256,9 +260,9 @@ __global__ void k_link_out(LoopMaps mp, const double2 *yb, const double2 *D, dou
 
 void branch_to_loop(const LoopMaps &mp, const double2 *yb, double2 *yl, double2 *scan,
                     double2 *partials, int R, hipStream_t st) {
-  k_drop_diff<<<dim3(cdiv(mp.nn, 256), R), 256, 0, st>>>(mp, yb, scan, R);
+  k_drop_diff<<<dim3(cdiv(mp.nn, 32), cdiv(R, 8)), 256, 0, st>>>(mp, yb, scan, R);
   scan_rows(scan, scan, mp.nn, mp.nn + 1, R, true, partials, st);
-  k_link_out<<<dim3(cdiv(mp.l, 256), R), 256, 0, st>>>(mp, yb, scan, yl, R);
+  k_link_out<<<dim3(cdiv(mp.l, 32), cdiv(R, 8)), 256, 0, st>>>(mp, yb, scan, yl, R);
 }
 
 // ===========================================================================
