@@ -1126,12 +1126,19 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
     fft_dif<NY, -1>(v);
     const int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
     const int fz = kz <= NZ ? kz : LZ - kz;
-    const float *gx = ghat + (long)fx * (NY + 1) * (NZ + 1) + fz;
+    // Ghat(fx, fy, fz) with fy the folded ky = k0 + half, k0 = 2 brev(p):
+    // fy = k0 + half for k0 < NY, (LY - k0 - 1) + (1 - half) otherwise.  The
+    // lane's part of the offset is one of two registers, the rest is uniform
+    // (scalar offset), so no vector address arithmetic per element.
+    constexpr unsigned K4 = (NZ + 1) * 4u;
+    const __amdgpu_buffer_rsrc_t rg =
+        buf_rsrc(ghat + (long)fx * (NY + 1) * (NZ + 1), (unsigned)((NY + 1) * (NZ + 1) * 4));
+    const unsigned va = (unsigned)fz * 4u + (unsigned)half * K4, vb = (unsigned)fz * 4u + (unsigned)(1 - half) * K4;
 #pragma unroll
     for (int p = 0; p < NY; ++p) {
-      const int ky = 2 * brev(p, clog2(NY)) + half;
-      const int fy = ky <= NY ? ky : LY - ky;
-      const float g = gx[fy * (NZ + 1)];
+      const int k0 = 2 * brev(p, clog2(NY));
+      const float g = k0 < NY ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, va, k0 * K4, 0))
+                              : __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, vb, (LY - k0 - 1) * K4, 0));
       v[p] = make_float2(v[p].x * g, v[p].y * g);
     }
     fft_dit<NY, +1>(v);
