@@ -1,0 +1,108 @@
+"""The package-trace configuration (meander traces, Sec. V's structure types;
+no paper geometry exists, the generator is seeded and synthetic).
+
+* Reduced instance of the same generator (2 traces, 1,580 triangles, FP32
+  grid with the pruned passes): R and L of the 2x2 port system within 0.5% of
+  the dense FP64 oracle (exact kernel, direct solve), like the bar.
+* Full size (32 traces, 200,196 triangles, 300,294 edges, 32 ports, grid
+  256 x 256 x 32, 35 M near pairs): the far-field product against the
+  oracle's explicit B^T (H * (B alpha)); the symmetry of the whole product
+  (K is symmetric, so x . K y = y . K x for the bilinear form, to FP32 level
+  for the grid part and FP64 level for the near field alone); a two-frequency
+  sweep of all 32 ports (64 right-hand sides) to a true residual of 1e-6 with
+  symmetric Z and positive-definite R and L.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+
+def _reduced():
+    return W.traces(ntrace=2, seed=7, area=0.5e-3, target_tris=1600, len_range=(0.3e-3, 0.5e-3),
+                    name="traces_reduced")
+
+
+@gpu
+def test_reduced_traces_rl_match_oracle():
+    import paper_2210_04891_amd as P
+    from oracle.mesh import RWGMesh
+    from oracle import integrals, solve as S
+    from systems import oracle_system
+    s = _reduced()
+    m = RWGMesh(s.V, s.T)
+    K = integrals.kernel_dense(m)
+    _, c, _, A, Zb = oracle_system(s, K)
+    f = np.array([1e9, 1e10])
+    ctx = P.Context(s, (32, 32, 16), near_kappa=1.5, grid_fp64=False)
+    assert ctx.get_option("fft_prune") == 1
+    Y, it, rr, code = ctx.solve_ports(f, tol=1e-7, maxit=300, restart=60, precond=1)
+    assert code == 0 and np.all(rr <= 1e-7)
+    R, L = P.extract_RL(f, Y)
+    for k in range(f.size):
+        om = 2 * np.pi * f[k]
+        Yo, _ = S.port_admittance(S.loop_impedance(A, Zb(om)), c.port_loop)
+        Ro, Lo, _ = S.extract_rl(Yo, om)
+        for i in range(2):
+            assert R[k, i, i] == pytest.approx(Ro[i, i], rel=5e-3), (k, i)
+            assert L[k, i, i] == pytest.approx(Lo[i, i], rel=5e-3), (k, i)
+        # mutual inductance of the two traces (small, so an absolute bound)
+        assert abs(L[k, 0, 1] - Lo[0, 1]) <= 5e-3 * Lo[0, 0]
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import paper_2210_04891_amd as P
+    s = W.config3_traces()
+    ctx = P.Context(s, (256, 256, 32), stencil=4, near_kappa=1.5, grid_fp64=False)
+    return s, ctx
+
+
+@gpu
+def test_config3_far_field_matches_oracle(c3):
+    import paper_2210_04891_amd as P
+    from oracle.mesh import RWGMesh
+    from oracle import pfft as PF
+    s, ctx = c3
+    m = RWGMesh(s.V, s.T)
+    op = PF.PFFTOperator(m, (256, 256, 32), 4, 1.5, with_near=False)
+    X = W.complex_normal(23, (2, m.nedge))
+    y = ctx.matvec(torch.from_numpy(X).cuda(), space=0, flags=P.PFFT_FAR_ONLY).cpu().numpy()
+    for r in range(2):
+        ref = op.far(X[r])
+        err = np.linalg.norm(y[r] - ref) / np.linalg.norm(ref)
+        assert err < 1e-5, err
+
+
+@gpu
+def test_config3_product_symmetric(c3):
+    import paper_2210_04891_amd as P
+    s, ctx = c3
+    b = ctx.sizes["b"]
+    X = W.complex_normal(29, (16, b))
+    Yv = W.complex_normal(31, (16, b))
+    for flags, tol in ((P.PFFT_NEAR_ONLY, 1e-12), (0, 2e-6)):
+        kx = ctx.matvec(torch.from_numpy(X).cuda(), space=0, flags=flags).cpu().numpy()
+        ky = ctx.matvec(torch.from_numpy(Yv).cuda(), space=0, flags=flags).cpu().numpy()
+        for r in range(16):
+            a, c = Yv[r] @ kx[r], X[r] @ ky[r]
+            scale = np.linalg.norm(Yv[r]) * np.linalg.norm(kx[r])
+            assert abs(a - c) <= tol * scale, (flags, r, abs(a - c) / scale)
+
+
+@gpu
+def test_config3_sweep_reciprocity_and_passivity(c3):
+    import paper_2210_04891_amd as P
+    s, ctx = c3
+    f = np.array([1e8, 1e10])
+    Y, it, rr, code = ctx.solve_ports(f, tol=1e-6, maxit=400, restart=40, precond=1)
+    assert code == 0 and np.all(rr <= 1e-6)
+    R, L = P.extract_RL(f, Y)
+    for k in range(f.size):
+        Z = np.linalg.inv(Y[k])
+        assert np.abs(Z - Z.T).max() <= 1e-4 * np.abs(Z).max(), k
+        assert np.all(np.linalg.eigvalsh(0.5 * (R[k] + R[k].T)) > 0), k
+        assert np.all(np.linalg.eigvalsh(0.5 * (L[k] + L[k].T)) > 0), k
