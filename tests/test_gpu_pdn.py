@@ -1,0 +1,91 @@
+"""The plane-and-via configuration (PDN-like, one conductor of genus
+vias - 1, several ports on it; the generator is seeded and synthetic).
+
+* Reduced instance (1 x 1 mm planes on a 100 um lattice, 2 vias, 2 ports,
+  1,104 triangles; FP32 grid with pruned passes): R and L of the 2x2 port
+  system within 0.5% of the dense FP64 oracle at 1 and 10 GHz.
+* Mid-size instance on the full configuration's 28.6 um lattice (2.86 x 2.86
+  mm, 8 vias, 4 ports, ~80k triangles, grid 128 x 128 x 16): the far-field
+  product against the oracle's explicit B^T (H * (B alpha)), and a 1 GHz
+  solve of the 4 ports to 1e-6 with symmetric Z and positive-definite R, L.
+  The full 10 x 10 mm, 100-via configuration (995,200 triangles) builds and
+  runs its product, but its band factorization of P (one conductor of
+  ~1 M nodes, band ~700) is out of reach of the envelope LDL^T.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+
+@gpu
+def test_reduced_pdn_rl_match_oracle():
+    import paper_2210_04891_amd as P
+    from oracle.mesh import RWGMesh
+    from oracle import integrals, solve as S
+    from systems import oracle_system
+    s = W.pdn(nx=10, ny=10, cell=100e-6, vias=[(2, 2), (6, 6)], block=2, ports=[(1, 6), (6, 1)], patch=2)
+    m = RWGMesh(s.V, s.T)
+    K = integrals.kernel_dense(m)
+    _, c, _, A, Zb = oracle_system(s, K)
+    f = np.array([1e9, 1e10])
+    ctx = P.Context(s, (32, 32, 16), near_kappa=1.5, grid_fp64=False)
+    Y, it, rr, code = ctx.solve_ports(f, tol=1e-7, maxit=300, restart=60, precond=1)
+    assert code == 0 and np.all(rr <= 1e-7)
+    R, L = P.extract_RL(f, Y)
+    for k in range(f.size):
+        om = 2 * np.pi * f[k]
+        Yo, _ = S.port_admittance(S.loop_impedance(A, Zb(om)), c.port_loop)
+        Ro, Lo, _ = S.extract_rl(Yo, om)
+        for i in range(2):
+            for j in range(2):
+                assert abs(R[k, i, j] - Ro[i, j]) <= 5e-3 * Ro[i, i], (k, i, j)
+                assert abs(L[k, i, j] - Lo[i, j]) <= 5e-3 * Lo[i, i], (k, i, j)
+
+
+def _mid():
+    rng = np.random.default_rng(7)
+    cell = 10e-3 / 350
+    vias = W.geometry._via_sites(rng, 100, 100, 6, 8, int(np.ceil(300e-6 / cell)), 2)
+    ports = [(30, 30), (30, 66), (66, 30), (66, 66)]
+    return W.pdn(nx=100, ny=100, cell=cell, vias=vias, block=6, ports=ports, name="pdn_mid")
+
+
+@pytest.fixture(scope="module")
+def mid():
+    import paper_2210_04891_amd as P
+    s = _mid()
+    ctx = P.Context(s, (128, 128, 16), stencil=4, near_kappa=1.5, grid_fp64=False)
+    return s, ctx
+
+
+@gpu
+def test_mid_pdn_far_field_matches_oracle(mid):
+    import paper_2210_04891_amd as P
+    from oracle.mesh import RWGMesh
+    from oracle import pfft as PF
+    s, ctx = mid
+    m = RWGMesh(s.V, s.T)
+    op = PF.PFFTOperator(m, (128, 128, 16), 4, 1.5, with_near=False)
+    X = W.complex_normal(41, (2, m.nedge))
+    y = ctx.matvec(torch.from_numpy(X).cuda(), space=0, flags=P.PFFT_FAR_ONLY).cpu().numpy()
+    for r in range(2):
+        ref = op.far(X[r])
+        assert np.linalg.norm(y[r] - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
+@gpu
+def test_mid_pdn_solve_reciprocity_and_passivity(mid):
+    import paper_2210_04891_amd as P
+    s, ctx = mid
+    f = np.array([1e9])
+    Y, it, rr, code = ctx.solve_ports(f, tol=1e-6, maxit=600, restart=60, precond=1)
+    assert code == 0 and np.all(rr <= 1e-6)
+    R, L = P.extract_RL(f, Y)
+    Z = np.linalg.inv(Y[0])
+    assert np.abs(Z - Z.T).max() <= 1e-4 * np.abs(Z).max()
+    assert np.all(np.linalg.eigvalsh(0.5 * (R[0] + R[0].T)) > 0)
+    assert np.all(np.linalg.eigvalsh(0.5 * (L[0] + L[0].T)) > 0)

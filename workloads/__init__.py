@@ -7,9 +7,9 @@ functions, no integrals, no loop analysis), so the oracle and the GPU path
 can both consume it without sharing any computation.
 """
 from .geometry import (Structure, box_bar, prism, paper_bar_e1, bond_wires,
-                       config1_bar, config2_wires, traces, config3_traces)
+                       config1_bar, config2_wires, traces, config3_traces, pdn, config4_pdn)
 from .vectors import complex_normal, real_normal
 
 __all__ = ["Structure", "box_bar", "prism", "paper_bar_e1", "bond_wires",
-           "config1_bar", "config2_wires", "traces", "config3_traces",
+           "config1_bar", "config2_wires", "traces", "config3_traces", "pdn", "config4_pdn",
            "complex_normal", "real_normal"]

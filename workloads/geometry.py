@@ -13,6 +13,7 @@ geometries are only shown in figures:
 * ``prism``         -- the 8-triangle prism of Fig. 1.
 * ``config2_wires`` -- 8 parabolic bond wires, 12-gon section, ~40k triangles.
 * ``config3_traces``-- 32 Manhattan meander traces in 156.25 um lanes.
+* ``config4_pdn``   -- two 10 x 10 mm planes joined by 100 vias, ~1 M triangles.
 """
 from dataclasses import dataclass, field
 import numpy as np
@@ -388,3 +389,198 @@ def traces(ntrace=32, seed=0, area=5e-3, width=20e-6, thick=15e-6, nw=4, nt=3,
 def config3_traces(seed=0):
     """32 meander traces on a 5 x 5 mm area, ~200k triangles, 32 ports."""
     return traces(seed=seed, name="config3_traces")
+
+
+def _zipper(inner, outer, ci, co):
+    """Triangles between two closed vertex rings around a common centre, each
+    listed counter-clockwise by angle (``ci``/``co``: their angles, increasing
+    from the same start); both rings are star-shaped about the centre, so
+    advancing along whichever ring has the next smaller angle never folds."""
+    ni, no = len(inner), len(outer)
+    ai = np.concatenate([ci, ci[:1] + 2 * np.pi])
+    ao = np.concatenate([co, co[:1] + 2 * np.pi])
+    tris = []
+    i = j = 0
+    while i < ni or j < no:
+        if j < no and (i >= ni or ao[j + 1] <= ai[i + 1]):
+            tris.append((inner[i % ni], outer[j % no], outer[(j + 1) % no]))
+            j += 1
+        else:
+            tris.append((inner[i % ni], outer[j % no], inner[(i + 1) % ni]))
+            i += 1
+    return tris
+
+
+def pdn(nx=350, ny=350, cell=10e-3 / 350, thick=35e-6, gap=200e-6, vias=(), block=6, radius=50e-6,
+        nfacet=12, ports=(), patch=4, name="pdn"):
+    """Two parallel copper planes joined by cylindrical vias, as one closed
+    surface (genus = number of vias - 1).
+
+    The planes span [0, nx cell] x [0, ny cell]; the lower one z in [0, thick],
+    the upper one z in [thick + gap, 2 thick + gap].  Their large faces are
+    lattices of cell x cell squares cut into two triangles.  A via joins the
+    lower plane's top face to the upper plane's bottom face: it occupies a
+    ``block`` x ``block`` cell block with lower corner ``vias[k]`` = (i, j),
+    whose interior lattice points are replaced by an ``nfacet``-gon hole of
+    the given radius at the block centre (the ring between the block's
+    boundary points and the hole is triangulated by angle), and its barrel is
+    an ``nfacet``-gon prism in about cell-high rings.  The side faces carry the
+    lattice spacing along the edges and about cell-high layers across.
+    Port k (``ports[k]`` = (i, j)): source = the ``patch`` x ``patch`` cells
+    at (i, j) of the upper plane's top face, sink = the same cells of the
+    lower plane's bottom face."""
+    nzl = max(1, int(round(thick / cell)))
+    nzb = max(1, int(round(gap / cell)))
+    zlev = [[p * (thick + gap) + thick * k / nzl for k in range(nzl + 1)] for p in range(2)]
+    xs = np.arange(nx + 1) * cell
+    ys = np.arange(ny + 1) * cell
+    inblock = np.zeros((nx, ny), dtype=bool)      # cells replaced by a via ring
+    hidden = np.zeros((nx + 1, ny + 1), dtype=bool)
+    for (bi, bj) in vias:
+        assert 0 < bi and bi + block < nx and 0 < bj and bj + block < ny, "via block off the plane"
+        assert not inblock[bi:bi + block, bj:bj + block].any(), "overlapping via blocks"
+        inblock[bi:bi + block, bj:bj + block] = True
+        hidden[bi + 1:bi + block, bj + 1:bj + block] = True
+    V = []
+    nv = 0
+
+    def add(pts):
+        nonlocal nv
+        pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+        V.append(pts)
+        ids = np.arange(nv, nv + pts.shape[0])
+        nv += pts.shape[0]
+        return ids
+
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    # big-face lattices: face (p, top) for plane p, top = 0 lower face, 1 upper
+    face = {}
+    for p in range(2):
+        for top in range(2):
+            z = zlev[p][nzl if top else 0]
+            holes = (p == 0 and top == 1) or (p == 1 and top == 0)
+            ids = -np.ones((nx + 1, ny + 1), dtype=np.int64)
+            keep = ~hidden if holes else np.ones_like(hidden)
+            ids[keep] = add(np.stack([X[keep], Y[keep], np.full(int(keep.sum()), z)], axis=1))
+            face[(p, top)] = ids
+    # intermediate z levels of the side faces: perimeter points only
+    per = [(i, 0) for i in range(nx)] + [(nx, j) for j in range(ny)] + \
+          [(i, ny) for i in range(nx, 0, -1)] + [(0, j) for j in range(ny, 0, -1)]
+    side = {}
+    for p in range(2):
+        for k in range(nzl + 1):
+            if k == 0:
+                side[(p, k)] = np.array([face[(p, 0)][i, j] for i, j in per])
+            elif k == nzl:
+                side[(p, k)] = np.array([face[(p, 1)][i, j] for i, j in per])
+            else:
+                side[(p, k)] = add([(xs[i], ys[j], zlev[p][k]) for i, j in per])
+    tris, tag = [], []
+    Vall = lambda: np.concatenate(V)   # noqa: E731
+    # large faces
+    for (p, top), ids in face.items():
+        holes = (p == 0 and top == 1) or (p == 1 and top == 0)
+        ii, jj = np.nonzero(~inblock) if holes else np.nonzero(np.ones((nx, ny), bool))
+        a, b, c, d = ids[ii, jj], ids[ii + 1, jj], ids[ii + 1, jj + 1], ids[ii, jj + 1]
+        if top:   # outward +z: counter-clockwise seen from above
+            t1, t2 = np.stack([a, b, c], 1), np.stack([a, c, d], 1)
+        else:
+            t1, t2 = np.stack([a, c, b], 1), np.stack([a, d, c], 1)
+        tt = np.empty((2 * len(ii), 3), dtype=np.int64)
+        tt[0::2], tt[1::2] = t1, t2
+        tris.append(tt)
+        tg = np.empty((2 * len(ii), 3), dtype=np.int64)
+        tg[:, 0], tg[:, 1], tg[:, 2] = (p * 2 + top), np.repeat(ii, 2), np.repeat(jj, 2)
+        tag.append(tg)
+    # side faces
+    npr = len(per)
+    for p in range(2):
+        for k in range(nzl):
+            lo, hi = side[(p, k)], side[(p, k + 1)]
+            q = np.arange(npr)
+            a, b, c, d = lo[q], lo[(q + 1) % npr], hi[(q + 1) % npr], hi[q]
+            # the perimeter runs counter-clockwise seen from above, so
+            # (a, b, c) winds outward
+            tt = np.empty((2 * npr, 3), dtype=np.int64)
+            tt[0::2], tt[1::2] = np.stack([a, b, c], 1), np.stack([a, c, d], 1)
+            tris.append(tt)
+            tag.append(np.full((2 * npr, 3), -1, dtype=np.int64))
+    # via rings and barrels
+    ang = 2 * np.pi * (np.arange(nfacet) + 0.5) / nfacet
+    extra = []
+    for (bi, bj) in vias:
+        cx, cy = (bi + block / 2) * cell, (bj + block / 2) * cell
+        bnd = [(bi + s, bj) for s in range(block)] + [(bi + block, bj + s) for s in range(block)] + \
+              [(bi + block - s, bj + block) for s in range(block)] + [(bi, bj + block - s) for s in range(block)]
+        bang = np.array([np.arctan2(ys[j] - cy, xs[i] - cx) for i, j in bnd])
+        # start both rings at the smallest angle of the boundary (a corner)
+        r0 = int(np.argmin(np.mod(bang, 2 * np.pi)))
+        bnd = bnd[r0:] + bnd[:r0]
+        bang = np.mod(np.concatenate([bang[r0:], bang[:r0]]) - 0.0, 2 * np.pi)
+        start = bang[0]
+        bang = np.mod(bang - start, 2 * np.pi)
+        hang = np.mod(ang - start, 2 * np.pi)
+        hord = np.argsort(hang)
+        rings = []
+        for s in range(nzb + 1):
+            z = thick + gap * s / nzb
+            rings.append(add(np.stack([cx + radius * np.cos(ang), cy + radius * np.sin(ang),
+                                       np.full(nfacet, z)], axis=1)))
+        for s, (p, top, outz) in ((0, (0, 1, 1.0)), (nzb, (1, 0, -1.0))):
+            ids = face[(p, top)]
+            outer = [ids[i, j] for i, j in bnd]
+            inner = [rings[s][h] for h in hord]
+            VV = Vall()
+            for t in _zipper(inner, outer, hang[hord], bang):
+                extra.append(_orient(VV, t, np.array([0.0, 0.0, outz])))
+        VV = Vall()
+        for s in range(nzb):
+            for h in range(nfacet):
+                h1 = (h + 1) % nfacet
+                a, b, c, d = rings[s][h], rings[s][h1], rings[s + 1][h1], rings[s + 1][h]
+                mid = 0.25 * (VV[a] + VV[b] + VV[c] + VV[d])
+                out = np.array([mid[0] - cx, mid[1] - cy, 0.0])
+                extra.append(_orient(VV, (a, b, c), out))
+                extra.append(_orient(VV, (a, c, d), out))
+    T = np.concatenate(tris + ([np.array(extra, dtype=np.int64)] if extra else []), axis=0).astype(np.int32)
+    tags = np.concatenate(tag + ([np.full((len(extra), 3), -1, dtype=np.int64)] if extra else []), axis=0)
+    Vc = Vall()
+    plist = []
+    for (pi, pj) in ports:
+        sel = lambda f: np.nonzero((tags[:, 0] == f) & (tags[:, 1] >= pi) & (tags[:, 1] < pi + patch) &  # noqa: E731
+                                   (tags[:, 2] >= pj) & (tags[:, 2] < pj + patch))[0].astype(np.int32)
+        plist.append((sel(3), sel(0)))   # source: upper plane's top face; sink: lower plane's bottom face
+    return Structure(name, Vc, T, plist, dict(nx=nx, ny=ny, cell=cell, thick=thick, gap=gap, vias=list(vias),
+                                              block=block, radius=radius, nfacet=nfacet, patch=patch))
+
+
+def _via_sites(rng, nx, ny, block, nvia, min_gap_cells, margin):
+    """Rejection-sampled lower corners of nvia via blocks, block centres at
+    least min_gap_cells apart and ``margin`` cells from the plane edge."""
+    out = []
+    tries = 0
+    while len(out) < nvia:
+        tries += 1
+        assert tries < 100000, "cannot place the vias"
+        i = int(rng.integers(margin, nx - margin - block))
+        j = int(rng.integers(margin, ny - margin - block))
+        if all((i - a) ** 2 + (j - b) ** 2 >= min_gap_cells ** 2 for a, b in out):
+            out.append((i, j))
+    return out
+
+
+def config4_pdn(seed=0, nx=350, nvia=100, nport=16):
+    """Two 10 x 10 mm planes, 35 um thick, 0.2 mm apart, joined by ``nvia``
+    vias of 100 um diameter (12 facets) at seeded positions at least 300 um
+    apart on the ~28.6 um lattice; ``nport`` ports as a square array of
+    ~114 um patches, source on the top face, sink directly below on the
+    bottom face.  ~1 M triangles at the default size."""
+    cell = 10e-3 / 350
+    rng = np.random.default_rng(1000 + seed)
+    block = 6
+    vias = _via_sites(rng, nx, nx, block, nvia, int(np.ceil(300e-6 / cell)), 2)
+    k = int(round(np.sqrt(nport)))
+    assert k * k == nport
+    step = nx // (k + 1)
+    ports = [(step * (a + 1) - 2, step * (b + 1) - 2) for a in range(k) for b in range(k)]
+    return pdn(nx=nx, ny=nx, cell=cell, vias=vias, block=block, ports=ports, name="config4_pdn")
