@@ -791,40 +791,76 @@ constexpr int brev(int k, int bits) {
   return r;
 }
 
-// decimation in frequency: natural order in, bit-reversed order out
+// Radix-2^2 in-register FFTs: two radix-2 stages at a time, arranged as a
+// radix-4 butterfly so that only three of every four points of a stage pair
+// take a general twiddle (the others take a quarter turn, which twmul makes
+// exact); the data order is that of the radix-2 algorithms.
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// decimation in frequency: natural order in, bit-reversed order out.  Stage
+// pair on blocks of B = N >> S points, quarters q = B / 4: with s = a + b,
+// d = a - b for the pairs (j, j + B/2), the four outputs of j < q are
+// (s_j + s_{j+q}), (s_j - s_{j+q}) W_B^{2j}, (d_j + r d_{j+q}) W_B^j and
+// (d_j - r d_{j+q}) W_B^{3j}, r the quarter turn W_4 of the transform's sign.
 template <int N, int SIGN, int S = 0>
 __device__ __forceinline__ void fft_dif(float2 (&v)[N]) {
-  if constexpr ((1 << S) < N) {
-    constexpr int half = N >> (S + 1);
+  constexpr int B = N >> S;
+  if constexpr (B >= 4) {
+    constexpr int h = B / 2, q = B / 4;
 #pragma unroll
-    for (int b = 0; b < (1 << S); ++b)
+    for (int blk = 0; blk < N / B; ++blk)
 #pragma unroll
-      for (int j = 0; j < half; ++j) {
-        const int i0 = b * 2 * half + j, i1 = i0 + half;
-        const float2 a = v[i0], c = v[i1];
-        v[i0] = make_float2(a.x + c.x, a.y + c.y);
-        v[i1] = twmul<SIGN>(make_float2(a.x - c.x, a.y - c.y), j, 2 * half);
+      for (int j = 0; j < q; ++j) {
+        const int i0 = blk * B + j, i1 = i0 + q, i2 = i0 + h, i3 = i2 + q;
+        const float2 s0 = cadd(v[i0], v[i2]), d0 = csub(v[i0], v[i2]);
+        const float2 s1 = cadd(v[i1], v[i3]), d1 = twmul<SIGN>(csub(v[i1], v[i3]), 1, 4);
+        v[i0] = cadd(s0, s1);
+        v[i1] = twmul<SIGN>(csub(s0, s1), 2 * j, B);
+        v[i2] = twmul<SIGN>(cadd(d0, d1), j, B);
+        v[i3] = twmul<SIGN>(csub(d0, d1), 3 * j, B);
       }
-    fft_dif<N, SIGN, S + 1>(v);
+    fft_dif<N, SIGN, S + 2>(v);
+  } else if constexpr (B == 2) {
+#pragma unroll
+    for (int i = 0; i < N; i += 2) {
+      const float2 a = v[i], c = v[i + 1];
+      v[i] = cadd(a, c);
+      v[i + 1] = csub(a, c);
+    }
   }
 }
 
-// decimation in time: bit-reversed order in, natural order out
+// decimation in time: bit-reversed order in, natural order out.  Stage pair
+// with halves h and 2h on blocks of B = 4 h: the inputs at j, j + h, j + 2h,
+// j + 3h (j < h) take W_B^0, W_B^{2j}, W_B^j, W_B^{3j} and then a radix-4
+// butterfly; a leftover last stage is radix 2.
 template <int N, int SIGN, int S = 0>
 __device__ __forceinline__ void fft_dit(float2 (&v)[N]) {
-  if constexpr ((1 << S) < N) {
-    constexpr int half = 1 << S;
+  constexpr int h = 1 << S, B = 4 * h;
+  if constexpr (B <= N) {
 #pragma unroll
-    for (int b = 0; b < N / (2 * half); ++b)
+    for (int blk = 0; blk < N / B; ++blk)
 #pragma unroll
-      for (int j = 0; j < half; ++j) {
-        const int i0 = b * 2 * half + j, i1 = i0 + half;
-        const float2 a = v[i0];
-        const float2 c = twmul<SIGN>(v[i1], j, 2 * half);
-        v[i0] = make_float2(a.x + c.x, a.y + c.y);
-        v[i1] = make_float2(a.x - c.x, a.y - c.y);
+      for (int j = 0; j < h; ++j) {
+        const int p0 = blk * B + j, p1 = p0 + h, p2 = p0 + 2 * h, p3 = p0 + 3 * h;
+        const float2 a = v[p0], b = twmul<SIGN>(v[p1], 2 * j, B);
+        const float2 c = twmul<SIGN>(v[p2], j, B), d = twmul<SIGN>(v[p3], 3 * j, B);
+        const float2 x0 = cadd(a, b), x1 = csub(a, b), y2 = cadd(c, d);
+        const float2 y3 = twmul<SIGN>(csub(c, d), 1, 4);
+        v[p0] = cadd(x0, y2);
+        v[p2] = csub(x0, y2);
+        v[p1] = cadd(x1, y3);
+        v[p3] = csub(x1, y3);
       }
-    fft_dit<N, SIGN, S + 1>(v);
+    fft_dit<N, SIGN, S + 2>(v);
+  } else if constexpr (2 * h == N) {
+#pragma unroll
+    for (int j = 0; j < h; ++j) {
+      const float2 a = v[j], c = twmul<SIGN>(v[j + h], j, 2 * h);
+      v[j] = cadd(a, c);
+      v[j + h] = csub(a, c);
+    }
   }
 }
 
