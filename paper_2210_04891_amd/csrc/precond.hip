@@ -579,13 +579,28 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
 // lane index), subtracts its product with the factor from every lane (one
 // complex FMA; the factor row is loaded rotated by p, so lane l takes the
 // entry of its own row and the zero padding masks everything outside the
-// band), and hands lane p mod 64 the right-hand side of position p + 64.  No
-// LDS, no barrier, no lane shifts; solved values are collected one per lane
-// and stored 64 rows at a time.  Rows past the band read from beyond the
-// factor buffer, which the buffer load returns as zeros.
+// band).  Lane p mod 64 itself takes the unit entry kept in the layouts' last
+// padding slot, which turns its sum into exactly zero; from there it gathers
+// the updates of position p + 64, whose right-hand side is added once per
+// block.  No LDS, no barrier, no lane shifts, no per-step selects; solved
+// values are collected one per lane (writelane) and stored 64 rows at a time.
+// Rows past the band read from beyond the factor buffer, which the buffer
+// load returns as zeros.
 __device__ __forceinline__ double dbl_lane(double v, int l) {
   const long long b = __builtin_bit_cast(long long, v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// v_writelane (the compiler intrinsic has no builtin spelling): returns old
+// with lane l set to the uniform val
+__device__ int amdgcn_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// v with lane l replaced by the uniform value u
+__device__ __forceinline__ double dbl_put(double v, double u, int l) {
+  const long long b = __builtin_bit_cast(long long, v), c = __builtin_bit_cast(long long, u);
+  const int lo = amdgcn_writelane((int)(c & 0xffffffffll), l, (int)(b & 0xffffffffll));
+  const int hi = amdgcn_writelane((int)(c >> 32), l, (int)(b >> 32));
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -642,18 +657,22 @@ __global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *f
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
         const int s = sb + q;
-        const double2 L = Lc[q];   // zero in lane s (padding)
+        const double2 L = Lc[q];   // lane s: the unit self entry, so its sum becomes exactly 0
         double fx = fma(-L.x, vx, ax), fy = fma(-L.x, vy, ay);
         fx = fma(L.y, vy, fx);
         fy = fma(-L.y, vx, fy);
+        yx = dbl_put(yx, vx, s);   // (vx, vy): the finished value of position s
+        yy = dbl_put(yy, vy, s);
         vx = dbl_lane(fx, (s + 1) & 63);
         vy = dbl_lane(fy, (s + 1) & 63);
-        const bool sel = lane == s;
-        yx = sel ? fx : yx;
-        yy = sel ? fy : yy;
-        ax = sel ? bc.x : fx;
-        ay = sel ? bc.y : fy;
+        ax = fx;
+        ay = fy;
       }
+      // the lanes finished in this block start position p + 64: their sums
+      // so far are the updates it already received, to which its right-hand
+      // side is added (bc is zero in every other lane)
+      ax += bc.x;
+      ay += bc.y;
 #pragma unroll
       for (int q = 0; q < RP; ++q) Lc[q] = Ln[q];
       bc = bn;
@@ -699,18 +718,22 @@ __global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *f
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
         const int s = sb + q;
-        const double2 L = Lc[q];   // zero in lane s (padding)
+        const double2 L = Lc[q];   // lane s: the unit self entry, so its sum becomes exactly 0
         double fx = fma(-L.x, vx, ax), fy = fma(-L.x, vy, ay);
         fx = fma(L.y, vy, fx);
         fy = fma(-L.y, vx, fy);
+        ox = dbl_put(ox, vx, s);   // (vx, vy): the finished value of position s
+        oy = dbl_put(oy, vy, s);
         vx = dbl_lane(fx, (s + 1) & 63);
         vy = dbl_lane(fy, (s + 1) & 63);
-        const bool sel = lane == s;
-        ox = sel ? fx : ox;
-        oy = sel ? fy : oy;
-        ax = sel ? bc.x : fx;
-        ay = sel ? bc.y : fy;
+        ax = fx;
+        ay = fy;
       }
+      // the lanes finished in this block start position p + 64: their sums
+      // so far are the updates it already received, to which its right-hand
+      // side is added (bc is zero in every other lane)
+      ax += bc.x;
+      ay += bc.y;
 #pragma unroll
       for (int q = 0; q < RP; ++q) Lc[q] = Ln[q];
       bc = bn;
@@ -830,6 +853,10 @@ __global__ void k_fac_assemble(FactorArgs a) {
   const double2 zero = make_double2(0, 0);
   for (int t = 0; t < a.pr; ++t) rowp[t] = zero;
   for (int t = 0; t < a.pc; ++t) colp[t] = zero;
+  // 64-entry layouts (band width at most 63): the last slot, never part of
+  // the band, holds 1 (the register-window solve's self entry)
+  if (a.pr == 64) rowp[63] = make_double2(1.0, 0.0);
+  if (a.pc == 64) colp[63] = make_double2(1.0, 0.0);
   if (super)
     for (int k = 0; k < i - fi; ++k) fr[k] = zero;
   double2 dsum = zero;

@@ -201,6 +201,14 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
         std::copy(f1.begin(), f1.end(), fe.begin() + (size_t)f * nfull);
       }
       if (bad) throw SetupError{PFFT_EFACTOR, "zero pivot in the nodal factorization"};
+      // 64-entry layouts: the unit self entry of the register-window solve
+      // in the last (padding) slot of every row, as the device assembly
+      // writes it
+      for (int f = 0; f < nf; ++f)
+        for (int i = 0; i < P->ps.nu; ++i) {
+          if (P->ps.pr == 64) env[(size_t)f * ne + (size_t)i * 64 + 63] = 1.0;
+          if (P->ps.pc == 64) ce[(size_t)f * nc + (size_t)i * 64 + 63] = 1.0;
+        }
       hip_ok(hipStreamSynchronize(st), "precond sync");
       P->omegas.clear();
       if (ne) hip_ok(hipMemcpy(P->d_env, env.data(), ne * nf * sizeof(double2), hipMemcpyHostToDevice), "env");
