@@ -114,7 +114,8 @@ void pfft_ctx::ensure_workspace(Workspace &w, int R) {
   w.yb = (double2 *)al(sizeof(double2) * (size_t)R * m.b);
   w.scan = (double2 *)al(sizeof(double2) * (size_t)R * (m.nn + 1));
   w.part = (double2 *)al(sizeof(double2) * scan_partials_size(m.nn + 1, R));
-  w.U = (double2 *)al(sizeof(double2) * (size_t)R * m.n * 4);
+  // U also holds the transposed loop vector inside the loop transforms
+  w.U = (double2 *)al(sizeof(double2) * (size_t)R * std::max<size_t>((size_t)m.n * 4, (size_t)m.l));
   w.coef = (double2 *)al(sizeof(double2) * 2 * (size_t)R);
   w.J = al(vs * (size_t)R * m.n * 4);
   w.Q = al(vs * (size_t)R * 3 * N);
@@ -151,7 +152,7 @@ void pfft_ctx::matvec_range(Workspace &w, int R, const double *omega, int space,
     PassHook *hk = timer.on ? &hook : nullptr;
     if (space == 1) {
       timer.begin(ST_LOOP_TO_BRANCH, st);
-      loop_to_branch(lm, xc, w.alpha, w.scan, w.part, Rn, st);
+      loop_to_branch(lm, xc, w.alpha, w.scan, w.part, w.U, Rn, st);   // U is free until interpolation
     } else {
       timer.begin(ST_LOOP_TO_BRANCH, st);
       transpose(xc, w.alpha, Rn, m.b, st);
@@ -199,7 +200,7 @@ void pfft_ctx::matvec_range(Workspace &w, int R, const double *omega, int space,
       timer.begin(ST_COMBINE, st);
       combine(cm, alpha, w.U, zs, jw, w.yb, Rn, mode, st);
       timer.begin(ST_BRANCH_TO_LOOP, st);
-      branch_to_loop(lm, w.yb, yc, w.scan, w.part, Rn, st);
+      branch_to_loop(lm, w.yb, yc, w.scan, w.part, w.U, Rn, st);   // U was last read by combine
       if (post) {
         PostOut o = *post;
         if (o.Ib) o.Ib += (size_t)r0 * (m.b + m.p);

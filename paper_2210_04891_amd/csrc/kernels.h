@@ -12,10 +12,8 @@ template <typename T> using V2 = typename vec2<T>::type;
 
 // ---- host launchers (all asynchronous on `st`) ----
 
-// Batched prefix sum over rows of complex128: out[r][k] = sum_{j<k} (exclusive)
-// or sum_{j<=k} (inclusive) of in[r][j], for R rows of length len, row stride ld.
-void scan_rows(const double2 *in, double2 *out, int len, int ld, int R, bool inclusive,
-               double2 *partials, hipStream_t st);
+// complex128 entries of the partial-sum scratch of a prefix scan down the
+// columns of a [len][R] array
 size_t scan_partials_size(int len, int R);
 
 struct LoopMaps {
@@ -32,11 +30,13 @@ struct LoopMaps {
   int nn, b, l;
 };
 
-// x, yl: loop vectors [R][l]; alpha, yb: branch vectors RHS-contiguous [b][R].
+// x, yl: loop vectors [R][l]; alpha, yb: branch vectors RHS-contiguous [b][R];
+// scan: [nn + 1][R] (after branch_to_loop it holds the node potentials);
+// lT: scratch of l R complex128 values (the loop vector transposed).
 void loop_to_branch(const LoopMaps &mp, const double2 *x, double2 *alpha, double2 *scan,
-                    double2 *partials, int R, hipStream_t st);
+                    double2 *partials, double2 *lT, int R, hipStream_t st);
 void branch_to_loop(const LoopMaps &mp, const double2 *yb, double2 *yl, double2 *scan,
-                    double2 *partials, int R, hipStream_t st);
+                    double2 *partials, double2 *lT, int R, hipStream_t st);
 // out[c][r] = in[r][c] (complex128)
 void transpose(const double2 *in, double2 *out, int rows, int cols, hipStream_t st);
 

@@ -68,154 +68,167 @@ static bool allow_lds(const void *fn, int bytes) {
 }
 
 // ===========================================================================
-// batched prefix sums (complex128), three phases, deterministic
+// batched prefix sums (complex128) down the columns of a [len][R] array
+// (right-hand sides contiguous), three phases, deterministic: chunk sums,
+// their scan, then each chunk's running sums
 // ===========================================================================
-constexpr int SCAN_T = 256, SCAN_E = 4, SCAN_B = SCAN_T * SCAN_E;
+constexpr int CS_RG = 64, CS_G = 8, CS_CH = 256;   // RHS per workgroup, row groups, rows per chunk
 
-size_t scan_partials_size(int len, int R) { return (size_t)cdiv(len, SCAN_B) * R; }
+size_t scan_partials_size(int len, int R) { return (size_t)cdiv(len, CS_CH) * (size_t)R; }
 
-__global__ void k_scan_block_sums(const double2 *in, double2 *part, int len, int ld, int nblk) {
-  int r = blockIdx.y, blk = blockIdx.x;
-  const double2 *row = in + (size_t)r * ld;
+__global__ void __launch_bounds__(CS_RG * CS_G) k_cscan_sums(const double2 *a, double2 *part, int len, int R) {
+  __shared__ double2 sh[CS_G][CS_RG];
+  const int lane = threadIdx.x % CS_RG, g = threadIdx.x / CS_RG, r = blockIdx.y * CS_RG + lane;
+  const int ch = blockIdx.x;
   double sx = 0, sy = 0;
-  int base = blk * SCAN_B + threadIdx.x * SCAN_E;
-  for (int k = 0; k < SCAN_E; ++k)
-    if (base + k < len) { sx += row[base + k].x; sy += row[base + k].y; }
-  __shared__ double shx[SCAN_T], shy[SCAN_T];
-  shx[threadIdx.x] = sx;
-  shy[threadIdx.x] = sy;
-  __syncthreads();
-  for (int s = SCAN_T / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) { shx[threadIdx.x] += shx[threadIdx.x + s]; shy[threadIdx.x] += shy[threadIdx.x + s]; }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[(size_t)r * nblk + blk] = make_double2(shx[0], shy[0]);
-}
-
-// exclusive scan of block sums, one workgroup per row
-__global__ void k_scan_partials(double2 *part, int nblk) {
-  int r = blockIdx.x;
-  double2 *row = part + (size_t)r * nblk;
-  __shared__ double shx[SCAN_T], shy[SCAN_T];
-  double cx = 0, cy = 0;
-  for (int c0 = 0; c0 < nblk; c0 += SCAN_T) {
-    int i = c0 + threadIdx.x;
-    double vx = i < nblk ? row[i].x : 0, vy = i < nblk ? row[i].y : 0;
-    shx[threadIdx.x] = vx;
-    shy[threadIdx.x] = vy;
-    __syncthreads();
-    for (int off = 1; off < SCAN_T; off <<= 1) {
-      double ax = threadIdx.x >= off ? shx[threadIdx.x - off] : 0;
-      double ay = threadIdx.x >= off ? shy[threadIdx.x - off] : 0;
-      __syncthreads();
-      shx[threadIdx.x] += ax;
-      shy[threadIdx.x] += ay;
-      __syncthreads();
+  if (r < R) {
+    const int k0 = ch * CS_CH + g * (CS_CH / CS_G), k1 = min(len, k0 + CS_CH / CS_G);
+    for (int k = k0; k < k1; ++k) {
+      const double2 v = a[(size_t)k * R + r];
+      sx += v.x;
+      sy += v.y;
     }
-    double incx = shx[threadIdx.x], incy = shy[threadIdx.x];
-    if (i < nblk) row[i] = make_double2(cx + incx - vx, cy + incy - vy);
-    double tx = shx[SCAN_T - 1], ty = shy[SCAN_T - 1];
-    __syncthreads();
-    cx += tx;
-    cy += ty;
   }
-}
-
-__global__ void k_scan_final(const double2 *in, double2 *out, const double2 *part, int len, int ld,
-                             int nblk, int inclusive) {
-  int r = blockIdx.y, blk = blockIdx.x;
-  const double2 *row = in + (size_t)r * ld;
-  double2 *orow = out + (size_t)r * ld;
-  int base = blk * SCAN_B + threadIdx.x * SCAN_E;
-  double vx[SCAN_E], vy[SCAN_E];
-  double sx = 0, sy = 0;
-  for (int k = 0; k < SCAN_E; ++k) {
-    bool ok = base + k < len;
-    vx[k] = ok ? row[base + k].x : 0;
-    vy[k] = ok ? row[base + k].y : 0;
-    sx += vx[k];
-    sy += vy[k];
-  }
-  __shared__ double shx[SCAN_T], shy[SCAN_T];
-  shx[threadIdx.x] = sx;
-  shy[threadIdx.x] = sy;
+  sh[g][lane] = make_double2(sx, sy);
   __syncthreads();
-  for (int off = 1; off < SCAN_T; off <<= 1) {
-    double ax = threadIdx.x >= off ? shx[threadIdx.x - off] : 0;
-    double ay = threadIdx.x >= off ? shy[threadIdx.x - off] : 0;
-    __syncthreads();
-    shx[threadIdx.x] += ax;
-    shy[threadIdx.x] += ay;
-    __syncthreads();
-  }
-  double2 p = part[(size_t)r * nblk + blk];
-  double cx = p.x + shx[threadIdx.x] - sx, cy = p.y + shy[threadIdx.x] - sy;
-  for (int k = 0; k < SCAN_E; ++k) {
-    if (inclusive) { cx += vx[k]; cy += vy[k]; }
-    if (base + k < len) orow[base + k] = make_double2(cx, cy);
-    if (!inclusive) { cx += vx[k]; cy += vy[k]; }
+  if (g == 0 && r < R) {
+    double tx = 0, ty = 0;
+    for (int j = 0; j < CS_G; ++j) {
+      tx += sh[j][lane].x;
+      ty += sh[j][lane].y;
+    }
+    part[(size_t)ch * R + r] = make_double2(tx, ty);
   }
 }
 
-void scan_rows(const double2 *in, double2 *out, int len, int ld, int R, bool inclusive,
-               double2 *partials, hipStream_t st) {
+// exclusive scan of the chunk sums over the nch chunks, per right-hand side
+__global__ void __launch_bounds__(CS_RG * CS_G) k_cscan_part(double2 *part, int nch, int R) {
+  __shared__ double2 sh[CS_G][CS_RG];
+  const int lane = threadIdx.x % CS_RG, g = threadIdx.x / CS_RG, r = blockIdx.x * CS_RG + lane;
+  const int per = (nch + CS_G - 1) / CS_G, c0 = g * per, c1 = min(nch, c0 + per);
+  double sx = 0, sy = 0;
+  if (r < R)
+    for (int cc = c0; cc < c1; ++cc) {
+      const double2 v = part[(size_t)cc * R + r];
+      sx += v.x;
+      sy += v.y;
+    }
+  sh[g][lane] = make_double2(sx, sy);
+  __syncthreads();
+  if (r >= R) return;
+  double cx = 0, cy = 0;
+  for (int j = 0; j < g; ++j) {
+    cx += sh[j][lane].x;
+    cy += sh[j][lane].y;
+  }
+  for (int cc = c0; cc < c1; ++cc) {
+    const double2 v = part[(size_t)cc * R + r];
+    part[(size_t)cc * R + r] = make_double2(cx, cy);
+    cx += v.x;
+    cy += v.y;
+  }
+}
+
+__global__ void __launch_bounds__(CS_RG * CS_G) k_cscan_final(const double2 *a, double2 *out, const double2 *part,
+                                                              int len, int R, int inclusive) {
+  __shared__ double2 sh[CS_G][CS_RG];
+  const int lane = threadIdx.x % CS_RG, g = threadIdx.x / CS_RG, r = blockIdx.y * CS_RG + lane;
+  const int ch = blockIdx.x;
+  const int k0 = ch * CS_CH + g * (CS_CH / CS_G), k1 = min(len, k0 + CS_CH / CS_G);
+  double sx = 0, sy = 0;
+  if (r < R)
+    for (int k = k0; k < k1; ++k) {
+      const double2 v = a[(size_t)k * R + r];
+      sx += v.x;
+      sy += v.y;
+    }
+  sh[g][lane] = make_double2(sx, sy);
+  __syncthreads();
+  if (r >= R) return;
+  const double2 p = part[(size_t)ch * R + r];
+  double cx = p.x, cy = p.y;
+  for (int j = 0; j < g; ++j) {
+    cx += sh[j][lane].x;
+    cy += sh[j][lane].y;
+  }
+  for (int k = k0; k < k1; ++k) {
+    const double2 v = a[(size_t)k * R + r];
+    if (inclusive) {
+      cx += v.x;
+      cy += v.y;
+    }
+    out[(size_t)k * R + r] = make_double2(cx, cy);
+    if (!inclusive) {
+      cx += v.x;
+      cy += v.y;
+    }
+  }
+}
+
+// in place on a [len][R] array
+static void scan_cols(double2 *a, int len, int R, bool inclusive, double2 *partials, hipStream_t st) {
   if (len <= 0 || R <= 0) return;
-  int nblk = (int)cdiv(len, SCAN_B);
-  k_scan_block_sums<<<dim3(nblk, R), SCAN_T, 0, st>>>(in, partials, len, ld, nblk);
-  k_scan_partials<<<R, SCAN_T, 0, st>>>(partials, nblk);
-  k_scan_final<<<dim3(nblk, R), SCAN_T, 0, st>>>(in, out, partials, len, ld, nblk, inclusive ? 1 : 0);
+  const int nch = (int)cdiv(len, CS_CH), ng = (int)cdiv(R, CS_RG);
+  k_cscan_sums<<<dim3(nch, ng), CS_RG * CS_G, 0, st>>>(a, partials, len, R);
+  k_cscan_part<<<ng, CS_RG * CS_G, 0, st>>>(partials, nch, R);
+  k_cscan_final<<<dim3(nch, ng), CS_RG * CS_G, 0, st>>>(a, a, partials, len, R, inclusive ? 1 : 0);
 }
 
 // ===========================================================================
-// A^T: loop currents -> branch currents (Eq. CurT) by a subtree-sum scan
+// A^T: loop currents -> branch currents (Eq. CurT) by a subtree-sum scan.
+// The scan runs down the preorder positions with the right-hand sides
+// contiguous ([n'+1][R]), so every gather of a position or a link reads R
+// consecutive values.  Threads are (position or branch, right-hand side) with
+// 8 right-hand sides fastest.
 // ===========================================================================
-// scan[r][k] (k < nn, preorder position) = sum of +-x over links ending at the
-// node; scan[r][nn] = 0.
-__global__ void k_inject(LoopMaps mp, const double2 *x, double2 *scan) {
-  int r = blockIdx.y;
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > mp.nn) return;
+// scan[k][r] (k < nn, preorder position) = sum of +-x over links ending at the
+// node; scan[nn][r] = 0.  xT: the loop vector as [l][R].
+__global__ void k_inject(LoopMaps mp, const double2 *xT, double2 *scan, int R) {
+  const int r = blockIdx.y * 8 + (threadIdx.x & 7);
+  const int k = blockIdx.x * 32 + (threadIdx.x >> 3);
+  if (k > mp.nn || r >= R) return;
   double sx = 0, sy = 0;
   if (k < mp.nn) {
-    const double2 *xr = x + (size_t)r * mp.l;
     for (int q = mp.inj_off[k]; q < mp.inj_off[k + 1]; ++q) {
-      double2 v = xr[mp.inj_link[q]];
-      double sg = mp.inj_sgn[q];
+      const double2 v = xT[(size_t)mp.inj_link[q] * R + r];
+      const double sg = mp.inj_sgn[q];
       sx += sg * v.x;
       sy += sg * v.y;
     }
   }
-  scan[(size_t)r * (mp.nn + 1) + k] = make_double2(sx, sy);
+  scan[(size_t)k * R + r] = make_double2(sx, sy);
 }
 
 // after the exclusive scan: twig current = +-(P[hi] - P[lo]), link current = x;
 // output alpha is RHS-contiguous: alpha[e][r]
-__global__ void k_branch_out(LoopMaps mp, const double2 *x, const double2 *pfx, double2 *alpha, int R) {
-  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)mp.b * R) return;
-  int e = (int)(idx / R), r = (int)(idx - (long)e * R);
-  int a = mp.br_a[e];
+__global__ void k_branch_out(LoopMaps mp, const double2 *xT, const double2 *pfx, double2 *alpha, int R) {
+  const int r = blockIdx.y * 8 + (threadIdx.x & 7);
+  const int e = blockIdx.x * 32 + (threadIdx.x >> 3);
+  if (e >= mp.b || r >= R) return;
+  const int a = mp.br_a[e];
   double2 v;
   if (a >= 0) {
-    v = x[(size_t)r * mp.l + a];
+    v = xT[(size_t)a * R + r];
   } else {
-    const double2 *p = pfx + (size_t)r * (mp.nn + 1);
-    double2 hi = p[mp.br_hi[e]], lo = p[mp.br_lo[e]];
-    double sg = mp.br_sg[e];
+    const double2 hi = pfx[(size_t)mp.br_hi[e] * R + r], lo = pfx[(size_t)mp.br_lo[e] * R + r];
+    const double sg = mp.br_sg[e];
     v = make_double2(sg * (hi.x - lo.x), sg * (hi.y - lo.y));
   }
-  alpha[idx] = v;
+  alpha[(size_t)e * R + r] = v;
 }
 
-void loop_to_branch(const LoopMaps &mp, const double2 *x, double2 *alpha, double2 *scan,
-                    double2 *partials, int R, hipStream_t st) {
-  k_inject<<<dim3(cdiv(mp.nn + 1, 256), R), 256, 0, st>>>(mp, x, scan);
-  scan_rows(scan, scan, mp.nn + 1, mp.nn + 1, R, false, partials, st);
-  k_branch_out<<<cdiv((long)mp.b * R, 256), 256, 0, st>>>(mp, x, scan, alpha, R);
+// x: [R][l]; xT: scratch of l R complex values
+void loop_to_branch(const LoopMaps &mp, const double2 *x, double2 *alpha, double2 *scan, double2 *partials,
+                    double2 *xT, int R, hipStream_t st) {
+  transpose(x, xT, R, mp.l, st);
+  k_inject<<<dim3(cdiv(mp.nn + 1, 32), cdiv(R, 8)), 256, 0, st>>>(mp, xT, scan, R);
+  scan_cols(scan, mp.nn + 1, R, false, partials, st);
+  k_branch_out<<<dim3(cdiv(mp.b, 32), cdiv(R, 8)), 256, 0, st>>>(mp, xT, scan, alpha, R);
 }
 
 // ===========================================================================
-// A: branch voltages -> loop voltages (Eq. VolT) by a potential scan
+// A: branch voltages -> loop voltages (Eq. VolT) by a potential scan, in the
+// same [n'+1][R] layout
 // ===========================================================================
 __device__ __forceinline__ double2 twig_drop(const LoopMaps &mp, const double2 *yb, int R, int pos) {
   int e = mp.pos_branch[pos];
@@ -225,9 +238,6 @@ __device__ __forceinline__ double2 twig_drop(const LoopMaps &mp, const double2 *
   return make_double2(sg * v.x, sg * v.y);
 }
 
-// Threads are (position, right-hand side) with 8 right-hand sides fastest: a
-// branch's 8 values are one 128-byte segment of yb[e][r], and each row of
-// the output gets 32 consecutive positions per workgroup.
 __global__ void k_drop_diff(LoopMaps mp, const double2 *yb, double2 *scan, int R) {
   const int r = blockIdx.y * 8 + (threadIdx.x & 7);
   const int k = blockIdx.x * 32 + (threadIdx.x >> 3);
@@ -239,11 +249,11 @@ __global__ void k_drop_diff(LoopMaps mp, const double2 *yb, double2 *scan, int R
     d.x -= z.x;
     d.y -= z.y;
   }
-  scan[(size_t)r * (mp.nn + 1) + k] = d;
+  scan[(size_t)k * R + r] = d;
 }
 
-// threads as in k_drop_diff: (link, right-hand side), 8 right-hand sides fastest
-__global__ void k_link_out(LoopMaps mp, const double2 *yb, const double2 *D, double2 *yl, int R) {
+// ylT[i][r]: the loop vector as [l][R]
+__global__ void k_link_out(LoopMaps mp, const double2 *yb, const double2 *D, double2 *ylT, int R) {
   const int r = blockIdx.y * 8 + (threadIdx.x & 7);
   const int i = blockIdx.x * 32 + (threadIdx.x >> 3);
   if (i >= mp.l || r >= R) return;
@@ -251,18 +261,20 @@ __global__ void k_link_out(LoopMaps mp, const double2 *yb, const double2 *D, dou
   double2 v = e < mp.b ? yb[(size_t)e * R + r] : make_double2(0, 0);
   int up = mp.link_upos[i], vp = mp.link_vpos[i];
   if (up >= 0) {
-    const double2 *Dr = D + (size_t)r * (mp.nn + 1);
-    v.x += Dr[vp].x - Dr[up].x;
-    v.y += Dr[vp].y - Dr[up].y;
+    const double2 dv = D[(size_t)vp * R + r], du = D[(size_t)up * R + r];
+    v.x += dv.x - du.x;
+    v.y += dv.y - du.y;
   }
-  yl[(size_t)r * mp.l + i] = v;
+  ylT[(size_t)i * R + r] = v;
 }
 
-void branch_to_loop(const LoopMaps &mp, const double2 *yb, double2 *yl, double2 *scan,
-                    double2 *partials, int R, hipStream_t st) {
+// yl: [R][l]; ylT: scratch of l R complex values
+void branch_to_loop(const LoopMaps &mp, const double2 *yb, double2 *yl, double2 *scan, double2 *partials,
+                    double2 *ylT, int R, hipStream_t st) {
   k_drop_diff<<<dim3(cdiv(mp.nn, 32), cdiv(R, 8)), 256, 0, st>>>(mp, yb, scan, R);
-  scan_rows(scan, scan, mp.nn, mp.nn + 1, R, true, partials, st);
-  k_link_out<<<dim3(cdiv(mp.l, 32), cdiv(R, 8)), 256, 0, st>>>(mp, yb, scan, yl, R);
+  scan_cols(scan, mp.nn, R, true, partials, st);
+  k_link_out<<<dim3(cdiv(mp.l, 32), cdiv(R, 8)), 256, 0, st>>>(mp, yb, scan, ylT, R);
+  transpose(ylT, yl, mp.l, R, st);
 }
 
 // ===========================================================================
@@ -2060,9 +2072,8 @@ __global__ void k_post_tri(GridMaps g, PostOut o, const double2 *alpha, const do
     double2 *out = o.J + ((size_t)r * g.n + t) * 3;
     for (int c = 0; c < 3; ++c) out[c] = make_double2(dx[c] * f, dy[c] * f);
   }
-  if (o.phi) {
-    const double2 *D = pot + (size_t)r * (nn + 1);
-    const double2 a = D[o.tri_pos[t]], z = D[o.tri_ref[t]];
+  if (o.phi) {   // pot: [nn + 1][R]
+    const double2 a = pot[(size_t)o.tri_pos[t] * R + r], z = pot[(size_t)o.tri_ref[t] * R + r];
     o.phi[(size_t)r * g.n + t] = make_double2(a.x - z.x, a.y - z.y);
   }
 }
