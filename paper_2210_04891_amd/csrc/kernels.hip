@@ -964,7 +964,7 @@ constexpr unsigned X_DROP = 0x80000000u;
 // 256-byte rows (two per wavefront instruction).  Pruned (PR): as
 // described above.
 template <int NX, bool PR>
-__global__ void __launch_bounds__(256) k_fft_x_fwd(const float2 *in, float2 *out, int C, int ncol,
+__global__ void __launch_bounds__(256, 3) k_fft_x_fwd(const float2 *in, float2 *out, int C, int ncol,
                                                    const float2 *xtw, const uint32_t *xmask, const uint8_t *cgrp) {
   constexpr int M = NX / 4, LM = clog2(M), WPC = NX / 32;
   constexpr int TP = M + 1;     // twiddle table pitch: the 8 rows fall in different banks
@@ -1128,7 +1128,12 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
   constexpr int P0 = NZ + 1;                 // staging [y][z] pitch
   constexpr int LZ = 2 * NZ, LY = 2 * NY;
   __shared__ float2 sm[LZ * PT];
-  const int t = threadIdx.x, half = t & 1, line = t >> 1;
+  // stages A and C: thread t works on line (row or column) t % NY, half
+  // t / NY; with NY = 64 the half is the wave index, so a half's twiddles are
+  // a scalar branch
+  const int t = threadIdx.x;
+  const int wl = t % NY;
+  const int wh = NY % 64 == 0 ? __builtin_amdgcn_readfirstlane(t / NY) : t / NY;
   const long kx = blockIdx.x / ch, chan = blockIdx.x - kx * ch;
   float2 *io = data + (chan * a.two_nx + kx) * (long)(NY * NZ);
   // stage 0: coalesced load of the NY x NZ plane (2 NY is a multiple of NZ,
@@ -1148,28 +1153,30 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
     }
   }
   __syncthreads();
-  // stage A: forward z half `half` of row `line`
+  // stage A: forward z half wh of row wl
   {
     float2 v[NZ];
 #pragma unroll
-    for (int z = 0; z < NZ; ++z) {
-      const float2 x = sm[line * P0 + z];
-      v[z] = half ? twmul<-1>(x, z, LZ) : x;
+    for (int z = 0; z < NZ; ++z) v[z] = sm[wl * P0 + z];
+    if (wh) {
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) v[z] = twmul<-1>(v[z], z, LZ);
     }
     fft_dif<NZ, -1>(v);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) sm[(2 * k + half) * PT + line] = v[brev(k, clog2(NZ))];
+    for (int k = 0; k < NZ; ++k) sm[(2 * k + wh) * PT + wl] = v[brev(k, clog2(NZ))];
   }
   __syncthreads();
-  // stage C: column kz = line, y half `half`: forward, spectrum, inverse
+  // stage C: column kz = wl, y half wh: forward, spectrum, inverse
   {
-    const int kz = line;
+    const int kz = wl, half = wh;
     float2 v[NY];
 #pragma unroll
-    for (int y = 0; y < NY; ++y) {
-      const float2 x = sm[kz * PT + y];
-      v[y] = half ? twmul<-1>(x, y, LY) : x;
+    for (int y = 0; y < NY; ++y) v[y] = sm[kz * PT + y];
+    if (half) {
+#pragma unroll
+      for (int y = 0; y < NY; ++y) v[y] = twmul<-1>(v[y], y, LY);
     }
     fft_dif<NY, -1>(v);
     const int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
@@ -1194,20 +1201,37 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
 #pragma unroll
       for (int n = 0; n < NY; ++n) v[n] = twmul<+1>(v[n], n, LY);
     }
-    // lane pair sum; lane `half` keeps n in [half NY/2, (half+1) NY/2).
-    // Column kz was read only by this lane pair (one wave, whose LDS
-    // accesses complete in order), so it is overwritten without a barrier.
+    // sum of the two halves through column kz: half h finishes n in
+    // [h NY/2, (h+1) NY/2) and hands the other range to its partner
+    __syncthreads();   // both halves have read the column
+    float2 *col = sm + kz * PT;
+    if (half) {
 #pragma unroll
-    for (int j = 0; j < NY / 2; ++j) {
-      const float2 lo = v[j], hi = v[j + NY / 2];
-      const float2 send = half ? lo : hi, keep = half ? hi : lo;
-      const float2 r = qperm2<0xB1>(send);   // lane ^ 1
-      sm[kz * PT + half * (NY / 2) + j] = make_float2(keep.x + r.x, keep.y + r.y);
+      for (int j = 0; j < NY / 2; ++j) col[j] = v[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NY / 2; ++j) col[NY / 2 + j] = v[NY / 2 + j];
+    }
+    __syncthreads();
+    if (half) {
+#pragma unroll
+      for (int j = 0; j < NY / 2; ++j) {
+        const float2 r = col[NY / 2 + j];
+        col[NY / 2 + j] = make_float2(v[NY / 2 + j].x + r.x, v[NY / 2 + j].y + r.y);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NY / 2; ++j) {
+        const float2 r = col[j];
+        col[j] = make_float2(v[j].x + r.x, v[j].y + r.y);
+      }
     }
   }
   __syncthreads();
-  // stage D: row n = line, z half `half`: inverse, crop, store
+  // stage D: row n = line, z half `half` (lane pairs, t = 2 line + half):
+  // inverse, crop, lane-pair sum, store
   {
+    const int half = t & 1, line = t >> 1;
     float2 v[NZ];
 #pragma unroll
     for (int k = 0; k < NZ; ++k) v[k] = sm[(2 * k + half) * PT + line];
