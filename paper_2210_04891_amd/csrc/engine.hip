@@ -292,6 +292,19 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
       if (kend < nn) end_pos[f[kend]++] = k;
     }
   }
+  // per position k, the signed branch voltages that make up D[k] before the
+  // scan: its own twig (sign s_k) then, negated, the twig of every node
+  // whose subtree ends at k; code = 2 e + (sign < 0)
+  std::vector<int> dd_off(nn + 1, 0), dd_code;
+  dd_code.reserve((size_t)nn + end_pos.size());
+  for (int k = 0; k < nn; ++k) {
+    if (pos_branch[k] >= 0) dd_code.push_back(2 * pos_branch[k] + (pos_sign[k] < 0 ? 1 : 0));
+    for (int q = end_cnt[k]; q < end_cnt[k + 1]; ++q) {
+      const int j = end_pos[q];
+      dd_code.push_back(2 * pos_branch[j] + (pos_sign[j] > 0 ? 1 : 0));
+    }
+    dd_off[k + 1] = (int)dd_code.size();
+  }
   std::vector<int> link_upos(l, -1), link_vpos(l, -1);
   for (int i = 0; i < l; ++i) {
     int e = m.links[i];
@@ -311,10 +324,8 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
   lm.br_lo = upload(c, br_lo, st);
   lm.br_hi = upload(c, br_hi, st);
   lm.br_sg = upload(c, br_sg, st);
-  lm.pos_branch = upload(c, pos_branch, st);
-  lm.pos_sign = upload(c, pos_sign, st);
-  lm.end_off = upload(c, end_cnt, st);
-  lm.end_pos = upload(c, end_pos, st);
+  lm.dd_off = upload(c, dd_off, st);
+  lm.dd_code = upload(c, dd_code, st);
   lm.link_branch = upload(c, m.links, st);
   lm.link_upos = upload(c, link_upos, st);
   lm.link_vpos = upload(c, link_vpos, st);

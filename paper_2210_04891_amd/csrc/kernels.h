@@ -22,10 +22,9 @@ struct LoopMaps {
   const int8_t *inj_sgn;
   const int *br_a, *br_lo, *br_hi;
   const int8_t *br_sg;
-  // branch -> loop (A): twig drop per position, subtree-end lists, link ends
-  const int *pos_branch;
-  const int8_t *pos_sign;
-  const int *end_off, *end_pos;
+  // branch -> loop (A): per position, the signed twig voltages entering its
+  // potential difference (code 2 e + (sign < 0)); link ends
+  const int *dd_off, *dd_code;
   const int *link_branch, *link_upos, *link_vpos;
   int nn, b, l;
 };

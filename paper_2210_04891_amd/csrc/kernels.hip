@@ -230,26 +230,35 @@ void loop_to_branch(const LoopMaps &mp, const double2 *x, double2 *alpha, double
 // A: branch voltages -> loop voltages (Eq. VolT) by a potential scan, in the
 // same [n'+1][R] layout
 // ===========================================================================
-__device__ __forceinline__ double2 twig_drop(const LoopMaps &mp, const double2 *yb, int R, int pos) {
-  int e = mp.pos_branch[pos];
-  if (e < 0) return make_double2(0, 0);
-  double2 v = yb[(size_t)e * R];
-  double sg = mp.pos_sign[pos];
-  return make_double2(sg * v.x, sg * v.y);
-}
-
+// D[k] = s_k V(twig of k) - sum of s_j V(twig of j) over the nodes j whose
+// subtree ends at k, from the flattened lists (same order of summation); the
+// index loads of four entries are issued before their value loads
 __global__ void k_drop_diff(LoopMaps mp, const double2 *yb, double2 *scan, int R) {
   const int r = blockIdx.y * 8 + (threadIdx.x & 7);
   const int k = blockIdx.x * 32 + (threadIdx.x >> 3);
   if (k >= mp.nn || r >= R) return;
-  const double2 *y = yb + r;   // yb[e][r]
-  double2 d = twig_drop(mp, y, R, k);
-  for (int q = mp.end_off[k]; q < mp.end_off[k + 1]; ++q) {
-    double2 z = twig_drop(mp, y, R, mp.end_pos[q]);
-    d.x -= z.x;
-    d.y -= z.y;
+  const int q0 = mp.dd_off[k], q1 = mp.dd_off[k + 1];
+  double dx = 0, dy = 0;
+  for (int q = q0; q < q1; q += 4) {
+    int code[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) code[u] = q + u < q1 ? mp.dd_code[q + u] : -1;
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = code[u] >= 0 ? yb[(size_t)(code[u] >> 1) * R + r] : make_double2(0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (code[u] >= 0) {
+        if (code[u] & 1) {
+          dx -= v[u].x;
+          dy -= v[u].y;
+        } else {
+          dx += v[u].x;
+          dy += v[u].y;
+        }
+      }
   }
-  scan[(size_t)k * R + r] = d;
+  scan[(size_t)k * R + r] = make_double2(dx, dy);
 }
 
 // ylT[i][r]: the loop vector as [l][R]
