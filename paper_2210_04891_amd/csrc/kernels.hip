@@ -1709,6 +1709,10 @@ __global__ void __launch_bounds__(256) k_interp_grp(GridMaps g, const float2 *ph
     const bool ok = threadIdx.x < 255 && chn < ch;
     const int c = ok ? chn % 3 : 0;
     const int cc = min(chn, ch - 1);
+    // the lane's M1 component as an exact blend (one factor is 1, the others
+    // 0), so the four weights stay uniform scalar loads rather than becoming
+    // a per-lane load of the selected one
+    const float e1 = c == 0 ? 1.f : 0.f, e2 = c == 1 ? 1.f : 0.f, e3 = c == 2 ? 1.f : 0.f;
     double a0x[IG], a0y[IG], a1x[IG], a1y[IG];
 #pragma unroll
     for (int q = 0; q < IG; ++q) a0x[q] = a0y[q] = a1x[q] = a1y[q] = 0;
@@ -1722,7 +1726,7 @@ __global__ void __launch_bounds__(256) k_interp_grp(GridMaps g, const float2 *ph
 #pragma unroll
         for (int q = 0; q < IG; ++q) {
           const auto *w = wq[q] + 4 * (kh + k);   // (M0, M1x, M1y, M1z)
-          const double m0 = (double)w[0], m1 = (double)(c == 0 ? w[1] : c == 1 ? w[2] : w[3]);
+          const double m0 = (double)w[0], m1 = (double)fmaf(e1, w[1], fmaf(e2, w[2], e3 * w[3]));
           a0x[q] += m1 * vx;
           a0y[q] += m1 * vy;
           a1x[q] += m0 * vx;
