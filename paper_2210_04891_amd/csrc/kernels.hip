@@ -101,18 +101,27 @@ __global__ void __launch_bounds__(CS_RG * CS_G) k_cscan_sums(const double2 *a, d
   }
 }
 
-// exclusive scan of the chunk sums over the nch chunks, per right-hand side
+// exclusive scan of the chunk sums over the nch chunks, per right-hand side;
+// a thread's chunk sums are read 8 at a time (all loads in flight before
+// the sums use them)
 __global__ void __launch_bounds__(CS_RG * CS_G) k_cscan_part(double2 *part, int nch, int R) {
+  constexpr int U = 8;
   __shared__ double2 sh[CS_G][CS_RG];
   const int lane = threadIdx.x % CS_RG, g = threadIdx.x / CS_RG, r = blockIdx.x * CS_RG + lane;
   const int per = (nch + CS_G - 1) / CS_G, c0 = g * per, c1 = min(nch, c0 + per);
+  const int rr = min(r, R - 1);
   double sx = 0, sy = 0;
-  if (r < R)
-    for (int cc = c0; cc < c1; ++cc) {
-      const double2 v = part[(size_t)cc * R + r];
-      sx += v.x;
-      sy += v.y;
-    }
+  for (int cb = c0; cb < c1; cb += U) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = part[(size_t)min(cb + u, c1 - 1) * R + rr];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (cb + u < c1) {
+        sx += v[u].x;
+        sy += v[u].y;
+      }
+  }
   sh[g][lane] = make_double2(sx, sy);
   __syncthreads();
   if (r >= R) return;
@@ -121,11 +130,17 @@ __global__ void __launch_bounds__(CS_RG * CS_G) k_cscan_part(double2 *part, int 
     cx += sh[j][lane].x;
     cy += sh[j][lane].y;
   }
-  for (int cc = c0; cc < c1; ++cc) {
-    const double2 v = part[(size_t)cc * R + r];
-    part[(size_t)cc * R + r] = make_double2(cx, cy);
-    cx += v.x;
-    cy += v.y;
+  for (int cb = c0; cb < c1; cb += U) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = part[(size_t)min(cb + u, c1 - 1) * R + r];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (cb + u < c1) {
+        part[(size_t)(cb + u) * R + r] = make_double2(cx, cy);
+        cx += v[u].x;
+        cy += v[u].y;
+      }
   }
 }
 
