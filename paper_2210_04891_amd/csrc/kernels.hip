@@ -910,6 +910,9 @@ template <int CTRL>
 __device__ __forceinline__ float2 qperm2(float2 v) {
   return make_float2(qperm<CTRL>(v.x), qperm<CTRL>(v.y));
 }
+// value of lane ^ 4: the half-row mirror (lane ^ 7 within each group of 8)
+// followed by the quad reversal (lane ^ 3), both DPP moves in registers
+__device__ __forceinline__ float xor4(float v) { return qperm<0x1B>(qperm<0x141>(v)); }
 __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -1123,7 +1126,7 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(const float2 *in, float2 *out
   for (int j = 0; j < M / 2; ++j) {
     const float2 lo = v[j], hi = v[j + M / 2];
     const float2 send = selb2(hm, lo, hi), keep = selb2(hm, hi, lo);
-    const float2 rv = make_float2(__shfl_xor(send.x, 4), __shfl_xor(send.y, 4));
+    const float2 rv = make_float2(xor4(send.x), xor4(send.y));   // lane ^ 4
     const float2 o = make_float2(keep.x + rv.x, keep.y + rv.y);
     // row x = 4 k1 + k2, k1 = brev(p), p = j + h M / 2
     const int k1a = brev(j, LM), k1b = brev(j + M / 2, LM);
