@@ -1142,8 +1142,11 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(const float2 *in, float2 *out
 }
 
 // One (channel, kx) plane per workgroup of 2 NY threads (NY = 2 NZ).  Block
-// b works on kx = b / ch, channel = b % ch, so consecutive workgroups share
-// the spectrum slice of one kx in L2.
+// b works on channel ch - 1 - b / 2Nx, kx = b % 2Nx: the X passes run over the
+// channels in ascending order, so this pass first reads the planes the
+// forward X pass wrote last and ends with the ones the inverse X pass reads
+// first, both while they are still in the memory-side cache.  The whole
+// spectrum fits in every L2.
 // Pruned (PR): column (y, z) enters as zero unless bit y of zmask[z] is set
 // (it holds no active node, and whatever the buffer holds there is not the
 // forward X pass's output); every column is still written.
@@ -1161,7 +1164,7 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
   const int t = threadIdx.x;
   const int wl = t % NY;
   const int wh = NY % 64 == 0 ? __builtin_amdgcn_readfirstlane(t / NY) : t / NY;
-  const long kx = blockIdx.x / ch, chan = blockIdx.x - kx * ch;
+  const long cb = blockIdx.x / a.two_nx, kx = blockIdx.x - cb * a.two_nx, chan = ch - 1 - cb;
   float2 *io = data + (chan * a.two_nx + kx) * (long)(NY * NZ);
   // stage 0: coalesced load of the NY x NZ plane (2 NY is a multiple of NZ,
   // so a thread's z is the same for every q).  Pruned: an inactive column's
