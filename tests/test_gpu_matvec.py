@@ -120,6 +120,22 @@ def test_loop_space_product(c1_oracle):
 
 
 @gpu
+def test_loop_space_product_many_rhs(c1_oracle):
+    """70 right-hand sides: the tree scans take the right-hand sides of a
+    position as one contiguous segment, in groups of 64, so the second group
+    is ragged.  Rows on both sides of the group boundary match the oracle's
+    loop-space product (Eqs. CurT, VolT)."""
+    ctx = _ctx(c1_oracle["s"])
+    c = c1_oracle["circ"]
+    om = 2 * np.pi * np.geomspace(1e7, 3e10, 70)
+    X = W.complex_normal(4, (70, c.nloop))
+    y = ctx.matvec(_dev(X), omega=om, space=1).cpu().numpy()
+    for r in (0, 31, 63, 64, 69):
+        ref_p = _oracle_loop(c1_oracle, c1_oracle["op"].apply, om[r], X[r])
+        assert _rel(y[r], ref_p) < 1e-6, r
+
+
+@gpu
 def test_tiled_near_field_product(c1_oracle):
     """The LDS-tiled near-field product gives the gather product's result to
     rounding and the oracle's loop-space product to the near-field

@@ -50,17 +50,20 @@ def _oracle_vb(o, omega, Ib):
 
 
 @gpu
-def test_post_outputs_of_synthetic_loop_currents(c1_oracle):
+@pytest.mark.parametrize("nrhs", [3, 70])
+def test_post_outputs_of_synthetic_loop_currents(c1_oracle, nrhs):
+    """nrhs 70: the right-hand sides of the tree scans run in two groups of
+    64 (the second ragged); rows on both sides of the boundary are checked."""
     from oracle import post as PO
     o = c1_oracle
     m, c = o["mesh"], o["circ"]
     A = c.loop_matrix()
     ctx = _ctx(o["s"])
-    om = 2 * np.pi * np.array([1e8, 2e9, 3e10])
-    X = W.complex_normal(21, (3, c.nloop))
+    om = 2 * np.pi * np.geomspace(1e8, 3e10, nrhs)
+    X = W.complex_normal(21, (nrhs, c.nloop))
     out = ctx.postprocess(torch.from_numpy(X).cuda(), om)
     res = {k: v.cpu().numpy() for k, v in out.items()}
-    for r in range(3):
+    for r in ((0, 1, 2) if nrhs == 3 else (0, 63, 64, 69)):
         Ib = PO.branch_currents(A, X[r])
         assert _rel(res["Ib"][r], Ib) < 1e-12
         J = PO.centroid_current(m, Ib[:m.nedge])
