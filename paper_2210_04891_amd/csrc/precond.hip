@@ -337,6 +337,13 @@ __global__ void k_pre_rhs(PrecondDev d, const int *fidx, const double2 *y, doubl
   work[(size_t)r * d.nu + x] = make_double2(-gx, -gy);
 }
 
+// Orders a wavefront's global stores of the solution vector before its later
+// loads of it.  Every solve workgroup is one wavefront and the only one that
+// touches its (conductor, right-hand side) slice, so workgroup scope is
+// enough; a device-scope fence would write back and invalidate the L2 of the
+// XCD each time.
+__device__ __forceinline__ void slice_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
 __device__ __forceinline__ double2 wave_sum(double2 v) {
   for (int off = 32; off > 0; off >>= 1) {
     v.x += __shfl_xor(v.x, off, 64);
@@ -407,7 +414,7 @@ __device__ void ldl_middle(const PrecondDev &d, int f, double2 *x, int lo, int m
       const double2 bs = x[s];
       x[s] = make_double2(bs.x - acc.x, bs.y - acc.y);
     }
-    __threadfence();
+    slice_fence();
     __syncthreads();
   }
   for (int i0 = lo; i0 < hi; i0 += 64 * SB) {
@@ -424,7 +431,7 @@ __device__ void ldl_middle(const PrecondDev &d, int f, double2 *x, int lo, int m
       if (i < hi) x[i] = cdiv2(xv[q], dv[q]);
     }
   }
-  __threadfence();
+  slice_fence();
   __syncthreads();
   for (int s = hi - 1; s >= mid; --s) {
     const int fs = d.first[s];
@@ -448,7 +455,7 @@ __device__ void ldl_middle(const PrecondDev &d, int f, double2 *x, int lo, int m
         }
       }
     }
-    __threadfence();
+    slice_fence();
     __syncthreads();
   }
 }
@@ -517,7 +524,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx,
       for (int q = 0; q < PF; ++q) cur[q] = nxt[q];
     }
   }
-  __threadfence();
+  slice_fence();
   __syncthreads();
   ldl_middle(d, f, x, lo, mid, hi, lane);
   // ---- backward, band rows
@@ -682,7 +689,7 @@ __global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *f
       if (b0 + lane < nb) x[lo + b0 + lane] = make_double2(yx, yy);
     }
   }
-  __threadfence();
+  slice_fence();
   __syncthreads();
   ldl_middle(d, f, x, lo, mid, hi, lane);
   // ---- backward, band rows: x = L^-T z, row by row from the last
