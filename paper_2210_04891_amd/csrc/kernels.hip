@@ -1079,6 +1079,7 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(const float2 *in, float2 *out
   constexpr int M = NX / 4, LM = clog2(M), WPC = NX / 32;
   constexpr int TP = M + 1;
   __shared__ float2 s_tw[8 * TP];
+  __shared__ float2 s_in[NX * 33];   // one half of the workgroup's input rows
   const unsigned c0 = (unsigned)(blockIdx.x * 32) % (unsigned)C;
   if (PR && !cgrp[c0 / 32u]) return;
   const int t = threadIdx.x, lane = t & 63, q = lane & 3, h = (lane >> 2) & 1, r = lane & 7;
@@ -1092,10 +1093,43 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(const float2 *in, float2 *out
   const unsigned C8 = (unsigned)C * 8u;
   float2 v[M];
   {
-    // rows kx = 2 (m + M q) + h
-    const unsigned vo = ((unsigned)chn * 2 * NX * C + c + (unsigned)(2 * M * q + h) * C) * 8u;
+    // rows kx = 2 (m + M q) + h, read as whole 256-byte segments of the
+    // workgroup's 32 columns and handed over through LDS, in two halves of
+    // m: half ph holds row 2 M q + ph M + j (j < M) at local row q M + j,
+    // column (cl + 8 q) mod 32 (the skew puts the four q of a lane's column
+    // in different banks)
+    const int cl = (t >> 6) * 8 + (lane >> 3);   // this lane's column in the workgroup
+    const unsigned base = ((unsigned)chn * 2 * NX * C + c0) * 8u;
+    constexpr int NL = NX / 8;                  // staged elements per thread and half
+    float2 g[NL];
+    auto fetch = [&](int ph) {
 #pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = buf_load2(rin, vo, 2u * m * C8);
+      for (int i = 0; i < NL; ++i) {
+        const int rl = (t >> 5) + 8 * i, qq = rl / M, j = rl - qq * M;
+        g[i] = buf_load2(rin, base + (unsigned)((2 * M * qq + ph * M + j) * C + (t & 31)) * 8u, 0);
+      }
+    };
+    auto put = [&]() {
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const int rl = (t >> 5) + 8 * i, qq = rl / M;
+        s_in[rl * 33 + (((t & 31) + 8 * qq) & 31)] = g[i];
+      }
+    };
+    auto take = [&](int ph) {
+#pragma unroll
+      for (int mm = 0; mm < M / 2; ++mm)
+        v[ph * (M / 2) + mm] = s_in[(q * M + 2 * mm + h) * 33 + ((cl + 8 * q) & 31)];
+    };
+    fetch(0);
+    put();
+    __syncthreads();
+    fetch(1);   // in flight while the first half is read
+    take(0);
+    __syncthreads();
+    put();
+    __syncthreads();
+    take(1);
   }
   const float sA = q < 2 ? 1.f : -1.f, sB = (q & 1) ? -1.f : 1.f, sk = q == 2 ? -1.f : 1.f;
   const bool q3 = q == 3;
