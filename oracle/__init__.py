@@ -11,9 +11,11 @@ Interconnects"):
 
 * ``mesh``      -- edges, modified RWG functions (Sec. II-C, Eq. RWG/ExpandJ),
                    Gram matrix of the basis (second term of Eq. Zb).
-* ``integrals`` -- analytic potential integrals of a flat triangle and the
-                   triangle-pair integrals of the 1/|r-r'| kernel (first term
-                   of Eq. Zb, static Green's function Eq. StaticGF).
+* ``integrals`` -- the triangle-pair integrals of the 1/|r-r'| kernel
+                   (first term of Eq. Zb, static Green's function
+                   Eq. StaticGF), both surfaces integrated numerically:
+                   Sauter-Schwab cubature on touching pairs, adaptive
+                   product rules elsewhere (C helper csrc/pairs.c).
 * ``circuit``   -- circuit graph, spanning tree, fundamental loops and the
                    loop matrix A (Sec. III, Eqs. VolT, CurT, LoopVandI,
                    FinalME).

@@ -9,7 +9,7 @@ OUT = os.path.join(HERE, "_pairs.so")
 
 
 def build(verbose=False):
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", SRC, "-o", OUT + ".tmp", "-lm"]
+    cmd = ["gcc", "-O3", "-fPIC", "-shared", "-fopenmp", SRC, "-o", OUT + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
