@@ -61,6 +61,7 @@ struct pfft_ctx {
   int grid_fp64 = 0;
   double sigma = 5.8e7, mu_r = 1.0;
   int max_chunk = 0;
+  size_t ws_budget = (size_t)24 << 30;   // product workspace bytes (chunk size)
   int device = 0;
   std::vector<void *> allocs;
   size_t dev_bytes = 0;

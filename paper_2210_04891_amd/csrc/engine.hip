@@ -86,15 +86,13 @@ static V *upload(pfft_ctx *c, const std::vector<V> &h, hipStream_t st) {
 size_t pfft_ctx::per_rhs_bytes() const {
   size_t vs = grid_fp64 ? sizeof(double2) : sizeof(float2);
   size_t N = (size_t)m.dims[0] * m.dims[1] * m.dims[2];
-  return 16 * ((size_t)m.b * 2 + (m.nn + 1) + 4 * (size_t)m.n + 2) + vs * (4 * (size_t)m.n + 21 * N);
+  const size_t grid = (9 + (convolve_uses_t2(gm, grid_fp64) ? 12 : 0)) * N;
+  return 16 * ((size_t)m.b * 2 + (m.nn + 1) + 4 * (size_t)m.n + 2) + vs * (4 * (size_t)m.n + grid);
 }
 
 int pfft_ctx::chunk_for(int R) const {
   int cap = max_chunk;
-  if (cap <= 0) {
-    size_t budget = (size_t)24 << 30;
-    cap = (int)std::max<size_t>(1, budget / per_rhs_bytes());
-  }
+  if (cap <= 0) cap = (int)std::max<size_t>(1, ws_budget / per_rhs_bytes());
   return std::max(1, std::min(R, cap));
 }
 
@@ -120,7 +118,7 @@ void pfft_ctx::ensure_workspace(Workspace &w, int R) {
   w.J = al(vs * (size_t)R * m.n * 4);
   w.Q = al(vs * (size_t)R * 3 * N);
   w.T1 = al(vs * (size_t)R * 6 * N);
-  w.T2 = al(vs * (size_t)R * 12 * N);
+  w.T2 = convolve_uses_t2(gm, grid_fp64) ? al(vs * (size_t)R * 12 * N) : nullptr;
   w.R = R;
   w.coef_on_device.clear();
 }
@@ -138,6 +136,14 @@ void pfft_ctx::matvec_range(Workspace &w, int R, const double *omega, int space,
   const int dim = space == 1 ? m.l : m.b;
   const int Rc = chunk_for(R);
   ensure_workspace(w, Rc);
+  if (!w.T2 && !(flags & PFFT_NEAR_ONLY) && convolve_uses_t2(gm, grid_fp64)) {
+    // a plan change since the workspace was sized now needs the unfused passes' buffer
+    const size_t vs = grid_fp64 ? sizeof(double2) : sizeof(float2);
+    void *p = nullptr;
+    hip_ok(hipMalloc(&p, vs * (size_t)w.R * 12 * m.dims[0] * m.dims[1] * m.dims[2]), "hipMalloc workspace");
+    w.allocs.push_back(p);
+    w.T2 = p;
+  }
   int mode = 0;
   if (!(flags & PFFT_NEAR_ONLY)) mode |= 1;
   if (!(flags & PFFT_FAR_ONLY)) mode |= 2;
@@ -733,6 +739,12 @@ pfft_status pfft_setup(const pfft_problem *pb, void *hip_stream, pfft_ctx **out)
                 pb->snk_tri, opt);
     hip_ok(hipGetDevice(&c->device), "hipGetDevice");
     build_device(c, (hipStream_t)hip_stream);
+    {
+      // product workspaces may take half of the memory left after setup
+      // (the rest is for the Krylov bases and preconditioner factors)
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->ws_budget = std::max(c->ws_budget, fr / 2);
+    }
     *out = c;
     return PFFT_OK;
   } catch (const SetupError &e) {

@@ -124,6 +124,8 @@ void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStrea
 template <>
 void interp_tri<float>(const GridMaps &g, const float2 *phi, double2 *U, int R, hipStream_t st, void *scratch);
 
+// Whether convolve needs its T2 argument (12 N values a right-hand side).
+bool convolve_uses_t2(const GridMaps &g, int fp64);
 // Full-length forward 3-D FFT of a (2Nx, 2Ny, 2Nz) complex128 array in place.
 void fft3_full_fp64(double2 *data, const int dims2[3], hipStream_t st);
 template <typename T>

@@ -1316,6 +1316,189 @@ __global__ void __launch_bounds__(2 * NY) k_fft_yz_reg(YZArgs a, float2 *data, c
   }
 }
 
+// Fused plane kernel for (channel, k_x) planes too large for one LDS tile:
+// N_y N_z = 8192 (256 x 32 or 512 x 16).  The zero-padded 2N_y x 2N_z plane
+// (256 KB) is never formed: its rows split into the even and odd y halves
+// ky = 2k + e_y, which are independent from the forward y transform up to
+// the cropped inverse one.  The workgroup has two groups of 256 threads
+// (four wavefronts each), one per half, each with its own N_y x N_z working
+// set in LDS (2 x 66-68 KB), and 32 points a thread.  Per half:
+//   A  forward y transform of every column z of x(y) W_{2N_y}^{y e_y}, as a
+//      four-step FFT N_y = 32 x N2 (N2 = N_y / 32): 32-point register FFTs
+//      over j1 (y = j2 + N2 j1, one thread per (z, j2)), the cross twiddle
+//      W_{N_y}^{j2 k1} from an LDS table, then N2-point register FFTs over j2
+//      after an exchange through LDS (k = k1 + 32 k2);
+//   B  rows k through LDS; per row both z halves e_z: forward N_z-point
+//      transform of r(z) W_{2N_z}^{z e_z}, times Ghat(k_x, 2k + e_y,
+//      2m + e_z), inverse transform, times W_{2N_z}^{-z e_z}, summed;
+//   C  the four-step inverse y transform back to the (z, j2) threads, times
+//      W_{2N_y}^{-y e_y}.
+// The halves are then summed through LDS (each finishes half of the
+// points), scaled by 1 / (4 N_y N_z) and stored in place.
+constexpr int BIG_T = 256;   // threads per half
+
+template <int NY, int NZ>
+struct BigPlane {
+  static_assert(NY * NZ == 32 * BIG_T, "32 points per thread");
+  static constexpr int N2 = NY / 32;            // second factor of the y transform
+  static constexpr int KS = 32 / N2;            // k1 values per thread in the N2 stage
+  static constexpr int RPT = NY / BIG_T;        // rows per thread in the z stage
+  static constexpr int PB = NZ + 1;             // row pitch (rows of consecutive lanes in different banks)
+  static constexpr int SZ_A = 32 * N2 * NZ + 2 * 32;
+  static constexpr int SZ_B = NY * PB;
+  static constexpr int SZ = SZ_A > SZ_B ? SZ_A : SZ_B;
+  static constexpr size_t LDS = sizeof(float2) * (2 * SZ + NY + N2);
+  // (k1, j2, z) layout, skewed by 2 slots per k1 so that the two k1 values
+  // of a wavefront in the N2 stage fall in different banks
+  __device__ static int ia(int k1, int j2, int z) { return (k1 * N2 + j2) * NZ + z + 2 * k1; }
+  __device__ static int ib(int k, int z) { return k * PB + z; }
+};
+
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+template <int NY, int NZ>
+__global__ void __launch_bounds__(2 * BIG_T) k_fft_yz_big(YZArgs a, float2 *data, const float *ghat, long ch) {
+  using L = BigPlane<NY, NZ>;
+  constexpr int N2 = L::N2, KS = L::KS, LY = 2 * NY, LZ = 2 * NZ;
+  constexpr int B2 = clog2(N2), BZ = clog2(NZ);
+  extern __shared__ float2 big_sm[];
+  float2 *twy = big_sm + 2 * L::SZ;      // W_{N_y}^k, k < N_y
+  float2 *twh = twy + NY;                // W_{2 N_y}^j, j < N2
+  const int ey = __builtin_amdgcn_readfirstlane(threadIdx.x / BIG_T);   // the half (wavefront-uniform)
+  const int t = threadIdx.x - ey * BIG_T;
+  float2 *S = big_sm + ey * L::SZ;
+  for (int k = threadIdx.x; k < NY; k += 2 * BIG_T) twy[k] = tw<-1>(k, NY);
+  if (threadIdx.x < N2) twh[threadIdx.x] = tw<-1>(threadIdx.x, LY);
+  // channels in descending order (the X passes run over them ascending)
+  const long cb = blockIdx.x / a.two_nx, kx = blockIdx.x - cb * a.two_nx, chan = ch - 1 - cb;
+  float2 *io = data + (chan * a.two_nx + kx) * (long)(NY * NZ);
+  const int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
+  const float *gpl = ghat + (long)fx * (NY + 1) * (NZ + 1);
+  const int za = t % NZ, j2 = t / NZ;     // column and y = j2 + N2 j1 (stages A, C); k1 = j2 + N2 i (N2 stage)
+  float2 v[32];
+#pragma unroll
+  for (int j1 = 0; j1 < 32; ++j1) v[j1] = io[(j2 + N2 * j1) * NZ + za];
+  __syncthreads();                                      // twiddle tables
+  if (ey) {
+    const float2 wl = twh[j2];
+#pragma unroll
+    for (int j1 = 0; j1 < 32; ++j1) v[j1] = twmul<-1>(cmulf(v[j1], wl), N2 * j1, LY);
+  }
+  fft_dif<32, -1>(v);                                   // v[p] = X(k1 = brev(p))
+#pragma unroll
+  for (int p = 1; p < 32; ++p) v[p] = cmulf(v[p], twy[j2 * brev(p, 5)]);
+#pragma unroll
+  for (int p = 0; p < 32; ++p) S[L::ia(brev(p, 5), j2, za)] = v[p];
+  __syncthreads();
+  {
+    float2 w[KS][N2];
+#pragma unroll
+    for (int i = 0; i < KS; ++i)
+#pragma unroll
+      for (int jj = 0; jj < N2; ++jj) w[i][jj] = S[L::ia(j2 + N2 * i, jj, za)];
+#pragma unroll
+    for (int i = 0; i < KS; ++i) fft_dif<N2, -1>(w[i]);   // w[i][p2] = Y(k1 + 32 brev(p2))
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KS; ++i)
+#pragma unroll
+      for (int p2 = 0; p2 < N2; ++p2) S[L::ib(j2 + N2 * i + 32 * brev(p2, B2), za)] = w[i][p2];
+  }
+  __syncthreads();
+  // z stage on this thread's rows
+#pragma unroll 1
+  for (int rr = 0; rr < L::RPT; ++rr) {
+    const int k = t + BIG_T * rr, ky = 2 * k + ey;
+    const int fy = ky <= NY ? ky : LY - ky;
+    const float *grow = gpl + fy * (NZ + 1);
+    float2 o[NZ];
+    {
+      float2 u[NZ];
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) u[z] = S[L::ib(k, z)];
+      fft_dif<NZ, -1>(u);                               // u[p] = Z(m = brev(p)), kz = 2 m
+#pragma unroll
+      for (int p = 0; p < NZ; ++p) {
+        const int kz = 2 * brev(p, BZ), fz = kz <= NZ ? kz : LZ - kz;
+        const float g = grow[fz];
+        u[p] = make_float2(u[p].x * g, u[p].y * g);
+      }
+      fft_dit<NZ, +1>(u);                               // natural z
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) o[z] = u[z];
+    }
+    {
+      float2 u[NZ];
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) u[z] = twmul<-1>(S[L::ib(k, z)], z, LZ);
+      fft_dif<NZ, -1>(u);                               // kz = 2 m + 1
+#pragma unroll
+      for (int p = 0; p < NZ; ++p) {
+        const int kz = 2 * brev(p, BZ) + 1, fz = kz <= NZ ? kz : LZ - kz;
+        const float g = grow[fz];
+        u[p] = make_float2(u[p].x * g, u[p].y * g);
+      }
+      fft_dit<NZ, +1>(u);
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) S[L::ib(k, z)] = cadd(o[z], twmul<+1>(u[z], z, LZ));
+    }
+  }
+  __syncthreads();
+  {
+    // inverse N2-point transforms over k2
+    float2 w[KS][N2];
+#pragma unroll
+    for (int i = 0; i < KS; ++i)
+#pragma unroll
+      for (int p2 = 0; p2 < N2; ++p2) w[i][p2] = S[L::ib(j2 + N2 * i + 32 * brev(p2, B2), za)];
+#pragma unroll
+    for (int i = 0; i < KS; ++i) fft_dit<N2, +1>(w[i]);   // w[i][j2'] natural
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KS; ++i)
+#pragma unroll
+      for (int jj = 0; jj < N2; ++jj) S[L::ia(j2 + N2 * i, jj, za)] = w[i][jj];
+  }
+  __syncthreads();
+  // inverse 32-point transforms over k1
+#pragma unroll
+  for (int p = 0; p < 32; ++p) v[p] = S[L::ia(brev(p, 5), j2, za)];
+#pragma unroll
+  for (int p = 1; p < 32; ++p) v[p] = cmulf(v[p], conjf2(twy[j2 * brev(p, 5)]));
+  fft_dit<32, +1>(v);                                   // v[j1] natural
+  if (ey) {
+    const float2 wl = conjf2(twh[j2]);
+#pragma unroll
+    for (int j1 = 0; j1 < 32; ++j1) v[j1] = twmul<+1>(cmulf(v[j1], wl), N2 * j1, LY);
+  }
+  // sum of the halves: half e finishes j1 in [16 e, 16 e + 16) and hands the
+  // other range to its partner through its own LDS area
+  __syncthreads();
+  float2 *X = big_sm + (1 - ey) * L::SZ;                // the partner reads here
+  float2 keep[16];
+  if (ey) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      X[t + BIG_T * j] = v[j];
+      keep[j] = v[16 + j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      X[t + BIG_T * j] = v[16 + j];
+      keep[j] = v[j];
+    }
+  }
+  __syncthreads();
+  const float sc = a.scale;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int j1 = 16 * ey + j;
+    const float2 r = S[t + BIG_T * j];
+    io[(j2 + N2 * j1) * NZ + za] = make_float2((keep[j].x + r.x) * sc, (keep[j].y + r.y) * sc);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fft_axis(FftArgs a, const V2<T> *in, V2<T> *out, const T *ghat) {
   extern __shared__ unsigned char smraw[];
@@ -1457,6 +1640,37 @@ static void launch_yz_reg(float2 *data, const float *ghat, const YZArgs &y, long
   else launch_yz_reg_n<16, 8>(data, ghat, y, ch, zmask, st);
 }
 
+// Big-plane kernel: FP32, (N_y, N_z) = (256, 32) or (512, 16), its LDS
+// (about 140 KB) granted.
+template <int NY, int NZ>
+static bool big_plane_lds() {
+  static int ok = -1;
+  if (ok < 0) {
+    int dev = 0, q = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) q = 0;
+    const int need = (int)BigPlane<NY, NZ>::LDS;
+    ok = need <= q && hipFuncSetAttribute((const void *)k_fft_yz_big<NY, NZ>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, need) == hipSuccess;
+    if (!ok) (void)hipGetLastError();
+  }
+  return ok == 1;
+}
+template <typename T>
+static bool big_plane_ok(const GridMaps &g, int Ny, int Nz) {
+  if (sizeof(T) != 4 || g.fft_plan == 1) return false;
+  if (Ny == 256 && Nz == 32) return big_plane_lds<256, 32>();
+  if (Ny == 512 && Nz == 16) return big_plane_lds<512, 16>();
+  return false;
+}
+static void launch_yz_big(float2 *data, const float *ghat, const YZArgs &y, long ch, hipStream_t st) {
+  const unsigned nb = (unsigned)(ch * y.two_nx);
+  if (y.ny == 256)
+    k_fft_yz_big<256, 32><<<nb, 2 * BIG_T, BigPlane<256, 32>::LDS, st>>>(y, data, ghat, ch);
+  else
+    k_fft_yz_big<512, 16><<<nb, 2 * BIG_T, BigPlane<512, 16>::LDS, st>>>(y, data, ghat, ch);
+}
+
 // Register X passes: FP32, N_x in {32, 64, 128, 256}, N_y N_z a multiple of
 // 32, one channel of the padded grid below 2^31 bytes.
 template <typename T>
@@ -1553,6 +1767,23 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
     if (hook) hook->done(st);
     return;
   }
+  if (big_plane_ok<T>(g, Ny, Nz)) {
+    if (hook) hook->pass(1, st);
+    YZArgs y{};
+    y.ny = Ny;
+    y.nz = Nz;
+    y.nx = Nx;
+    y.two_nx = 2 * Nx;
+    y.scale = 1.0f / (4.0f * Ny * Nz);
+    launch_yz_big((float2 *)T1, (const float *)g.ghat, y, ch, st);
+    if (hook) hook->pass(4, st);
+    if (xreg)
+      launch_x_reg((const float2 *)T1, (float2 *)Q, Nx, (long)Ny * Nz, ch, +1, g.xtw, xm, cg, st);
+    else
+      fft_axis<T>(T1, Q, ch, (long)Ny * Nz, 2 * Nx, Nx, 2 * Nx, +1, 1.0f / (2.0f * Nx), nullptr, nullptr, st);
+    if (hook) hook->done(st);
+    return;
+  }
   if (4L * Ny * Nz <= 8192 && allow_lds((const void *)k_fft_yz<T>, (int)yz_lds)) {
     // fused Y, Z(+ spectrum), inverse Z, inverse Y on each (channel, kx) plane
     if (hook) hook->pass(1, st);
@@ -1585,6 +1816,17 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
   if (hook) hook->pass(4, st);
   fft_axis<T>(T1, Q, ch, (long)Ny * Nz, 2 * Nx, Nx, 2 * Nx, +1, 1.0f / (2.0f * Nx), nullptr, nullptr, st);
   if (hook) hook->done(st);
+}
+
+// Whether convolve needs the T2 buffer (the unfused Y / Z passes): false
+// wherever a fused plane kernel takes the Y, Z and inverse passes.
+bool convolve_uses_t2(const GridMaps &g, int fp64) {
+  const int Ny = g.dims[1], Nz = g.dims[2];
+  if (!fp64 && (reg_plane_ok<float>(g, Ny, Nz) || big_plane_ok<float>(g, Ny, Nz))) return false;
+  const int vs = fp64 ? (int)sizeof(double2) : (int)sizeof(float2);
+  const size_t yz_lds = (size_t)(2 * Ny + 2 * Nz + 2 * Ny * (2 * Nz + 1)) * vs;
+  const void *fn = fp64 ? (const void *)k_fft_yz<double> : (const void *)k_fft_yz<float>;
+  return !(4L * Ny * Nz <= 8192 && allow_lds(fn, (int)yz_lds));
 }
 
 void fft3_full_fp64(double2 *data, const int d2[3], hipStream_t st) {
