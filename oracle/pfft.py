@@ -21,7 +21,9 @@ Readings fixed here (the paper leaves them open):
 * H(g - g') = 1/|x_g - x_g'| and H(0) := 0 (every pair whose stencils share
   a node is near, so H(0) never reaches a far pair);
 * near pairs: stencil index boxes overlap in every dimension, or the
-  centroid distance is below kappa * max_d (O_s - 1) h_d;
+  centroid distance is below kappa * max_d (O_s - 1) h_d, or the two
+  triangles share a vertex (their singular entries are always computed
+  directly, also on a grid much finer than the triangles);
 * pre-correction: L_d = sum over near triangle pairs of (exact block -
   the same pair through the grid), so near pairs get exact values and far
   pairs the grid values.
@@ -189,6 +191,26 @@ def near_pairs(mesh, grid, kappa=1.5):
     keep = box | (d < rad)
     ti, tj = ti[keep], tj[keep]
     n = mesh.ntri
+    # pairs that share a vertex are singular: always computed directly
+    # (near), even where the grid is much finer than the triangles
+    vt = mesh.T.reshape(-1)
+    tri = np.repeat(np.arange(n), 3)
+    order_v = np.argsort(vt, kind="stable")
+    vs, ts = vt[order_v], tri[order_v]
+    starts = np.searchsorted(vs, np.arange(mesh.V.shape[0] + 1))
+    ta, tb = [], []
+    for v in range(mesh.V.shape[0]):
+        group = ts[starts[v]:starts[v + 1]]
+        if group.size > 1:
+            A, B = np.meshgrid(group, group, indexing="ij")
+            sel = A < B
+            ta.append(A[sel])
+            tb.append(B[sel])
+    if ta:
+        tpair = np.unique(np.stack([np.concatenate(ta), np.concatenate(tb)], axis=1), axis=0)
+        have = np.stack([np.minimum(ti, tj), np.maximum(ti, tj)], axis=1)
+        allp = np.unique(np.concatenate([have, tpair]), axis=0)
+        ti, tj = allp[:, 0], allp[:, 1]
     ti_all = np.concatenate([ti, tj, np.arange(n)])
     tj_all = np.concatenate([tj, ti, np.arange(n)])
     order = np.lexsort((tj_all, ti_all))

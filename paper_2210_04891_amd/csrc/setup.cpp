@@ -553,10 +553,24 @@ static void build_nearfield(HostModel &m, const SetupOptions &opt) {
     for (int d = 0; d < 3; ++d) cidx[t][d] = (int64_t)std::floor((m.cen[3 * t + d] - lo[d]) / cell);
     cells[ckey(cidx[t][0], cidx[t][1], cidx[t][2])].push_back(t);
   }
+  // triangles around each vertex: a pair that shares a vertex is always near
+  // (its singular entries are computed directly), whatever the grid spacing
+  const int nvert = (int)(m.V.size() / 3);
+  std::vector<int> vt_off(nvert + 1, 0), vt_tri(3 * (size_t)n);
+  for (int k = 0; k < 3 * n; ++k) vt_off[m.T[k] + 1]++;
+  for (int v = 0; v < nvert; ++v) vt_off[v + 1] += vt_off[v];
+  {
+    std::vector<int> fill(vt_off.begin(), vt_off.end() - 1);
+    for (int k = 0; k < 3 * n; ++k) vt_tri[fill[m.T[k]]++] = k / 3;
+  }
   std::vector<std::vector<int>> nb(n);
 #pragma omp parallel for schedule(dynamic, 256)
   for (int t = 0; t < n; ++t) {
     auto &out = nb[t];
+    for (int i = 0; i < 3; ++i) {
+      const int v = m.T[3 * t + i];
+      for (int k = vt_off[v]; k < vt_off[v + 1]; ++k) out.push_back(vt_tri[k]);
+    }
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dz = -1; dz <= 1; ++dz) {
@@ -572,6 +586,7 @@ static void build_nearfield(HostModel &m, const SetupOptions &opt) {
           }
         }
     std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
   }
   m.near_off.assign(n + 1, 0);
   for (int t = 0; t < n; ++t) m.near_off[t + 1] = m.near_off[t] + (int)nb[t].size();
@@ -708,10 +723,17 @@ static void build_nearfield(HostModel &m, const SetupOptions &opt) {
       }
     }
   }
+  // (touching pairs are in every near list by construction; a miss is
+  // reported after the parallel loop, never thrown inside it)
+  int missing = 0;
   auto find_q = [&](int t, int u) -> int {
     const int *beg = &m.near_tri[m.near_off[t]], *end = &m.near_tri[m.near_off[t + 1]];
     const int *it = std::lower_bound(beg, end, u);
-    if (it == end || *it != u) fail(-4, "internal: touching pair missing from near list");
+    if (it == end || *it != u) {
+#pragma omp atomic write
+      missing = 1;
+      return -1;
+    }
     return (int)(m.near_off[t] + (it - beg));
   };
   // diagonal of the exact K (for Z_b^N = diag(Z_b)): the two triangles of e
@@ -726,6 +748,7 @@ static void build_nearfield(HostModel &m, const SetupOptions &opt) {
       for (int c = 0; c < 2; ++c) {
         int t = ts[a], u = ts[c];
         int q = find_q(t, u);
+        if (q < 0) continue;
         int i = 0, j = 0;
         while (m.tri_edge[3 * t + i] != e) ++i;
         while (m.tri_edge[3 * u + j] != e) ++j;
@@ -734,6 +757,7 @@ static void build_nearfield(HostModel &m, const SetupOptions &opt) {
       }
     m.kdiag[e] = acc;
   }
+  if (missing) fail(-4, "internal: touching pair missing from near list");
   // edge-level CSR: row e gathers the blocks of (t, u), t in {T+, T-}, u near t
   m.nf_rowptr.assign(b + 1, 0);
   std::vector<std::vector<int>> rcol(b);

@@ -106,6 +106,32 @@ def test_precorrection_matches_oracle(c1, c1_host):
     assert np.abs(D).max() <= 1e-6 * abs(ref).max()
 
 
+def test_fine_grid_keeps_touching_pairs_near():
+    """A grid much finer than the triangles (the paper's bar on 256 x 64 x 64,
+    spacing 0.8 x 0.13 x 0.08 um against 8-16 um triangles): triangles that
+    share a vertex are near although their stencils are far apart, so the
+    singular pairs of Eq. Lb are computed directly; the library's L_d has the
+    oracle's sparsity and values."""
+    import scipy.sparse as sp
+    from oracle.mesh import RWGMesh
+    from oracle import pfft as PF
+    s = W.paper_bar_e1()
+    m = RWGMesh(s.V, s.T)
+    grid = (256, 64, 64)
+    h = P.HostModel(s, grid, 4, 1.5)
+    rp = h.get("near_rowptr", np.int64)
+    Ld = sp.csr_matrix((h.get("near_val", np.float64), h.get("near_col", np.int32), rp),
+                       shape=(m.nedge, m.nedge))
+    ref = PF.precorrection(m, PF.Grid(m.V, grid, 4), 1.5)
+    assert Ld.nnz == ref.nnz
+    assert np.abs((Ld - ref).toarray()).max() <= 1e-6 * abs(ref).max()
+    # every edge's own row holds its two triangles' other edges
+    for e in range(0, m.nedge, 37):
+        cols = set(Ld.indices[rp[e]:rp[e + 1]])
+        for t in (m.tplus[e], m.tminus[e]):
+            assert set(m.tri_edge[t]) <= cols
+
+
 def test_kernel_diagonal_matches_dense(c1, c1_host):
     s, h = c1_host
     kd = h.get("kdiag", np.float64)
