@@ -105,6 +105,22 @@ pfft_status pfft_sizes(const pfft_ctx *c, int64_t out[10]);
 pfft_status pfft_matvec(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t space,
                         int32_t flags, const void *x_dev, void *y_dev, void *hip_stream);
 
+/* pfft_matvec without any device allocation inside the call, for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layouts and results as
+ * pfft_matvec, except that the preconditioner flags (PRECOND, PRECOND_ONLY,
+ * LEARNED_ONLY) are rejected with PFFT_EINVAL: they need per-frequency
+ * factors.  The product's workspace is carved from a fixed 128 MiB scratch
+ * array that the library holds on each GPU it runs on until the process
+ * ends; right-hand sides are processed in chunks that fit it, and a problem
+ * whose single right-hand side needs more returns PFFT_ENOMEM (message
+ * states both sizes).  Every call on one GPU shares that GPU's scratch
+ * (from every context): calls that overlap on one GPU race, so the caller
+ * serialises them (one stream, or events).  Nothing in the scratch needs to
+ * start at zero. */
+pfft_status pfft_matvec_noalloc(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t space,
+                                int32_t flags, const void *x_dev, void *y_dev, void *hip_stream);
+
 /* Solve A Z_b A^T I_l = V_l (Eq. FinalME) for every (frequency, port):
  * V_l = 1 V on the port's source loop, other ports shorted (Sec. V), with
  * right-preconditioned flexible GMRES (restart `restart`, x0 = 0, relative

@@ -47,6 +47,7 @@ struct Learned;   // learned correction network
 // Per-product workspace for up to R right-hand sides (one per stream lane).
 struct Workspace {
   int R = 0;
+  bool fixed = false;   // carved from caller-independent scratch: never (re)allocated
   std::vector<void *> allocs;
   double2 *alpha = nullptr, *scan = nullptr, *part = nullptr, *U = nullptr, *yb = nullptr, *coef = nullptr;
   void *J = nullptr, *Q = nullptr, *T1 = nullptr, *T2 = nullptr;
@@ -63,6 +64,8 @@ struct pfft_ctx {
   int max_chunk = 0;
   size_t ws_budget = (size_t)24 << 30;   // product workspace bytes (chunk size)
   int device = 0;
+  void *scratch = nullptr;   // this device's no-allocation scratch (address of the static array)
+  pfft::Workspace ws_fixed;  // carved from scratch by pfft_matvec_noalloc
   std::vector<void *> allocs;
   size_t dev_bytes = 0;
   pfft::LoopMaps lm{};

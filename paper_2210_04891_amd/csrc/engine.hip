@@ -5,7 +5,10 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 
 #include "engine.h"
 
@@ -98,6 +101,7 @@ int pfft_ctx::chunk_for(int R) const {
 
 void pfft_ctx::ensure_workspace(Workspace &w, int R) {
   if (R <= w.R) return;
+  if (w.fixed) throw DeviceError{PFFT_ENOMEM, "fixed scratch too small for the chunk"};
   for (void *p : w.allocs) hipFree(p);
   w.allocs.clear();
   auto al = [&](size_t bytes) {
@@ -134,9 +138,10 @@ void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const do
 void pfft_ctx::matvec_range(Workspace &w, int R, const double *omega, int space, int flags, const double2 *x,
                             double2 *y, hipStream_t st, const PostOut *post) {
   const int dim = space == 1 ? m.l : m.b;
-  const int Rc = chunk_for(R);
+  const int Rc = w.fixed ? std::min(w.R, R) : chunk_for(R);
   ensure_workspace(w, Rc);
   if (!w.T2 && !(flags & PFFT_NEAR_ONLY) && convolve_uses_t2(gm, grid_fp64)) {
+    if (w.fixed) throw DeviceError{PFFT_ENOMEM, "the fixed scratch was carved without the unfused FFT buffer"};
     // a plan change since the workspace was sized now needs the unfused passes' buffer
     const size_t vs = grid_fp64 ? sizeof(double2) : sizeof(float2);
     void *p = nullptr;
@@ -709,6 +714,72 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Fixed scratch of the no-allocation product (pfft_matvec_noalloc).  Each GPU
+// holds its own copy of this array from the first use of the library until
+// the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns with that device current (kept per device).
+// ---------------------------------------------------------------------------
+static constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_addr;
+
+// the current device's scratch address (looked up once per device)
+static void *device_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) return it->second;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    throw DeviceError{PFFT_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+  g_scratch_addr[dev] = p;
+  return p;
+}
+
+// Lays out the product workspace for R right-hand sides from base (256-byte
+// aligned pieces) and returns its size; assigns the pointers when w is given.
+static size_t carve_workspace(const pfft_ctx *c, int R, unsigned char *base, Workspace *w) {
+  const HostModel &m = c->m;
+  const size_t vs = c->grid_fp64 ? sizeof(double2) : sizeof(float2);
+  const size_t N = (size_t)m.dims[0] * m.dims[1] * m.dims[2];
+  const bool t2 = convolve_uses_t2(c->gm, c->grid_fp64);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    void *p = base ? base + off : nullptr;
+    off += (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
+    return p;
+  };
+  void *alpha = take(sizeof(double2) * (size_t)R * m.b);
+  void *yb = take(sizeof(double2) * (size_t)R * m.b);
+  void *scan = take(sizeof(double2) * (size_t)R * (m.nn + 1));
+  void *part = take(sizeof(double2) * scan_partials_size(m.nn + 1, R));
+  void *U = take(sizeof(double2) * (size_t)R * std::max<size_t>((size_t)m.n * 4, (size_t)m.l));
+  void *coef = take(sizeof(double2) * 2 * (size_t)R);
+  void *J = take(vs * (size_t)R * m.n * 4);
+  void *Q = take(vs * (size_t)R * 3 * N);
+  void *T1 = take(vs * (size_t)R * 6 * N);
+  void *T2 = t2 ? take(vs * (size_t)R * 12 * N) : nullptr;
+  if (w) {
+    w->alpha = (double2 *)alpha;
+    w->yb = (double2 *)yb;
+    w->scan = (double2 *)scan;
+    w->part = (double2 *)part;
+    w->U = (double2 *)U;
+    w->coef = (double2 *)coef;
+    w->J = J;
+    w->Q = Q;
+    w->T1 = T1;
+    w->T2 = T2;
+    w->R = R;
+    w->fixed = true;
+    w->allocs.clear();
+    w->coef_on_device.clear();   // another call may have changed the scratch
+  }
+  return off;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -738,6 +809,7 @@ pfft_status pfft_setup(const pfft_problem *pb, void *hip_stream, pfft_ctx **out)
     build_model(c->m, pb->V, pb->nv, pb->T, pb->nt, pb->nport, pb->src_off, pb->src_tri, pb->snk_off,
                 pb->snk_tri, opt);
     hip_ok(hipGetDevice(&c->device), "hipGetDevice");
+    c->scratch = device_scratch(c->device);
     build_device(c, (hipStream_t)hip_stream);
     {
       // product workspaces may take half of the memory left after setup
@@ -818,6 +890,57 @@ pfft_status pfft_matvec(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t 
     return (pfft_status)e.code;
   } catch (const SetupError &e) {
     set_error("pfft_matvec: " + e.msg);
+    return (pfft_status)e.code;
+  }
+}
+
+pfft_status pfft_matvec_noalloc(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t space, int32_t flags,
+                                const void *x_dev, void *y_dev, void *hip_stream) {
+  if (!c || !x_dev || !y_dev || nrhs < 0 || (space != 0 && space != 1)) {
+    set_error("pfft_matvec_noalloc: bad argument");
+    return PFFT_EINVAL;
+  }
+  if (space == 1 && !omega && nrhs > 0) {
+    set_error("pfft_matvec_noalloc: loop space needs omega");
+    return PFFT_EINVAL;
+  }
+  if ((flags & PFFT_FAR_ONLY) && (flags & PFFT_NEAR_ONLY)) {
+    set_error("pfft_matvec_noalloc: FAR_ONLY and NEAR_ONLY are exclusive");
+    return PFFT_EINVAL;
+  }
+  if (flags & (PFFT_PRECOND | PFFT_PRECOND_ONLY | PFFT_LEARNED_ONLY)) {
+    set_error("pfft_matvec_noalloc: the preconditioner flags need per-frequency factors (use pfft_matvec)");
+    return PFFT_EINVAL;
+  }
+  if (x_dev == y_dev) {
+    set_error("pfft_matvec_noalloc: x and y must not alias");
+    return PFFT_EINVAL;
+  }
+  if (nrhs == 0) return PFFT_OK;
+  const size_t one = carve_workspace(c, 1, nullptr, nullptr);
+  if (one > NOALLOC_SCRATCH_BYTES) {
+    set_error("pfft_matvec_noalloc: one right-hand side needs " + std::to_string(one) +
+              " bytes of scratch; the fixed scratch holds " + std::to_string(NOALLOC_SCRATCH_BYTES));
+    return PFFT_ENOMEM;
+  }
+  try {
+    hip_ok(hipSetDevice(c->device), "hipSetDevice");
+    // the largest chunk that fits (workspace size grows with R)
+    int rfit = 1;
+    while (rfit < nrhs) {
+      const int nx = std::min(2 * rfit, (int)nrhs);
+      if (carve_workspace(c, nx, nullptr, nullptr) > NOALLOC_SCRATCH_BYTES) break;
+      rfit = nx;
+    }
+    carve_workspace(c, rfit, (unsigned char *)c->scratch, &c->ws_fixed);
+    c->matvec_range(c->ws_fixed, nrhs, omega, space, flags, (const double2 *)x_dev, (double2 *)y_dev,
+                    (hipStream_t)hip_stream);
+    return PFFT_OK;
+  } catch (const DeviceError &e) {
+    set_error("pfft_matvec_noalloc: " + e.msg);
+    return (pfft_status)e.code;
+  } catch (const SetupError &e) {
+    set_error("pfft_matvec_noalloc: " + e.msg);
     return (pfft_status)e.code;
   }
 }

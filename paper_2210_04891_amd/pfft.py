@@ -29,7 +29,7 @@ EXPORTS = ("pfft_setup", "pfft_sizes", "pfft_matvec", "solve_ports", "extract_RL
            "pfft_stage_times", "pfft_precond_save", "pfft_learned_collect", "pfft_learned_train",
            "pfft_learned_clear", "pfft_learned_stats", "pfft_mlp_grad", "pfft_learned_eval",
            "pfft_set_option", "pfft_get_option", "pfft_autotune", "solve_ports_lgmres",
-           "solve_ports_loops", "pfft_postprocess")
+           "solve_ports_loops", "pfft_postprocess", "pfft_matvec_noalloc")
 
 STAGES = ("loop_to_branch", "tri_current", "project", "fft_x", "fft_y", "fft_z_conv", "ifft_y",
           "ifft_x", "interp", "combine", "branch_to_loop", "precond")
@@ -72,6 +72,8 @@ def load():
     lib.pfft_sizes.restype = i32
     lib.pfft_matvec.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp]
     lib.pfft_matvec.restype = i32
+    lib.pfft_matvec_noalloc.argtypes = [vp, i32, vp, i32, i32, vp, vp, vp]
+    lib.pfft_matvec_noalloc.restype = i32
     lib.solve_ports.argtypes = [vp, i32, vp, dbl, i32, i32, i32, vp, vp, vp, vp]
     lib.solve_ports.restype = i32
     lib.solve_ports_lgmres.argtypes = [vp, i32, vp, dbl, i32, i32, i32, vp, vp, vp, vp]
@@ -241,6 +243,26 @@ class Context:
         _check(load().pfft_matvec(self._h, R, _ptr(om) if om is not None else None, space, flags,
                                   ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                   _stream_handle(stream)))
+        return y
+
+    def matvec_noalloc(self, x, omega=None, space=1, flags=0, out=None, stream=None):
+        """matvec through pfft_matvec_noalloc (no device allocation inside
+        the call; the library's fixed scratch holds the workspace); y must be
+        given or is allocated here, before the call."""
+        import torch
+        assert x.dtype == torch.complex128 and x.is_cuda and x.dim() == 2
+        x = x.contiguous()
+        R = x.shape[0]
+        dim = self.sizes["l"] if space == 1 else self.sizes["b"]
+        if x.shape[1] != dim:
+            raise ValueError("x has %d columns, expected %d" % (x.shape[1], dim))
+        y = torch.empty_like(x) if out is None else out
+        om = None
+        if space == 1:
+            om = np.ascontiguousarray(np.broadcast_to(np.asarray(omega, np.float64), (R,)))
+        _check(load().pfft_matvec_noalloc(self._h, R, _ptr(om) if om is not None else None, space, flags,
+                                          ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                          _stream_handle(stream)))
         return y
 
     def solve_ports(self, freqs_hz, tol=1e-6, maxit=500, restart=60, precond=1, stream=None):
