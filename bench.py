@@ -1,16 +1,21 @@
 """Benchmark of the pFFT loop-analysis hot path on one MI355X.
 
-Workload (default): the bond-wire array -- 8 parabolic-arch wires, 25 um
-diameter (12 facets), span 2 mm, arch height 300 um, pitch 100 um, 39,936
-triangles, 8 ports x 10 log-spaced frequencies 1 MHz - 10 GHz = 80 right-hand
-sides, FP32 complex grid convolution on a 256 x 64 x 32 grid, FP64 near field.
+Workload (default): the package-trace configuration -- 32 seeded Manhattan
+meander traces (20 x 15 um section, 3-8 turns, 2-6 mm long) on a 5 x 5 mm
+area, 200,196 triangles, 32 ports x 16 log-spaced frequencies 0.1-10 GHz =
+512 right-hand sides, FP32 complex grid convolution on a 256 x 256 x 32 grid,
+FP64 near field.
 
 One step = one application of the preconditioned loop operator P^-1 Z_l to
-all 80 right-hand sides (tree scan A^T, projection, three-axis FFT
+all 512 right-hand sides (tree scan A^T, projection, three-axis FFT
 convolution, interpolation, near-field + Gram combine, tree scan A,
 preconditioner), inputs resident on the device.  value = right-hand-side
-matvecs per second.  The sweep solve (all ports x frequencies to a 1e-6 true
-relative residual) is timed once after the steps.
+matvecs per second.  After the steps: per-stage HIP-event times, the
+roofline of the dominant kernel, the branch-space product against exact
+dense-kernel rows of the oracle (sampled edges), the bond-wire array (39,936
+triangles, 80 RHS) as a second measured workload, the sweep solve (all ports
+x frequencies to a 1e-6 true relative residual, plain and learned
+preconditioner) and the oracle's stored-kernel matvec timed on the host.
 
 Prints one JSON line.
 """
@@ -33,6 +38,13 @@ FP32_PEAK_TFLOPS = 157.3
 FP32_NOPACK_TFLOPS = 78.6
 
 
+def traces_workload():
+    import workloads as W
+    s = W.config3_traces()
+    freqs = np.logspace(8, 10, 16)
+    return s, freqs, (256, 256, 32)
+
+
 def wires_workload():
     import workloads as W
     s = W.config2_wires()
@@ -40,9 +52,19 @@ def wires_workload():
     return s, freqs, (256, 64, 32)
 
 
+WORKLOADS = {
+    "traces": (traces_workload, "package traces: 32 meander traces, 200,196 triangles, 32 ports x 16 freqs "
+                                "(0.1-10 GHz) = 512 RHS, grid 256x256x32, O_s=4, kappa=1.5"),
+    "wires": (wires_workload, "bond-wire array: 8 wires, 39,936 triangles, 8 ports x 10 freqs = 80 RHS, "
+                              "grid 256x64x32, O_s=4, kappa=1.5"),
+}
+
+
 def stage_bytes(sz, R, vbytes=8):
     """Algorithmic HBM bytes of one launch of each stage for R right-hand
-    sides (each input and output touched once; matrix data read once)."""
+    sides (each input and output touched once; matrix data read once).  The
+    fused plane kernel ("fft_y") reads and writes the 2 N_g points of each
+    channel's x-transformed grid once."""
     N, n, b, l, nn = sz["Ng"], sz["n"], sz["b"], sz["l"], sz["nprime"]
     ch = 3 * R
     return {
@@ -50,9 +72,7 @@ def stage_bytes(sz, R, vbytes=8):
         "tri_current": R * (16 * b + 4 * vbytes * n) + 12 * n,
         "project": ch * N * vbytes + R * 4 * vbytes * n + 64 * n * (4 + 4 * (vbytes // 2)),
         "fft_x": ch * N * vbytes * 3,          # read N, write 2N
-        "fft_y": ch * N * vbytes * 6,          # read 2N, write 4N
-        "fft_z_conv": ch * N * vbytes * 8,     # read 4N, write 4N
-        "ifft_y": ch * N * vbytes * 6,         # read 4N, write 2N
+        "fft_y": ch * N * vbytes * 4,          # fused plane: read 2N, write 2N
         "ifft_x": ch * N * vbytes * 3,         # read 2N, write N
         "interp": ch * N * vbytes + R * 64 * n + 64 * n * 4 * (vbytes // 2),
         "combine": R * (16 * b * 2 + 64 * n) + 12 * sz["nnz_near"] + 60 * b,
@@ -60,11 +80,15 @@ def stage_bytes(sz, R, vbytes=8):
     }
 
 
+def _fft(n):
+    """5 N log2 N flops of an N-point complex FFT."""
+    return 5 * n * int(np.log2(n)) if n > 1 else 0
+
+
 def yz_plane_flops(ny, nz):
-    """FFT flops of the fused plane kernel for one (channel, k_x) plane:
-    5 N log2 N per N-point transform, the 6-flop split twiddles of each
-    zero-padded transform (two N-point halves), the real spectrum product and
-    the half sums of the cropped inverses."""
+    """FFT flops of the register plane kernel (planes up to 64 x 32) for one
+    (channel, k_x) plane: the z and y transforms of both zero-padding halves,
+    their split twiddles, the real spectrum product and the half sums."""
     ly, lz = int(np.log2(ny)), int(np.log2(nz))
     z_fwd = ny * (2 * 5 * nz * lz + 6 * nz)
     y_fwd = 2 * nz * (2 * 5 * ny * ly + 6 * ny)
@@ -74,13 +98,29 @@ def yz_plane_flops(ny, nz):
     return z_fwd + y_fwd + mult + y_inv + z_inv
 
 
-def measured_traffic(stage):
-    """HBM bytes per launch of a stage from the committed counter runs
-    (profiles/bond_wires80_traffic.json: rocprofv3 FETCH_SIZE and WRITE_SIZE,
-    each scaled by a 1 GiB copy), or None when the table has no entry or the
-    kernel sources changed since the counters were taken."""
+def big_plane_flops(ny, nz):
+    """Flops of the big-plane kernel (256 x 32, 512 x 16 planes) for one
+    (channel, k_x) plane, per y half e_y: the forward and inverse N_y-point y
+    transforms of the N_z columns (four-step: 5 N log2 N plus 6 flops per
+    cross twiddle), the modulation and demodulation of the odd half, and per
+    row both z halves (forward and inverse N_z-point transforms, the odd
+    half's twiddles, the real spectrum product, the half sum); then the sum
+    of the two y halves and the scale."""
+    tot = 0
+    for ey in (0, 1):
+        y = nz * (2 * (_fft(ny) + 6 * ny) + (2 * 6 * ny if ey else 0))
+        z = ny * (2 * 2 * _fft(nz) + 2 * 6 * nz + 2 * 2 * nz + 2 * nz)
+        tot += y + z
+    return tot + 4 * ny * nz
+
+
+def measured_traffic(stage, table):
+    """HBM bytes per launch of a stage from a committed counter table
+    (profiles/<table>.json: rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled
+    by a 1 GiB copy), or None when the table has no entry or the kernel
+    sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(HERE, "profiles", "bond_wires80_traffic.json")
+    path = os.path.join(HERE, "profiles", table + ".json")
     try:
         tab = json.load(open(path))
     except (OSError, ValueError):
@@ -95,42 +135,123 @@ def measured_traffic(stage):
     return None if ent is None else int(ent["read_bytes"] + ent["write_bytes"])
 
 
-def cpu_oracle_baseline(structure, budget_s=12.0):
-    """The oracle's dense kernel matvec, rows computed exactly on the fly
-    (closed-form inner / graded outer quadrature), timed on a bounded sample
-    of rows and scaled to one full RHS matvec."""
+def exact_rows_check(ctx, structure, nrow=24, nrhs=4, seed=0):
+    """The branch-space product K alpha on the GPU against exact dense-kernel
+    rows of the oracle (both surfaces integrated numerically) at nrow sampled
+    edges, for nrhs seeded right-hand sides: relative 2-norm error over the
+    sampled entries and the largest entry error relative to the largest
+    entry.  Returns (dict, rows, alpha, seconds spent on the rows)."""
+    import torch
+    import workloads as W
     from oracle.mesh import RWGMesh
     from oracle import integrals as I
     m = RWGMesh(structure.V, structure.T)
-    rng = np.random.default_rng(0)
-    alpha = rng.standard_normal(m.nedge) + 1j * rng.standard_normal(m.nedge)
-    rows = rng.choice(m.nedge, 64, replace=False)
+    rows = np.sort(np.random.default_rng(seed).choice(m.nedge, nrow, replace=False))
     t0 = time.perf_counter()
-    done = 0
-    for e in rows:
-        r = I.kernel_rows(m, [e])[0]
-        _ = r @ alpha
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = (time.perf_counter() - t0) / done
-    per_matvec = dt * m.nedge
+    Krows = I.kernel_rows(m, rows)
+    t_rows = time.perf_counter() - t0
+    X = W.complex_normal(seed + 1, (nrhs, m.nedge))
+    y = ctx.matvec(torch.from_numpy(X).cuda(), space=0).cpu().numpy()[:, rows]
+    ref = X @ Krows.T
+    return ({"rows": int(nrow), "rhs": int(nrhs),
+             "rel_err_2norm": float(np.linalg.norm(y - ref) / np.linalg.norm(ref)),
+             "max_abs_err_rel_to_max": float(np.abs(y - ref).max() / np.abs(ref).max())},
+            Krows, X, t_rows)
+
+
+def cpu_oracle_baseline(Krows, X, nrhs_full, b, t_rows):
+    """The oracle's matvec with a stored dense kernel (numpy BLAS on the host
+    cores): a block of stored rows (the exact sampled rows repeated to 512)
+    times the right-hand sides as a real matrix times complex columns, timed
+    and scaled to the b rows of one full product of nrhs_full right-hand
+    sides.  Extrapolated: the full K (b x b doubles) does not fit in memory."""
+    reps = max(1, 512 // Krows.shape[0])
+    Kb = np.ascontiguousarray(np.tile(Krows, (reps, 1)))
+    Xr = np.ascontiguousarray(np.tile(X.T, (1, max(1, nrhs_full // X.shape[0])))[:, :nrhs_full])
+    Xre, Xim = np.ascontiguousarray(Xr.real), np.ascontiguousarray(Xr.imag)
+    _ = Kb[:8] @ Xre[:, :8]
+    t0 = time.perf_counter()
+    _ = Kb @ Xre
+    _ = Kb @ Xim
+    dt = time.perf_counter() - t0
+    per_row = dt / Kb.shape[0]
+    full = per_row * b
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / per_matvec, "unit": "RHS-matvecs/s", "cores": threads, "kind": "oracle",
-            "sample": "%d exact dense-kernel rows (of %d) on the fly, scaled to a full K.alpha" % (done, m.nedge)}
+    return {"value": nrhs_full / full, "unit": "RHS-matvecs/s", "cores": threads, "kind": "oracle",
+            "sample": "stored-kernel K.alpha: %d stored rows (%d exact oracle rows, repeated) x %d right-hand "
+                      "sides with numpy BLAS in %.2f s, scaled to the %d rows of a full product "
+                      "(extrapolated; exact rows took %.1f s to integrate)"
+                      % (Kb.shape[0], Krows.shape[0], nrhs_full, dt, b, t_rows)}
+
+
+def roofline(stages, sz, R, grid):
+    """Roofline of the dominant kernel (largest share of the step)."""
+    nbytes = stage_bytes(sz, R)
+    dom = max((k for k in stages if stages[k][1] > 0), key=lambda k: stages[k][0])
+    ms, calls = stages[dom]
+    avg_s = ms / 1e3 / calls
+    gx, gy, gz = grid
+    big = (gy, gz) in ((256, 32), (512, 16))
+    reg = (gy, gz) in ((64, 32), (32, 16), (16, 8))
+    if dom == "fft_y" and (big or reg):
+        # the fused plane kernels issue vector ALU work at their limit (packed
+        # FP32 is not used): FFT flops against the FP32 vector peak, with the
+        # HBM figure beside
+        per_plane = big_plane_flops(gy, gz) if big else yz_plane_flops(gy, gz)
+        flops = 3 * R * 2 * gx * per_plane
+        achieved = flops / avg_s / 1e12
+        return {"kernel": "k_fft_yz_big" if big else "k_fft_yz_reg", "stage": dom, "bound": "alu",
+                "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "avg_launch_ms": round(ms / calls, 4),
+                "flops_per_launch": int(flops), "peak_without_packed_fp32": FP32_NOPACK_TFLOPS,
+                "frac_without_packed_fp32": round(achieved / FP32_NOPACK_TFLOPS, 4),
+                "hbm_GBs": round(nbytes[dom] / avg_s / 1e9, 1), "bytes_per_launch": int(nbytes[dom])}
+    if dom in nbytes:
+        achieved = nbytes[dom] / avg_s / 1e9
+        return {"stage": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms / calls, 4),
+                "bytes_per_launch": int(nbytes[dom])}
+    return {"stage": dom, "bound": "latency", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": None, "avg_launch_ms": round(ms / calls, 4)}
+
+
+def run_steps(ctx, R, omega, steps, warmup, flags):
+    import torch
+    sz = ctx.sizes
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.standard_normal((R, sz["l"])) + 1j * rng.standard_normal((R, sz["l"]))).cuda()
+    y = torch.empty_like(x)
+    for _ in range(warmup):
+        ctx.matvec(x, omega, space=1, flags=flags, out=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.matvec(x, omega, space=1, flags=flags, out=y)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # per-stage HIP-event timing on the library's stream
+    psteps = max(1, min(steps, 3))
+    ctx.profile(True)
+    for _ in range(psteps):
+        ctx.matvec(x, omega, space=1, flags=flags, out=y)
+    torch.cuda.synchronize()
+    stages = ctx.stage_times()
+    ctx.profile(False)
+    del x, y
+    return dt, stages, psteps
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="traces")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction sweep arm")
-    ap.add_argument("--no-split", action="store_true",
-                    help="run every product on one stream (the per-kernel profile runs use this so that kernel "
-                         "durations are not shared with a concurrent stream)")
+    ap.add_argument("--no-second", action="store_true", help="skip the second (bond-wire) workload")
+    ap.add_argument("--no-check", action="store_true", help="skip the exact-row check and the CPU baseline")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before the steps, copy a buffer of this size three times (device to device) so that "
                          "hardware byte counters can be scaled against a transfer of known size")
@@ -143,7 +264,8 @@ def main():
     import torch
     import paper_2210_04891_amd as P
 
-    s, freqs, grid = wires_workload()
+    make, label = WORKLOADS[args.workload]
+    s, freqs, grid = make()
     p = len(s.ports)
     R = p * len(freqs)
     t_setup = time.perf_counter()
@@ -152,10 +274,6 @@ def main():
     t_setup = time.perf_counter() - t_setup
     sz = ctx.sizes
     omega = np.repeat(2 * np.pi * freqs, p)
-    rng = np.random.default_rng(0)
-    x = torch.from_numpy(rng.standard_normal((R, sz["l"])) + 1j * rng.standard_normal((R, sz["l"]))).cuda()
-    y = torch.empty_like(x)
-    flags = P.PFFT_PRECOND
     if args.copy_probe_mb > 0:
         a = torch.ones(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -163,59 +281,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    if args.no_split:
-        ctx.set_option("stream_split", 0)
-    for _ in range(args.warmup):
-        ctx.matvec(x, omega, space=1, flags=flags, out=y)
-    torch.cuda.synchronize()
-    # timed region: the steps as they run in the solver (right-hand sides
-    # split over two streams unless --no-split)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.matvec(x, omega, space=1, flags=flags, out=y)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt, stages, psteps = run_steps(ctx, R, omega, args.steps, args.warmup, P.PFFT_PRECOND)
     value = R * args.steps / dt
-    # per-stage HIP-event timing (one stream, so each kernel's duration is its
-    # own): the roofline of the dominant kernel
-    psteps = max(1, min(args.steps, 5))
-    ctx.profile(True)
-    for _ in range(psteps):
-        ctx.matvec(x, omega, space=1, flags=flags, out=y)
-    torch.cuda.synchronize()
-    stages = ctx.stage_times()
-    ctx.profile(False)
-    # roofline of the dominant kernel (by total time inside the timed region)
-    nbytes = stage_bytes(sz, R)
-    if stages.get("fft_z_conv", (0, 0))[1] == 0 and stages.get("fft_y", (0, 0))[1] > 0:
-        # fused (Y, Z + spectrum, inverse Z, inverse Y) plane kernel: reads and
-        # writes the 2 N_g points of each channel once
-        nbytes["fft_y"] = 3 * R * sz["Ng"] * 8 * 4
-    dom = max((k for k in stages if stages[k][1] > 0), key=lambda k: stages[k][0])
-    ms, calls = stages[dom]
-    avg_s = ms / 1e3 / calls
-    fused = stages.get("fft_z_conv", (0, 0))[1] == 0
-    if dom == "fft_y" and fused:
-        # the fused plane kernel issues vector ALU work at its limit (packed
-        # FP32 is not used): report FFT flops against the FP32 vector peak,
-        # with its HBM figure beside
-        gx, gy, gz = grid
-        flops = 3 * R * 2 * gx * yz_plane_flops(gy, gz)
-        achieved = flops / avg_s / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom),
-                "avg_launch_ms": round(ms / calls, 4), "flops_per_launch": int(flops),
-                "peak_without_packed_fp32": FP32_NOPACK_TFLOPS,
-                "frac_without_packed_fp32": round(achieved / FP32_NOPACK_TFLOPS, 4),
-                "hbm_GBs": round(nbytes[dom] / avg_s / 1e9, 1), "bytes_per_launch": int(nbytes[dom])}
-    elif dom in nbytes:
-        achieved = nbytes[dom] / avg_s / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
-                "avg_launch_ms": round(ms / calls, 4), "bytes_per_launch": int(nbytes[dom])}
-    else:
-        roof = {"kernel": dom, "bound": "latency", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None, "avg_launch_ms": round(ms / calls, 4)}
+    roof = roofline(stages, sz, R, grid)
+    table = {"traces": "package_traces512_traffic", "wires": "bond_wires80_traffic"}[args.workload]
+    roof["traffic"] = measured_traffic(roof["stage"], table)
     out = {
         "metric": "pFFT matvecs/s (% HBM peak); sweep solve time learned vs plain @1e-6 resid",
         "value": round(value, 2),
@@ -229,9 +299,7 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32 grid / fp64 near field, scans, preconditioner",
         "data": "synthetic",
-        "config": {"workload": "bond-wire array: 8 wires, 39,936 triangles, 8 ports x 10 freqs = 80 RHS, "
-                               "grid 256x64x32, O_s=4, kappa=1.5",
-                   "triangles": sz["n"], "loops": sz["l"], "rhs": R, "grid": list(grid),
+        "config": {"workload": label, "triangles": sz["n"], "loops": sz["l"], "rhs": R, "grid": list(grid),
                    "near_nnz": sz["nnz_near"], "setup_s": round(t_setup, 2)},
         "roofline": roof,
         "stages_ms_per_step": {k: round(v[0] / psteps, 4) for k, v in stages.items() if v[1]},
@@ -239,24 +307,27 @@ def main():
         "device": {"name": torch.cuda.get_device_name(0),
                    "lds_per_block": getattr(torch.cuda.get_device_properties(0), "shared_memory_per_block", None)},
     }
+    # whole-product model bytes per step (the algorithmic bytes of every
+    # stage) over the step time, against the HBM peak
+    model = sum(stage_bytes(sz, R).values())
+    out["model_bytes_per_step"] = int(model)
+    out["model_GBs_frac"] = round(model / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
+    Krows = X = None
+    t_rows = 0.0
+    if not args.no_check:
+        chk, Krows, X, t_rows = exact_rows_check(ctx, s)
+        out["matvec_vs_oracle"] = chk
     if not args.no_sweep:
-        # plain preconditioner, all ports x frequencies batched (80 RHS)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         Y, it, rr, code = ctx.solve_ports(freqs, tol=1e-6, maxit=400, restart=60, precond=1)
         t_sweep = time.perf_counter() - t1
-        # plain preconditioner, one frequency (8 RHS) per call
-        t2 = time.perf_counter()
-        for f in freqs:
-            ctx.solve_ports([f], tol=1e-6, maxit=400, restart=60, precond=1)
-        t_perf = time.perf_counter() - t2
-        out["sweep"] = {"plain_s": round(t_sweep, 3), "plain_per_frequency_s": round(t_perf, 3),
-                        "status": int(code), "iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 2),
-                        "max_relres": float(rr.max()), "learned_s": None}
+        out["sweep"] = {"rhs": R, "plain_s": round(t_sweep, 3), "status": int(code), "iters_max": int(it.max()),
+                        "iters_mean": round(float(it.mean()), 2), "max_relres": float(rr.max()), "learned_s": None}
         if not args.no_learned:
-            # learned correction: pairs from plain solves at 8 frequencies
-            # between the bench frequencies, device training, then the sweep
-            f_train = 10.0 ** (6.2 + 3.6 * np.arange(8) / 7.0)
+            # learned correction: pairs from plain solves at frequencies between
+            # the sweep's, device training, then the same sweep
+            f_train = np.sqrt(freqs[:-1] * freqs[1:])[::2]
             t3 = time.perf_counter()
             rows = ctx.learned_collect(f_train, tol=1e-8, maxit=40)
             t_collect = time.perf_counter() - t3
@@ -274,8 +345,21 @@ def main():
                                  "learned_rhs_switched_to_plain": n_off, "learned_rhs_applications": n_apply,
                                  "learned_collect_s": round(t_collect, 2), "learned_train_s": round(t_train, 2),
                                  "learned_training_rows": int(rows)})
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_oracle_baseline(s)
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_second and args.workload == "traces":
+        # the bond-wire array, same step definition, as a second workload
+        s2, f2, g2 = wires_workload()
+        ctx2 = P.Context(s2, g2, stencil=4, near_kappa=1.5, grid_fp64=False)
+        R2 = len(s2.ports) * len(f2)
+        dt2, st2, ps2 = run_steps(ctx2, R2, np.repeat(2 * np.pi * f2, len(s2.ports)), 20, 3, P.PFFT_PRECOND)
+        out["second_workload"] = {"workload": WORKLOADS["wires"][1], "value": round(R2 * 20 / dt2, 2),
+                                  "unit": "RHS-matvecs/s", "ms_per_step": round(dt2 / 20 * 1e3, 3),
+                                  "stages_ms_per_step": {k: round(v[0] / ps2, 4) for k, v in st2.items() if v[1]}}
+        ctx2.close()
+    if not args.no_cpu_baseline and Krows is not None:
+        out["cpu_baseline"] = cpu_oracle_baseline(Krows, X, R, sz["b"], t_rows)
     print(json.dumps(out), flush=True)
 
 

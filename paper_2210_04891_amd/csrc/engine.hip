@@ -671,9 +671,13 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
   cm.cmax = 0;
   cm.comb_plan = c->plans.comb;
   cm.crc = 16;
-  for (int trial = 0; trial < 12 && cm.ctile == 0 && b > 0; ++trial) {
-    // 16 right-hand sides per workgroup with rows 32, 16, .. 1; then 8
-    const int rc = trial < 6 ? 16 : 8, tr = 32 >> (trial % 6);
+  // (right-hand sides, rows) per workgroup, in order of preference; every
+  // candidate has at least 128 threads (near fields with long rows, such as
+  // the package traces' 580 nonzeros a row, take 4 right-hand sides over 64
+  // or 32 rows; without a fit the gather kernel runs)
+  static const int cand[][2] = {{16, 32}, {16, 16}, {16, 8}, {8, 32}, {8, 16}, {4, 64}, {4, 32}};
+  for (int trial = 0; trial < 7 && cm.ctile == 0 && b > 0; ++trial) {
+    const int rc = cand[trial][0], tr = cand[trial][1];
     const int ucap = combine_tile_cap(rc);
     const int nt = (b + tr - 1) / tr;
     std::vector<int> ct_off(nt + 1, 0);
@@ -1140,6 +1144,16 @@ extern "C" pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *v
   if (!c || !name || !value) {
     set_error("pfft_get_option: bad argument");
     return PFFT_EINVAL;
+  }
+  // read-only: the near-field tile shape chosen at setup (0 when the gather
+  // kernel runs)
+  if (std::string(name) == "combine_tile_rows") {
+    *value = c->cm.ctile > 0 ? c->cm.ctr : 0;
+    return PFFT_OK;
+  }
+  if (std::string(name) == "combine_tile_rhs") {
+    *value = c->cm.ctile > 0 ? c->cm.crc : 0;
+    return PFFT_OK;
   }
   int *slot = option_slot(c, name);
   if (!slot) {

@@ -145,7 +145,7 @@ struct CombineMaps {
   // [T ctr, (T+1) ctr) read only the columns ct_col[ct_off[T] .. ct_off[T+1])
   // (ascending), nf_slot[q] is nf_col[q]'s position in its tile's list and
   // no list is longer than cmax.  ctile = 0: no tiles (gather only).
-  int ctr, ctile, cmax, crc;   // crc: right-hand sides per workgroup (8 or 16)
+  int ctr, ctile, cmax, crc;   // crc: right-hand sides per workgroup (4, 8 or 16)
   const int *ct_off, *ct_col;
   const uint16_t *nf_slot;
   int comb_plan;            // 0 tiled product when available, 1 gather

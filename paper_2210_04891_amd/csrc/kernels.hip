@@ -2160,6 +2160,11 @@ template <int K>
 __device__ __forceinline__ int row_bcast(int v) {
   return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xF, 0xF, false);
 }
+// lane K of each quad of lanes to the whole quad (DPP quad_perm [K,K,K,K])
+template <int K>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, K * 0x55, 0xF, 0xF, false);
+}
 // f(integral_constant<int, K>) for K = B .. E - 1
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -2284,6 +2289,63 @@ __global__ void __launch_bounds__(512) k_combine_tiled(CombineMaps c, const doub
     }
     kx += ax;
     ky += ay;
+  } else if ((mode & 2) && CRC == 4) {
+    // the 4 lanes of a row (a DPP quad) load 4 nonzeros at a time, one each,
+    // and broadcast them in turn (quad_perm); loads run eight batches ahead.
+    // Same summation order as above (nonzero j of the row to the partial
+    // sum of its parity, in order).
+    const int64_t q0 = c.nf_rowptr[e], q1 = e0 < c.b ? c.nf_rowptr[e + 1] : q0;
+    const int64_t qlast = max(c.nf_rowptr[c.b] - 1, (int64_t)0);
+    double ax = 0, ay = 0;
+    auto batch = [&](double vc, int sc) {
+      double2 xv[4];
+      static_for<0, 4>([&](auto KK) {
+        constexpr int K = decltype(KK)::value;
+        xv[K] = sA[quad_bcast<K>(sc) * CRC + rr];
+      });
+      const int vlo = __double2loint(vc), vhi = __double2hiint(vc);
+      static_for<0, 4>([&](auto KK) {
+        constexpr int K = decltype(KK)::value;
+        const double v = __hiloint2double(quad_bcast<K>(vhi), quad_bcast<K>(vlo));
+        if (K & 1) {
+          ax += v * xv[K].x;
+          ay += v * xv[K].y;
+        } else {
+          kx += v * xv[K].x;
+          ky += v * xv[K].y;
+        }
+      });
+    };
+    constexpr int NB = 8;
+    auto fetch = [&](int64_t q, double &v, int &sl) {
+      const int64_t qc = min(q, qlast);
+      const double vv = c.nf_val[qc];
+      const int ss = (int)c.nf_slot[qc];
+      v = q < q1 ? vv : 0.0;
+      sl = q < q1 ? ss : 0;
+    };
+    double vb[NB];
+    int sb[NB];
+    int64_t qb = q0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) fetch(qb + 4 * j + rr, vb[j], sb[j]);
+    while (__any(qb < q1)) {
+      double vn[NB];
+      int sn[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) fetch(qb + 4 * (NB + j) + rr, vn[j], sn[j]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (__any(qb + 4 * j < q1)) batch(vb[j], sb[j]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        vb[j] = vn[j];
+        sb[j] = sn[j];
+      }
+      qb += 4 * NB;
+    }
+    kx += ax;
+    ky += ay;
   } else if (mode & 2) {
     const int64_t q0 = c.nf_rowptr[e], q1 = e0 < c.b ? c.nf_rowptr[e + 1] : q0;
     int64_t q = q0;
@@ -2338,15 +2400,19 @@ void combine(const CombineMaps &c, const double2 *alpha, const double2 *U, const
              const double2 *jw, double2 *y, int R, int mode, hipStream_t st) {
   static const bool lds16 = allow_lds((const void *)k_combine_tiled<16>, CLDS);
   static const bool lds8 = allow_lds((const void *)k_combine_tiled<8>, CLDS);
+  static const bool lds4 = allow_lds((const void *)k_combine_tiled<4>, CLDS);
   // the choice does not depend on R, so a product gives the same result
   // however its right-hand sides are split
-  if (c.ctile > 0 && c.comb_plan == 0 && (mode & 2) && (c.crc == 16 ? lds16 : lds8)) {
+  const bool lds_ok = c.crc == 16 ? lds16 : c.crc == 8 ? lds8 : lds4;
+  if (c.ctile > 0 && c.comb_plan == 0 && (mode & 2) && lds_ok) {
     const unsigned nb = (unsigned)c.ctile * (unsigned)cdiv(R, c.crc);
     const size_t lds = (size_t)c.cmax * c.crc * sizeof(double2);
     if (c.crc == 16)
       k_combine_tiled<16><<<nb, c.ctr * 16, lds, st>>>(c, alpha, U, zs, jw, y, R, mode);
-    else
+    else if (c.crc == 8)
       k_combine_tiled<8><<<nb, c.ctr * 8, lds, st>>>(c, alpha, U, zs, jw, y, R, mode);
+    else
+      k_combine_tiled<4><<<nb, c.ctr * 4, lds, st>>>(c, alpha, U, zs, jw, y, R, mode);
   } else {
     k_combine<<<cdiv((long)c.b * R, 256), 256, 0, st>>>(c, alpha, U, zs, jw, y, R, mode);
   }

@@ -180,6 +180,40 @@ def test_tiled_near_field_product_16(nrhs):
 
 
 @gpu
+@pytest.mark.parametrize("nrhs", [8, 13])
+def test_tiled_near_field_product_4(c1, nrhs):
+    """Long near-field rows (the bar with kappa = 4: about 1,200 nonzeros a
+    row, like the package traces' 580): the tiles stage 4 right-hand sides
+    over 32 or 64 rows and share each row's nonzeros across a lane quad.
+    Tiled against gather (same summation order) in both spaces, with a
+    ragged last group, and the near field against the oracle's L_d."""
+    import paper_2210_04891_amd as P
+    from oracle import pfft as PF
+    ctx = P.Context(c1["s"], GRID, stencil=4, near_kappa=4.0, grid_fp64=True)
+    assert ctx.get_option("combine_tile_rhs") == 4
+    assert ctx.get_option("combine_tile_rows") in (32, 64)
+    b, l = ctx.sizes["b"], ctx.sizes["l"]
+    om = 2 * np.pi * np.geomspace(1e7, 3e10, nrhs)
+    for space, dim in ((0, b), (1, l)):
+        X = _dev(W.complex_normal(17 + space, (nrhs, dim)))
+        ctx.set_option("combine_plan", 0)
+        yt = ctx.matvec(X, omega=om, space=space).cpu().numpy()
+        ctx.set_option("combine_plan", 1)
+        yg = ctx.matvec(X, omega=om, space=space).cpu().numpy()
+        for r in range(nrhs):
+            assert _rel(yt[r], yg[r]) < 1e-13, (space, r)
+    ctx.set_option("combine_plan", 0)
+    X = W.complex_normal(19, (nrhs, b))
+    yn = ctx.matvec(_dev(X), space=0, flags=P.PFFT_NEAR_ONLY).cpu().numpy()
+    Ld = PF.precorrection(c1["mesh"], PF.Grid(c1["mesh"].V, GRID, 4), 4.0)
+    assert ctx.sizes["nnz_near"] == Ld.nnz
+    for r in (0, nrhs - 1):
+        ref = Ld @ X[r]
+        assert _rel(yn[r], ref) < 1e-6
+        assert np.abs(yn[r] - ref).max() < 1e-6 * np.abs(ref).max()
+
+
+@gpu
 def test_loop_transforms_alone(c1_oracle):
     """With the grid term only, compare A^T/A against the explicit loop
     matrix at FP64 rounding: y = A (j w/4pi K_far + Zs G) A^T x."""
