@@ -86,6 +86,7 @@ struct pfft_ctx {
     int factor = 0;   // 0 preconditioner factored on the device, 1 on the host
     int comb = 0;     // 0 LDS-tiled near-field product when the tiles fit, 1 gather
     int prune = 1;    // 1 register FFT passes skip grid columns and nodes no stencil touches
+    int near_dense = 1;  // 1 near field on FP64 matrix cores over dense row tiles (when built)
   } plans;
   pfft::StageTimer timer;
   // solver state

@@ -671,6 +671,49 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
   cm.cmax = 0;
   cm.comb_plan = c->plans.comb;
   cm.crc = 16;
+  // dense row tiles of 32 rows for the matrix-core product, built when the
+  // tiles are at least half full (near fields are geometric neighbourhoods,
+  // so consecutive rows share most columns)
+  cm.dn_tiles = 0;
+  cm.near_dense = c->plans.near_dense;
+  if (b > 0) {
+    const int nt = (b + 31) / 32;
+    std::vector<std::vector<int>> cols(nt);
+    std::vector<int> nu(nt);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int T = 0; T < nt; ++T) {
+      const int64_t q0 = m.nf_rowptr[(size_t)T * 32], q1 = m.nf_rowptr[std::min(b, (T + 1) * 32)];
+      std::vector<int> u(m.nf_col.begin() + q0, m.nf_col.begin() + q1);
+      std::sort(u.begin(), u.end());
+      u.erase(std::unique(u.begin(), u.end()), u.end());
+      nu[T] = (int)u.size();
+      const int pad = u.empty() ? 0 : u[0];
+      while (u.size() % 16 != 0 || u.empty()) u.push_back(pad);
+      cols[T] = std::move(u);
+    }
+    std::vector<int64_t> off(nt + 1, 0);
+    for (int T = 0; T < nt; ++T) off[T + 1] = off[T] + (int64_t)cols[T].size();
+    const double fill = (double)m.nf_rowptr[b] / (32.0 * (double)off[nt]);
+    if (fill >= 0.5) {
+      std::vector<int> dcol(off[nt]);
+      std::vector<double> dval(32 * (size_t)off[nt], 0.0);
+#pragma omp parallel for schedule(dynamic, 64)
+      for (int T = 0; T < nt; ++T) {
+        std::copy(cols[T].begin(), cols[T].end(), dcol.begin() + off[T]);
+        double *V = dval.data() + 32 * off[T];
+        for (int e = T * 32; e < std::min(b, (T + 1) * 32); ++e)
+          for (int64_t q = m.nf_rowptr[e]; q < m.nf_rowptr[e + 1]; ++q) {
+            const int k = (int)(std::lower_bound(cols[T].begin(), cols[T].begin() + nu[T], m.nf_col[q]) -
+                                cols[T].begin());
+            V[((size_t)(k / 4) * 32 + (e - T * 32)) * 4 + k % 4] = m.nf_val[q];
+          }
+      }
+      cm.dn_off = upload(c, off, st);
+      cm.dn_col = upload(c, dcol, st);
+      cm.dn_val = upload(c, dval, st);
+      cm.dn_tiles = nt;
+    }
+  }
   // (right-hand sides, rows) per workgroup, in order of preference; every
   // candidate has at least 128 threads (near fields with long rows, such as
   // the package traces' 580 nonzeros a row, take 4 right-hand sides over 64
@@ -1115,6 +1158,7 @@ int *option_slot(pfft_ctx *c, const std::string &name) {
   if (name == "factor_plan") return &c->plans.factor;
   if (name == "combine_plan") return &c->plans.comb;
   if (name == "fft_prune") return &c->plans.prune;
+  if (name == "near_dense") return &c->plans.near_dense;
   return nullptr;
 }
 void sync_plans(pfft_ctx *c) {
@@ -1122,6 +1166,7 @@ void sync_plans(pfft_ctx *c) {
   c->gm.proj_plan = c->plans.proj;
   c->gm.prune = c->plans.prune;
   c->cm.comb_plan = c->plans.comb;
+  c->cm.near_dense = c->plans.near_dense;
 }
 }  // namespace
 
@@ -1203,8 +1248,8 @@ extern "C" pfft_status pfft_autotune(pfft_ctx *c, int32_t nrhs, const double *om
       return (double)t[reps / 2];
     };
     std::string js = "{";
-    const char *names[5] = {"fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split"};
-    for (int o = 0; o < 5; ++o) {
+    const char *names[6] = {"fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split", "near_dense"};
+    for (int o = 0; o < 6; ++o) {
       int *slot = option_slot(c, names[o]);
       double best = 1e300;
       int arg = *slot;

@@ -149,12 +149,24 @@ struct CombineMaps {
   const int *ct_off, *ct_col;
   const uint16_t *nf_slot;
   int comb_plan;            // 0 tiled product when available, 1 gather
+  // Dense row tiles of the near-field matrix for the FP64 matrix-core
+  // product: tile T covers rows [32 T, 32 T + 32) and the columns
+  // dn_col[dn_off[T] .. dn_off[T+1]) (ascending, padded with zero values to
+  // a multiple of 4); its values are dn_val[32 dn_off[T] ..] in k-major
+  // quads: entry (row, k) at 32 dn_off[T] + ((k / 4) 32 + row) 4 + k % 4.
+  // dn_tiles = 0: not built (tiles too sparse).  near_dense 1: use them.
+  int dn_tiles, near_dense;
+  const int64_t *dn_off;
+  const int *dn_col;
+  const double *dn_val;
 };
 
 // y[e][r] = zs[r] * (G a)[e] + jw[r] * (far[e] + (L_d a)[e]); far from U;
 // alpha, y RHS-contiguous [b][R], U [n][R][4].
 // mode bits: 1 far, 2 near, 4 gram (zs, jw ignored when gram bit is clear
-// and kscale = 1: y = far + near).
+// and kscale = 1: y = far + near).  With dense near-field tiles (dn_tiles >
+// 0, near_dense 1) the near part is a matrix-core product written to y
+// first and read back by the combining kernel.
 void combine(const CombineMaps &c, const double2 *alpha, const double2 *U, const double2 *zs,
              const double2 *jw, double2 *y, int R, int mode, hipStream_t st);
 // Longest column list of a near-field row tile that the tiled product can

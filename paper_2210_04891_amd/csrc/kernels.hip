@@ -2092,7 +2092,12 @@ __global__ void k_combine(CombineMaps c, const double2 *alpha, const double2 *U,
       ky += s * vy;
     }
   }
-  if (mode & 2) {
+  if (mode & 8) {
+    // near part already in y (dense-tile product)
+    const double2 v = y[idx];
+    kx += v.x;
+    ky += v.y;
+  } else if (mode & 2) {
     // four nonzeros per step: their column and value loads, then the four
     // gathers, are independent (more loads in flight).  Summation order, the
     // same in every near-field kernel: nonzero j of the row goes to the even
@@ -2396,6 +2401,68 @@ __global__ void __launch_bounds__(512) k_combine_tiled(CombineMaps c, const doub
   if (live) y[(size_t)e * R + r] = out;
 }
 
+// Near-field product on FP64 matrix cores over dense row tiles: y_near =
+// L_T a for each tile T (32 rows x its column list), with the right-hand
+// sides as 2R real columns (re, im interleaved, which is alpha's memory
+// layout).  One workgroup per (tile, 64 right-hand sides): wave w computes
+// the 32 rows x real columns [32 w, 32 w + 32) of its chunk as 2 x 2 blocks
+// of v_mfma_f64_16x16x4 (lane l holds A: row l % 16, k l / 16; B: k l / 16,
+// column l % 16; D register i: row l / 16 + 4 i, column l % 16), k in
+// steps of 4 over the tile's columns.  A comes from the tile's values (shared by the tile's
+// workgroups through the caches), B from alpha's rows of the tile's columns.
+// Real columns past 2R read a clamped address and are not stored.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int DN_RHS = 64;   // right-hand sides per workgroup
+
+__global__ void __launch_bounds__(256) k_near_dense(CombineMaps c, const double *alpha, double *y, int R) {
+  const int nch = (R + DN_RHS - 1) / DN_RHS;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int T = lb / nch, r0 = (lb - T * nch) * DN_RHS;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ka = lane >> 4, ra = lane & 15;
+  const int64_t k0 = c.dn_off[T], nk = c.dn_off[T + 1] - k0;   // a multiple of 16
+  const double *A = c.dn_val + 32 * k0 + ra * 4 + ka;
+  const int *cols = c.dn_col + k0 + ka;
+  const long R2 = 2L * R;
+  const long n0 = 2L * r0 + 32 * w + ra, n1 = n0 + 16;
+  const long m0 = min(n0, R2 - 1), m1 = min(n1, R2 - 1);
+  dbl4 acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
+  for (int64_t kq = 0; kq < nk; kq += 16) {
+    // four k-steps: all loads first, then the sixteen products
+    long col[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) col[s] = cols[kq + 4 * s];
+    double a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      a0[s] = A[(kq + 4 * s) * 32];
+      a1[s] = A[(kq + 4 * s) * 32 + 64];
+      b0[s] = alpha[col[s] * R2 + m0];
+      b1[s] = alpha[col[s] * R2 + m1];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b1[s], acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b0[s], acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], acc11, 0, 0, 0);
+    }
+  }
+  const int e0 = 32 * T + ka;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = e0 + 4 * i, f = e0 + 16 + 4 * i;
+    if (e < c.b) {
+      if (n0 < R2) y[(long)e * R2 + n0] = acc00[i];
+      if (n1 < R2) y[(long)e * R2 + n1] = acc01[i];
+    }
+    if (f < c.b) {
+      if (n0 < R2) y[(long)f * R2 + n0] = acc10[i];
+      if (n1 < R2) y[(long)f * R2 + n1] = acc11[i];
+    }
+  }
+}
+
 void combine(const CombineMaps &c, const double2 *alpha, const double2 *U, const double2 *zs,
              const double2 *jw, double2 *y, int R, int mode, hipStream_t st) {
   static const bool lds16 = allow_lds((const void *)k_combine_tiled<16>, CLDS);
@@ -2404,6 +2471,13 @@ void combine(const CombineMaps &c, const double2 *alpha, const double2 *U, const
   // the choice does not depend on R, so a product gives the same result
   // however its right-hand sides are split
   const bool lds_ok = c.crc == 16 ? lds16 : c.crc == 8 ? lds8 : lds4;
+  if ((mode & 2) && c.dn_tiles > 0 && c.near_dense) {
+    // near part on the matrix cores into y, then far, Gram and coefficients
+    const unsigned nb = (unsigned)c.dn_tiles * (unsigned)cdiv(R, DN_RHS);
+    k_near_dense<<<nb, 256, 0, st>>>(c, (const double *)alpha, (double *)y, R);
+    k_combine<<<cdiv((long)c.b * R, 256), 256, 0, st>>>(c, alpha, U, zs, jw, y, R, (mode & ~2) | 8);
+    return;
+  }
   if (c.ctile > 0 && c.comb_plan == 0 && (mode & 2) && lds_ok) {
     const unsigned nb = (unsigned)c.ctile * (unsigned)cdiv(R, c.crc);
     const size_t lds = (size_t)c.cmax * c.crc * sizeof(double2);

@@ -66,13 +66,13 @@ def test_plans_agree_and_autotune(wires):
     om = 2 * np.pi * np.repeat(np.array([1e9, 1e10]), 10)
     x = torch.from_numpy(W.complex_normal(31, (om.size, l))).cuda()
     ref = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
-    for name in ("fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split"):
+    for name in ("fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split", "near_dense"):
         ctx.set_option(name, 1 - ctx.get_option(name))
         y = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
         ctx.set_option(name, 1 - ctx.get_option(name))
         assert np.linalg.norm(y - ref) <= 2e-6 * np.linalg.norm(ref), name
     rep = ctx.autotune(om, reps=2)
-    for name in ("fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split"):
+    for name in ("fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split", "near_dense"):
         assert rep[name]["chosen"] in (0, 1)
         assert ctx.get_option(name) == rep[name]["chosen"]
         assert rep[name]["0"] > 0 and rep[name]["1"] > 0

@@ -142,6 +142,7 @@ def test_tiled_near_field_product(c1_oracle):
     quadrature agreement.  The bar's tiles stage 8 right-hand sides per
     workgroup (here 8 + 8 + 4)."""
     ctx = _ctx(c1_oracle["s"])
+    ctx.set_option("near_dense", 0)
     c = c1_oracle["circ"]
     om = 2 * np.pi * np.geomspace(1e7, 3e10, 20)
     X = W.complex_normal(9, (20, c.nloop))
@@ -167,6 +168,7 @@ def test_tiled_near_field_product_16(nrhs):
     import paper_2210_04891_amd as P
     s = W.bond_wires(nwire=2, nseg=24, span=0.4e-3, height=80e-6)
     ctx = P.Context(s, (32, 32, 16), stencil=4, near_kappa=1.5, grid_fp64=True)
+    ctx.set_option("near_dense", 0)
     b, l = ctx.sizes["b"], ctx.sizes["l"]
     om = 2 * np.pi * np.geomspace(1e7, 3e10, nrhs)
     for space, dim in ((0, b), (1, l)):
@@ -190,6 +192,7 @@ def test_tiled_near_field_product_4(c1, nrhs):
     import paper_2210_04891_amd as P
     from oracle import pfft as PF
     ctx = P.Context(c1["s"], GRID, stencil=4, near_kappa=4.0, grid_fp64=True)
+    ctx.set_option("near_dense", 0)
     assert ctx.get_option("combine_tile_rhs") == 4
     assert ctx.get_option("combine_tile_rows") in (32, 64)
     b, l = ctx.sizes["b"], ctx.sizes["l"]
@@ -211,6 +214,47 @@ def test_tiled_near_field_product_4(c1, nrhs):
         ref = Ld @ X[r]
         assert _rel(yn[r], ref) < 1e-6
         assert np.abs(yn[r] - ref).max() < 1e-6 * np.abs(ref).max()
+
+
+@gpu
+@pytest.mark.parametrize("case", ["bar_kappa1.5", "bar_kappa4", "wires"])
+@pytest.mark.parametrize("nrhs", [5, 64, 70])
+def test_dense_near_field_matches_csr(c1, case, nrhs):
+    """The near field on FP64 matrix cores over dense 32-row tiles (default
+    where the tiles are at least half full) against the CSR gather product:
+    the same products summed in another order, so equal to FP64 rounding;
+    ragged tiles (rows past b) and ragged right-hand-side chunks (5, 70) in
+    both spaces, and the near-only branch product against the oracle."""
+    import paper_2210_04891_amd as P
+    from oracle import pfft as PF
+    if case == "wires":
+        s = W.bond_wires(nwire=2, nseg=24, span=0.4e-3, height=80e-6)
+        grid, kappa, m = (32, 32, 16), 1.5, None
+    else:
+        s, grid, kappa, m = c1["s"], GRID, float(case.split("kappa")[1]), c1["mesh"]
+    ctx = P.Context(s, grid, stencil=4, near_kappa=kappa, grid_fp64=True)
+    assert ctx.get_option("near_dense") == 1
+    b, l = ctx.sizes["b"], ctx.sizes["l"]
+    om = 2 * np.pi * np.geomspace(1e7, 3e10, nrhs)
+    for space, dim in ((0, b), (1, l)):
+        X = _dev(W.complex_normal(23 + space, (nrhs, dim)))
+        ctx.set_option("near_dense", 1)
+        yd = ctx.matvec(X, omega=om, space=space).cpu().numpy()
+        ctx.set_option("near_dense", 0)
+        ctx.set_option("combine_plan", 1)
+        yg = ctx.matvec(X, omega=om, space=space).cpu().numpy()
+        ctx.set_option("combine_plan", 0)
+        for r in range(nrhs):
+            assert _rel(yd[r], yg[r]) < 1e-12, (space, r)
+    if m is not None:
+        ctx.set_option("near_dense", 1)
+        X = W.complex_normal(29, (nrhs, b))
+        yn = ctx.matvec(_dev(X), space=0, flags=P.PFFT_NEAR_ONLY).cpu().numpy()
+        Ld = PF.precorrection(m, PF.Grid(m.V, grid, 4), kappa)
+        for r in (0, nrhs - 1):
+            ref = Ld @ X[r]
+            assert _rel(yn[r], ref) < 1e-6
+            assert np.abs(yn[r] - ref).max() < 1e-6 * np.abs(ref).max()
 
 
 @gpu
