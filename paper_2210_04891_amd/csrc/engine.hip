@@ -523,21 +523,23 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
     // masks of the pruned FFT passes
     const int Nx = m.dims[0], Ny = m.dims[1], Nz = m.dims[2];
     const long C = (long)Ny * Nz;
-    if (Nx % 32 == 0 && C % 32 == 0 && Ny <= 64) {
+    if (Nx % 32 == 0 && C % 32 == 0) {
       const int wpc = Nx / 32;
-      std::vector<uint32_t> xm((size_t)C * wpc, 0u);
+      std::vector<uint32_t> xm((size_t)C * wpc, 0u), ca((size_t)(C / 32), 0u);
       std::vector<uint64_t> zm(Nz, 0u);
       std::vector<uint8_t> cg((size_t)(C / 32), 0);
       for (int node : act) {
         const int z = node % Nz, y = (node / Nz) % Ny, x = node / (Nz * Ny);
         const long col = (long)y * Nz + z;
         xm[(size_t)col * wpc + x / 32] |= 1u << (x % 32);
-        zm[z] |= 1ull << y;
+        if (Ny <= 64) zm[z] |= 1ull << y;
         cg[col / 32] = 1;
+        ca[col / 32] |= 1u << (col % 32);
       }
       g.xmask = upload(c, xm, st);
-      g.zmask = upload(c, zm, st);
+      g.zmask = Ny <= 64 ? upload(c, zm, st) : nullptr;
       g.cgrp = upload(c, cg, st);
+      g.colact = upload(c, ca, st);
     }
     g.prune = c->plans.prune;
     if (!c->grid_fp64 && (Nx == 32 || Nx == 64 || Nx == 128 || Nx == 256)) {

@@ -92,11 +92,13 @@ struct GridMaps {
   // plane kernel reads only the columns that hold an active node.
   // xmask[c (Nx / 32) + w] bit b: node (x = 32 w + b, column c = y Nz + z)
   // active; cgrp[k]: columns [32 k, 32 k + 32) hold an active node;
-  // zmask[z] bit y: column (y, z) holds one (Ny <= 64).  Null where the grid
-  // shape does not allow it.
+  // zmask[z] bit y: column (y, z) holds one (Ny <= 64); colact[c / 32] bit
+  // c % 32: column c holds one (any Ny).  Null where the grid shape does not
+  // allow it.
   const uint32_t *xmask;
   const uint64_t *zmask;
   const uint8_t *cgrp;
+  const uint32_t *colact;
   int prune;
   // twiddles of the register X passes (FP32 grid), k2 the 2-bit reversal of
   // q, m < Nx / 4: forward xtw[4 h + q][m] = (-1)^q W_{2Nx}^{(2 k2 + h) m};

@@ -1356,8 +1356,9 @@ struct BigPlane {
 
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
-template <int NY, int NZ>
-__global__ void __launch_bounds__(2 * BIG_T) k_fft_yz_big(YZArgs a, float2 *data, const float *ghat, long ch) {
+template <int NY, int NZ, bool PR>
+__global__ void __launch_bounds__(2 * BIG_T) k_fft_yz_big(YZArgs a, float2 *data, const float *ghat, long ch,
+                                                          const uint32_t *colact) {
   using L = BigPlane<NY, NZ>;
   constexpr int N2 = L::N2, KS = L::KS, LY = 2 * NY, LZ = 2 * NZ;
   constexpr int B2 = clog2(N2), BZ = clog2(NZ);
@@ -1376,8 +1377,20 @@ __global__ void __launch_bounds__(2 * BIG_T) k_fft_yz_big(YZArgs a, float2 *data
   const float *gpl = ghat + (long)fx * (NY + 1) * (NZ + 1);
   const int za = t % NZ, j2 = t / NZ;     // column and y = j2 + N2 j1 (stages A, C); k1 = j2 + N2 i (N2 stage)
   float2 v[32];
+  if (PR) {
+    // pruned: a column without an active node enters as zero (whatever the
+    // buffer holds there); the load's offset then lies beyond the plane
+    const __amdgpu_buffer_rsrc_t rio = buf_rsrc(io, (unsigned)(NY * NZ * 8));
 #pragma unroll
-  for (int j1 = 0; j1 < 32; ++j1) v[j1] = io[(j2 + N2 * j1) * NZ + za];
+    for (int j1 = 0; j1 < 32; ++j1) {
+      const int cidx = (j2 + N2 * j1) * NZ + za;
+      const unsigned on = (colact[cidx >> 5] >> (cidx & 31)) & 1u;
+      v[j1] = buf_load2(rio, on ? (unsigned)cidx * 8u : X_DROP, 0);
+    }
+  } else {
+#pragma unroll
+    for (int j1 = 0; j1 < 32; ++j1) v[j1] = io[(j2 + N2 * j1) * NZ + za];
+  }
   __syncthreads();                                      // twiddle tables
   if (ey) {
     const float2 wl = twh[j2];
@@ -1650,8 +1663,11 @@ static bool big_plane_lds() {
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) q = 0;
     const int need = (int)BigPlane<NY, NZ>::LDS;
-    ok = need <= q && hipFuncSetAttribute((const void *)k_fft_yz_big<NY, NZ>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, need) == hipSuccess;
+    ok = need <= q &&
+         hipFuncSetAttribute((const void *)k_fft_yz_big<NY, NZ, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             need) == hipSuccess &&
+         hipFuncSetAttribute((const void *)k_fft_yz_big<NY, NZ, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             need) == hipSuccess;
     if (!ok) (void)hipGetLastError();
   }
   return ok == 1;
@@ -1663,12 +1679,21 @@ static bool big_plane_ok(const GridMaps &g, int Ny, int Nz) {
   if (Ny == 512 && Nz == 16) return big_plane_lds<512, 16>();
   return false;
 }
-static void launch_yz_big(float2 *data, const float *ghat, const YZArgs &y, long ch, hipStream_t st) {
+// colact non-null: pruned (columns without an active node read as zero)
+static void launch_yz_big(float2 *data, const float *ghat, const YZArgs &y, long ch, const uint32_t *colact,
+                          hipStream_t st) {
   const unsigned nb = (unsigned)(ch * y.two_nx);
-  if (y.ny == 256)
-    k_fft_yz_big<256, 32><<<nb, 2 * BIG_T, BigPlane<256, 32>::LDS, st>>>(y, data, ghat, ch);
-  else
-    k_fft_yz_big<512, 16><<<nb, 2 * BIG_T, BigPlane<512, 16>::LDS, st>>>(y, data, ghat, ch);
+  if (y.ny == 256) {
+    if (colact)
+      k_fft_yz_big<256, 32, true><<<nb, 2 * BIG_T, BigPlane<256, 32>::LDS, st>>>(y, data, ghat, ch, colact);
+    else
+      k_fft_yz_big<256, 32, false><<<nb, 2 * BIG_T, BigPlane<256, 32>::LDS, st>>>(y, data, ghat, ch, nullptr);
+  } else {
+    if (colact)
+      k_fft_yz_big<512, 16, true><<<nb, 2 * BIG_T, BigPlane<512, 16>::LDS, st>>>(y, data, ghat, ch, colact);
+    else
+      k_fft_yz_big<512, 16, false><<<nb, 2 * BIG_T, BigPlane<512, 16>::LDS, st>>>(y, data, ghat, ch, nullptr);
+  }
 }
 
 // Register X passes: FP32, N_x in {32, 64, 128, 256}, N_y N_z a multiple of
@@ -1730,7 +1755,8 @@ static void launch_x_reg(const float2 *in, float2 *out, int Nx, long C, long ch,
 template <typename T>
 static bool prune_ok(const GridMaps &g, long ch) {
   const int Nx = g.dims[0], Ny = g.dims[1], Nz = g.dims[2];
-  return g.prune && g.xmask && reg_x_ok<T>(g, Nx, (long)Ny * Nz, ch) && reg_plane_ok<T>(g, Ny, Nz);
+  if (!(g.prune && g.xmask && reg_x_ok<T>(g, Nx, (long)Ny * Nz, ch))) return false;
+  return (reg_plane_ok<T>(g, Ny, Nz) && g.zmask) || (big_plane_ok<T>(g, Ny, Nz) && g.colact);
 }
 
 template <typename T>
@@ -1775,7 +1801,7 @@ void convolve(const GridMaps &g, V2<T> *Q, V2<T> *T1, V2<T> *T2, int R, hipStrea
     y.nx = Nx;
     y.two_nx = 2 * Nx;
     y.scale = 1.0f / (4.0f * Ny * Nz);
-    launch_yz_big((float2 *)T1, (const float *)g.ghat, y, ch, st);
+    launch_yz_big((float2 *)T1, (const float *)g.ghat, y, ch, pr ? g.colact : nullptr, st);
     if (hook) hook->pass(4, st);
     if (xreg)
       launch_x_reg((const float2 *)T1, (float2 *)Q, Nx, (long)Ny * Nz, ch, +1, g.xtw, xm, cg, st);

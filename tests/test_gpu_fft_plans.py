@@ -47,6 +47,11 @@ def test_plane_plans_match_oracle(case):
     ctx = P.Context(s, grid, near_kappa=1.5, grid_fp64=False)
     X = W.complex_normal(21, (nrhs, m.nedge))
     y_reg = _far(ctx, X, "register")
+    ctx.set_option("fft_prune", 0)
+    y_dense = _far(ctx, X, "register")
+    ctx.set_option("fft_prune", 1)
+    # the pruned passes skip only zeros: same bits
+    assert np.array_equal(y_reg, y_dense)
     y_lds = _far(ctx, X, "lds")
     for r in range(nrhs):
         ref = op.far(X[r])
