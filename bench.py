@@ -272,6 +272,7 @@ def main():
     ctx = P.Context(s, grid, stencil=4, near_kappa=1.5, grid_fp64=False)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
+    print("bench: setup %.1f s" % t_setup, file=sys.stderr, flush=True)
     sz = ctx.sizes
     omega = np.repeat(2 * np.pi * freqs, p)
     if args.copy_probe_mb > 0:
@@ -283,6 +284,7 @@ def main():
         del a, b
     dt, stages, psteps = run_steps(ctx, R, omega, args.steps, args.warmup, P.PFFT_PRECOND)
     value = R * args.steps / dt
+    print("bench: %d steps, %.1f ms/step" % (args.steps, dt / args.steps * 1e3), file=sys.stderr, flush=True)
     roof = roofline(stages, sz, R, grid)
     table = {"traces": "package_traces512_traffic", "wires": "bond_wires80_traffic"}[args.workload]
     roof["traffic"] = measured_traffic(roof["stage"], table)

@@ -7,8 +7,11 @@ The oracle cannot form the 23.6 M-entry pre-correction at this size in a test,
 but it computes any row of it: for 64 sampled edges, the exact-minus-grid
 blocks of every near pair of their two triangles (Eq. Lb), summed into those
 rows.  The GPU's near-field product must match those rows to the quadrature
-agreement of the two sides (1e-6 relative per row).  The far-field product at
-this size is compared with the oracle in the FFT-plan tests.
+agreement of the two sides (1e-6 relative per row).  The same launch shape is
+also checked against exact dense-kernel rows (the pFFT accuracy target,
+1e-3), in the loop space on the loops with the fewest branches, and the far
+field at 80 right-hand sides (channel-split X launches) against the oracle's
+explicit grid product.
 """
 import numpy as np
 import pytest
@@ -97,3 +100,75 @@ def test_bench_sweep_reciprocity_and_passivity(bench_ctx):
         assert np.abs(Z - Z.T).max() <= 1e-4 * np.abs(Z).max(), k
         assert np.all(np.linalg.eigvalsh(0.5 * (R[k] + R[k].T)) > 0), k
         assert np.all(np.linalg.eigvalsh(0.5 * (L[k] + L[k].T)) > 0), k
+
+
+@gpu
+def test_bench_product_matches_exact_kernel_rows(bench_ctx):
+    """The whole branch-space product K alpha in the bench's launch shape (80
+    right-hand sides, FP32 grid with pruned passes, matrix-core near field)
+    against exact dense-kernel rows of the oracle at 64 sampled edges: each
+    right-hand side's sampled entries within 1e-3 (2-norm) and every entry
+    within 1e-3 of the largest."""
+    from oracle.mesh import RWGMesh
+    from oracle import integrals as I
+    s, ctx, freqs = bench_ctx
+    m = RWGMesh(s.V, s.T)
+    rows = np.sort(np.random.default_rng(3).choice(m.nedge, 64, replace=False))
+    Krows = I.kernel_rows(m, rows)
+    X = W.complex_normal(7, (80, m.nedge))
+    y = ctx.matvec(torch.from_numpy(X).cuda(), space=0).cpu().numpy()[:, rows]
+    ref = X @ Krows.T
+    for r in range(80):
+        assert np.linalg.norm(y[r] - ref[r]) <= 1e-3 * np.linalg.norm(ref[r]), r
+    assert np.abs(y - ref).max() <= 1e-3 * np.abs(ref).max()
+
+
+@gpu
+def test_bench_far_field_80_rhs_matches_oracle(bench_ctx):
+    """The grid term alone at 80 right-hand sides (the X launches are split by
+    channel to stay below 2^31 bytes) against the oracle's explicit
+    B^T (H * (B alpha)) on four of them, 2-norm and entry by entry."""
+    import paper_2210_04891_amd as P
+    from oracle.mesh import RWGMesh
+    from oracle import pfft as PF
+    s, ctx, freqs = bench_ctx
+    m = RWGMesh(s.V, s.T)
+    op = PF.PFFTOperator(m, (256, 64, 32), 4, 1.5, with_near=False)
+    X = W.complex_normal(9, (80, m.nedge))
+    y = ctx.matvec(torch.from_numpy(X).cuda(), space=0, flags=P.PFFT_FAR_ONLY).cpu().numpy()
+    for r in (0, 27, 53, 79):
+        ref = op.far(X[r])
+        assert np.linalg.norm(y[r] - ref) <= 5e-6 * np.linalg.norm(ref), r
+        assert np.abs(y[r] - ref).max() <= 5e-5 * np.abs(ref).max(), r
+
+
+@gpu
+def test_bench_loop_product_on_short_loops(bench_ctx):
+    """The loop-space product Z_l x (Eq. FinalME) at the bench's 80
+    right-hand sides (8 ports x 10 frequencies) on the 24 loops with the
+    fewest branches, against the oracle: y_l[j] = sum_b A[j, b] (Z_s G +
+    j w mu / 4 pi K)[b, :] A^T x with exact kernel rows of every branch of
+    those loops and the oracle's own loop matrix and Gram matrix (1e-3, the
+    pFFT target, per right-hand side)."""
+    from oracle.mesh import RWGMesh, gram_matrix
+    from oracle.circuit import Circuit
+    from oracle import integrals as I, solve as S
+    s, ctx, freqs = bench_ctx
+    m = RWGMesh(s.V, s.T)
+    c = Circuit(m, s.ports)
+    A = c.loop_matrix().tocsr()
+    size = np.diff(A.indptr)
+    loops = np.sort(np.argsort(size, kind="stable")[:24])
+    br = np.unique(A[loops].indices)
+    br = br[br < m.nedge]                       # source branches carry no impedance
+    Krows = I.kernel_rows(m, br)
+    G = gram_matrix(m, weight=S.triangle_impedance(m, c, 1.0).real).tocsr()[br]
+    om = 2 * np.pi * np.repeat(freqs, ctx.nport)
+    X = W.complex_normal(15, (om.size, c.nloop))
+    y = ctx.matvec(torch.from_numpy(X).cuda(), omega=om, space=1).cpu().numpy()[:, loops]
+    Asub = A[loops][:, br].toarray()
+    for r in range(om.size):
+        alpha = (A.T @ X[r])[:m.nedge]
+        zb = S.surface_impedance(om[r], 5.8e7) * (G @ alpha) + 1j * om[r] * S.MU0 / (4 * np.pi) * (Krows @ alpha)
+        ref = Asub @ zb
+        assert np.linalg.norm(y[r] - ref) <= 1e-3 * np.linalg.norm(ref), r

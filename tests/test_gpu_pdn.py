@@ -89,3 +89,25 @@ def test_mid_pdn_solve_reciprocity_and_passivity(mid):
     assert np.abs(Z - Z.T).max() <= 1e-4 * np.abs(Z).max()
     assert np.all(np.linalg.eigvalsh(0.5 * (R[0] + R[0].T)) > 0)
     assert np.all(np.linalg.eigvalsh(0.5 * (L[0] + L[0].T)) > 0)
+
+
+@gpu
+@pytest.mark.parametrize("grid", [(512, 128, 16), (512, 512, 16)])
+def test_mid_pdn_far_field_pdn_grid_shapes(grid):
+    """The PDN grid's shapes on the mid-size instance: 512-point X lines (the
+    full PDN's N_x; zero-padded 1024-point transforms) and the 512 x 16
+    plane of the big-plane kernel, against the oracle's explicit grid
+    product (2-norm and entry by entry)."""
+    import paper_2210_04891_amd as P
+    from oracle.mesh import RWGMesh
+    from oracle import pfft as PF
+    s = _mid()
+    m = RWGMesh(s.V, s.T)
+    ctx = P.Context(s, grid, stencil=4, near_kappa=1.5, grid_fp64=False)
+    op = PF.PFFTOperator(m, grid, 4, 1.5, with_near=False)
+    X = W.complex_normal(43, (2, m.nedge))
+    y = ctx.matvec(torch.from_numpy(X).cuda(), space=0, flags=P.PFFT_FAR_ONLY).cpu().numpy()
+    for r in range(2):
+        ref = op.far(X[r])
+        assert np.linalg.norm(y[r] - ref) <= 1e-5 * np.linalg.norm(ref)
+        assert np.abs(y[r] - ref).max() <= 1e-4 * np.abs(ref).max()
