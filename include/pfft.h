@@ -337,8 +337,13 @@ pfft_status pfft_stage_times(pfft_ctx *c, double ms[16], int64_t calls[16]);
  * "node_of_tri", "parent", "parent_branch", "pre", "sub", "anchor" (int32),
  * "M0" [n][64], "M1" [n][64][3], "gram_val" [b][5], "near_val", "kdiag",
  * "grid" (double[9]: N, h, x0), "gram_col" [b][5], "near_col" (int32),
- * "near_rowptr" (int64[b+1]).  pfft_host_get writes *len_bytes always and
- * copies when dst is non-null and cap_bytes is large enough. */
+ * "near_rowptr" (int64[b+1]); the preconditioner's structure (built on
+ * the host, Sec. IV-A): "precond_info" / "precond_info_nd" (int64[7]: nu, W,
+ * Wc, nested dissection used, supernodes, largest front, levels; automatic
+ * ordering / nested dissection forced) and "nd_check_1GHz" (double: relative
+ * residual of a host supernodal solve of the nodal system at 1 GHz).
+ * pfft_host_get writes *len_bytes always and copies when dst is non-null and
+ * cap_bytes is large enough. */
 typedef struct pfft_host_model pfft_host_model;
 pfft_status pfft_host_setup(const pfft_problem *pb, pfft_host_model **out);
 pfft_status pfft_host_get(const pfft_host_model *h, const char *name, void *dst, int64_t cap_bytes,

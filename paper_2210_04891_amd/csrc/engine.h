@@ -87,6 +87,7 @@ struct pfft_ctx {
     int comb = 0;     // 0 LDS-tiled near-field product when the tiles fit, 1 gather
     int prune = 1;    // 1 register FFT passes skip grid columns and nodes no stencil touches
     int near_dense = 1;  // 1 near field on FP64 matrix cores over dense row tiles (when built)
+    int nd = 0;       // preconditioner ordering: 0 nested dissection for wide bands only, 1 always
   } plans;
   pfft::StageTimer timer;
   // solver state
@@ -136,6 +137,9 @@ void pfft_ctx::run_split(int R, hipStream_t st, Fn &&fn) {
   }
 }
 
+// 1 / 0 when the context's preconditioner uses nested dissection or the
+// band, -1 before it is built (defined with the solver)
+int precond_uses_nd(const pfft_ctx *c);
 // P^-1 (Z_l x) or P^-1 x in loop space (defined with the solver)
 pfft_status pfft_internal_precond_matvec(pfft_ctx *c, int R, const double *omega, int flags,
                                          const double2 *x, double2 *y, hipStream_t st);

@@ -1161,6 +1161,7 @@ int *option_slot(pfft_ctx *c, const std::string &name) {
   if (name == "combine_plan") return &c->plans.comb;
   if (name == "fft_prune") return &c->plans.prune;
   if (name == "near_dense") return &c->plans.near_dense;
+  if (name == "nd_plan") return &c->plans.nd;
   return nullptr;
 }
 void sync_plans(pfft_ctx *c) {
@@ -1200,6 +1201,12 @@ extern "C" pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *v
   }
   if (std::string(name) == "combine_tile_rhs") {
     *value = c->cm.ctile > 0 ? c->cm.crc : 0;
+    return PFFT_OK;
+  }
+  // read-only: whether the preconditioner built so far uses nested
+  // dissection (-1 before the first preconditioned product or solve)
+  if (std::string(name) == "precond_nd") {
+    *value = precond_uses_nd(c);
     return PFFT_OK;
   }
   int *slot = option_slot(c, name);

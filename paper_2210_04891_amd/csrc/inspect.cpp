@@ -1,4 +1,5 @@
 // Host-only inspection of the setup model (no device work).
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -63,6 +64,7 @@ pfft_status pfft_host_get(const pfft_host_model *h, const char *name, void *dst,
   const HostModel &m = h->m;
   std::string k(name);
   int64_t n = -1;
+  try {
   if (k == "links") n = put(m.links, dst, cap_bytes);
   else if (k == "port_loop") n = put(m.port_loop, dst, cap_bytes);
   else if (k == "tplus") n = put(m.tplus, dst, cap_bytes);
@@ -85,11 +87,20 @@ pfft_status pfft_host_get(const pfft_host_model *h, const char *name, void *dst,
     std::vector<double> g = {(double)m.dims[0], (double)m.dims[1], (double)m.dims[2], m.h[0], m.h[1], m.h[2],
                              m.x0[0], m.x0[1], m.x0[2]};
     n = put(g, dst, cap_bytes);
+  } else if (k == "precond_info" || k == "precond_info_nd") {
+    n = put(precond_info(m, k == "precond_info_nd" ? 1 : 0), dst, cap_bytes);
+  } else if (k == "nd_check_1GHz") {
+    std::vector<double> v = {nd_solve_check(m, 2 * M_PI * 1e9)};
+    n = put(v, dst, cap_bytes);
   } else if (k == "sizes") {
     std::vector<int64_t> sz = {m.n, m.nn, m.b, m.l, m.s, m.p,
                                m.nf_rowptr.empty() ? 0 : m.nf_rowptr.back(),
                                (int64_t)m.dims[0] * m.dims[1] * m.dims[2], m.npairs, 0};
     n = put(sz, dst, cap_bytes);
+  }
+  } catch (const SetupError &e) {
+    set_error("pfft_host_get: " + e.msg);
+    return (pfft_status)e.code;
   }
   if (n < 0) {
     set_error("pfft_host_get: unknown array " + k);

@@ -71,6 +71,15 @@ void build_model(HostModel &m, const double *V, int nv, const int *T, int n, int
                  const int *src_off, const int *src_tri, const int *snk_off,
                  const int *snk_tri, const SetupOptions &opt);
 
+// Host checks of the preconditioner's ordering and factorization (no
+// device work): structure sizes [nu, W, Wc, nd, supernodes, largest front,
+// levels] for nd_mode (0 automatic, 1 nested dissection), and the relative
+// residual |L_w x - b| / |b| of a supernodal solve (host mirror of the
+// device sweeps) with the nested-dissection factors at omega, for a fixed
+// right-hand side.
+std::vector<int64_t> precond_info(const HostModel &m, int nd_mode);
+double nd_solve_check(const HostModel &m, double omega);
+
 // Closed-form flat-triangle potentials: V0 = int 1/R, V1 = int (r'-r)/R.
 void tri_potentials(const double r[3], const double Q[9], double *V0, double V1[3]);
 

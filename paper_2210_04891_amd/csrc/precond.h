@@ -51,9 +51,44 @@ struct PrecondStruct {
   // per link: branch id (mesh) or -(port+1)
   std::vector<int> link_kind;
   std::vector<int> port_loop;
+  // ---- nested-dissection ordering (nd = true): a conductor's unknowns are
+  // ordered by recursive geometric bisection with vertex separators (each
+  // separator after the two halves it splits, a conductor's port
+  // supernodes after everything else), and L_w is factored by supernodes:
+  // supernode s holds the contiguous unknowns [sn_start[s], sn_start[s+1])
+  // and, below them, the rows st_ids[st_off[s] .. st_off[s+1]) (its
+  // "structure": ascending unknowns of ancestor supernodes).  The band
+  // fields above (first, env_off, clast, col_off, W, Wc) are unused then.
+  bool nd = false;
+  int nsn = 0;
+  std::vector<int> sn_start;        // [nsn + 1]
+  std::vector<int> sn_parent;       // [nsn] (-1: root of a conductor)
+  std::vector<int> sn_height;       // [nsn] 0 for supernodes without children
+  std::vector<int64_t> st_off;      // [nsn + 1]
+  std::vector<int> st_ids;          // structure rows
+  std::vector<int> st_pos;          // position of each structure row in the parent's front
+  std::vector<int> ch_off, ch_ids;  // children of each supernode
+  std::vector<int> lvl_off, lvl_sn; // supernodes grouped by height
+  std::vector<int> lvl_front;       // largest ns + nst of each level
+  std::vector<int64_t> l11_off;     // [nsn + 1] ns^2 values each
+  std::vector<int64_t> l21_off;     // [nsn + 1] ns * nst values each
+  int max_front = 0;                // largest ns + nst
 };
 
-void build_precond_struct(const HostModel &m, PrecondStruct &ps);
+// nd_mode: 0 nested dissection only for conductors whose reverse
+// Cuthill-McKee band would be wider than the band solvers take (then for all
+// of them), 1 nested dissection always.
+void build_precond_struct(const HostModel &m, PrecondStruct &ps, int nd_mode = 0);
+// Supernodal (multifrontal) LDL^T of L_w on a nested-dissection structure for
+// one frequency: l11 [ps.l11_off[nsn]] unit-lower pivot blocks stored by
+// columns (entry (i, k) of supernode s at l11_off[s] + k ns + i), l11t the
+// same blocks stored by rows, l21 [ps.l21_off[nsn]] the rows below them by
+// columns (entry (t, k) at l21_off[s] + k nst + t), diag [nu], yinv [b].
+// Returns false on a zero pivot.
+bool factor_precond_nd(const HostModel &m, const PrecondStruct &ps, double omega, double sigma, double mu_r,
+                       std::vector<std::complex<double>> &l11, std::vector<std::complex<double>> &l11t,
+                       std::vector<std::complex<double>> &l21, std::vector<std::complex<double>> &diag,
+                       std::vector<std::complex<double>> &yinv);
 
 // Factor for one angular frequency: envelope values (unit lower L), diagonal
 // and the branch admittances 1/D_e.  Returns false on a zero pivot.
@@ -109,6 +144,17 @@ struct PrecondDev {
   const int *link_kind, *port_loop;
   int64_t nnz_env;
   int ldl_plan;          // 0 register window when W, Wc <= 63; 1 LDS window
+  // nested-dissection solve (nd = 1): supernode structure as in
+  // PrecondStruct, factors per frequency ([nf][nl11], [nf][nl21]), and the
+  // forward sweep's update vectors [R][st_off[nsn]]
+  int nd, nsn, nlvl, max_front;
+  const int *sn_start, *st_ids, *st_pos, *ch_off, *ch_ids, *lvl_off, *lvl_sn;
+  const int64_t *st_off, *l11_off, *l21_off;
+  int64_t nl11, nl21, nst_tot;
+  const double2 *l11, *l11t, *l21;
+  double2 *uvec;
+  const int *lvl_off_host;     // lvl_off in host memory (the launch loop)
+  const int *lvl_front_host;   // largest front of each level, host
 };
 
 // z = P^-1 y for R right-hand sides; fidx[r] selects the factor of RHS r
@@ -133,6 +179,9 @@ struct Precond {
   double *d_gdiag = nullptr, *d_kdiag = nullptr, *d_om = nullptr;
   int *d_status = nullptr;
   int factor_plan = -1;                  // plan the current factors were made with
+  int nd_mode = 0;                       // nd_mode the structure was built with
+  // nested-dissection factors and the forward sweep's update vectors
+  double2 *d_l11 = nullptr, *d_l11t = nullptr, *d_l21 = nullptr, *d_uvec = nullptr;
 };
 
 }  // namespace pfft

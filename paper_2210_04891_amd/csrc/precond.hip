@@ -19,7 +19,15 @@ static constexpr double MU0 = 4e-7 * M_PI;
 // ---------------------------------------------------------------------------
 // structure: supernodes, grounds, reverse Cuthill-McKee order, envelope
 // ---------------------------------------------------------------------------
-void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
+void nd_order_conductor(const std::vector<std::vector<int>> &adj, const std::vector<double> &xyz,
+                        const std::vector<int> &mem, const std::vector<int> &dmem, std::vector<int> &stamp,
+                        int &next, std::vector<int> &unk, PrecondStruct &ps);
+void nd_symbolic(const std::vector<std::vector<int>> &uadj, PrecondStruct &ps);
+
+// widest band row above which a conductor is ordered by nested dissection
+static constexpr int ND_BAND_MAX = 256;
+
+void build_precond_struct(const HostModel &m, PrecondStruct &ps, int nd_mode) {
   const int nn = m.nn, b = m.b, p = m.p;
   // ports: sink node merged into source node, phi_K = phi_S - s_k
   std::vector<int> rep(nn), off_port(nn, -1), role(nn, 0);
@@ -140,7 +148,65 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
   ps.comp_off[ps.ncomp] = next;
   ps.nu = next;
   const int nu = ps.nu;
+  // the band's widest row: nested dissection instead when it is too wide
+  // (or always, nd_mode 1)
+  int wband = 0;
+  for (int x = 0; x < nn; ++x) {
+    if (unk[x] < 0 || dense[x]) continue;
+    for (int y : madj[x])
+      if (unk[y] >= 0 && !dense[y]) wband = std::max(wband, std::abs(unk[x] - unk[y]));
+  }
+  ps.nd = nd_mode == 1 || wband > ND_BAND_MAX;
+  if (ps.nd) {
+    // node coordinates: mean centroid of a node's triangles
+    std::vector<double> xyz(3 * (size_t)nn, 0.0);
+    std::vector<int> cnt(nn, 0);
+    for (int t = 0; t < m.n; ++t) {
+      const int x = rep[m.node_of_tri[t]];
+      for (int d = 0; d < 3; ++d) xyz[3 * x + d] += m.cen[3 * t + d];
+      cnt[x]++;
+    }
+    for (int x = 0; x < nn; ++x)
+      if (cnt[x])
+        for (int d = 0; d < 3; ++d) xyz[3 * x + d] /= cnt[x];
+    // band-member adjacency without ground and port supernodes
+    std::vector<std::vector<int>> badj(nn);
+    for (int x = 0; x < nn; ++x) {
+      if (rep[x] != x || dense[x] || x == ground[comp[x]]) continue;
+      for (int y : madj[x])
+        if (y != ground[comp[y]] && !dense[y]) badj[x].push_back(y);
+    }
+    std::fill(unk.begin(), unk.end(), -1);
+    next = 0;
+    ps.nsn = 0;
+    ps.sn_start.clear();
+    ps.sn_parent.clear();
+    std::vector<int> stamp(nn, 0);
+    for (int c = 0; c < ps.ncomp; ++c) {
+      ps.comp_off[c] = next;
+      nd_order_conductor(badj, xyz, members[c], dmembers[c], stamp, next, unk, ps);
+      ps.comp_mid[c] = ps.comp_off[c];
+    }
+    ps.comp_off[ps.ncomp] = next;
+    if (next != nu) throw SetupError{-4, "internal: nested dissection lost unknowns"};
+    std::vector<std::vector<int>> uadj(nu);
+    for (int x = 0; x < nn; ++x) {
+      if (unk[x] < 0) continue;
+      for (int y : madj[x])
+        if (unk[y] >= 0) uadj[unk[x]].push_back(unk[y]);
+    }
+    nd_symbolic(uadj, ps);
+    // no band structure
+    ps.first.resize(nu);
+    std::iota(ps.first.begin(), ps.first.end(), 0);
+    ps.env_off.assign(nu + 1, 0);
+    ps.clast = ps.first;
+    ps.col_off.assign(nu + 1, 0);
+    ps.W = ps.Wc = 0;
+    ps.pr = ps.pc = 1;
+  }
   // envelope
+  if (!ps.nd) {
   ps.first.assign(nu, 0);
   for (int x = 0; x < nn; ++x) {
     if (unk[x] < 0) continue;
@@ -175,6 +241,7 @@ void build_precond_struct(const HostModel &m, PrecondStruct &ps) {
   } else {
     ps.pr = std::max(ps.W, 1);
     ps.pc = std::max(ps.Wc, 1);
+  }
   }
   // branches
   ps.br_ru.resize(b);
@@ -793,9 +860,138 @@ __global__ void k_pre_out(PrecondDev d, const int *fidx, const double2 *y, const
   z[(size_t)r * d.l + i] = out;
 }
 
+// ---------------------------------------------------------------------------
+// nested-dissection solve: one workgroup per (supernode of a level,
+// right-hand side), levels by height.  Forward (leaves first): the
+// supernode's front vector in LDS is its right-hand side entries plus its
+// children's update vectors (extend-add by their positions in its front);
+// unit-lower solve with its pivot block; its own update vector = the
+// front's structure part minus L21 y, kept for its parent.  Backward (root
+// first): z = y / D - L21^T x(structure) with the ancestors' final values,
+// then the transposed unit-lower solve.  Deterministic: every sum has a
+// fixed order (no atomics).
+// ---------------------------------------------------------------------------
+constexpr int ND_T = 256;
+
+__global__ void __launch_bounds__(ND_T) k_nd_fwd(PrecondDev d, const int *fidx, double2 *work, int q0) {
+  extern __shared__ double2 ndF[];
+  const int s = d.lvl_sn[q0 + blockIdx.x], r = blockIdx.y, tid = threadIdx.x;
+  const int f = fidx[r];
+  const int sa = d.sn_start[s], ns = d.sn_start[s + 1] - sa;
+  const int64_t so = d.st_off[s];
+  const int nst = (int)(d.st_off[s + 1] - so);
+  double2 *x = work + (size_t)r * d.nu;
+  double2 *u = d.uvec + (size_t)r * d.nst_tot;
+  for (int i = tid; i < ns; i += ND_T) ndF[i] = x[sa + i];
+  for (int t = tid; t < nst; t += ND_T) ndF[ns + t] = make_double2(0, 0);
+  __syncthreads();
+  for (int q = d.ch_off[s]; q < d.ch_off[s + 1]; ++q) {
+    const int c = d.ch_ids[q];
+    const int64_t co = d.st_off[c];
+    const int nc = (int)(d.st_off[c + 1] - co);
+    for (int t = tid; t < nc; t += ND_T) {
+      const int p = d.st_pos[co + t];
+      const double2 v = u[co + t];
+      ndF[p].x += v.x;
+      ndF[p].y += v.y;
+    }
+    __syncthreads();
+  }
+  const double2 *L = d.l11 + (size_t)f * d.nl11 + d.l11_off[s];   // by columns
+  for (int k = 0; k < ns; ++k) {
+    const double2 yk = ndF[k];
+    const double2 *Lk = L + (size_t)k * ns;
+    for (int i = k + 1 + tid; i < ns; i += ND_T) {
+      const double2 l = Lk[i];
+      ndF[i].x -= l.x * yk.x - l.y * yk.y;
+      ndF[i].y -= l.x * yk.y + l.y * yk.x;
+    }
+    __syncthreads();
+  }
+  const double2 *L21 = d.l21 + (size_t)f * d.nl21 + d.l21_off[s];   // [k][t]
+  for (int t = tid; t < nst; t += ND_T) {
+    double2 acc = ndF[ns + t];
+    for (int k = 0; k < ns; ++k) {
+      const double2 l = L21[(size_t)k * nst + t], yk = ndF[k];
+      acc.x -= l.x * yk.x - l.y * yk.y;
+      acc.y -= l.x * yk.y + l.y * yk.x;
+    }
+    u[so + t] = acc;
+  }
+  for (int i = tid; i < ns; i += ND_T) x[sa + i] = ndF[i];
+}
+
+__global__ void __launch_bounds__(ND_T) k_nd_bwd(PrecondDev d, const int *fidx, double2 *work, int q0) {
+  extern __shared__ double2 ndF[];
+  const int s = d.lvl_sn[q0 + blockIdx.x], r = blockIdx.y, tid = threadIdx.x;
+  const int f = fidx[r];
+  const int sa = d.sn_start[s], ns = d.sn_start[s + 1] - sa;
+  const int64_t so = d.st_off[s];
+  const int nst = (int)(d.st_off[s + 1] - so);
+  double2 *x = work + (size_t)r * d.nu;
+  const double2 *dg = d.diag + (size_t)f * d.nu;
+  for (int t = tid; t < nst; t += ND_T) ndF[ns + t] = x[d.st_ids[so + t]];
+  __syncthreads();
+  const double2 *L21 = d.l21 + (size_t)f * d.nl21 + d.l21_off[s];   // [k][t]
+  for (int i = tid; i < ns; i += ND_T) {
+    double2 z = cdiv2(x[sa + i], dg[sa + i]);
+    const double2 *Li = L21 + (size_t)i * nst;
+    for (int t = 0; t < nst; ++t) {
+      const double2 l = Li[t], v = ndF[ns + t];
+      z.x -= l.x * v.x - l.y * v.y;
+      z.y -= l.x * v.y + l.y * v.x;
+    }
+    ndF[i] = z;
+  }
+  __syncthreads();
+  const double2 *Lt = d.l11t + (size_t)f * d.nl11 + d.l11_off[s];   // by rows
+  for (int k = ns - 1; k > 0; --k) {
+    const double2 xk = ndF[k];
+    const double2 *Lk = Lt + (size_t)k * ns;   // row k: L(k, i), i < k
+    for (int i = tid; i < k; i += ND_T) {
+      const double2 l = Lk[i];
+      ndF[i].x -= l.x * xk.x - l.y * xk.y;
+      ndF[i].y -= l.x * xk.y + l.y * xk.x;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < ns; i += ND_T) x[sa + i] = ndF[i];
+}
+
+static void nd_solve(const PrecondDev &d, const int *fidx, double2 *work, int R, hipStream_t st) {
+  static int lds_cap = -1;
+  if (lds_cap < 0) {
+    int dev = 0, q = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) q = 65536;
+    lds_cap = q;
+    if (hipFuncSetAttribute((const void *)k_nd_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, q) != hipSuccess ||
+        hipFuncSetAttribute((const void *)k_nd_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, q) != hipSuccess) {
+      (void)hipGetLastError();
+      lds_cap = 65536;
+    }
+  }
+  for (int h = 0; h < d.nlvl; ++h) {
+    const size_t lds = sizeof(double2) * (size_t)std::max(1, d.lvl_front_host[h]);
+    if (lds > (size_t)lds_cap) throw SetupError{-1, "nested-dissection front larger than LDS"};
+    const int q0 = d.lvl_off_host[h], n = d.lvl_off_host[h + 1] - q0;
+    if (n > 0) k_nd_fwd<<<dim3(n, R), ND_T, lds, st>>>(d, fidx, work, q0);
+  }
+  for (int h = d.nlvl - 1; h >= 0; --h) {
+    const size_t lds = sizeof(double2) * (size_t)std::max(1, d.lvl_front_host[h]);
+    const int q0 = d.lvl_off_host[h], n = d.lvl_off_host[h + 1] - q0;
+    if (n > 0) k_nd_bwd<<<dim3(n, R), ND_T, lds, st>>>(d, fidx, work, q0);
+  }
+}
+
 void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, double2 *z, double2 *work, int R,
                    hipStream_t st) {
   k_pre_rhs<<<dim3((d.nu + 255) / 256, R), 256, 0, st>>>(d, fidx, y, work);
+  if (d.nd) {
+    nd_solve(d, fidx, work, R, st);
+    k_pre_out<<<dim3((d.l + 255) / 256, R), 256, 0, st>>>(d, fidx, y, work, z);
+    return;
+  }
   // the window must hold max(W, Wc) + PF entries: a block of PF rows reaches
   // W (backward) or Wc (forward) beyond its last row while its own rows are
   // still pending
@@ -803,6 +999,8 @@ void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, doubl
   const int span = std::max(d.W, d.Wc) + PF;
   if ((double)d.nu * std::max(d.pr, d.pc) * 16.0 + 1024.0 >= 2147483647.0)
     throw SetupError{-1, "preconditioner band larger than 2 GB per frequency"};
+  // the circular LDS window of the widest solve holds 4096 entries
+  if (!ldl_reg_plan(d) && span >= 4096) throw SetupError{-1, "preconditioner band too wide for the band solve"};
   if (ldl_reg_plan(d))
     k_ldl_solve_reg<<<g, 64, 0, st>>>(d, fidx, work);
   else if (span < 128)

@@ -43,8 +43,14 @@ static void precond_free(Precond *p) {
   if (p->d_full) hipFree(p->d_full);
   if (p->d_om) hipFree(p->d_om);
   if (p->d_status) hipFree(p->d_status);
+  if (p->d_l11) hipFree(p->d_l11);
+  if (p->d_l11t) hipFree(p->d_l11t);
+  if (p->d_l21) hipFree(p->d_l21);
+  if (p->d_uvec) hipFree(p->d_uvec);
   delete p;
 }
+
+int precond_uses_nd(const pfft_ctx *c) { return c->pre && c->pre->built ? (c->pre->ps.nd ? 1 : 0) : -1; }
 
 void pfft_ctx_free(pfft_ctx *c) {
   precond_free(c->pre);
@@ -63,11 +69,18 @@ void pfft_ctx_free(pfft_ctx *c) {
 // Builds the structure once, factors every distinct frequency of omega[0..R)
 // and uploads the per-RHS factor index.
 Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStream_t st) {
+  if (c->pre && c->pre->built && c->pre->nd_mode != c->plans.nd) {
+    // the ordering plan changed: rebuild structure and factors
+    hip_ok(hipStreamSynchronize(st), "precond rebuild sync");
+    precond_free(c->pre);
+    c->pre = nullptr;
+  }
   if (!c->pre) c->pre = new Precond();
   Precond *P = c->pre;
   const HostModel &m = c->m;
   if (!P->built) {
-    build_precond_struct(m, P->ps);
+    P->nd_mode = c->plans.nd;
+    build_precond_struct(m, P->ps, P->nd_mode);
     if (std::max(P->ps.W, P->ps.Wc) + 8 >= 4096)
       throw SetupError{PFFT_EINVAL, "preconditioner envelope wider than 4087"};
     PrecondDev &d = P->dev;
@@ -110,6 +123,27 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
         if (m.gram_col[5 * e + q] == e) gd[e] += m.gram_val[5 * e + q];
     P->d_gdiag = pre_upload(P, gd);
     P->d_kdiag = pre_upload(P, m.kdiag);
+    d.nd = ps.nd ? 1 : 0;
+    if (ps.nd) {
+      d.nsn = ps.nsn;
+      d.nlvl = (int)ps.lvl_off.size() - 1;
+      d.max_front = ps.max_front;
+      d.sn_start = pre_upload(P, ps.sn_start);
+      d.st_ids = pre_upload(P, ps.st_ids);
+      d.st_pos = pre_upload(P, ps.st_pos);
+      d.ch_off = pre_upload(P, ps.ch_off);
+      d.ch_ids = pre_upload(P, ps.ch_ids);
+      d.lvl_off = pre_upload(P, ps.lvl_off);
+      d.lvl_sn = pre_upload(P, ps.lvl_sn);
+      d.st_off = pre_upload(P, ps.st_off);
+      d.l11_off = pre_upload(P, ps.l11_off);
+      d.l21_off = pre_upload(P, ps.l21_off);
+      d.nl11 = ps.l11_off[ps.nsn];
+      d.nl21 = ps.l21_off[ps.nsn];
+      d.nst_tot = ps.st_off[ps.nsn];
+      d.lvl_off_host = P->ps.lvl_off.data();
+      d.lvl_front_host = P->ps.lvl_front.data();
+    }
     P->built = true;
   }
   // distinct frequencies of this batch
@@ -143,7 +177,43 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
       hip_ok(hipMalloc(&P->d_status, (size_t)nf * (P->ps.ncomp + 1) * sizeof(int)), "hipMalloc status");
       P->cap_f = nf;
     }
-    if (c->plans.factor == 0 && factor_device_ok(P->ps)) {
+    if (P->ps.nd) {
+      // supernodal factors on the host (each factorization is parallel inside)
+      const PrecondStruct &ps = P->ps;
+      const size_t n11 = ps.l11_off[ps.nsn], n21 = ps.l21_off[ps.nsn];
+      std::vector<std::complex<double>> a11(nf * n11), a11t(nf * n11), a21(nf * n21),
+          dg((size_t)nf * ps.nu), yi((size_t)nf * m.b);
+      for (int f = 0; f < nf; ++f) {
+        std::vector<std::complex<double>> e1, e2, e3, d1, y1;
+        if (!factor_precond_nd(m, ps, uniq[f], c->sigma, c->mu_r, e1, e2, e3, d1, y1))
+          throw SetupError{PFFT_EFACTOR, "zero pivot in the nodal factorization"};
+        std::copy(e1.begin(), e1.end(), a11.begin() + f * n11);
+        std::copy(e2.begin(), e2.end(), a11t.begin() + f * n11);
+        std::copy(e3.begin(), e3.end(), a21.begin() + f * n21);
+        std::copy(d1.begin(), d1.end(), dg.begin() + (size_t)f * ps.nu);
+        std::copy(y1.begin(), y1.end(), yi.begin() + (size_t)f * m.b);
+      }
+      hip_ok(hipStreamSynchronize(st), "precond sync");
+      P->omegas.clear();
+      if (P->d_l11) hipFree(P->d_l11);
+      if (P->d_l11t) hipFree(P->d_l11t);
+      if (P->d_l21) hipFree(P->d_l21);
+      P->d_l11 = P->d_l11t = P->d_l21 = nullptr;
+      hip_ok(hipMalloc(&P->d_l11, std::max<size_t>(16, nf * n11 * sizeof(double2))), "hipMalloc nd l11");
+      hip_ok(hipMalloc(&P->d_l11t, std::max<size_t>(16, nf * n11 * sizeof(double2))), "hipMalloc nd l11t");
+      hip_ok(hipMalloc(&P->d_l21, std::max<size_t>(16, nf * n21 * sizeof(double2))), "hipMalloc nd l21");
+      if (n11) {
+        hip_ok(hipMemcpy(P->d_l11, a11.data(), nf * n11 * sizeof(double2), hipMemcpyHostToDevice), "l11");
+        hip_ok(hipMemcpy(P->d_l11t, a11t.data(), nf * n11 * sizeof(double2), hipMemcpyHostToDevice), "l11t");
+      }
+      if (n21) hip_ok(hipMemcpy(P->d_l21, a21.data(), nf * n21 * sizeof(double2), hipMemcpyHostToDevice), "l21");
+      if (ps.nu)
+        hip_ok(hipMemcpy(P->d_diag, dg.data(), (size_t)ps.nu * nf * sizeof(double2), hipMemcpyHostToDevice), "diag");
+      hip_ok(hipMemcpy(P->d_yinv, yi.data(), (size_t)m.b * nf * sizeof(double2), hipMemcpyHostToDevice), "yinv");
+      P->dev.l11 = P->d_l11;
+      P->dev.l11t = P->d_l11t;
+      P->dev.l21 = P->d_l21;
+    } else if (c->plans.factor == 0 && factor_device_ok(P->ps)) {
       // device factorization, ordered after earlier work on st that reads the old factors
       hip_ok(hipMemcpyAsync(P->d_om, uniq.data(), nf * sizeof(double), hipMemcpyHostToDevice, st), "omegas");
       FactorArgs fa;
@@ -237,6 +307,13 @@ Precond *pfft::precond_prepare(pfft_ctx *c, int R, const double *omega, hipStrea
     hip_ok(hipMalloc(&P->d_work, std::max<size_t>(16, (size_t)R * P->ps.nu * sizeof(double2))), "hipMalloc work");
     hip_ok(hipMalloc(&P->d_fidx, (size_t)R * sizeof(int)), "hipMalloc fidx");
     hip_ok(hipMalloc(&P->d_tmp, (size_t)R * m.l * sizeof(double2)), "hipMalloc tmp");
+    if (P->ps.nd) {
+      if (P->d_uvec) hipFree(P->d_uvec);
+      P->d_uvec = nullptr;
+      hip_ok(hipMalloc(&P->d_uvec, std::max<size_t>(16, (size_t)R * P->ps.st_off[P->ps.nsn] * sizeof(double2))),
+             "hipMalloc nd updates");
+      P->dev.uvec = P->d_uvec;
+    }
     P->cap_R = R;
     P->fidx_host.clear();
   }

@@ -8,9 +8,9 @@ vias - 1, several ports on it; the generator is seeded and synthetic).
   mm, 8 vias, 4 ports, ~80k triangles, grid 128 x 128 x 16): the far-field
   product against the oracle's explicit B^T (H * (B alpha)), and a 1 GHz
   solve of the 4 ports to 1e-6 with symmetric Z and positive-definite R, L.
-  The full 10 x 10 mm, 100-via configuration (995,200 triangles) builds and
-  runs its product, but its band factorization of P (one conductor of
-  ~1 M nodes, band ~700) is out of reach of the envelope LDL^T.
+  Its single conductor's band would exceed 256, so P is factored by nested
+  dissection (supernodal LDL^T); the full 10 x 10 mm, 100-via configuration
+  (995,200 triangles, one conductor of ~1 M nodes) is solved the same way.
 """
 import numpy as np
 import pytest
@@ -84,6 +84,9 @@ def test_mid_pdn_solve_reciprocity_and_passivity(mid):
     f = np.array([1e9])
     Y, it, rr, code = ctx.solve_ports(f, tol=1e-6, maxit=600, restart=60, precond=1)
     assert code == 0 and np.all(rr <= 1e-6)
+    # one conductor of 82k nodes: its band would exceed 256, so the nodal
+    # system is factored by nested dissection
+    assert ctx.get_option("precond_nd") == 1
     R, L = P.extract_RL(f, Y)
     Z = np.linalg.inv(Y[0])
     assert np.abs(Z - Z.T).max() <= 1e-4 * np.abs(Z).max()

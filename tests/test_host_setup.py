@@ -154,3 +154,20 @@ def test_setup_rejects_bad_topology():
     with pytest.raises(P.PfftError) as ei:
         P.HostModel(s, (64, 8, 12))
     assert ei.value.code == -1
+
+
+def test_preconditioner_ordering_choice_and_nd_factor():
+    """The band path for narrow bands (bar, wires), nested dissection where
+    the band would be too wide or when forced; the host mirror of the
+    supernodal sweeps solves the nodal system to rounding."""
+    cases = [(W.config1_bar(), (64, 8, 8)), (W.paper_bar_e1(), (32, 8, 8)),
+             (W.pdn(nx=10, ny=10, cell=100e-6, vias=[(2, 2), (6, 6)], block=2, ports=[(1, 6), (6, 1)], patch=2),
+              (32, 32, 16))]
+    for s, grid in cases:
+        h = P.HostModel(s, grid, 4, 1.5)
+        auto = h.get("precond_info", np.int64)
+        nd = h.get("precond_info_nd", np.int64)
+        assert auto[3] == 0 and 0 < auto[1] <= 256
+        assert nd[3] == 1 and nd[0] == auto[0] and nd[4] > 1
+        assert h.get("nd_check_1GHz", np.float64)[0] < 1e-12
+
