@@ -1376,22 +1376,34 @@ __global__ void __launch_bounds__(2 * BIG_T) k_fft_yz_big(YZArgs a, float2 *data
   const int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
   const float *gpl = ghat + (long)fx * (NY + 1) * (NZ + 1);
   const int za = t % NZ, j2 = t / NZ;     // column and y = j2 + N2 j1 (stages A, C); k1 = j2 + N2 i (N2 stage)
+  // the plane is read from memory once: each half loads 16 of a thread's
+  // 32 points (j1 = 16 e_y + j) into its own LDS area, in the plane's own
+  // order (y, z), and both halves then take all 32 from there
   float2 v[32];
-  if (PR) {
-    // pruned: a column without an active node enters as zero (whatever the
-    // buffer holds there); the load's offset then lies beyond the plane
-    const __amdgpu_buffer_rsrc_t rio = buf_rsrc(io, (unsigned)(NY * NZ * 8));
+  {
+    float2 *P0 = big_sm, *P1 = big_sm + L::SZ;
+    float2 *Pm = ey ? P1 : P0;
+    if (PR) {
+      // pruned: a column without an active node enters as zero (whatever the
+      // buffer holds there); the load's offset then lies beyond the plane
+      const __amdgpu_buffer_rsrc_t rio = buf_rsrc(io, (unsigned)(NY * NZ * 8));
 #pragma unroll
-    for (int j1 = 0; j1 < 32; ++j1) {
-      const int cidx = (j2 + N2 * j1) * NZ + za;
-      const unsigned on = (colact[cidx >> 5] >> (cidx & 31)) & 1u;
-      v[j1] = buf_load2(rio, on ? (unsigned)cidx * 8u : X_DROP, 0);
+      for (int j = 0; j < 16; ++j) {
+        const int cidx = (j2 + N2 * (16 * ey + j)) * NZ + za;
+        const unsigned on = (colact[cidx >> 5] >> (cidx & 31)) & 1u;
+        v[j] = buf_load2(rio, on ? (unsigned)cidx * 8u : X_DROP, 0);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = io[(j2 + N2 * (16 * ey + j)) * NZ + za];
     }
-  } else {
 #pragma unroll
-    for (int j1 = 0; j1 < 32; ++j1) v[j1] = io[(j2 + N2 * j1) * NZ + za];
+    for (int j = 0; j < 16; ++j) Pm[(j2 + N2 * j) * NZ + za] = v[j];
+    __syncthreads();                                    // twiddle tables and the plane
+#pragma unroll
+    for (int j1 = 0; j1 < 32; ++j1) v[j1] = (j1 < 16 ? P0 : P1)[(j2 + N2 * (j1 & 15)) * NZ + za];
+    __syncthreads();                                    // both halves done before S is reused
   }
-  __syncthreads();                                      // twiddle tables
   if (ey) {
     const float2 wl = twh[j2];
 #pragma unroll
