@@ -341,14 +341,23 @@ pfft_status pfft_stage_times(pfft_ctx *c, double ms[16], int64_t calls[16]);
  * the host, Sec. IV-A): "precond_info" / "precond_info_nd" (int64[7]: nu, W,
  * Wc, nested dissection used, supernodes, largest front, levels; automatic
  * ordering / nested dissection forced) and "nd_check_1GHz" (double: relative
- * residual of a host supernodal solve of the nodal system at 1 GHz).
+ * residual of a host supernodal solve of the nodal system at 1 GHz), and
+ * "setup_ms" (double[8]: wall time of the set-up phases: topology, circuit,
+ * Gram, grid, near lists, near pair blocks, near CSR, device build).
  * pfft_host_get writes *len_bytes always and copies when dst is non-null and
- * cap_bytes is large enough. */
+ * cap_bytes is large enough.  The host-only model computes the near-field
+ * pair blocks (Sec. IV-B step 4, Eq. Lb) in a host loop; pfft_setup
+ * computes them on the device with the same pair routine. */
 typedef struct pfft_host_model pfft_host_model;
 pfft_status pfft_host_setup(const pfft_problem *pb, pfft_host_model **out);
 pfft_status pfft_host_get(const pfft_host_model *h, const char *name, void *dst, int64_t cap_bytes,
                           int64_t *len_bytes);
 void pfft_host_free(pfft_host_model *h);
+/* The same named arrays from a device context's host copy of its model
+ * (after pfft_setup; its near-field values come from the device pair
+ * blocks).  Same conventions and errors as pfft_host_get; the context owns
+ * the data, dst is host memory of cap_bytes. */
+pfft_status pfft_ctx_get(const pfft_ctx *c, const char *name, void *dst, int64_t cap_bytes, int64_t *len_bytes);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfft.so")
 
-SOURCES = ["setup.cpp", "inspect.cpp", "nd.hip", "kernels.hip", "engine.hip", "solver.hip", "precond.hip",
+SOURCES = ["setup.cpp", "inspect.cpp", "nd.hip", "nearblk.hip", "kernels.hip", "engine.hip", "solver.hip", "precond.hip",
            "learned.hip"]
 ARCH = os.environ.get("PFFT_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-Wno-unused-result"]

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -835,6 +836,31 @@ extern "C" {
 
 const char *pfft_last_error(void) { return g_err.c_str(); }
 
+pfft_status pfft_ctx_get(const pfft_ctx *c, const char *name, void *dst, int64_t cap_bytes, int64_t *len_bytes) {
+  if (!c || !name || !len_bytes) {
+    set_error("pfft_ctx_get: null argument");
+    return PFFT_EINVAL;
+  }
+  const std::string k(name);
+  int64_t n = -1;
+  try {
+    n = model_get(c->m, k, dst, cap_bytes);
+  } catch (const SetupError &e) {
+    set_error("pfft_ctx_get: " + e.msg);
+    return (pfft_status)e.code;
+  }
+  if (n < 0) {
+    set_error("pfft_ctx_get: unknown array " + k);
+    return PFFT_EINVAL;
+  }
+  *len_bytes = n;
+  if (dst && cap_bytes < n) {
+    set_error("pfft_ctx_get: buffer too small");
+    return PFFT_EINVAL;
+  }
+  return PFFT_OK;
+}
+
 pfft_status pfft_setup(const pfft_problem *pb, void *hip_stream, pfft_ctx **out) {
   if (!pb || !out) {
     set_error("pfft_setup: null argument");
@@ -855,11 +881,17 @@ pfft_status pfft_setup(const pfft_problem *pb, void *hip_stream, pfft_ctx **out)
     opt.stencil = pb->stencil;
     opt.kappa = pb->near_kappa;
     opt.contact_zs = pb->contact_zs;
+    opt.device_blocks = 1;
+    opt.stream = hip_stream;
     build_model(c->m, pb->V, pb->nv, pb->T, pb->nt, pb->nport, pb->src_off, pb->src_tri, pb->snk_off,
                 pb->snk_tri, opt);
     hip_ok(hipGetDevice(&c->device), "hipGetDevice");
     c->scratch = device_scratch(c->device);
-    build_device(c, (hipStream_t)hip_stream);
+    {
+      const auto t0 = std::chrono::steady_clock::now();
+      build_device(c, (hipStream_t)hip_stream);
+      c->m.setup_ms[7] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
     {
       // product workspaces may take half of the memory left after setup
       // (the rest is for the Krylov bases and preconditioner factors)

@@ -56,6 +56,10 @@ struct HostModel {
   std::vector<double> nf_val;
   // ---- diagonal of K for the preconditioner ----
   std::vector<double> kdiag;      // [b]
+  // ---- wall time of the set-up phases, ms: topology, circuit, Gram, grid,
+  // near lists, near blocks, near CSR (incl. diag K), device build (kernel
+  // spectrum, product maps; device contexts only) ----
+  double setup_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 struct SetupOptions {
@@ -63,6 +67,17 @@ struct SetupOptions {
   int stencil;
   double kappa;
   int contact_zs;
+  int device_blocks = 0;          // near-field pair blocks on the current device
+  void *stream = nullptr;         // (hipStream_t) for that work
+};
+
+// Unordered near pairs (t <= u) sorted by the class of t's outer rule (0:
+// the pair touches; 1, 2, 3: separated, 7-point rule on 64, 16, 4
+// sub-triangles); idx is the pair's position in the t-major order.
+struct NearPairList {
+  std::vector<int> t, u;
+  std::vector<int64_t> idx;
+  int64_t cls_end[4] = {0, 0, 0, 0};
 };
 
 // Builds everything except the kernel spectrum (computed on the device).
@@ -78,9 +93,15 @@ void build_model(HostModel &m, const double *V, int nv, const int *T, int n, int
 // device sweeps) with the nested-dissection factors at omega, for a fixed
 // right-hand side.
 std::vector<int64_t> precond_info(const HostModel &m, int nd_mode);
+// The model's arrays by name: bytes (copied into dst when cap allows), or
+// -1 for an unknown name.
+int64_t model_get(const HostModel &m, const std::string &name, void *dst, int64_t cap);
 double nd_solve_check(const HostModel &m, double omega);
 
-// Closed-form flat-triangle potentials: V0 = int 1/R, V1 = int (r'-r)/R.
-void tri_potentials(const double r[3], const double Q[9], double *V0, double V1[3]);
+// Scaled (direct - grid) blocks of every pair into blk[9 * idx] and the
+// scaled direct blocks of the touching pairs (class 0, in list order) into
+// dirb, on the current device (stream) or in a host loop.  Throws SetupError.
+void near_pair_blocks(const HostModel &m, const NearPairList &pl, const std::vector<double> &Htab,
+                      const int Dm[3], const int S[3], bool device, void *stream, double *blk, double *dirb);
 
 }  // namespace pfft

@@ -7,6 +7,7 @@
 //  * near pairs, direct integrals, grid blocks  -- Sec. IV-B step 4, Eq. Lb
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -19,6 +20,10 @@
 namespace pfft {
 
 static void fail(int code, const std::string &msg) { throw SetupError{code, msg}; }
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 static inline void sub3(const double *a, const double *b, double *c) {
   c[0] = a[0] - b[0]; c[1] = a[1] - b[1]; c[2] = a[2] - b[2];
@@ -344,199 +349,10 @@ static void build_grid(HostModel &m, const SetupOptions &opt) {
 }
 
 // ---------------------------------------------------------------------------
-// closed-form potentials of a flat triangle (Wilton-Rao-Glisson / Graglia)
-// ---------------------------------------------------------------------------
-void tri_potentials(const double r[3], const double Q[9], double *V0out, double V1[3]) {
-  double e1[3], e2[3], nrm[3];
-  sub3(Q + 3, Q, e1);
-  sub3(Q + 6, Q, e2);
-  cross3(e1, e2, nrm);
-  double nn = std::sqrt(dot3(nrm, nrm));
-  for (int d = 0; d < 3; ++d) nrm[d] /= nn;
-  double rq[3];
-  sub3(r, Q, rq);
-  double w0 = dot3(rq, nrm), aw = std::fabs(w0);
-  double rho[3] = {r[0] - w0 * nrm[0], r[1] - w0 * nrm[1], r[2] - w0 * nrm[2]};
-  double V0 = 0, Vr[3] = {0, 0, 0};
-  for (int i = 0; i < 3; ++i) {
-    const double *qa = Q + 3 * i, *qb = Q + 3 * ((i + 1) % 3);
-    double L[3];
-    sub3(qb, qa, L);
-    double len = std::sqrt(dot3(L, L));
-    double lu[3] = {L[0] / len, L[1] / len, L[2] / len}, u[3];
-    cross3(lu, nrm, u);
-    double ar[3];
-    sub3(qa, rho, ar);
-    double t0 = dot3(ar, u), sm = dot3(ar, lu), sp = sm + len;
-    double R02 = t0 * t0 + w0 * w0;
-    double Rm = std::sqrt(R02 + sm * sm), Rp = std::sqrt(R02 + sp * sp);
-    double f = 0, beta = 0;
-    if (R02 > 1e-28 * len * len) {
-      double Ap = sp >= 0 ? Rp + sp : R02 / (Rp - sp);
-      double Am = sm >= 0 ? Rm + sm : R02 / (Rm - sm);
-      f = std::log(Ap / Am);
-      beta = std::atan2(t0 * sp, R02 + aw * Rp) - std::atan2(t0 * sm, R02 + aw * Rm);
-    }
-    V0 += t0 * f - aw * beta;
-    double g = 0.5 * (R02 * f + sp * Rp - sm * Rm);
-    for (int d = 0; d < 3; ++d) Vr[d] += u[d] * g;
-  }
-  *V0out = V0;
-  for (int d = 0; d < 3; ++d) V1[d] = Vr[d] - w0 * V0 * nrm[d];
-}
-
-// Gauss-Legendre nodes/weights on [0, 1] (Newton iteration on P_q).
-static void gauss_legendre01(int q, std::vector<double> &x, std::vector<double> &w) {
-  x.resize(q);
-  w.resize(q);
-  for (int i = 0; i < q; ++i) {
-    double z = std::cos(M_PI * (i + 0.75) / (q + 0.5)), dp = 1;
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1, p1 = z;
-      for (int k = 2; k <= q; ++k) {
-        double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      dp = q * (z * p1 - p0) / (z * z - 1);
-      double dz = p1 / dp;
-      z -= dz;
-      if (std::fabs(dz) < 1e-16) break;
-    }
-    x[i] = 0.5 * (1 - z);
-    w[i] = 1.0 / ((1 - z * z) * dp * dp);
-  }
-}
-
-// Outer rule for pairs that touch: t is cut into three pieces from its
-// centroid; each piece maps (s, u) in [0,1]^2 to (1-u)(edge point s) + u c,
-// with u = v^2 (graded toward the edge, where the outer integrand behaves
-// like d log d) and s = sigma^2/(sigma^2 + (1-sigma)^2) (graded toward the
-// vertices); Gauss-Legendre in (sigma, v).  Barycentric points, weights
-// summing to 1.
-struct OuterRule {
-  std::vector<double> lam, w;
-};
-static OuterRule make_graded_rule(int q) {
-  std::vector<double> x, wx;
-  gauss_legendre01(q, x, wx);
-  OuterRule R;
-  for (int k = 0; k < 3; ++k)
-    for (int a = 0; a < q; ++a) {
-      double sg = x[a];
-      double A = sg * sg, B = (1 - sg) * (1 - sg);
-      double s = A / (A + B);
-      double ds = 2 * sg * (1 - sg) / ((A + B) * (A + B));
-      for (int b2 = 0; b2 < q; ++b2) {
-        double v = x[b2], u = v * v, du = 2 * v;
-        double base[3] = {0, 0, 0};
-        base[k] = 1 - s;
-        base[(k + 1) % 3] = s;
-        for (int d = 0; d < 3; ++d) R.lam.push_back((1 - u) * base[d] + u / 3.0);
-        R.w.push_back(2.0 / 3.0 * (1 - u) * wx[a] * ds * wx[b2] * du);
-      }
-    }
-  return R;
-}
-
-static void block_with_rule(const double *P, const double *Q, const OuterRule &rule, double M[9]) {
-  double e1[3], e2[3], c[3];
-  sub3(P + 3, P, e1);
-  sub3(P + 6, P, e2);
-  cross3(e1, e2, c);
-  double A = 0.5 * std::sqrt(dot3(c, c));
-  for (int k = 0; k < 9; ++k) M[k] = 0;
-  size_t nq = rule.w.size();
-  for (size_t q = 0; q < nq; ++q) {
-    const double *lam = &rule.lam[3 * q];
-    double r[3];
-    for (int d = 0; d < 3; ++d) r[d] = lam[0] * P[d] + lam[1] * P[3 + d] + lam[2] * P[6 + d];
-    double V0, V1[3];
-    tri_potentials(r, Q, &V0, V1);
-    double w = rule.w[q] * A;
-    for (int i = 0; i < 3; ++i) {
-      double a[3];
-      sub3(r, P + 3 * i, a);
-      double aV1 = dot3(a, V1);
-      for (int j = 0; j < 3; ++j) {
-        double bq[3];
-        sub3(r, Q + 3 * j, bq);
-        M[3 * i + j] += w * (aV1 + dot3(a, bq) * V0);
-      }
-    }
-  }
-}
-
-// Raw block M[i][j] = int_t int_t' (r - p_i).(r' - q_j)/|r - r'|: closed-form
-// inner integral, outer 7-point rule on 4^level congruent sub-triangles of t.
-static void exact_block(const double *P, const double *Q, int level, double M[9]) {
-  double A;
-  {
-    double e1[3], e2[3], c[3];
-    sub3(P + 3, P, e1);
-    sub3(P + 6, P, e2);
-    cross3(e1, e2, c);
-    A = 0.5 * std::sqrt(dot3(c, c));
-  }
-  for (int k = 0; k < 9; ++k) M[k] = 0;
-  int nsub = 1 << (2 * level);
-  // sub-triangles in barycentric coordinates generated on the fly
-  struct Tri { double b[3][3]; };
-  Tri stack_[1 << 8];
-  int ns = 1;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) stack_[0].b[i][j] = (i == j);
-  for (int lv = 0; lv < level; ++lv) {
-    Tri nxt[1 << 8];
-    int nn = 0;
-    for (int q = 0; q < ns; ++q) {
-      const auto &T = stack_[q];
-      double m01[3], m12[3], m20[3];
-      for (int d = 0; d < 3; ++d) {
-        m01[d] = 0.5 * (T.b[0][d] + T.b[1][d]);
-        m12[d] = 0.5 * (T.b[1][d] + T.b[2][d]);
-        m20[d] = 0.5 * (T.b[2][d] + T.b[0][d]);
-      }
-      const double *sets[4][3] = {{T.b[0], m01, m20}, {m01, T.b[1], m12}, {m20, m12, T.b[2]}, {m01, m12, m20}};
-      for (int s = 0; s < 4; ++s) {
-        for (int v = 0; v < 3; ++v)
-          for (int d = 0; d < 3; ++d) nxt[nn].b[v][d] = sets[s][v][d];
-        ++nn;
-      }
-    }
-    ns = nn;
-    for (int q = 0; q < ns; ++q) stack_[q] = nxt[q];
-  }
-  double wsub = A / nsub;
-  for (int sidx = 0; sidx < ns; ++sidx) {
-    const auto &S = stack_[sidx];
-    for (int q = 0; q < 7; ++q) {
-      double lam[3];
-      for (int v = 0; v < 3; ++v)
-        lam[v] = D7_L[q][0] * S.b[0][v] + D7_L[q][1] * S.b[1][v] + D7_L[q][2] * S.b[2][v];
-      double r[3];
-      for (int d = 0; d < 3; ++d) r[d] = lam[0] * P[d] + lam[1] * P[3 + d] + lam[2] * P[6 + d];
-      double V0, V1[3];
-      tri_potentials(r, Q, &V0, V1);
-      double w = D7_W[q] * wsub;
-      for (int i = 0; i < 3; ++i) {
-        double a[3];
-        sub3(r, P + 3 * i, a);
-        double aV1 = dot3(a, V1);
-        for (int j = 0; j < 3; ++j) {
-          double bq[3];
-          sub3(r, Q + 3 * j, bq);
-          M[3 * i + j] += w * (aV1 + dot3(a, bq) * V0);
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // near pairs, exact minus grid blocks, edge-level CSR (Sec. IV-B step 4)
 // ---------------------------------------------------------------------------
 static void build_nearfield(HostModel &m, const SetupOptions &opt) {
+  const double tl0 = now_ms();
   const int n = m.n;
   const double hmax = std::max(m.h[0], std::max(m.h[1], m.h[2]));
   const double rad = opt.kappa * 3.0 * hmax;
@@ -600,8 +416,8 @@ static void build_nearfield(HostModel &m, const SetupOptions &opt) {
     poff[t + 1] = poff[t] + c;
   }
   m.npairs = poff[n];
+  const double tl1 = now_ms();
   std::vector<double> blk(9 * (size_t)m.npairs);   // scaled (exact - grid)
-  std::vector<double> exb(9 * (size_t)m.npairs);   // scaled exact
   // grid Green's function table over offsets within [-Dmax, Dmax]^3
   int Dm[3] = {0, 0, 0};
   for (int t = 0; t < n; ++t)
@@ -624,84 +440,55 @@ static void build_nearfield(HostModel &m, const SetupOptions &opt) {
     for (int i = 0; i < 3; ++i) r = std::max(r, std::sqrt(dot3(&m.pl[9 * t + 3 * i], &m.pl[9 * t + 3 * i])));
     radius[t] = r;
   }
-  const OuterRule graded = make_graded_rule(16);
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int t = 0; t < n; ++t) {
-    double P[9], Q[9];
-    for (int v = 0; v < 3; ++v)
-      for (int d = 0; d < 3; ++d) P[3 * v + d] = m.V[3 * m.T[3 * t + v] + d];
-    // moments of t: m_t[g] = (M0, M1x, M1y, M1z)
-    const double *M0t = &m.M0[64 * (size_t)t], *M1t = &m.M1[192 * (size_t)t];
-    int64_t pk = poff[t];
-    for (int q = m.near_off[t]; q < m.near_off[t + 1]; ++q) {
-      int u = m.near_tri[q];
-      if (u < t) continue;
-      for (int v = 0; v < 3; ++v)
-        for (int d = 0; d < 3; ++d) Q[3 * v + d] = m.V[3 * m.T[3 * u + v] + d];
-      // --- exact block, rule by proximity
-      int shared = 0;
-      for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) shared += m.T[3 * t + a] == m.T[3 * u + c];
-      double dd[3];
-      sub3(&m.cen[3 * t], &m.cen[3 * u], dd);
-      double ratio = (std::sqrt(dot3(dd, dd)) - radius[t] - radius[u]) / std::max(radius[t], radius[u]);
-      double E[9];
-      if (shared > 0) {
-        block_with_rule(P, Q, graded, E);
-      } else {
-        int level = ratio < 0.5 ? 3 : (ratio < 2.0 ? 2 : 1);
-        exact_block(P, Q, level, E);
+  // the pairs sorted by the outer rule their proximity asks for (class 0:
+  // the pair shares a vertex; 1, 2, 3: separated, with the rule on 64, 16
+  // or 4 sub-triangles of t as the gap shrinks relative to the triangles)
+  NearPairList pl;
+  {
+    std::vector<int8_t> cls(m.npairs);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int t = 0; t < n; ++t) {
+      int64_t pk = poff[t];
+      for (int q = m.near_off[t]; q < m.near_off[t + 1]; ++q) {
+        const int u = m.near_tri[q];
+        if (u < t) continue;
+        int shared = 0;
+        for (int a = 0; a < 3; ++a)
+          for (int c = 0; c < 3; ++c) shared += m.T[3 * t + a] == m.T[3 * u + c];
+        double dd[3];
+        sub3(&m.cen[3 * t], &m.cen[3 * u], dd);
+        const double ratio = (std::sqrt(dot3(dd, dd)) - radius[t] - radius[u]) / std::max(radius[t], radius[u]);
+        cls[pk++] = shared > 0 ? 0 : (ratio < 0.5 ? 1 : (ratio < 2.0 ? 2 : 3));
       }
-      if (u == t) {
-        for (int i = 0; i < 3; ++i)
-          for (int j = i + 1; j < 3; ++j) {
-            double s = 0.5 * (E[3 * i + j] + E[3 * j + i]);
-            E[3 * i + j] = E[3 * j + i] = s;
-          }
+    }
+    int64_t cnt[4] = {0, 0, 0, 0};
+    for (int64_t k = 0; k < m.npairs; ++k) cnt[cls[k]]++;
+    int64_t pos[4] = {0, cnt[0], cnt[0] + cnt[1], cnt[0] + cnt[1] + cnt[2]};
+    for (int c = 0; c < 4; ++c) pl.cls_end[c] = pos[c] + cnt[c];
+    pl.t.resize(m.npairs);
+    pl.u.resize(m.npairs);
+    pl.idx.resize(m.npairs);
+    for (int t = 0; t < n; ++t) {
+      int64_t pk = poff[t];
+      for (int q = m.near_off[t]; q < m.near_off[t + 1]; ++q) {
+        const int u = m.near_tri[q];
+        if (u < t) continue;
+        const int64_t r = pos[cls[pk]]++;
+        pl.t[r] = t;
+        pl.u[r] = u;
+        pl.idx[r] = pk++;
       }
-      // --- grid block through the stencils
-      const double *M0u = &m.M0[64 * (size_t)u], *M1u = &m.M1[192 * (size_t)u];
-      int da[3];
-      for (int d = 0; d < 3; ++d) da[d] = m.anchor[3 * t + d] - m.anchor[3 * u + d];
-      double X[4][4] = {{0}};
-      for (int g = 0; g < 64; ++g) {
-        int gi = g >> 4, gj = (g >> 2) & 3, gk = g & 3;
-        double tmp[4] = {0, 0, 0, 0};
-        for (int h = 0; h < 64; ++h) {
-          int hi = h >> 4, hj = (h >> 2) & 3, hk = h & 3;
-          double H = Htab[((size_t)(da[0] + gi - hi + Dm[0]) * S[1] + (da[1] + gj - hj + Dm[1])) * S[2] +
-                          (da[2] + gk - hk + Dm[2])];
-          tmp[0] += H * M0u[h];
-          tmp[1] += H * M1u[3 * h];
-          tmp[2] += H * M1u[3 * h + 1];
-          tmp[3] += H * M1u[3 * h + 2];
-        }
-        double mt[4] = {M0t[g], M1t[3 * g], M1t[3 * g + 1], M1t[3 * g + 2]};
-        for (int a = 0; a < 4; ++a)
-          for (int c = 0; c < 4; ++c) X[a][c] += mt[a] * tmp[c];
-      }
-      const double *plt = &m.pl[9 * t], *plu = &m.pl[9 * u];
-      double *out = &blk[9 * pk];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          double g = 0;
-          for (int c = 0; c < 3; ++c)
-            g += X[1 + c][1 + c] - plu[3 * j + c] * X[1 + c][0] - plt[3 * i + c] * X[0][1 + c] +
-                 plt[3 * i + c] * plu[3 * j + c] * X[0][0];
-          double sc = m.tri_sign[3 * t + i] * m.tri_sign[3 * u + j] / (4.0 * m.area[t] * m.area[u]);
-          out[3 * i + j] = sc * (E[3 * i + j] - g);
-          exb[9 * pk + 3 * i + j] = sc * E[3 * i + j];
-        }
-      if (u == t) {
-        for (int i = 0; i < 3; ++i)
-          for (int j = i + 1; j < 3; ++j) {
-            double s = 0.5 * (out[3 * i + j] + out[3 * j + i]);
-            out[3 * i + j] = out[3 * j + i] = s;
-          }
-      }
-      ++pk;
     }
   }
+  const int64_t ntouch = pl.cls_end[0];
+  std::vector<double> exb(9 * (size_t)ntouch);     // scaled direct blocks of the touching pairs
+  near_pair_blocks(m, pl, Htab, Dm, S, opt.device_blocks != 0, opt.stream, blk.data(), exb.data());
+  // unordered pair -> its row in exb (touching pairs only)
+  std::vector<int> touch_row(m.npairs, -1);
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < ntouch; ++r) touch_row[pl.idx[r]] = (int)r;
+  pl = NearPairList();
+  const double tl2 = now_ms();
   // ordered entry q of t's list -> unordered block index and transpose flag
   std::vector<int64_t> qblk(m.near_tri.size());
   std::vector<uint8_t> qtr(m.near_tri.size());
@@ -752,7 +539,13 @@ static void build_nearfield(HostModel &m, const SetupOptions &opt) {
         int i = 0, j = 0;
         while (m.tri_edge[3 * t + i] != e) ++i;
         while (m.tri_edge[3 * u + j] != e) ++j;
-        const double *B = &exb[9 * qblk[q]];
+        const int tr = touch_row[qblk[q]];
+        if (tr < 0) {
+#pragma omp atomic write
+          missing = 1;
+          continue;
+        }
+        const double *B = &exb[9 * (size_t)tr];
         acc += qtr[q] ? B[3 * j + i] : B[3 * i + j];
       }
     m.kdiag[e] = acc;
@@ -798,6 +591,9 @@ static void build_nearfield(HostModel &m, const SetupOptions &opt) {
     std::copy(rcol[e].begin(), rcol[e].end(), m.nf_col.begin() + m.nf_rowptr[e]);
     std::copy(rval[e].begin(), rval[e].end(), m.nf_val.begin() + m.nf_rowptr[e]);
   }
+  m.setup_ms[4] = tl1 - tl0;
+  m.setup_ms[5] = tl2 - tl1;
+  m.setup_ms[6] = now_ms() - tl2;
 }
 
 void build_model(HostModel &m, const double *V, int nv, const int *T, int n, int nport,
@@ -812,11 +608,20 @@ void build_model(HostModel &m, const double *V, int nv, const int *T, int n, int
   m.T.assign(T, T + 3 * (size_t)n);
   for (int k = 0; k < 3 * n; ++k)
     if (m.T[k] < 0 || m.T[k] >= nv) fail(-1, "vertex id out of range");
+  auto t0 = now_ms();
   build_topology(m);
+  auto t1 = now_ms();
   build_circuit(m, nport, src_off, src_tri, snk_off, snk_tri);
+  auto t2 = now_ms();
   build_gram(m, opt.contact_zs);
+  auto t3 = now_ms();
   build_grid(m, opt);
+  auto t4 = now_ms();
   build_nearfield(m, opt);
+  m.setup_ms[0] = t1 - t0;
+  m.setup_ms[1] = t2 - t1;
+  m.setup_ms[2] = t3 - t2;
+  m.setup_ms[3] = t4 - t3;
 }
 
 }  // namespace pfft

@@ -25,7 +25,7 @@ STATUS = {0: "PFFT_OK", -1: "PFFT_EINVAL", -2: "PFFT_ETOPO", -3: "PFFT_ENOMEM",
 
 EXPORTS = ("pfft_setup", "pfft_sizes", "pfft_matvec", "solve_ports", "extract_RL",
            "pfft_precond_load", "pfft_destroy", "pfft_last_error",
-           "pfft_host_setup", "pfft_host_get", "pfft_host_free", "pfft_profile",
+           "pfft_host_setup", "pfft_host_get", "pfft_host_free", "pfft_ctx_get", "pfft_profile",
            "pfft_stage_times", "pfft_precond_save", "pfft_learned_collect", "pfft_learned_train",
            "pfft_learned_clear", "pfft_learned_stats", "pfft_mlp_grad", "pfft_learned_eval",
            "pfft_set_option", "pfft_get_option", "pfft_autotune", "solve_ports_lgmres",
@@ -94,6 +94,8 @@ def load():
     lib.pfft_host_setup.restype = i32
     lib.pfft_host_get.argtypes = [vp, ctypes.c_char_p, vp, i64, ctypes.POINTER(i64)]
     lib.pfft_host_get.restype = i32
+    lib.pfft_ctx_get.argtypes = [vp, ctypes.c_char_p, vp, i64, ctypes.POINTER(i64)]
+    lib.pfft_ctx_get.restype = i32
     lib.pfft_host_free.argtypes = [vp]
     lib.pfft_host_free.restype = None
     lib.pfft_profile.argtypes = [vp, i32]
@@ -328,6 +330,16 @@ class Context:
     def set_option(self, name, value):
         """Plan options: fft_plan, ldl_plan, project_plan, graphs (0 or 1)."""
         _check(load().pfft_set_option(self._h, name.encode(), int(value)))
+
+    def model_array(self, name, dtype):
+        """A named array of the context's host model (pfft_ctx_get)."""
+        lib = load()
+        n = ctypes.c_int64()
+        _check(lib.pfft_ctx_get(self._h, name.encode(), None, 0, ctypes.byref(n)))
+        out = np.empty(n.value // np.dtype(dtype).itemsize, dtype=dtype)
+        _check(lib.pfft_ctx_get(self._h, name.encode(), ctypes.c_void_p(out.ctypes.data), n.value,
+                                ctypes.byref(n)))
+        return out
 
     def get_option(self, name):
         v = ctypes.c_int64()
