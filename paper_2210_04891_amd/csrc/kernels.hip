@@ -10,6 +10,7 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "xcd.h"
 
 namespace pfft {
 
@@ -34,15 +35,6 @@ template <typename T>
 __device__ __forceinline__ V2<T> cscale(V2<T> a, T s) { return cmk<T>(a.x * s, a.y * s); }
 
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
-
-// XCD-aware block order.  The dispatcher sends workgroup b to XCD b % 8, and
-// each XCD has its own L2; this bijection gives XCD x the contiguous range of
-// logical blocks [x*(nb/8) + min(x, nb%8), ...), so neighbouring rows, which
-// gather overlapping data, share one L2.
-__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
-  const unsigned x = b & 7u, k = b >> 3, q = nb >> 3, rem = nb & 7u;
-  return x * q + (x < rem ? x : rem) + k;
-}
 
 // Largest dynamic LDS allocation one workgroup may request (capped at 128 KB).
 static int lds_budget() {
@@ -409,8 +401,12 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
   extern __shared__ unsigned char smraw[];
   constexpr int PS = proj_pitch<T>();
   V2<T> *sJ = (V2<T> *)smraw;   // [tcap][PS]: (rr, comp) at rr * 4 + comp, rr < RB
-  const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
-  const int rb0 = blockIdx.y * RB, nrb = min(RB, R - rb0);
+  // one workgroup per (tile, group of RB right-hand sides), the groups of a
+  // tile consecutive on one XCD: they read the tile's triangle and gather
+  // lists through that XCD's L2
+  const int ngrp = (R + RB - 1) / RB;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), tile = lb / ngrp;
+  const int rb0 = (lb - tile * ngrp) * RB, nrb = min(RB, R - rb0);
   const int t0 = g.tt_off[tile], nt = g.tt_off[tile + 1] - t0;
   const int ns = min(nt, g.tcap);
   // staging: SU (triangle index, moment) load pairs in flight per thread,
@@ -548,8 +544,8 @@ void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st)
   const size_t lds = (size_t)g.tcap * proj_pitch<T>() * sizeof(V2<T>);
   if (lds_ok && g.proj_plan == 0 && lds <= (size_t)lds_max) {
     const unsigned ntile = (unsigned)g.ntile[0] * g.ntile[1] * g.ntile[2];
-    k_project_tiled<T><<<dim3(ntile, cdiv(R, RC * ProjRG<T>::v)), 512, lds, st>>>(g, J, Q, R,
-                                                                                 prune_ok<T>(g, 3L * R) ? 1 : 0);
+    k_project_tiled<T><<<dim3(ntile * cdiv(R, RC * ProjRG<T>::v)), 512, lds, st>>>(g, J, Q, R,
+                                                                                  prune_ok<T>(g, 3L * R) ? 1 : 0);
   } else {
     k_project<T><<<dim3(cdiv(g.N, 256), cdiv(R, PRG)), 256, 0, st>>>(g, J, Q, R);
   }
@@ -2027,9 +2023,13 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *uniform_ro
 __global__ void __launch_bounds__(256) k_interp_grp(GridMaps g, const float2 *phiT, double2 *U, int R) {
   constexpr int IG = INTERP_GROUP;
   __shared__ double2 s0[IG][256];
-  const int grp = (int)xcd_block(blockIdx.x, gridDim.x);
-  const int q0 = g.ig_off[grp], gn = g.ig_off[grp + 1] - q0;
+  // one workgroup per (block of 255 channels, group), the groups of one
+  // channel block consecutive: an XCD's workgroups then read neighbouring
+  // groups' stencil nodes within one channel block, a working set that
+  // fits its L2
   const int ch = 3 * R;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), cbk = lb / g.nig, grp = lb - cbk * g.nig;
+  const int q0 = g.ig_off[grp], gn = g.ig_off[grp + 1] - q0;
   int tq[IG];
   const __attribute__((address_space(4))) float *wq[IG];
 #pragma unroll
@@ -2039,7 +2039,8 @@ __global__ void __launch_bounds__(256) k_interp_grp(GridMaps g, const float2 *ph
   }
   const __attribute__((address_space(4))) int *ia = uniform_ro(g.ig_act + (size_t)grp * 64);
   constexpr int KC = 16;   // node values in flight per lane
-  for (int base = 0; base < ch; base += 255) {
+  {
+    const int base = cbk * 255;   // 85 right-hand sides x 3 channels
     const int chn = base + threadIdx.x;
     const bool ok = threadIdx.x < 255 && chn < ch;
     const int c = ok ? chn % 3 : 0;
@@ -2103,7 +2104,7 @@ void interp_tri<float>(const GridMaps &g, const float2 *phi, double2 *U, int R, 
   float2 *phiT = (float2 *)scratch;
   const int ch = 3 * R;
   k_transpose_c64<<<dim3(cdiv(g.nact, 32), cdiv(ch, 32)), 256, 0, st>>>(phi, phiT, ch, g.N, g.nact, g.act);
-  if (g.nig > 0) k_interp_grp<<<(unsigned)g.nig, 256, 0, st>>>(g, phiT, U, R);
+  if (g.nig > 0) k_interp_grp<<<(unsigned)g.nig * cdiv(ch, 255), 256, 0, st>>>(g, phiT, U, R);
 }
 
 // ===========================================================================

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "precond.h"
+#include "xcd.h"
 
 namespace pfft {
 
@@ -528,9 +529,9 @@ __device__ void ldl_middle(const PrecondDev &d, int f, double2 *x, int lo, int m
 }
 
 template <int WP>
-__global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx, double2 *work) {
+__global__ void __launch_bounds__(64) k_ldl_solve(PrecondDev d, const int *fidx, double2 *work, int R) {
   __shared__ double2 win[WP];
-  const int c = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), c = lb / R, r = lb - c * R, lane = threadIdx.x;
   const int lo = d.comp_off[c], hi = d.comp_off[c + 1], mid = d.comp_mid[c];
   if (lo >= hi) return;
   const int f = fidx[r];
@@ -680,8 +681,8 @@ __device__ __forceinline__ double dbl_put(double v, double u, int l) {
 
 constexpr int RP = 32;   // rows of factor data in flight per buffer
 
-__global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *fidx, double2 *work) {
-  const int c = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+__global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *fidx, double2 *work, int R) {
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), c = lb / R, r = lb - c * R, lane = threadIdx.x;
   const int lo = d.comp_off[c], hi = d.comp_off[c + 1], mid = d.comp_mid[c];
   if (lo >= hi) return;
   const int f = fidx[r];
@@ -873,9 +874,10 @@ __global__ void k_pre_out(PrecondDev d, const int *fidx, const double2 *y, const
 // ---------------------------------------------------------------------------
 constexpr int ND_T = 256;
 
-__global__ void __launch_bounds__(ND_T) k_nd_fwd(PrecondDev d, const int *fidx, double2 *work, int q0) {
+__global__ void __launch_bounds__(ND_T) k_nd_fwd(PrecondDev d, const int *fidx, double2 *work, int q0, int R) {
   extern __shared__ double2 ndF[];
-  const int s = d.lvl_sn[q0 + blockIdx.x], r = blockIdx.y, tid = threadIdx.x;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), qf = lb / R, r = lb - qf * R, tid = threadIdx.x;
+  const int s = d.lvl_sn[q0 + qf];
   const int f = fidx[r];
   const int sa = d.sn_start[s], ns = d.sn_start[s + 1] - sa;
   const int64_t so = d.st_off[s];
@@ -921,9 +923,10 @@ __global__ void __launch_bounds__(ND_T) k_nd_fwd(PrecondDev d, const int *fidx, 
   for (int i = tid; i < ns; i += ND_T) x[sa + i] = ndF[i];
 }
 
-__global__ void __launch_bounds__(ND_T) k_nd_bwd(PrecondDev d, const int *fidx, double2 *work, int q0) {
+__global__ void __launch_bounds__(ND_T) k_nd_bwd(PrecondDev d, const int *fidx, double2 *work, int q0, int R) {
   extern __shared__ double2 ndF[];
-  const int s = d.lvl_sn[q0 + blockIdx.x], r = blockIdx.y, tid = threadIdx.x;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), qf = lb / R, r = lb - qf * R, tid = threadIdx.x;
+  const int s = d.lvl_sn[q0 + qf];
   const int f = fidx[r];
   const int sa = d.sn_start[s], ns = d.sn_start[s + 1] - sa;
   const int64_t so = d.st_off[s];
@@ -975,12 +978,14 @@ static void nd_solve(const PrecondDev &d, const int *fidx, double2 *work, int R,
     const size_t lds = sizeof(double2) * (size_t)std::max(1, d.lvl_front_host[h]);
     if (lds > (size_t)lds_cap) throw SetupError{-1, "nested-dissection front larger than LDS"};
     const int q0 = d.lvl_off_host[h], n = d.lvl_off_host[h + 1] - q0;
-    if (n > 0) k_nd_fwd<<<dim3(n, R), ND_T, lds, st>>>(d, fidx, work, q0);
+    // one workgroup per (front, right-hand side), a front's right-hand
+    // sides consecutive on one XCD (they share its factor blocks)
+    if (n > 0) k_nd_fwd<<<dim3((unsigned)n * (unsigned)R), ND_T, lds, st>>>(d, fidx, work, q0, R);
   }
   for (int h = d.nlvl - 1; h >= 0; --h) {
     const size_t lds = sizeof(double2) * (size_t)std::max(1, d.lvl_front_host[h]);
     const int q0 = d.lvl_off_host[h], n = d.lvl_off_host[h + 1] - q0;
-    if (n > 0) k_nd_bwd<<<dim3(n, R), ND_T, lds, st>>>(d, fidx, work, q0);
+    if (n > 0) k_nd_bwd<<<dim3((unsigned)n * (unsigned)R), ND_T, lds, st>>>(d, fidx, work, q0, R);
   }
 }
 
@@ -995,22 +1000,26 @@ void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, doubl
   // the window must hold max(W, Wc) + PF entries: a block of PF rows reaches
   // W (backward) or Wc (forward) beyond its last row while its own rows are
   // still pending
-  dim3 g(d.ncomp, R);
+  // one workgroup per (conductor, right-hand side), the right-hand sides of
+  // a conductor consecutive on one XCD: right-hand sides of one frequency
+  // (adjacent in the solver's order) then read the same factor rows
+  // through that XCD's L2
+  const dim3 g((unsigned)d.ncomp * (unsigned)R);
   const int span = std::max(d.W, d.Wc) + PF;
   if ((double)d.nu * std::max(d.pr, d.pc) * 16.0 + 1024.0 >= 2147483647.0)
     throw SetupError{-1, "preconditioner band larger than 2 GB per frequency"};
   // the circular LDS window of the widest solve holds 4096 entries
   if (!ldl_reg_plan(d) && span >= 4096) throw SetupError{-1, "preconditioner band too wide for the band solve"};
   if (ldl_reg_plan(d))
-    k_ldl_solve_reg<<<g, 64, 0, st>>>(d, fidx, work);
+    k_ldl_solve_reg<<<g, 64, 0, st>>>(d, fidx, work, R);
   else if (span < 128)
-    k_ldl_solve<128><<<g, 64, 0, st>>>(d, fidx, work);
+    k_ldl_solve<128><<<g, 64, 0, st>>>(d, fidx, work, R);
   else if (span < 512)
-    k_ldl_solve<512><<<g, 64, 0, st>>>(d, fidx, work);
+    k_ldl_solve<512><<<g, 64, 0, st>>>(d, fidx, work, R);
   else if (span < 2048)
-    k_ldl_solve<2048><<<g, 64, 0, st>>>(d, fidx, work);
+    k_ldl_solve<2048><<<g, 64, 0, st>>>(d, fidx, work, R);
   else
-    k_ldl_solve<4096><<<g, 64, 0, st>>>(d, fidx, work);
+    k_ldl_solve<4096><<<g, 64, 0, st>>>(d, fidx, work, R);
   k_pre_out<<<dim3((d.l + 255) / 256, R), 256, 0, st>>>(d, fidx, y, work, z);
 }
 
