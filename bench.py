@@ -135,6 +135,26 @@ def measured_traffic(stage, table):
     return None if ent is None else int(ent["read_bytes"] + ent["write_bytes"])
 
 
+def measured_step_bytes(table):
+    """HBM bytes of one whole step (every kernel of the product) from the
+    same committed counter table, or None when it is stale or absent."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", table + ".json")
+    try:
+        tab = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    for rel, sha in tab.get("sources_sha256", {}).items():
+        try:
+            if hashlib.sha256(open(os.path.join(HERE, rel), "rb").read()).hexdigest() != sha:
+                return None
+        except OSError:
+            return None
+    if "step_read_bytes" not in tab:
+        return None
+    return int(tab["step_read_bytes"] + tab["step_write_bytes"])
+
+
 def exact_rows_check(ctx, structure, nrow=24, nrhs=4, seed=0):
     """The branch-space product K alpha on the GPU against exact dense-kernel
     rows of the oracle (both surfaces integrated numerically) at nrow sampled
@@ -241,6 +261,84 @@ def run_steps(ctx, R, omega, steps, warmup, flags):
     return dt, stages, psteps
 
 
+def protocol_layout(seed):
+    """A layout of the package-trace generator for the learned-correction
+    protocol: 32 meander traces on 5 x 5 mm, triangle count drawn (seeded)
+    from 20k-100k, grid 128 x 128 x 16 (39 um cells, about the mesh step of
+    a 100k-triangle layout; the package-trace configuration's 256 x 256 x 32
+    grid matches its 200k triangles)."""
+    import workloads as W
+    target = int(np.random.default_rng(7919 + seed).integers(20_000, 100_001))
+    s = W.traces(seed=seed, target_tris=target, name="traces_s%d" % seed)
+    return s, (128, 128, 16)
+
+
+def learned_protocol(train_seeds, eval_seeds, freqs_eval=(1e8, 4.6e8, 2.2e9, 1e10), steps_per_layout=300,
+                     log=None):
+    """Train the correction network over seeded layouts (weights carried from
+    one layout's context to the next), then compare plain and learned FGMRES
+    sweeps (all ports x freqs_eval, 1e-6 true relative residual) on unseen
+    layouts, the learned sweep with the convergence judge measured on the
+    last training layout.  Returns a dict with per-layout records and the
+    medians."""
+    import torch
+    import paper_2210_04891_amd as P
+    fe = np.asarray(freqs_eval, np.float64)
+    f_train = np.sqrt(fe[:-1] * fe[1:])
+    blob, judge, rows_total, t_train = None, 0, 0, 0.0
+    for k, sd in enumerate(train_seeds):
+        s, grid = protocol_layout(sd)
+        ctx = P.Context(s, grid, stencil=4, near_kappa=1.5, grid_fp64=False)
+        t0 = time.perf_counter()
+        if blob is not None:
+            ctx.precond_load(blob)
+        rows = ctx.learned_collect(f_train, tol=1e-8, maxit=40)
+        ctx.learned_train(steps_per_layout, batch=8192, hidden=256, lr=1e-3, seed=sd)
+        blob = ctx.precond_save()
+        judge = ctx.get_option("learned_judge_ppm")   # plain per-step factor x 1.1, from this collection
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t0
+        rows_total += rows
+        if log:
+            log("protocol: train layout %d (seed %d, %d triangles): %d rows, loss %.4f"
+                % (k, sd, ctx.sizes["n"], rows, ctx.learned_eval()))
+        ctx.close()
+    recs = []
+    for sd in eval_seeds:
+        s, grid = protocol_layout(sd)
+        ctx = P.Context(s, grid, stencil=4, near_kappa=1.5, grid_fp64=False)
+        p = len(s.ports)
+        om = np.repeat(2 * np.pi * fe, p)
+        # factor P and size the workspaces before either timed sweep
+        ctx.matvec(torch.zeros((om.size, ctx.sizes["l"]), dtype=torch.complex128, device="cuda"),
+                   omega=om, space=1, flags=P.PFFT_PRECOND)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Y1, it1, rr1, c1 = ctx.solve_ports(fe, tol=1e-6, maxit=600, restart=60, precond=1)
+        t1 = time.perf_counter()
+        ctx.precond_load(blob)
+        ctx.set_option("learned_judge_ppm", judge)
+        Y2, it2, rr2, c2 = ctx.solve_ports(fe, tol=1e-6, maxit=600, restart=60, precond=2)
+        t2 = time.perf_counter()
+        n_apply, n_fall, n_off = ctx.learned_stats()
+        rec = {"seed": int(sd), "triangles": int(ctx.sizes["n"]), "rhs": int(om.size),
+               "plain_s": round(t1 - t0, 3), "learned_s": round(t2 - t1, 3),
+               "plain_iters_median": float(np.median(it1)), "learned_iters_median": float(np.median(it2)),
+               "plain_status": int(c1), "learned_status": int(c2),
+               "learned_max_relres": float(rr2.max()), "learned_rhs_switched_to_plain": int(n_off),
+               "Y_rel_diff": float(np.abs(Y2 - Y1).max() / np.abs(Y1).max())}
+        recs.append(rec)
+        if log:
+            log("protocol: eval seed %d: %s" % (sd, json.dumps(rec)))
+        ctx.close()
+    med = lambda key: float(np.median([r[key] for r in recs]))
+    return {"train_layouts": len(train_seeds), "train_rows": int(rows_total), "train_s": round(t_train, 1),
+            "judge_factor": judge * 1e-6,
+            "eval_layouts": len(eval_seeds), "median_plain_s": med("plain_s"),
+            "median_learned_s": med("learned_s"), "median_plain_iters": med("plain_iters_median"),
+            "median_learned_iters": med("learned_iters_median"), "layouts": recs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +350,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction sweep arm")
     ap.add_argument("--no-second", action="store_true", help="skip the second (bond-wire) workload")
     ap.add_argument("--no-check", action="store_true", help="skip the exact-row check and the CPU baseline")
+    ap.add_argument("--learned-protocol", default="",
+                    help="TRAIN,EVAL: train the correction network on TRAIN seeded trace layouts (seeds 0..) and "
+                         "compare plain and learned sweeps on EVAL unseen ones (seeds 10000..); prints its own "
+                         "JSON line and exits")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before the steps, copy a buffer of this size three times (device to device) so that "
                          "hardware byte counters can be scaled against a transfer of known size")
@@ -264,6 +366,12 @@ def main():
     import torch
     import paper_2210_04891_amd as P
 
+    if args.learned_protocol:
+        ntr, nev = (int(x) for x in args.learned_protocol.split(","))
+        res = learned_protocol(list(range(ntr)), list(range(10_000, 10_000 + nev)),
+                               log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps({"learned_protocol": res}), flush=True)
+        return
     make, label = WORKLOADS[args.workload]
     s, freqs, grid = make()
     p = len(s.ports)
@@ -314,6 +422,10 @@ def main():
     model = sum(stage_bytes(sz, R).values())
     out["model_bytes_per_step"] = int(model)
     out["model_GBs_frac"] = round(model / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
+    # the same ratio with the bytes the HBM counters saw over a whole step
+    sb = measured_step_bytes(table)
+    out["counter_bytes_per_step"] = sb
+    out["counter_GBs_frac"] = None if sb is None else round(sb / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
     Krows = X = None
     t_rows = 0.0
     if not args.no_check:

@@ -191,8 +191,14 @@ pfft_status extract_RL(int32_t nfreq, int32_t nport, const double *freq_hz, cons
  * s_z = sqrt(l)/|z| (2-norms).  Loop i gets the features
  *   x_i = ( Re v_i s_v, Im v_i s_v, Re z_i s_z, Im z_i s_z,
  *           (log10 f - 8)/2, [i is a port source link], [i is a contact
- *           self-loop], Re D_e/|D_e| of its link branch e (0 for a port) )
- * (D_e = Z_b(e,e) of Eq. Zb), rounded to bf16, and the network
+ *           self-loop], Re D_e/|D_e| of its link branch e (0 for a port),
+ *           a1_i, a2_i )
+ * (D_e = Z_b(e,e) of Eq. Zb), where a1_i is the mean of (Re v_j s_v,
+ * Im v_j s_v, Re z_j s_z, Im z_j s_z) over ring 1 of loop i (the other
+ * loops whose link branch ends at one of the two end nodes of i's link
+ * branch) and a2_i the same mean over ring 2 (loops whose link branch ends
+ * at a node one branch away from those end nodes, not in ring 1; zeros for
+ * an empty ring): 16 features, rounded to bf16, and the network
  *   y_i = W3 relu(W2 relu(W1 x_i + b1) + b2) + b3      (2 outputs)
  * gives M(v)_i = z_i + (y_i0 + j y_i1)/s_z.  If some y of a right-hand side
  * is not finite or sum_i |y_i|^2 > 16 l, that right-hand side keeps z.
@@ -201,7 +207,7 @@ pfft_status extract_RL(int32_t nfreq, int32_t nport, const double *freq_hz, cons
  * in FP32 and feeds each as a bf16 hi + lo pair (about 16 mantissa bits).
  *
  * Weight blob (little endian), exchanged by pfft_precond_load/_save:
- *   int32 magic 0x504D4C50, int32 F (= 8), int32 H (hidden width), int32 O (= 2)
+ *   int32 magic 0x504D4C50, int32 F (= 16), int32 H (hidden width), int32 O (= 2)
  *   bf16 W1[H][F], W2[H][H], W3[O][H]   (row-major), zero-padded to 4 bytes
  *   float32 b1[H], b2[H], b3[O]
  * size = 16 + 4*ceil((H*F + H*H + O*H)/2) + 4*(2H + O) bytes.            */
@@ -300,10 +306,24 @@ pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const 
  *                    interpolation reads it): the X passes skip groups of 32
  *                    (y, z) grid lines without such a node, the forward X pass
  *                    reads and the inverse one writes only those nodes, the
- *                    (y, z) plane kernel reads and writes only the lines
- *                    that hold one, and the tiled projection does not write
+ *                    (y, z) plane kernels read only the lines that hold
+ *                    one (the small-plane kernel also writes only those),
+ *                    and the tiled projection does not write
  *                    node chunks without a contribution; 0 dense passes.
  *                    The product is the same bit for bit.
+ *   "near_dense"   1 (default) the near-field product runs over dense
+ *                    32-row tiles on the FP64 matrix cores where the tiles
+ *                    are at least half full, 0 the CSR paths of combine_plan
+ *   "learned_judge_ppm" the learned correction's convergence judge: a
+ *                    right-hand side whose residual falls by less than this
+ *                    factor (parts per million) per step over two steps is
+ *                    switched back to plain P; pfft_learned_collect sets it
+ *                    (1.1 x the plain median factor), a caller may carry it
+ *                    to another context; 0 disables switching.  Values in
+ *                    [0, 1e6).
+ * Read-only: "combine_tile_rows", "combine_tile_rhs" (the LDS row tile
+ * chosen at setup, 0 when none fits), "precond_nd" (1 when the current
+ * preconditioner uses nested dissection, -1 before the first use of P).
  * PFFT_EINVAL for an unknown name or value. */
 pfft_status pfft_set_option(pfft_ctx *c, const char *name, int64_t value);
 pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *value);

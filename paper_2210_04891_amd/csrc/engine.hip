@@ -12,6 +12,7 @@
 #include <string>
 
 #include "engine.h"
+#include "learned.h"
 
 namespace pfft {
 
@@ -1210,6 +1211,16 @@ extern "C" pfft_status pfft_set_option(pfft_ctx *c, const char *name, int64_t va
     set_error("pfft_set_option: bad argument");
     return PFFT_EINVAL;
   }
+  // the learned correction's convergence judge, parts per million of the
+  // per-step residual factor (0 disables it)
+  if (std::string(name) == "learned_judge_ppm") {
+    if (value < 0 || value >= 1000000) {
+      set_error("pfft_set_option: learned_judge_ppm must lie in [0, 1e6)");
+      return PFFT_EINVAL;
+    }
+    learned_set_judge(c, (double)value * 1e-6);
+    return PFFT_OK;
+  }
   int *slot = option_slot(c, name);
   if (!slot || value < 0 || value > 1) {
     set_error(std::string("pfft_set_option: unknown option or value: ") + name);
@@ -1239,6 +1250,10 @@ extern "C" pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *v
   // dissection (-1 before the first preconditioned product or solve)
   if (std::string(name) == "precond_nd") {
     *value = precond_uses_nd(c);
+    return PFFT_OK;
+  }
+  if (std::string(name) == "learned_judge_ppm") {
+    *value = (int64_t)std::llround(learned_judge_factor(c) * 1e6);
     return PFFT_OK;
   }
   int *slot = option_slot(c, name);

@@ -20,6 +20,8 @@ bool learned_apply(pfft_ctx *c, int R, const double *omega, const double2 *v, do
 // when the training pairs were collected (times a 1.1 margin); 0 when unknown.
 double learned_judge_factor(pfft_ctx *c);
 void learned_judged_off(pfft_ctx *c, int n);
+// Sets the convergence judge's per-step factor (0 disables switching).
+void learned_set_judge(pfft_ctx *c, double factor);
 void learned_free(pfft_ctx *c);
 
 // One-cycle port solve with the plain preconditioner (restart = maxit,

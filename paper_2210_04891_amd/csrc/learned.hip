@@ -1,6 +1,6 @@
 // Learned correction of the preconditioner inside flexible GMRES.
 //
-// A per-loop multilayer perceptron (F = 8 inputs, two ReLU layers of width
+// A per-loop multilayer perceptron (F = 16 inputs, two ReLU layers of width
 // H, 2 outputs) refines M(v) = P^-1 v.  Its matrix products run on the gfx950
 // matrix cores (v_mfma_f32_32x32x8_bf16: bf16 operands, FP32 accumulation);
 // biases, ReLU, the loss and Adam are FP32 vector code.  Training pairs come
@@ -24,7 +24,7 @@ namespace pfft {
 
 namespace {
 
-constexpr int F_IN = 8;
+constexpr int F_IN = 16;
 constexpr int F_OUT = 2;
 constexpr uint32_t MAGIC = 0x504D4C50u;  // "PMLP"
 constexpr double DELTA_CAP2 = 16.0;      // fallback when sum |y|^2 > 16 l
@@ -270,14 +270,36 @@ struct FeatArgs {
   const int *link_kind;     // [l] mesh branch or -(port+1)
   const uint8_t *self_loop; // [l]
   const float *logf;        // [R]
+  const int *n1_off, *n1;   // ring-1 link neighbours of each loop (CSR over loops)
+  const int *n2_off, *n2;   // ring-2 link neighbours
   int l, b, R;
-  uint16_t *X;              // [R*l][8]
+  uint16_t *X;              // [R*l][16]
 };
+
+// mean of (v sv, z sz) over the loops nb[off[i] .. off[i+1]) of RHS r
+__device__ inline void ring_mean(const FeatArgs &a, const int *off, const int *nb, int i, size_t base, double sv,
+                                 double sz, float out[4]) {
+  const int k0 = off[i], k1 = off[i + 1];
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int k = k0; k < k1; ++k) {
+    const double2 vj = a.v[base + nb[k]], zj = a.z[base + nb[k]];
+    s0 += vj.x;
+    s1 += vj.y;
+    s2 += zj.x;
+    s3 += zj.y;
+  }
+  const double w = k1 > k0 ? 1.0 / (k1 - k0) : 0.0;
+  out[0] = (float)(s0 * w * sv);
+  out[1] = (float)(s1 * w * sv);
+  out[2] = (float)(s2 * w * sz);
+  out[3] = (float)(s3 * w * sz);
+}
 
 __global__ __launch_bounds__(256) void k_features(FeatArgs a) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (long long)a.R * a.l) return;
   const int r = (int)(idx / a.l), i = (int)(idx - (long long)r * a.l);
+  const size_t base = (size_t)r * a.l;
   const double nv = a.nrm[2 * r], nz = a.nrm[2 * r + 1];
   const double sv = nv > 0 ? sqrt(a.l / nv) : 0.0, sz = nz > 0 ? sqrt(a.l / nz) : 0.0;
   const double2 vv = a.v[idx], zz = a.z[idx];
@@ -288,14 +310,20 @@ __global__ __launch_bounds__(256) void k_features(FeatArgs a) {
     const double ay = sqrt(y.x * y.x + y.y * y.y);
     f7 = ay > 0 ? (float)(y.x / ay) : 0.f;   // Re D / |D| = Re(1/D) / |1/D|
   }
-  const float f[F_IN] = {(float)(vv.x * sv), (float)(vv.y * sv), (float)(zz.x * sz), (float)(zz.y * sz),
-                         a.logf[r], e < 0 ? 1.f : 0.f, a.self_loop[i] ? 1.f : 0.f, f7};
-  uint4 pk;
-  pk.x = (uint32_t)to_bf16(f[0]) | ((uint32_t)to_bf16(f[1]) << 16);
-  pk.y = (uint32_t)to_bf16(f[2]) | ((uint32_t)to_bf16(f[3]) << 16);
-  pk.z = (uint32_t)to_bf16(f[4]) | ((uint32_t)to_bf16(f[5]) << 16);
-  pk.w = (uint32_t)to_bf16(f[6]) | ((uint32_t)to_bf16(f[7]) << 16);
-  reinterpret_cast<uint4 *>(a.X)[idx] = pk;
+  float f[F_IN] = {(float)(vv.x * sv), (float)(vv.y * sv), (float)(zz.x * sz), (float)(zz.y * sz),
+                   a.logf[r], e < 0 ? 1.f : 0.f, a.self_loop[i] ? 1.f : 0.f, f7};
+  ring_mean(a, a.n1_off, a.n1, i, base, sv, sz, f + 8);
+  ring_mean(a, a.n2_off, a.n2, i, base, sv, sz, f + 12);
+  uint4 pk[2];
+  for (int h = 0; h < 2; ++h) {
+    const float *g = f + 8 * h;
+    pk[h].x = (uint32_t)to_bf16(g[0]) | ((uint32_t)to_bf16(g[1]) << 16);
+    pk[h].y = (uint32_t)to_bf16(g[2]) | ((uint32_t)to_bf16(g[3]) << 16);
+    pk[h].z = (uint32_t)to_bf16(g[4]) | ((uint32_t)to_bf16(g[5]) << 16);
+    pk[h].w = (uint32_t)to_bf16(g[6]) | ((uint32_t)to_bf16(g[7]) << 16);
+  }
+  reinterpret_cast<uint4 *>(a.X)[2 * idx] = pk[0];
+  reinterpret_cast<uint4 *>(a.X)[2 * idx + 1] = pk[1];
 }
 
 // ok[r] = every y of RHS r finite and sum |y|^2 <= cap2
@@ -665,6 +693,7 @@ struct Learned {
   uint8_t *en = nullptr;        // [cap_R] device enable mask
   std::vector<uint8_t> en_host;
   uint8_t *self_loop = nullptr; // [l]
+  int *n1_off = nullptr, *n1 = nullptr, *n2_off = nullptr, *n2 = nullptr;  // link-neighbour rings
   // inference
   Acts act;
   long long cap_rows = 0;
@@ -704,6 +733,84 @@ Learned *learned_of(pfft_ctx *c, hipStream_t st) {
   }
   dev_alloc((void **)&L->self_loop, m.l, "self loops");
   hip_ok(hipMemcpyAsync(L->self_loop, sl.data(), m.l, hipMemcpyHostToDevice, st), "self loops");
+  // link neighbours of loop i (loop i = the cycle of link branch links[i]):
+  // ring 1, the other links at the two end nodes of its link; ring 2, the
+  // links at the nodes one branch away from those ends (not in ring 1)
+  {
+    const int nn = m.nn, nbr = (int)m.bu.size();
+    std::vector<int> ln_off(nn + 1, 0), ln, adj_off(nn + 1, 0), adj;
+    for (int i = 0; i < m.l; ++i) {
+      const int e = m.links[i];
+      ln_off[m.bu[e] + 1]++;
+      if (m.bv[e] != m.bu[e]) ln_off[m.bv[e] + 1]++;
+    }
+    for (int k = 0; k < nn; ++k) ln_off[k + 1] += ln_off[k];
+    ln.resize(ln_off[nn]);
+    {
+      std::vector<int> fill(ln_off.begin(), ln_off.end() - 1);
+      for (int i = 0; i < m.l; ++i) {
+        const int e = m.links[i];
+        ln[fill[m.bu[e]]++] = i;
+        if (m.bv[e] != m.bu[e]) ln[fill[m.bv[e]]++] = i;
+      }
+    }
+    for (int e = 0; e < nbr; ++e)
+      if (m.bu[e] != m.bv[e]) {
+        adj_off[m.bu[e] + 1]++;
+        adj_off[m.bv[e] + 1]++;
+      }
+    for (int k = 0; k < nn; ++k) adj_off[k + 1] += adj_off[k];
+    adj.resize(adj_off[nn]);
+    {
+      std::vector<int> fill(adj_off.begin(), adj_off.end() - 1);
+      for (int e = 0; e < nbr; ++e)
+        if (m.bu[e] != m.bv[e]) {
+          adj[fill[m.bu[e]]++] = m.bv[e];
+          adj[fill[m.bv[e]]++] = m.bu[e];
+        }
+    }
+    std::vector<int> o1(m.l + 1, 0), o2(m.l + 1, 0), r1, r2;
+    std::vector<std::vector<int>> s1(m.l), s2(m.l);
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int i = 0; i < m.l; ++i) {
+      const int e = m.links[i];
+      const int ends[2] = {m.bu[e], m.bv[e]};
+      auto &a1 = s1[i];
+      auto &a2 = s2[i];
+      for (int x : ends)
+        for (int k = ln_off[x]; k < ln_off[x + 1]; ++k)
+          if (ln[k] != i) a1.push_back(ln[k]);
+      std::sort(a1.begin(), a1.end());
+      a1.erase(std::unique(a1.begin(), a1.end()), a1.end());
+      for (int x : ends)
+        for (int q = adj_off[x]; q < adj_off[x + 1]; ++q) {
+          const int y = adj[q];
+          for (int k = ln_off[y]; k < ln_off[y + 1]; ++k)
+            if (ln[k] != i && !std::binary_search(a1.begin(), a1.end(), ln[k])) a2.push_back(ln[k]);
+        }
+      std::sort(a2.begin(), a2.end());
+      a2.erase(std::unique(a2.begin(), a2.end()), a2.end());
+    }
+    for (int i = 0; i < m.l; ++i) {
+      o1[i + 1] = o1[i] + (int)s1[i].size();
+      o2[i + 1] = o2[i] + (int)s2[i].size();
+    }
+    r1.reserve(o1[m.l]);
+    r2.reserve(o2[m.l]);
+    for (int i = 0; i < m.l; ++i) {
+      r1.insert(r1.end(), s1[i].begin(), s1[i].end());
+      r2.insert(r2.end(), s2[i].begin(), s2[i].end());
+    }
+    auto up = [&](int **d, const std::vector<int> &h, const char *what) {
+      dev_alloc((void **)d, std::max<size_t>(h.size(), 1) * sizeof(int), what);
+      if (!h.empty()) hip_ok(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, st), what);
+    };
+    up(&L->n1_off, o1, "ring 1");
+    up(&L->n1, r1, "ring 1");
+    up(&L->n2_off, o2, "ring 2");
+    up(&L->n2, r2, "ring 2");
+    hip_ok(hipStreamSynchronize(st), "rings");
+  }
   dev_alloc((void **)&L->stats, 2 * sizeof(long long), "learned stats");
   hip_ok(hipMemsetAsync(L->stats, 0, 2 * sizeof(long long), st), "learned stats");
   hip_ok(hipStreamSynchronize(st), "learned init");
@@ -747,7 +854,8 @@ void features(pfft_ctx *c, Learned *L, Precond *P, int R, const double *omega, c
   ensure_infer(L, R, l);
   set_logf(L, R, omega, st);
   k_norms<<<R, 256, 0, st>>>(v, z, l, L->nrm);
-  FeatArgs a{v, z, L->nrm, P->d_fidx, P->dev.yinv, P->dev.link_kind, L->self_loop, L->logf, l, c->m.b, R, L->X};
+  FeatArgs a{v, z, L->nrm, P->d_fidx, P->dev.yinv, P->dev.link_kind, L->self_loop, L->logf,
+             L->n1_off, L->n1, L->n2_off, L->n2, l, c->m.b, R, L->X};
   const long long n = (long long)R * l;
   k_features<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a);
 }
@@ -793,6 +901,8 @@ pfft_status fail(const char *where, const std::string &msg, int code) {
 
 double learned_judge_factor(pfft_ctx *c) { return c->learned ? c->learned->judge : 0.0; }
 
+void learned_set_judge(pfft_ctx *c, double factor) { learned_of(c, nullptr)->judge = factor; }
+
 void learned_judged_off(pfft_ctx *c, int n) {
   if (c->learned) c->learned->judged_off += n;
 }
@@ -831,6 +941,8 @@ void learned_free(pfft_ctx *c) {
   L->bact.release();
   L->grads.release();
   clear_set(L);
+  for (void *p : {(void *)L->n1_off, (void *)L->n1, (void *)L->n2_off, (void *)L->n2})
+    if (p) hipFree(p);
   for (void *p : {(void *)L->stats, (void *)L->en, (void *)L->self_loop, (void *)L->X, (void *)L->nrm, (void *)L->ok,
                   (void *)L->logf, (void *)L->Xb, (void *)L->Tb, (void *)L->wb, (void *)L->d_loss})
     if (p) hipFree(p);
@@ -848,7 +960,7 @@ pfft_status pfft_precond_load(pfft_ctx *c, const void *blob, int64_t nbytes) {
   Shape s;
   if (!c || !parse_header(blob, nbytes, s)) return fail("pfft_precond_load", "malformed weight blob", PFFT_EINVAL);
   if (s.F != F_IN || s.O != F_OUT)
-    return fail("pfft_precond_load", "the correction network needs F = 8 inputs and O = 2 outputs", PFFT_EINVAL);
+    return fail("pfft_precond_load", "the correction network needs F = 16 inputs and O = 2 outputs", PFFT_EINVAL);
   try {
     hip_ok(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t st = nullptr;
