@@ -280,6 +280,9 @@ pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const 
  *                    most 63, 1 LDS-window band solve
  *   "project_plan" 0 tiled projection (tile moments staged in LDS),
  *                  1 node-major gather
+ *   "project_rhs"  tiled projection (FP32 grid): 0 16 right-hand sides per
+ *                    workgroup, 1 (default) eight (half the LDS staging, two
+ *                    workgroups per CU; the sums are the same bit for bit)
  *   "graphs"       1 solve_ports replays the product and P^-1 of each FGMRES
  *                    iteration as HIP graphs (after one eager iteration),
  *                  0 eager launches
@@ -330,8 +333,9 @@ pfft_status pfft_get_option(pfft_ctx *c, const char *name, int64_t *value);
 
 /* Times the preconditioned product P^-1 Z_l x (one FGMRES step) for nrhs
  * right-hand sides at omega[nrhs] (host, rad/s) for each value of fft_plan,
- * ldl_plan, project_plan, combine_plan and stream_split in turn (median of reps runs after one warm-up),
- * keeps the fastest value of each and writes a JSON report of the timings
+ * ldl_plan, project_plan, project_rhs, combine_plan, stream_split and
+ * near_dense in turn (median of reps runs after one warm-up), keeps the
+ * fastest value of each and writes a JSON report of the timings
  * (milliseconds) and choices into report[cap] (host, NUL-terminated, may be
  * NULL).  Allocates two nrhs x l complex128 device vectors for the run. */
 pfft_status pfft_autotune(pfft_ctx *c, int32_t nrhs, const double *omega, int32_t reps, char *report,

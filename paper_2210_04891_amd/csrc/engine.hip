@@ -508,6 +508,7 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
     }
     g.fft_plan = c->plans.fft;
     g.proj_plan = c->plans.proj;
+    g.proj_rhs = c->plans.proj_rhs;
     g.tt_off = upload(c, tt_off, st);
     g.tt_tri = upload(c, tt_tri, st);
     g.pg_loc = upload(c, pg_loc, st);
@@ -1188,6 +1189,7 @@ int *option_slot(pfft_ctx *c, const std::string &name) {
   if (name == "fft_plan") return &c->plans.fft;
   if (name == "ldl_plan") return &c->plans.ldl;
   if (name == "project_plan") return &c->plans.proj;
+  if (name == "project_rhs") return &c->plans.proj_rhs;
   if (name == "graphs") return &c->plans.graphs;
   if (name == "stream_split") return &c->plans.stream_split;
   if (name == "factor_plan") return &c->plans.factor;
@@ -1200,6 +1202,7 @@ int *option_slot(pfft_ctx *c, const std::string &name) {
 void sync_plans(pfft_ctx *c) {
   c->gm.fft_plan = c->plans.fft;
   c->gm.proj_plan = c->plans.proj;
+  c->gm.proj_rhs = c->plans.proj_rhs;
   c->gm.prune = c->plans.prune;
   c->cm.comb_plan = c->plans.comb;
   c->cm.near_dense = c->plans.near_dense;
@@ -1304,8 +1307,9 @@ extern "C" pfft_status pfft_autotune(pfft_ctx *c, int32_t nrhs, const double *om
       return (double)t[reps / 2];
     };
     std::string js = "{";
-    const char *names[6] = {"fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split", "near_dense"};
-    for (int o = 0; o < 6; ++o) {
+    const char *names[7] = {"fft_plan", "ldl_plan", "project_plan", "project_rhs", "combine_plan", "stream_split",
+                            "near_dense"};
+    for (int o = 0; o < 7; ++o) {
       int *slot = option_slot(c, names[o]);
       double best = 1e300;
       int arg = *slot;

@@ -59,6 +59,7 @@ struct GridMaps {
   // (ascending); pg_loc[q] = position of pg_tri[q] in its node's tile list;
   // the first tcap triangles of a tile are staged in LDS
   int tile[3], ntile[3], tcap;
+  int proj_rhs;          // tiled projection (FP32): 0 16 right-hand sides per workgroup, 1 eight
   const int *tt_off, *tt_tri, *pg_loc;
   // per tile, its local node indices with the most contributions first, so
   // the nodes of one wavefront have similar gather lengths

@@ -389,17 +389,17 @@ template <> struct ProjRG<double> { static constexpr int v = 1; };
 // that the 16-byte reads of lanes gathering different triangles spread over
 // the banks (a pitch that is a multiple of 128 bytes maps them to two bank
 // groups)
-template <typename T> constexpr int proj_pitch() {
-  return ProjRG<T>::v * ProjRC<T>::v * 4 + 16 / (int)sizeof(V2<T>);
+template <typename T, int RG> constexpr int proj_pitch() {
+  return RG * ProjRC<T>::v * 4 + 16 / (int)sizeof(V2<T>);
 }
 
 // skip_empty: node chunks without any contribution are not written (the
 // pruned FFT passes never read inactive nodes)
-template <typename T>
+template <typename T, int RG>
 __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *J, V2<T> *Q, int R, int skip_empty) {
-  constexpr int RC = ProjRC<T>::v, RG = ProjRG<T>::v, RB = RC * RG;
+  constexpr int RC = ProjRC<T>::v, RB = RC * RG;
   extern __shared__ unsigned char smraw[];
-  constexpr int PS = proj_pitch<T>();
+  constexpr int PS = proj_pitch<T, RG>();
   V2<T> *sJ = (V2<T> *)smraw;   // [tcap][PS]: (rr, comp) at rr * 4 + comp, rr < RB
   // one workgroup per (tile, group of RB right-hand sides), the groups of a
   // tile consecutive on one XCD: they read the tile's triangle and gather
@@ -535,20 +535,29 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
 template <typename T>
 static bool prune_ok(const GridMaps &g, long ch);
 
-template <typename T>
-void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st) {
+template <typename T, int RG>
+static bool project_tiled(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st) {
   constexpr int RC = ProjRC<T>::v;
   // largest staging any context asks for: 232 (FP32) or 376 (FP64) triangles
-  constexpr int lds_max = (sizeof(T) == 4 ? 232 : 376) * proj_pitch<T>() * (int)sizeof(V2<T>);
-  static const bool lds_ok = allow_lds((const void *)k_project_tiled<T>, lds_max);
-  const size_t lds = (size_t)g.tcap * proj_pitch<T>() * sizeof(V2<T>);
-  if (lds_ok && g.proj_plan == 0 && lds <= (size_t)lds_max) {
-    const unsigned ntile = (unsigned)g.ntile[0] * g.ntile[1] * g.ntile[2];
-    k_project_tiled<T><<<dim3(ntile * cdiv(R, RC * ProjRG<T>::v)), 512, lds, st>>>(g, J, Q, R,
-                                                                                  prune_ok<T>(g, 3L * R) ? 1 : 0);
-  } else {
-    k_project<T><<<dim3(cdiv(g.N, 256), cdiv(R, PRG)), 256, 0, st>>>(g, J, Q, R);
+  constexpr int lds_max = (sizeof(T) == 4 ? 232 : 376) * proj_pitch<T, RG>() * (int)sizeof(V2<T>);
+  static const bool lds_ok = allow_lds((const void *)k_project_tiled<T, RG>, lds_max);
+  const size_t lds = (size_t)g.tcap * proj_pitch<T, RG>() * sizeof(V2<T>);
+  if (!lds_ok || lds > (size_t)lds_max) return false;
+  const unsigned ntile = (unsigned)g.ntile[0] * g.ntile[1] * g.ntile[2];
+  k_project_tiled<T, RG><<<dim3(ntile * cdiv(R, RC * RG)), 512, lds, st>>>(g, J, Q, R, prune_ok<T>(g, 3L * R) ? 1 : 0);
+  return true;
+}
+
+template <typename T>
+void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st) {
+  if (g.proj_plan == 0) {
+    // 16 (FP32, default) or 8 right-hand sides per workgroup: the smaller
+    // staging area lets two workgroups share a CU
+    if (sizeof(T) == 4 && g.proj_rhs == 1 ? project_tiled<T, ProjRG<T>::v / 2 ? ProjRG<T>::v / 2 : 1>(g, J, Q, R, st)
+                                          : project_tiled<T, ProjRG<T>::v>(g, J, Q, R, st))
+      return;
   }
+  k_project<T><<<dim3(cdiv(g.N, 256), cdiv(R, PRG)), 256, 0, st>>>(g, J, Q, R);
 }
 
 // ===========================================================================
@@ -1366,8 +1375,12 @@ __global__ void __launch_bounds__(2 * BIG_T) k_fft_yz_big(YZArgs a, float2 *data
   float2 *S = big_sm + ey * L::SZ;
   for (int k = threadIdx.x; k < NY; k += 2 * BIG_T) twy[k] = tw<-1>(k, NY);
   if (threadIdx.x < N2) twh[threadIdx.x] = tw<-1>(threadIdx.x, LY);
-  // channels in descending order (the X passes run over them ascending)
-  const long cb = blockIdx.x / a.two_nx, kx = blockIdx.x - cb * a.two_nx, chan = ch - 1 - cb;
+  // planes k_x-major over the channels, in XCD-contiguous ranges: the
+  // channels of one k_x read the same spectrum plane, which then stays in
+  // the XCD's L2 (in channel-major order every workgroup refetched its
+  // 34 KB plane)
+  const long lb = (long)xcd_block(blockIdx.x, gridDim.x);
+  const long kx = lb / ch, chan = lb - kx * ch;
   float2 *io = data + (chan * a.two_nx + kx) * (long)(NY * NZ);
   const int fx = kx <= a.nx ? (int)kx : a.two_nx - (int)kx;
   const float *gpl = ghat + (long)fx * (NY + 1) * (NZ + 1);

@@ -66,13 +66,15 @@ def test_plans_agree_and_autotune(wires):
     om = 2 * np.pi * np.repeat(np.array([1e9, 1e10]), 10)
     x = torch.from_numpy(W.complex_normal(31, (om.size, l))).cuda()
     ref = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
-    for name in ("fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split", "near_dense"):
+    for name in ("fft_plan", "ldl_plan", "project_plan", "project_rhs", "combine_plan", "stream_split",
+                 "near_dense"):
         ctx.set_option(name, 1 - ctx.get_option(name))
         y = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND).cpu().numpy()
         ctx.set_option(name, 1 - ctx.get_option(name))
         assert np.linalg.norm(y - ref) <= 2e-6 * np.linalg.norm(ref), name
     rep = ctx.autotune(om, reps=2)
-    for name in ("fft_plan", "ldl_plan", "project_plan", "combine_plan", "stream_split", "near_dense"):
+    for name in ("fft_plan", "ldl_plan", "project_plan", "project_rhs", "combine_plan", "stream_split",
+                 "near_dense"):
         assert rep[name]["chosen"] in (0, 1)
         assert ctx.get_option(name) == rep[name]["chosen"]
         assert rep[name]["0"] > 0 and rep[name]["1"] > 0
@@ -139,3 +141,17 @@ def test_option_errors(wires):
         ctx.set_option("fft_plan", 2)
     with pytest.raises(P.PfftError):
         ctx.get_option("no_such_plan")
+
+
+@gpu
+def test_projection_rhs_groups_same_bits(wires):
+    """The tiled projection with 16 or 8 right-hand sides per workgroup sums
+    every node in the same order: the far field is the same bit for bit."""
+    import paper_2210_04891_amd as P
+    ctx = _ctx(wires)
+    b = ctx.sizes["b"]
+    x = torch.from_numpy(W.complex_normal(33, (21, b))).cuda()
+    ref = ctx.matvec(x, space=0, flags=P.PFFT_FAR_ONLY).cpu().numpy()
+    ctx.set_option("project_rhs", 1 - ctx.get_option("project_rhs"))
+    y = ctx.matvec(x, space=0, flags=P.PFFT_FAR_ONLY).cpu().numpy()
+    assert np.array_equal(y, ref)
