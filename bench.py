@@ -390,6 +390,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    # the autotuner picks each plan (FFT passes, band solve, projection tile
+    # shape, near-field kernel, stream split) on this workload's product
+    t_tune = time.perf_counter()
+    tune = ctx.autotune(omega, reps=3)
+    t_tune = time.perf_counter() - t_tune
+    print("bench: autotune %.1f s: %s" % (t_tune, {k: v["chosen"] for k, v in tune.items()}), file=sys.stderr,
+          flush=True)
     dt, stages, psteps = run_steps(ctx, R, omega, args.steps, args.warmup, P.PFFT_PRECOND)
     value = R * args.steps / dt
     print("bench: %d steps, %.1f ms/step" % (args.steps, dt / args.steps * 1e3), file=sys.stderr, flush=True)
@@ -410,7 +417,8 @@ def main():
         "dtype": "fp32 grid / fp64 near field, scans, preconditioner",
         "data": "synthetic",
         "config": {"workload": label, "triangles": sz["n"], "loops": sz["l"], "rhs": R, "grid": list(grid),
-                   "near_nnz": sz["nnz_near"], "setup_s": round(t_setup, 2)},
+                   "near_nnz": sz["nnz_near"], "setup_s": round(t_setup, 2),
+                   "plans": {k: v["chosen"] for k, v in tune.items()}, "autotune_s": round(t_tune, 2)},
         "roofline": roof,
         "stages_ms_per_step": {k: round(v[0] / psteps, 4) for k, v in stages.items() if v[1]},
         "stage_sum_ms": round(sum(v[0] for v in stages.values()) / psteps, 3),
@@ -467,9 +475,12 @@ def main():
         s2, f2, g2 = wires_workload()
         ctx2 = P.Context(s2, g2, stencil=4, near_kappa=1.5, grid_fp64=False)
         R2 = len(s2.ports) * len(f2)
-        dt2, st2, ps2 = run_steps(ctx2, R2, np.repeat(2 * np.pi * f2, len(s2.ports)), 20, 3, P.PFFT_PRECOND)
+        om2 = np.repeat(2 * np.pi * f2, len(s2.ports))
+        tune2 = ctx2.autotune(om2, reps=3)
+        dt2, st2, ps2 = run_steps(ctx2, R2, om2, 20, 3, P.PFFT_PRECOND)
         out["second_workload"] = {"workload": WORKLOADS["wires"][1], "value": round(R2 * 20 / dt2, 2),
                                   "unit": "RHS-matvecs/s", "ms_per_step": round(dt2 / 20 * 1e3, 3),
+                                  "plans": {k: v["chosen"] for k, v in tune2.items()},
                                   "stages_ms_per_step": {k: round(v[0] / ps2, 4) for k, v in st2.items() if v[1]}}
         ctx2.close()
     if not args.no_cpu_baseline and Krows is not None:

@@ -81,7 +81,7 @@ struct pfft_ctx {
     int fft = 0;      // 0 register-resident FFT passes where the shape allows, 1 LDS Stockham
     int ldl = 0;      // 0 register-window band solve when the band fits a wave, 1 LDS window
     int proj = 0;     // 0 tiled projection, 1 node-major gather
-    int proj_rhs = 1; // tiled projection (FP32): 0 16 right-hand sides per workgroup, 1 eight
+    int proj_rhs = 0; // tiled projection (FP32): 0 16 right-hand sides per workgroup, 1 eight
     int graphs = 1;   // 1 FGMRES replays the product and P^-1 as HIP graphs
     int stream_split = 0;  // 1: the right-hand sides of a product are split over two streams
     int factor = 0;   // 0 preconditioner factored on the device, 1 on the host

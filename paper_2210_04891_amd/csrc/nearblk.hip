@@ -266,7 +266,7 @@ void subdivided_rule(int level, std::vector<double> &R) {
 }
 
 void dev_ok(hipError_t e, const char *what) {
-  if (e != hipSuccess) throw SetupError{-5, std::string("near-field blocks: ") + what + ": " + hipGetErrorString(e)};
+  if (e != hipSuccess) throw SetupError{-4, std::string("near-field blocks: ") + what + ": " + hipGetErrorString(e)};
 }
 
 template <class X>

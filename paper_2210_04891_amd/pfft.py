@@ -64,6 +64,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libpfft.so is not built (run python -m paper_2210_04891_amd.build)")
+    # PyTorch, which provides the callers' device memory and streams, is
+    # loaded first: on a process whose first HIP call came from this library
+    # without it, the runtime has reported no device
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.pfft_setup.argtypes = [ctypes.POINTER(_Problem), vp, ctypes.POINTER(vp)]

@@ -171,3 +171,18 @@ def test_preconditioner_ordering_choice_and_nd_factor():
         assert nd[3] == 1 and nd[0] == auto[0] and nd[4] > 1
         assert h.get("nd_check_1GHz", np.float64)[0] < 1e-12
 
+
+
+def test_wide_conductor_selects_nested_dissection():
+    """A 1 x 1 mm plate of 132 x 132 cells (70,752 triangles, one conductor
+    of 70,226 nodes): its RCM band would be ~2 x 132 > 256, so the automatic
+    ordering takes nested dissection (the band solve, whose LDS window holds
+    4,096 entries, only ever meets bands up to 256), and the host mirror of
+    the supernodal sweeps solves the nodal system to rounding.  The grid is
+    fine (4 um cells) so that the near field stays small."""
+    xs = np.linspace(0, 1e-3, 133)
+    s = W.geometry.box_bar(xs, xs, np.array([0.0, 10e-6]), name="plate")
+    h = P.HostModel(s, (256, 256, 8), 4, 1.5)
+    auto = h.get("precond_info", np.int64)
+    assert auto[3] == 1 and auto[4] > 1000 and auto[6] > 5
+    assert h.get("nd_check_1GHz", np.float64)[0] < 1e-12

@@ -90,15 +90,15 @@ def box_bar(xs, ys, zs, split4=(), name="bar"):
                     ijk[a2] = j + dj
                     return P(*ijk)
                 p00, p10, p01, p11 = idx(0, 0), idx(1, 0), idx(0, 1), idx(1, 1)
+                V = pool.xyz      # coordinates so far (a list: no copy per cell)
                 if (fname, i, j) in split4:
-                    V = pool.array()
                     cen = 0.25 * (V[p00] + V[p10] + V[p01] + V[p11])
                     pc = pool.get(("C", fname, i, j), cen)
                     quad = [(p00, p10), (p10, p11), (p11, p01), (p01, p00)]
                     cand = [(pc, u, v) for u, v in quad]
                 else:
                     cand = [(p00, p10, p11), (p00, p11, p01)]
-                V = pool.array()
+                V = pool.xyz
                 for t in cand:
                     tris.append(_orient(V, t, np.array(nrm, float)))
                     face_of.append(fname)
