@@ -604,10 +604,12 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
   if (c->grid_fp64) {
     g.pg_w = upload(c, pg_w, st);
     g.tri_w = upload(c, tri_w, st);
+    g.tri_wd = (const double *)g.tri_w;
   } else {
     std::vector<float> a(pg_w.begin(), pg_w.end()), bb(tri_w.begin(), tri_w.end());
     g.pg_w = upload(c, a, st);
     g.tri_w = upload(c, bb, st);
+    g.tri_wd = upload(c, tri_w, st);
   }
   // ---- kernel spectrum: FFT of the circulant-embedded grid Green's function
   {

@@ -53,6 +53,7 @@ struct GridMaps {
   const int *pg_tri;
   const void *pg_w;      // [nnz][4] (M0, M1x, M1y, M1z) in T
   const void *tri_w;     // [n][64][4] same weights, triangle-major, in T
+  const double *tri_wd;  // the same in FP64 (the grouped interpolation's scalar weights)
   const void *ghat;      // [(Nx+1)(Ny+1)(Nz+1)] real spectrum in T
   // projection tiles of tile[0] x tile[1] x tile[2] nodes (z fastest):
   // triangles whose stencil meets tile T are tt_tri[tt_off[T] .. tt_off[T+1])

@@ -1952,80 +1952,39 @@ __global__ void k_interp_tri(GridMaps g, const V2<T> *phi, double2 *U, int R) {
   }
 }
 
-// FP32 path: phi is first transposed to node-major [N_a][3R] (channel
-// innermost) over the N_a active nodes only (those some triangle's stencil
-// touches; every other node is never read), then one workgroup per triangle
-// reads each stencil node's 3R channels as one coalesced row; the triangle's
-// weights and the nodes' compact indices are uniform (scalar loads).  Lane
-// (r, c) accumulates M1_c phi_c and M0 phi_c; the three components of U0 are
-// summed through LDS.
-// out[a][r] = in[r][act[a]] for the na active nodes (in: rows x N, out: na x rows)
-__global__ void __launch_bounds__(256) k_transpose_c64(const float2 *in, float2 *out, int rows, int N, int na,
+// FP32 path: phi ([R][3][N], grid channel 3r + c) is first transposed to
+// node-major [N_a][3][R] (component-major, right-hand side innermost) over
+// the N_a active nodes only (those some triangle's stencil touches; every
+// other node is never read).  One workgroup per (active-node tile of 32,
+// component c, block of 32 right-hand sides): reads of 32 channels' node
+// rows, writes of 32 consecutive right-hand sides of a node through an LDS
+// tile.
+__global__ void __launch_bounds__(256) k_transpose_c64(const float2 *in, float2 *out, int R, int N, int na,
                                                        const int *act) {
   __shared__ float2 tile[32][33];
-  const int a0 = (int)xcd_block(blockIdx.x, gridDim.x) * 32, r0 = blockIdx.y * 32;
+  const int a0 = (int)xcd_block(blockIdx.x, gridDim.x) * 32;
+  const int c = blockIdx.y % 3, r0 = (blockIdx.y / 3) * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
   const int node = a0 + tx < na ? act[a0 + tx] : 0;
   for (int k = ty; k < 32; k += 8) {
     const int r = r0 + k;
-    if (r < rows && a0 + tx < na) tile[k][tx] = in[(size_t)r * N + node];
+    if (r < R && a0 + tx < na) tile[k][tx] = in[(size_t)(3 * r + c) * N + node];
   }
   __syncthreads();
   for (int k = ty; k < 32; k += 8) {
     const int a = a0 + k, r = r0 + tx;
-    if (r < rows && a < na) out[(size_t)a * rows + r] = tile[tx][k];
-  }
-}
-
-__global__ void __launch_bounds__(256) k_interp_nm(GridMaps g, const float2 *phiT, double2 *U, int R) {
-  __shared__ double2 s0[256];
-  const int t = (int)xcd_block(blockIdx.x, gridDim.x);
-  const int ch = 3 * R;
-  const int Ny = g.dims[1], Nz = g.dims[2];
-  const float *w = (const float *)g.tri_w + (size_t)t * 256;
-  const int ax = g.anchor[3 * t], ay = g.anchor[3 * t + 1], az = g.anchor[3 * t + 2];
-  // passes of 255 channels (85 right-hand sides), so the three components of
-  // a right-hand side are always in the same pass
-  for (int base = 0; base < ch; base += 255) {
-    const int chn = base + threadIdx.x;
-    const bool ok = threadIdx.x < 255 && chn < ch;
-    const int c = ok ? chn % 3 : 0;
-    double a0x = 0, a0y = 0, a1x = 0, a1y = 0;
-#pragma unroll 8
-    for (int k = 0; k < 64; ++k) {
-      const int i = k >> 4, j = (k >> 2) & 3, l = k & 3;
-      const long node = ((long)(ax + i) * Ny + (ay + j)) * Nz + (az + l);
-      const int an = g.act_of[node];
-      const float m0 = w[4 * k], m1 = w[4 * k + 1 + c];
-      const float2 v = ok ? phiT[(size_t)an * ch + chn] : make_float2(0.f, 0.f);
-      a0x += (double)m1 * v.x;
-      a0y += (double)m1 * v.y;
-      a1x += (double)m0 * v.x;
-      a1y += (double)m0 * v.y;
-    }
-    s0[threadIdx.x] = make_double2(a0x, a0y);
-    __syncthreads();
-    if (ok) {
-      const int r = chn / 3;
-      double2 *o = U + ((size_t)t * R + r) * 4;   // U[t][r][4]
-      o[1 + c] = make_double2(a1x, a1y);
-      if (c == 0) {
-        const int lt = threadIdx.x;   // components 1, 2 of this r are lanes lt + 1, lt + 2 (same pass)
-        const double2 p0 = s0[lt], p1 = s0[lt + 1], p2 = s0[lt + 2];
-        o[0] = make_double2(p0.x + p1.x + p2.x, p0.y + p1.y + p2.y);
-      }
-    }
-    __syncthreads();
+    if (r < R && a < na) out[(size_t)a * 3 * R + (size_t)c * R + r] = tile[tx][k];
   }
 }
 
 // Triangles with the same anchor read the same 64 stencil nodes: a
-// workgroup takes up to INTERP_GROUP of them, and each lane (channel) reads a
-// node's value once for all of them.  The nodes' active positions and the
-// triangles' weights are uniform (scalar loads; a lane picks its component's
-// M1 from the four weights by selection), and a lane's node values are
-// loaded KC at a time before they are used.  Per (triangle, channel) the
-// sums run over k = 0 .. 63 in order, as in k_interp_nm.
+// workgroup takes up to INTERP_GROUP of them and a block of 64 right-hand
+// sides, each of its three wavefronts one component c of the grid
+// potential (lane = right-hand side), and reads a node's value once for all
+// of the group's triangles.  The nodes' active positions and the triangles'
+// FP64 weights (M0 and the wavefront's M1 component) are uniform, so they
+// are scalar loads; a lane's node values are loaded KC at a time before they
+// are used.  Per (triangle, channel) the sums run over k = 0 .. 63 in order.
 // read-only data addressed uniformly: through the constant address space the
 // compiler may use scalar loads even though the kernel also stores to memory
 template <typename T>
@@ -2033,75 +1992,65 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *uniform_ro
   return (const __attribute__((address_space(4))) T *)p;
 }
 
-__global__ void __launch_bounds__(256) k_interp_grp(GridMaps g, const float2 *phiT, double2 *U, int R) {
+__global__ void __launch_bounds__(192) k_interp_grp(GridMaps g, const float2 *phiT, double2 *U, int R) {
   constexpr int IG = INTERP_GROUP;
-  __shared__ double2 s0[IG][256];
-  // one workgroup per (block of 255 channels, group), the groups of one
-  // channel block consecutive: an XCD's workgroups then read neighbouring
-  // groups' stencil nodes within one channel block, a working set that
+  __shared__ double2 s0[IG][3][64];
+  // one workgroup per (block of 64 right-hand sides, group), the groups of
+  // one block consecutive: an XCD's workgroups then read neighbouring
+  // groups' stencil nodes within one block of channels, a working set that
   // fits its L2
   const int ch = 3 * R;
-  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), cbk = lb / g.nig, grp = lb - cbk * g.nig;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), rbk = lb / g.nig, grp = lb - rbk * g.nig;
   const int q0 = g.ig_off[grp], gn = g.ig_off[grp + 1] - q0;
+  const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int r = rbk * 64 + lane;
+  const bool ok = r < R;
+  const int cc = c * R + min(r, R - 1);   // phiT[a][c][r]
   int tq[IG];
-  const __attribute__((address_space(4))) float *wq[IG];
+  const __attribute__((address_space(4))) double *wq[IG];
 #pragma unroll
   for (int q = 0; q < IG; ++q) {
     tq[q] = g.ig_tri[q0 + min(q, gn - 1)];
-    wq[q] = uniform_ro((const float *)g.tri_w + (size_t)tq[q] * 256);
+    wq[q] = uniform_ro(g.tri_wd + (size_t)tq[q] * 256);
   }
   const __attribute__((address_space(4))) int *ia = uniform_ro(g.ig_act + (size_t)grp * 64);
   constexpr int KC = 16;   // node values in flight per lane
-  {
-    const int base = cbk * 255;   // 85 right-hand sides x 3 channels
-    const int chn = base + threadIdx.x;
-    const bool ok = threadIdx.x < 255 && chn < ch;
-    const int c = ok ? chn % 3 : 0;
-    const int cc = min(chn, ch - 1);
-    // the lane's M1 component as an exact blend (one factor is 1, the others
-    // 0), so the four weights stay uniform scalar loads rather than becoming
-    // a per-lane load of the selected one
-    const float e1 = c == 0 ? 1.f : 0.f, e2 = c == 1 ? 1.f : 0.f, e3 = c == 2 ? 1.f : 0.f;
-    double a0x[IG], a0y[IG], a1x[IG], a1y[IG];
+  double a0x[IG], a0y[IG], a1x[IG], a1y[IG];
 #pragma unroll
-    for (int q = 0; q < IG; ++q) a0x[q] = a0y[q] = a1x[q] = a1y[q] = 0;
-    for (int kh = 0; kh < 64; kh += KC) {
-      float2 v[KC];
+  for (int q = 0; q < IG; ++q) a0x[q] = a0y[q] = a1x[q] = a1y[q] = 0;
+  for (int kh = 0; kh < 64; kh += KC) {
+    float2 v[KC];
 #pragma unroll
-      for (int k = 0; k < KC; ++k) v[k] = phiT[(size_t)ia[kh + k] * ch + cc];
+    for (int k = 0; k < KC; ++k) v[k] = phiT[(size_t)ia[kh + k] * ch + cc];
 #pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        const double vx = ok ? (double)v[k].x : 0.0, vy = ok ? (double)v[k].y : 0.0;
-#pragma unroll
-        for (int q = 0; q < IG; ++q) {
-          const auto *w = wq[q] + 4 * (kh + k);   // (M0, M1x, M1y, M1z)
-          const double m0 = (double)w[0], m1 = (double)fmaf(e1, w[1], fmaf(e2, w[2], e3 * w[3]));
-          a0x[q] += m1 * vx;
-          a0y[q] += m1 * vy;
-          a1x[q] += m0 * vx;
-          a1y[q] += m0 * vy;
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < IG; ++q) s0[q][threadIdx.x] = make_double2(a0x[q], a0y[q]);
-    __syncthreads();
-    if (ok) {
-      const int r = chn / 3;
+    for (int k = 0; k < KC; ++k) {
+      const double vx = ok ? (double)v[k].x : 0.0, vy = ok ? (double)v[k].y : 0.0;
 #pragma unroll
       for (int q = 0; q < IG; ++q) {
-        if (q < gn) {
-          double2 *o = U + ((size_t)tq[q] * R + r) * 4;   // U[t][r][4]
-          o[1 + c] = make_double2(a1x[q], a1y[q]);
-          if (c == 0) {
-            const int lt = threadIdx.x;
-            const double2 p0 = s0[q][lt], p1 = s0[q][lt + 1], p2 = s0[q][lt + 2];
-            o[0] = make_double2(p0.x + p1.x + p2.x, p0.y + p1.y + p2.y);
-          }
+        const auto *w = wq[q] + 4 * (kh + k);   // (M0, M1x, M1y, M1z)
+        const double m0 = w[0], m1 = w[1 + c];
+        a0x[q] += m1 * vx;
+        a0y[q] += m1 * vy;
+        a1x[q] += m0 * vx;
+        a1y[q] += m0 * vy;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < IG; ++q) s0[q][c][lane] = make_double2(a0x[q], a0y[q]);
+  __syncthreads();
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < IG; ++q) {
+      if (q < gn) {
+        double2 *o = U + ((size_t)tq[q] * R + r) * 4;   // U[t][r][4]
+        o[1 + c] = make_double2(a1x[q], a1y[q]);
+        if (c == 0) {
+          const double2 p0 = s0[q][0][lane], p1 = s0[q][1][lane], p2 = s0[q][2][lane];
+          o[0] = make_double2(p0.x + p1.x + p2.x, p0.y + p1.y + p2.y);
         }
       }
     }
-    __syncthreads();
   }
 }
 
@@ -2113,11 +2062,10 @@ void interp_tri(const GridMaps &g, const V2<T> *phi, double2 *U, int R, hipStrea
 
 template <>
 void interp_tri<float>(const GridMaps &g, const float2 *phi, double2 *U, int R, hipStream_t st, void *scratch) {
-  // node-major copy of phi (N x 3R complex64) in the caller's free scratch
+  // node-major copy of phi ([N_a][3][R] complex64) in the caller's free scratch
   float2 *phiT = (float2 *)scratch;
-  const int ch = 3 * R;
-  k_transpose_c64<<<dim3(cdiv(g.nact, 32), cdiv(ch, 32)), 256, 0, st>>>(phi, phiT, ch, g.N, g.nact, g.act);
-  if (g.nig > 0) k_interp_grp<<<(unsigned)g.nig * cdiv(ch, 255), 256, 0, st>>>(g, phiT, U, R);
+  k_transpose_c64<<<dim3(cdiv(g.nact, 32), 3 * cdiv(R, 32)), 256, 0, st>>>(phi, phiT, R, g.N, g.nact, g.act);
+  if (g.nig > 0) k_interp_grp<<<(unsigned)g.nig * cdiv(R, 64), 192, 0, st>>>(g, phiT, U, R);
 }
 
 // ===========================================================================
