@@ -354,6 +354,9 @@ def main():
                     help="TRAIN,EVAL: train the correction network on TRAIN seeded trace layouts (seeds 0..) and "
                          "compare plain and learned sweeps on EVAL unseen ones (seeds 10000..); prints its own "
                          "JSON line and exits")
+    ap.add_argument("--plan", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a plan option instead of running the autotuner (repeatable; e.g. for profiler runs "
+                         "that should not include the autotuner's trial products)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before the steps, copy a buffer of this size three times (device to device) so that "
                          "hardware byte counters can be scaled against a transfer of known size")
@@ -393,9 +396,15 @@ def main():
     # the autotuner picks each plan (FFT passes, band solve, projection tile
     # shape, near-field kernel, stream split) on this workload's product
     t_tune = time.perf_counter()
-    tune = ctx.autotune(omega, reps=3)
+    if args.plan:
+        for kv in args.plan:
+            name, val = kv.split("=")
+            ctx.set_option(name, int(val))
+        tune = {name: {"chosen": ctx.get_option(name)} for name in (kv.split("=")[0] for kv in args.plan)}
+    else:
+        tune = ctx.autotune(omega, reps=3)
     t_tune = time.perf_counter() - t_tune
-    print("bench: autotune %.1f s: %s" % (t_tune, {k: v["chosen"] for k, v in tune.items()}), file=sys.stderr,
+    print("bench: plans (%.1f s): %s" % (t_tune, {k: v["chosen"] for k, v in tune.items()}), file=sys.stderr,
           flush=True)
     dt, stages, psteps = run_steps(ctx, R, omega, args.steps, args.warmup, P.PFFT_PRECOND)
     value = R * args.steps / dt
