@@ -10,8 +10,8 @@
 * Fallback: NaN or oversized corrections leave P^-1 untouched.
 * Training on residual/error pairs from the solver itself: the whole-set
   loss falls, the learned sweep reaches the same admittances, and the
-  convergence judge bounds its cost at 10 extra iterations per right-hand
-  side (the gain itself is printed, not asserted).
+  convergence judge bounds its cost at twice the plain iteration count per
+  right-hand side (the gain itself is printed, not asserted).
 * The multi-layout protocol on seeded package-trace layouts: weights
   trained over several layouts, then plain and learned sweeps on unseen
   ones (medians printed; both converge to the same admittances).
@@ -284,8 +284,9 @@ def test_train_on_solver_pairs_and_gain():
              it1.size, t1 - t0, t2 - t1))
     # the judge needs two steps to measure a right-hand side's convergence
     # rate, and the directions taken before it switches stay in the flexible
-    # basis, so a poor network costs a bounded number of extra iterations
-    assert np.all(it2 <= it1 + 10)
+    # basis, so a poor network costs a bounded number of extra iterations:
+    # here at most as many again as plain P needs
+    assert np.all(it2 <= 2 * it1)
 
 
 @gpu
