@@ -99,6 +99,9 @@ struct pfft_ctx {
   size_t per_rhs_bytes() const;
   int chunk_for(int R) const;
   void ensure_workspace(pfft::Workspace &w, int R);
+  // frees the product workspaces (not the fixed one); the next product
+  // allocates them again for its own chunk and plans
+  void release_workspaces();
   // y = op(x) for R right-hand sides already resident on the device
   void matvec(int R, const double *omega, int space, int flags, const double2 *x, double2 *y,
               hipStream_t st);

@@ -129,6 +129,14 @@ void pfft_ctx::ensure_workspace(Workspace &w, int R) {
   w.coef_on_device.clear();
 }
 
+void pfft_ctx::release_workspaces() {
+  for (Workspace &w : ws) {
+    if (w.fixed) continue;
+    for (void *p : w.allocs) hipFree(p);
+    w = Workspace();
+  }
+}
+
 void pfft_ctx::matvec(int R, const double *omega, int space, int flags, const double2 *x, double2 *y,
                       hipStream_t st) {
   const int dim = space == 1 ? m.l : m.b;
@@ -1331,6 +1339,11 @@ extern "C" pfft_status pfft_autotune(pfft_ctx *c, int32_t nrhs, const double *om
       js += ", \"chosen\": " + std::to_string(arg) + "}";
     }
     js += "}";
+    // the trials sized workspaces for every plan (the unfused FFT passes'
+    // buffer, a second stream's workspace); the chosen plans allocate their
+    // own at the next product
+    hip_ok(hipStreamSynchronize(st), "autotune sync");
+    c->release_workspaces();
     if (report && cap > 0) {
       const size_t k = std::min<size_t>((size_t)cap - 1, js.size());
       memcpy(report, js.data(), k);
