@@ -464,6 +464,7 @@ def main():
             t_collect = time.perf_counter() - t3
             t4 = time.perf_counter()
             ctx.learned_train(600, batch=8192, hidden=256, lr=1e-3, seed=0)
+            ctx.learned_clear()      # the training set (tens of GB here) is not needed by the sweep
             torch.cuda.synchronize()
             t_train = time.perf_counter() - t4
             t5 = time.perf_counter()

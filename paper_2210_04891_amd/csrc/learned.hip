@@ -620,14 +620,25 @@ struct Acts {
   }
 };
 
-void forward(const Net &n, long long rows, const uint16_t *X, Acts &a, hipStream_t st) {
+void forward(const Net &n, long long rows, const uint16_t *X, Acts &a, hipStream_t st, float *Y = nullptr) {
   const Shape &s = n.s;
   const int M = (int)rows, t = a.f32 ? 1 : 0;
   float *h1f = t ? (float *)a.H1 : nullptr, *h2f = t ? (float *)a.H2 : nullptr;
   uint16_t *h1b = t ? nullptr : (uint16_t *)a.H1, *h2b = t ? nullptr : (uint16_t *)a.H2;
   gemm({M, s.H, s.F, X, s.F, 1, 0, n.W1(), 1, s.F, 0, n.b1(), nullptr, 1, h1f, h1b, s.H}, st);
   gemm({M, s.H, s.H, a.H1, s.H, 1, t, n.W2(), 1, s.H, 0, n.b2(), nullptr, 1, h2f, h2b, s.H}, st);
-  gemm({M, s.O, s.H, a.H2, s.H, 1, t, n.W3(), 1, s.H, 0, n.b3(), nullptr, 0, a.Y, nullptr, s.O}, st);
+  gemm({M, s.O, s.H, a.H2, s.H, 1, t, n.W3(), 1, s.H, 0, n.b3(), nullptr, 0, Y ? Y : a.Y, nullptr, s.O}, st);
+}
+
+// inference over many rows in chunks of at most INFER_CHUNK (the hidden
+// activations of a chunk: 2 x INFER_CHUNK x H bf16), outputs into Y[rows][2]
+constexpr long long INFER_CHUNK = 1LL << 22;
+void forward_chunked(const Net &n, long long rows, const uint16_t *X, Acts &a, float *Y, hipStream_t st) {
+  a.ensure(std::min(rows, INFER_CHUNK), n.s.H, false);
+  for (long long r0 = 0; r0 < rows; r0 += INFER_CHUNK) {
+    const long long m = std::min(INFER_CHUNK, rows - r0);
+    forward(n, m, X + r0 * n.s.F, a, st, Y + 2 * r0);
+  }
 }
 
 // backward buffers for B rows (FP32)
@@ -694,8 +705,10 @@ struct Learned {
   std::vector<uint8_t> en_host;
   uint8_t *self_loop = nullptr; // [l]
   int *n1_off = nullptr, *n1 = nullptr, *n2_off = nullptr, *n2 = nullptr;  // link-neighbour rings
-  // inference
+  // inference (hidden activations per chunk of rows; outputs of all rows)
   Acts act;
+  float *Yall = nullptr;
+  long long cap_y = 0;
   long long cap_rows = 0;
   uint16_t *X = nullptr;
   int cap_R = 0;
@@ -924,10 +937,14 @@ bool learned_apply(pfft_ctx *c, int R, const double *omega, const double2 *v, do
     L->en_host = en;
   }
   const long long rows = (long long)R * l;
-  L->act.ensure(rows, L->net.s.H, false);
-  forward(L->net, rows, L->X, L->act, st);
-  k_check<<<R, 256, 0, st>>>(L->act.Y, l, DELTA_CAP2 * l, L->ok);
-  k_correct<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(z, L->act.Y, L->nrm, L->ok, L->en, l, R);
+  if (rows > L->cap_y) {
+    if (L->Yall) hipFree(L->Yall);
+    dev_alloc((void **)&L->Yall, (size_t)rows * F_OUT * 4, "mlp outputs");
+    L->cap_y = rows;
+  }
+  forward_chunked(L->net, rows, L->X, L->act, L->Yall, st);
+  k_check<<<R, 256, 0, st>>>(L->Yall, l, DELTA_CAP2 * l, L->ok);
+  k_correct<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(z, L->Yall, L->nrm, L->ok, L->en, l, R);
   k_stats<<<1, 1, 0, st>>>(L->ok, L->en, R, L->stats);
   hip_ok(hipGetLastError(), "learned apply");
   return true;
@@ -941,7 +958,7 @@ void learned_free(pfft_ctx *c) {
   L->bact.release();
   L->grads.release();
   clear_set(L);
-  for (void *p : {(void *)L->n1_off, (void *)L->n1, (void *)L->n2_off, (void *)L->n2})
+  for (void *p : {(void *)L->n1_off, (void *)L->n1, (void *)L->n2_off, (void *)L->n2, (void *)L->Yall})
     if (p) hipFree(p);
   for (void *p : {(void *)L->stats, (void *)L->en, (void *)L->self_loop, (void *)L->X, (void *)L->nrm, (void *)L->ok,
                   (void *)L->logf, (void *)L->Xb, (void *)L->Tb, (void *)L->wb, (void *)L->d_loss})
