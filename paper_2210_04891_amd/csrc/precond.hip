@@ -681,14 +681,15 @@ __device__ __forceinline__ double dbl_put(double v, double u, int l) {
 
 constexpr int RP = 32;   // rows of factor data in flight per buffer
 
-__global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *fidx, double2 *work, int R) {
-  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), c = lb / R, r = lb - c * R, lane = threadIdx.x;
-  const int lo = d.comp_off[c], hi = d.comp_off[c + 1], mid = d.comp_mid[c];
-  if (lo >= hi) return;
-  const int f = fidx[r];
+// The forward and backward band sweeps of one conductor for NR right-hand
+// sides of the same frequency (x[j] their slices of the work vector): the
+// factor rows are loaded once and feed NR independent substitution chains,
+// whose instructions the scheduler interleaves.
+template <int NR>
+__device__ __forceinline__ void band_sweeps(const PrecondDev &d, int f, double2 *const (&x)[NR], int lo, int mid,
+                                            int hi, int lane) {
   const double2 *rowp = d.env + (size_t)f * d.nu * 64;
   const double2 *colp = d.colenv + (size_t)f * d.nu * 64;
-  double2 *x = work + (size_t)r * d.nu;
   const double2 zero = make_double2(0, 0);
   const unsigned bytes = (unsigned)d.nu * 1024u;
   const __amdgpu_buffer_rsrc_t rrow = __builtin_amdgcn_make_buffer_rsrc((void *)rowp, (short)0, (int)bytes, 0x00020000);
@@ -696,127 +697,188 @@ __global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *f
   const int nb = mid - lo;
   // ---- forward, band rows: y = L^-1 b, column by column
   if (nb > 0) {
-    double ax, ay;
-    {
-      const double2 v = lane < nb ? x[lo + lane] : zero;
-      ax = v.x;
-      ay = v.y;
+    double ax[NR], ay[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      const double2 v = lane < nb ? x[j][lo + lane] : zero;
+      ax[j] = v.x;
+      ay[j] = v.y;
     }
     // right-hand side entering at step p (lane p mod 64) for the RP steps of
     // the block starting at p0: position p + 64
-    auto bload = [&](int p0) -> double2 {
+    auto bload = [&](int j, int p0) -> double2 {
       const int pl = (lane - p0) & 63, row = lo + p0 + pl + 64;
-      return (pl < RP && row < mid) ? x[row] : zero;
+      return (pl < RP && row < mid) ? x[j][row] : zero;
     };
-    double2 Lc[RP], Ln[RP], bc, bn;
+    double2 Lc[RP], Ln[RP], bc[NR], bn[NR];
 #pragma unroll
     for (int q = 0; q < RP; ++q)
       Lc[q] = band_load(rcol, (unsigned)((lane - q - 1) & 63) * 16u, q < nb ? (unsigned)(lo + q) * 1024u : bytes);
-    bc = bload(0);
-    double yx = 0, yy = 0;
-    // value of the current position, read one step ahead from the updated
-    // window (the hand-over of lane p mod 64 does not touch lane p + 1)
-    double vx = dbl_lane(ax, 0), vy = dbl_lane(ay, 0);
+    double yx[NR], yy[NR], vx[NR], vy[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      bc[j] = bload(j, 0);
+      yx[j] = yy[j] = 0;
+      // value of the current position, read one step ahead from the updated
+      // window (the hand-over of lane p mod 64 does not touch lane p + 1)
+      vx[j] = dbl_lane(ax[j], 0);
+      vy[j] = dbl_lane(ay[j], 0);
+    }
     for (int p0 = 0; p0 < nb; p0 += RP) {
       // positions [p0 - 64, p0) done: store them before this block's prefetch,
       // so no wait on the store drains the prefetch (vmcnt is in order)
-      if (p0 > 0 && (p0 & 63) == 0) x[lo + p0 - 64 + lane] = make_double2(yx, yy);
+      if (p0 > 0 && (p0 & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < NR; ++j) x[j][lo + p0 - 64 + lane] = make_double2(yx[j], yy[j]);
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
         const int p = p0 + RP + q;
         Ln[q] = band_load(rcol, (unsigned)((lane - p - 1) & 63) * 16u, p < nb ? (unsigned)(lo + p) * 1024u : bytes);
       }
-      bn = bload(p0 + RP);
+#pragma unroll
+      for (int j = 0; j < NR; ++j) bn[j] = bload(j, p0 + RP);
       __builtin_amdgcn_sched_barrier(0);
       const int sb = p0 & 63;
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
         const int s = sb + q;
         const double2 L = Lc[q];   // lane s: the unit self entry, so its sum becomes exactly 0
-        double fx = fma(-L.x, vx, ax), fy = fma(-L.x, vy, ay);
-        fx = fma(L.y, vy, fx);
-        fy = fma(-L.y, vx, fy);
-        yx = dbl_put(yx, vx, s);   // (vx, vy): the finished value of position s
-        yy = dbl_put(yy, vy, s);
-        vx = dbl_lane(fx, (s + 1) & 63);
-        vy = dbl_lane(fy, (s + 1) & 63);
-        ax = fx;
-        ay = fy;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+          double fx = fma(-L.x, vx[j], ax[j]), fy = fma(-L.x, vy[j], ay[j]);
+          fx = fma(L.y, vy[j], fx);
+          fy = fma(-L.y, vx[j], fy);
+          yx[j] = dbl_put(yx[j], vx[j], s);   // (vx, vy): the finished value of position s
+          yy[j] = dbl_put(yy[j], vy[j], s);
+          vx[j] = dbl_lane(fx, (s + 1) & 63);
+          vy[j] = dbl_lane(fy, (s + 1) & 63);
+          ax[j] = fx;
+          ay[j] = fy;
+        }
       }
       // the lanes finished in this block start position p + 64: their sums
       // so far are the updates it already received, to which its right-hand
       // side is added (bc is zero in every other lane)
-      ax += bc.x;
-      ay += bc.y;
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        ax[j] += bc[j].x;
+        ay[j] += bc[j].y;
+        bc[j] = bn[j];
+      }
 #pragma unroll
       for (int q = 0; q < RP; ++q) Lc[q] = Ln[q];
-      bc = bn;
     }
     {  // the last, partial batch
       const int b0 = (nb - 1) & ~63;
-      if (b0 + lane < nb) x[lo + b0 + lane] = make_double2(yx, yy);
+      if (b0 + lane < nb)
+#pragma unroll
+        for (int j = 0; j < NR; ++j) x[j][lo + b0 + lane] = make_double2(yx[j], yy[j]);
     }
   }
   slice_fence();
   __syncthreads();
-  ldl_middle(d, f, x, lo, mid, hi, lane);
+#pragma unroll
+  for (int j = 0; j < NR; ++j) ldl_middle(d, f, x[j], lo, mid, hi, lane);
   // ---- backward, band rows: x = L^-T z, row by row from the last
   if (nb > 0) {
-    double ax, ay;
-    {
+    double ax[NR], ay[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
       const int row = mid - 1 - lane;
-      const double2 v = row >= lo ? x[row] : zero;
-      ax = v.x;
-      ay = v.y;
+      const double2 v = row >= lo ? x[j][row] : zero;
+      ax[j] = v.x;
+      ay[j] = v.y;
     }
-    auto bload = [&](int p0) -> double2 {
+    auto bload = [&](int j, int p0) -> double2 {
       const int pl = (lane - p0) & 63, row = mid - 1 - (p0 + pl + 64);
-      return (pl < RP && row >= lo) ? x[row] : zero;
+      return (pl < RP && row >= lo) ? x[j][row] : zero;
     };
-    double2 Lc[RP], Ln[RP], bc, bn;
+    double2 Lc[RP], Ln[RP], bc[NR], bn[NR];
 #pragma unroll
     for (int q = 0; q < RP; ++q)
       Lc[q] = band_load(rrow, (unsigned)((lane - q - 1) & 63) * 16u, q < nb ? (unsigned)(mid - 1 - q) * 1024u : bytes);
-    bc = bload(0);
-    double ox = 0, oy = 0;
-    double vx = dbl_lane(ax, 0), vy = dbl_lane(ay, 0);
+    double ox[NR], oy[NR], vx[NR], vy[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      bc[j] = bload(j, 0);
+      ox[j] = oy[j] = 0;
+      vx[j] = dbl_lane(ax[j], 0);
+      vy[j] = dbl_lane(ay[j], 0);
+    }
     for (int p0 = 0; p0 < nb; p0 += RP) {
-      if (p0 > 0 && (p0 & 63) == 0) x[mid - 1 - (p0 - 64 + lane)] = make_double2(ox, oy);
+      if (p0 > 0 && (p0 & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < NR; ++j) x[j][mid - 1 - (p0 - 64 + lane)] = make_double2(ox[j], oy[j]);
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
         const int p = p0 + RP + q;
         Ln[q] = band_load(rrow, (unsigned)((lane - p - 1) & 63) * 16u, p < nb ? (unsigned)(mid - 1 - p) * 1024u : bytes);
       }
-      bn = bload(p0 + RP);
+#pragma unroll
+      for (int j = 0; j < NR; ++j) bn[j] = bload(j, p0 + RP);
       __builtin_amdgcn_sched_barrier(0);
       const int sb = p0 & 63;
 #pragma unroll
       for (int q = 0; q < RP; ++q) {
         const int s = sb + q;
         const double2 L = Lc[q];   // lane s: the unit self entry, so its sum becomes exactly 0
-        double fx = fma(-L.x, vx, ax), fy = fma(-L.x, vy, ay);
-        fx = fma(L.y, vy, fx);
-        fy = fma(-L.y, vx, fy);
-        ox = dbl_put(ox, vx, s);   // (vx, vy): the finished value of position s
-        oy = dbl_put(oy, vy, s);
-        vx = dbl_lane(fx, (s + 1) & 63);
-        vy = dbl_lane(fy, (s + 1) & 63);
-        ax = fx;
-        ay = fy;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+          double fx = fma(-L.x, vx[j], ax[j]), fy = fma(-L.x, vy[j], ay[j]);
+          fx = fma(L.y, vy[j], fx);
+          fy = fma(-L.y, vx[j], fy);
+          ox[j] = dbl_put(ox[j], vx[j], s);   // (vx, vy): the finished value of position s
+          oy[j] = dbl_put(oy[j], vy[j], s);
+          vx[j] = dbl_lane(fx, (s + 1) & 63);
+          vy[j] = dbl_lane(fy, (s + 1) & 63);
+          ax[j] = fx;
+          ay[j] = fy;
+        }
       }
-      // the lanes finished in this block start position p + 64: their sums
-      // so far are the updates it already received, to which its right-hand
-      // side is added (bc is zero in every other lane)
-      ax += bc.x;
-      ay += bc.y;
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        ax[j] += bc[j].x;
+        ay[j] += bc[j].y;
+        bc[j] = bn[j];
+      }
 #pragma unroll
       for (int q = 0; q < RP; ++q) Lc[q] = Ln[q];
-      bc = bn;
     }
     {  // the last, partial batch
       const int b0 = (nb - 1) & ~63;
-      if (b0 + lane < nb) x[mid - 1 - (b0 + lane)] = make_double2(ox, oy);
+      if (b0 + lane < nb)
+#pragma unroll
+        for (int j = 0; j < NR; ++j) x[j][mid - 1 - (b0 + lane)] = make_double2(ox[j], oy[j]);
     }
+  }
+}
+
+// One wavefront per (conductor, right-hand side) or, with NR = 2, per
+// (conductor, pair of consecutive right-hand sides): a pair of the same
+// frequency shares its factor-row loads; a pair of two frequencies (or a
+// last single right-hand side) is solved one after the other.
+template <int NR>
+__global__ void __launch_bounds__(64) k_ldl_solve_reg(PrecondDev d, const int *fidx, double2 *work, int R) {
+  const int ng = (R + NR - 1) / NR;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x), c = lb / ng, r = (lb - c * ng) * NR, lane = threadIdx.x;
+  const int lo = d.comp_off[c], hi = d.comp_off[c + 1], mid = d.comp_mid[c];
+  if (lo >= hi) return;
+  double2 *xa = work + (size_t)r * d.nu;
+  const int f = fidx[r];
+  if (NR == 2 && r + 1 < R && fidx[r + 1] == f) {
+    double2 *const xs[2] = {xa, work + (size_t)(r + 1) * d.nu};
+    band_sweeps<2>(d, f, xs, lo, mid, hi, lane);
+    return;
+  }
+  {
+    double2 *const xs[1] = {xa};
+    band_sweeps<1>(d, f, xs, lo, mid, hi, lane);
+  }
+  if (NR == 2 && r + 1 < R) {
+    slice_fence();
+    __syncthreads();
+    double2 *const xs[1] = {work + (size_t)(r + 1) * d.nu};
+    band_sweeps<1>(d, fidx[r + 1], xs, lo, mid, hi, lane);
   }
 }
 
@@ -1010,8 +1072,12 @@ void precond_apply(const PrecondDev &d, const int *fidx, const double2 *y, doubl
     throw SetupError{-1, "preconditioner band larger than 2 GB per frequency"};
   // the circular LDS window of the widest solve holds 4096 entries
   if (!ldl_reg_plan(d) && span >= 4096) throw SetupError{-1, "preconditioner band too wide for the band solve"};
-  if (ldl_reg_plan(d))
-    k_ldl_solve_reg<<<g, 64, 0, st>>>(d, fidx, work, R);
+  if (ldl_reg_plan(d) && d.ncomp * R >= 4 * 1024)
+    // many more chains than SIMDs (one wavefront per SIMD at 256 VGPRs):
+    // two right-hand sides per wavefront halve the rounds
+    k_ldl_solve_reg<2><<<dim3((unsigned)d.ncomp * (unsigned)((R + 1) / 2)), 64, 0, st>>>(d, fidx, work, R);
+  else if (ldl_reg_plan(d))
+    k_ldl_solve_reg<1><<<g, 64, 0, st>>>(d, fidx, work, R);
   else if (span < 128)
     k_ldl_solve<128><<<g, 64, 0, st>>>(d, fidx, work, R);
   else if (span < 512)

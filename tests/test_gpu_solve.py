@@ -193,3 +193,26 @@ def test_solve_ports_rejects_bad_input(c1):
     # an unreachable tolerance within 2 iterations reports non-convergence
     Y, it, rr, code = ctx.solve_ports([1e9], tol=1e-12, maxit=2, restart=2)
     assert code == -5 and it[0, 0] == 2 and rr[0, 0] > 1e-12
+
+
+@gpu
+def test_band_solve_pairs_of_right_hand_sides():
+    """With many more (conductor, right-hand side) chains than SIMDs the band
+    solve carries two right-hand sides per wavefront, sharing the factor rows
+    when they have the same frequency and solving them in turn when not.
+    2,200 right-hand sides on a two-wire array (2 conductors: 4,400 chains),
+    frequencies in runs (shared rows) and then alternating (the two-frequency
+    pairs): P^-1 equals the LDS-window band solve's to rounding."""
+    import paper_2210_04891_amd as P
+    s = W.bond_wires(nwire=2, nseg=24, span=0.4e-3, height=80e-6)
+    ctx = P.Context(s, (32, 32, 16), near_kappa=1.5, grid_fp64=False)
+    l = ctx.sizes["l"]
+    f = np.array([1e8, 2e9, 3e10])
+    om = 2 * np.pi * np.concatenate([np.repeat(f, 400), np.tile(f, 333), f[:1]])
+    assert om.size == 2200
+    x = torch.from_numpy(W.complex_normal(51, (om.size, l))).cuda()
+    y = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND_ONLY).cpu().numpy()
+    ctx.set_option("ldl_plan", 1)
+    ref = ctx.matvec(x, omega=om, flags=P.PFFT_PRECOND_ONLY).cpu().numpy()
+    err = np.linalg.norm(y - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-12, err.max()
