@@ -427,6 +427,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": label, "triangles": sz["n"], "loops": sz["l"], "rhs": R, "grid": list(grid),
                    "near_nnz": sz["nnz_near"], "setup_s": round(t_setup, 2),
+                   "setup_phases_ms": dict(zip(("topology", "circuit", "gram", "grid", "near_lists",
+                                                "near_pair_blocks_device", "near_csr", "device_build"),
+                                               np.round(ctx.model_array("setup_ms", np.float64), 1).tolist())),
                    "plans": {k: v["chosen"] for k, v in tune.items()}, "autotune_s": round(t_tune, 2)},
         "roofline": roof,
         "stages_ms_per_step": {k: round(v[0] / psteps, 4) for k, v in stages.items() if v[1]},
