@@ -33,7 +33,7 @@ sys.path.insert(0, HERE)
 HBM_PEAK_GBS = 8000.0
 # MI355X vector FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6
 # TFLOP/s per instruction stream; packed FP32 doubles it to the published
-# 157.3 TFLOP/s (this build does not emit packed FP32)
+# 157.3 TFLOP/s (the library's kernels are compiled without packed FP32)
 FP32_PEAK_TFLOPS = 157.3
 FP32_NOPACK_TFLOPS = 78.6
 
@@ -362,8 +362,8 @@ def main():
                          "hardware byte counters can be scaled against a transfer of known size")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the whole hot path on a single "
-              "MI355X (sharding over right-hand sides is a design note, not built); use --gpus 1",
+        print("bench.py measures one GPU: the library runs the whole hot path on a single "
+              "MI355X (sharding over right-hand sides is described, not built); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import torch
