@@ -1,5 +1,6 @@
 // Context of the C ABI: host model, device arrays, workspaces.
 #pragma once
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -73,9 +74,10 @@ struct pfft_ctx {
   pfft::CombineMaps cm{};
   // per-product workspaces and the two stream lanes the right-hand sides
   // are split over (fork/join by events on the caller's stream)
-  pfft::Workspace ws[2];
-  hipStream_t lane[2] = {nullptr, nullptr};
-  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  pfft::Workspace ws[kLanes];
+  static constexpr int kLanes = 4;   // stream lanes of the split product
+  hipStream_t lane[kLanes] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kLanes] = {};
   // plan options (pfft_set_option, pfft_autotune)
   struct Plans {
     int fft = 0;      // 0 register-resident FFT passes where the shape allows, 1 LDS Stockham
@@ -83,7 +85,7 @@ struct pfft_ctx {
     int proj = 0;     // 0 tiled projection, 1 node-major gather
     int proj_rhs = 0; // tiled projection (FP32): 0 16 right-hand sides per workgroup, 1 eight
     int graphs = 1;   // 1 FGMRES replays the product and P^-1 as HIP graphs
-    int stream_split = 0;  // 1: the right-hand sides of a product are split over two streams
+    int stream_split = 0;  // 1: the right-hand sides of a product are split over kLanes streams
     int factor = 0;   // 0 preconditioner factored on the device, 1 on the host
     int comb = 0;     // 0 LDS-tiled near-field product when the tiles fit, 1 gather
     int prune = 1;    // 1 register FFT passes skip grid columns and nodes no stencil touches
@@ -113,7 +115,7 @@ struct pfft_ctx {
   // device maps of the post-processing (built on first use)
   int *d_tri_pos = nullptr, *d_tri_ref = nullptr, *d_port_loop = nullptr;
   // Runs fn(r0, rn, stream, workspace) for the right-hand sides [0, R),
-  // split over the two stream lanes when enabled (not while profiling).
+  // split over the kLanes stream lanes when enabled (not while profiling).
   template <typename Fn> void run_split(int R, hipStream_t st, Fn &&fn);
   bool split_ok(int R) const { return plans.stream_split == 1 && !timer.on && R >= 8; }
 };
@@ -124,17 +126,18 @@ void pfft_ctx::run_split(int R, hipStream_t st, Fn &&fn) {
     fn(0, R, st, ws[0]);
     return;
   }
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < kLanes; ++i)
     if (!lane[i]) {
       pfft::hip_ok(hipStreamCreateWithFlags(&lane[i], hipStreamNonBlocking), "lane stream");
       pfft::hip_ok(hipEventCreateWithFlags(&ev_join[i], hipEventDisableTiming), "lane event");
     }
   if (!ev_fork) pfft::hip_ok(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "fork event");
   pfft::hip_ok(hipEventRecord(ev_fork, st), "fork");
-  const int half = (R + 1) / 2;
-  for (int i = 0; i < 2; ++i) {
+  const int q = (R + kLanes - 1) / kLanes;
+  for (int i = 0; i < kLanes; ++i) {
+    const int r0 = i * q, rn = std::min(R, r0 + q) - r0;
+    if (rn <= 0) break;
     pfft::hip_ok(hipStreamWaitEvent(lane[i], ev_fork, 0), "fork wait");
-    const int r0 = i ? half : 0, rn = i ? R - half : half;
     fn(r0, rn, lane[i], ws[i]);
     pfft::hip_ok(hipEventRecord(ev_join[i], lane[i]), "join");
     pfft::hip_ok(hipStreamWaitEvent(st, ev_join[i], 0), "join wait");

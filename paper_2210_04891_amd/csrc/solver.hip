@@ -57,7 +57,7 @@ void pfft_ctx_free(pfft_ctx *c) {
   learned_free(c);
   for (auto &w : c->ws)
     for (void *p : w.allocs) hipFree(p);
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < pfft_ctx::kLanes; ++i) {
     if (c->lane[i]) hipStreamDestroy(c->lane[i]);
     if (c->ev_join[i]) hipEventDestroy(c->ev_join[i]);
   }
