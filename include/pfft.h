@@ -287,10 +287,10 @@ pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const 
  *                    iteration as HIP graphs (after one eager iteration),
  *                  0 eager launches
  *   "stream_split" 1 the right-hand sides of a product (and of P^-1) are
- *                    split into four parts run on four streams of the
+ *                    split into two halves run on two streams of the
  *                    context (default priority), forked from and joined to
- *                    the caller's stream with events, so kernels of one part
- *                    can overlap those of the others (not while profiling);
+ *                    the caller's stream with events, so kernels of one half
+ *                    can overlap those of the other (not while profiling);
  *                    0 (default) one stream
  *   "combine_plan" 0 near-field product over row tiles with the tile's
  *                    columns of x staged in LDS (when every tile's column list
