@@ -740,22 +740,31 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
     const int nt = (b + tr - 1) / tr;
     std::vector<int> ct_off(nt + 1, 0);
     std::vector<std::vector<int>> cols(nt);
-    bool fits = true;
+    // a candidate fails at its first tile whose column list overflows the
+    // staging area; the other threads then stop sorting
+    int over = 0;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int T = 0; T < nt; ++T) {
+      int seen;
+#pragma omp atomic read
+      seen = over;
+      if (seen) continue;
       const int64_t q0 = m.nf_rowptr[(size_t)T * tr], q1 = m.nf_rowptr[std::min(b, (T + 1) * tr)];
       std::vector<int> u(m.nf_col.begin() + q0, m.nf_col.begin() + q1);
       std::sort(u.begin(), u.end());
       u.erase(std::unique(u.begin(), u.end()), u.end());
+      if ((int)u.size() > ucap) {
+#pragma omp atomic write
+        over = 1;
+      }
       cols[T] = std::move(u);
     }
+    if (over) continue;
     int umax = 0;
     for (int T = 0; T < nt; ++T) {
       umax = std::max(umax, (int)cols[T].size());
       ct_off[T + 1] = ct_off[T] + (int)cols[T].size();
     }
-    if (umax > ucap) fits = false;
-    if (!fits) continue;
     cm.crc = rc;
     std::vector<int> ct_col(ct_off[nt]);
     std::vector<uint16_t> slot(m.nf_col.size());
