@@ -574,14 +574,23 @@ static void build_device(pfft_ctx *c, hipStream_t st) {
   }
   {
     // triangles sorted by anchor (then index); runs of one anchor cut into
-    // groups of INTERP_GROUP
+    // groups of INTERP_GROUP, in Z-order (Morton) of their anchors: the
+    // groups that run at the same time on an XCD then cover a compact block
+    // of the grid and share most of their stencil nodes in its L2
     std::vector<int> ord(n);
     for (int t = 0; t < n; ++t) ord[t] = t;
-    auto key = [&](int t) {
-      return ((long)m.anchor[3 * t] * m.dims[1] + m.anchor[3 * t + 1]) * m.dims[2] + m.anchor[3 * t + 2];
+    auto spread3 = [](uint64_t v) {   // bit i of v to bit 3 i
+      uint64_t r = 0;
+      for (int i = 0; i < 21; ++i) r |= ((v >> i) & 1ull) << (3 * i);
+      return r;
     };
+    std::vector<uint64_t> mkey(n);
+    for (int t = 0; t < n; ++t)
+      mkey[t] = (spread3((uint64_t)m.anchor[3 * t]) << 2) | (spread3((uint64_t)m.anchor[3 * t + 1]) << 1) |
+                spread3((uint64_t)m.anchor[3 * t + 2]);
+    auto key = [&](int t) { return mkey[t]; };
     std::sort(ord.begin(), ord.end(), [&](int a2, int b2) {
-      const long ka = key(a2), kb = key(b2);
+      const uint64_t ka = key(a2), kb = key(b2);
       return ka != kb ? ka < kb : a2 < b2;
     });
     std::vector<int> ig_off{0};
