@@ -76,9 +76,13 @@ typedef struct {
 } pfft_problem;
 
 /* Build a context: topology, loop basis, Gram blocks, grid and projection
- * weights, kernel spectrum, near-field pre-correction (Sec. II-IV).  Work that
- * needs the GPU runs on hip_stream (a hipStream_t, may be NULL).  *out is
- * owned by the caller and released with pfft_destroy. */
+ * weights, kernel spectrum, near-field pre-correction (Sec. II-IV).  The
+ * near pairs' blocks (direct integral minus the grid's own interaction,
+ * Eq. Lb) are computed on the current device, one thread per pair; lists
+ * and the edge-level CSR are built on the host.  Work that needs the GPU
+ * runs on hip_stream (a hipStream_t, may be NULL).  Device-side failures
+ * return PFFT_EDEVICE (or PFFT_ENOMEM).  *out is owned by the caller and
+ * released with pfft_destroy. */
 pfft_status pfft_setup(const pfft_problem *pb, void *hip_stream, pfft_ctx **out);
 
 /* out[0..9] = n, n', b, l, s, p, nnz of the near-field matrix, N_g,
