@@ -114,11 +114,11 @@ def big_plane_flops(ny, nz):
     return tot + 4 * ny * nz
 
 
-def measured_traffic(stage, table):
-    """HBM bytes per launch of a stage from a committed counter table
-    (profiles/<table>.json: rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled
-    by a 1 GiB copy), or None when the table has no entry or the kernel
-    sources changed since the counters were taken."""
+def traffic_table(table):
+    """A committed counter table (profiles/<table>.json: rocprofv3
+    FETCH_SIZE and WRITE_SIZE per kernel, each scaled by a 1 GiB copy), or
+    None when it is absent or the kernel sources changed since the counters
+    were taken."""
     import hashlib
     path = os.path.join(HERE, "profiles", table + ".json")
     try:
@@ -131,26 +131,21 @@ def measured_traffic(stage, table):
                 return None
         except OSError:
             return None
-    ent = tab.get("stages", {}).get(stage)
+    return tab
+
+
+def measured_traffic(stage, table):
+    """HBM bytes per launch of a stage from the counter table, or None."""
+    tab = traffic_table(table)
+    ent = None if tab is None else tab.get("stages", {}).get(stage)
     return None if ent is None else int(ent["read_bytes"] + ent["write_bytes"])
 
 
 def measured_step_bytes(table):
     """HBM bytes of one whole step (every kernel of the product) from the
-    same committed counter table, or None when it is stale or absent."""
-    import hashlib
-    path = os.path.join(HERE, "profiles", table + ".json")
-    try:
-        tab = json.load(open(path))
-    except (OSError, ValueError):
-        return None
-    for rel, sha in tab.get("sources_sha256", {}).items():
-        try:
-            if hashlib.sha256(open(os.path.join(HERE, rel), "rb").read()).hexdigest() != sha:
-                return None
-        except OSError:
-            return None
-    if "step_read_bytes" not in tab:
+    counter table, or None."""
+    tab = traffic_table(table)
+    if tab is None or "step_read_bytes" not in tab:
         return None
     return int(tab["step_read_bytes"] + tab["step_write_bytes"])
 
