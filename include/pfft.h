@@ -285,8 +285,9 @@ pfft_status pfft_mlp_grad(int32_t rows, const void *blob, int64_t nbytes, const 
  *   "project_plan" 0 tiled projection (tile moments staged in LDS),
  *                  1 node-major gather
  *   "project_rhs"  tiled projection (FP32 grid): 0 (default) 16 right-hand
- *                    sides per workgroup, 1 eight (half the LDS staging, two
- *                    workgroups per CU; the sums are the same bit for bit)
+ *                    sides per workgroup, 1 eight (half the LDS staging per
+ *                    workgroup, twice the workgroups; the sums are the same
+ *                    bit for bit)
  *   "graphs"       1 solve_ports replays the product and P^-1 of each FGMRES
  *                    iteration as HIP graphs (after one eager iteration),
  *                  0 eager launches

@@ -551,8 +551,9 @@ static bool project_tiled(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hi
 template <typename T>
 void project(const GridMaps &g, const V2<T> *J, V2<T> *Q, int R, hipStream_t st) {
   if (g.proj_plan == 0) {
-    // 16 (FP32, default) or 8 right-hand sides per workgroup: the smaller
-    // staging area lets two workgroups share a CU
+    // 16 (FP32, default) or 8 right-hand sides per workgroup: half the
+    // staging per workgroup and twice the workgroups (at about 160 VGPRs one
+    // 512-thread workgroup runs per CU either way)
     if (sizeof(T) == 4 && g.proj_rhs == 1 ? project_tiled<T, ProjRG<T>::v / 2 ? ProjRG<T>::v / 2 : 1>(g, J, Q, R, st)
                                           : project_tiled<T, ProjRG<T>::v>(g, J, Q, R, st))
       return;
