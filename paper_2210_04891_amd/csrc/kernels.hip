@@ -488,15 +488,16 @@ __global__ void __launch_bounds__(512) k_project_tiled(GridMaps g, const V2<T> *
 #pragma unroll
           for (int c = 0; c < 4; ++c) jv[q][c] = q < nr ? jt[4 * q + c] : cmk<T>(0, 0);
       }
+      // two fused multiply-adds per output (J0 M1_c, then - J_c M0)
 #pragma unroll
       for (int q = 0; q < RC; ++q) {
         const V2<T> j0 = jv[q][0], jx = jv[q][1], jy = jv[q][2], jz = jv[q][3];
-        acc[q][0] += j0.x * m1x - jx.x * m0;
-        acc[q][1] += j0.y * m1x - jx.y * m0;
-        acc[q][2] += j0.x * m1y - jy.x * m0;
-        acc[q][3] += j0.y * m1y - jy.y * m0;
-        acc[q][4] += j0.x * m1z - jz.x * m0;
-        acc[q][5] += j0.y * m1z - jz.y * m0;
+        acc[q][0] = fma(-jx.x, m0, fma(j0.x, m1x, acc[q][0]));
+        acc[q][1] = fma(-jx.y, m0, fma(j0.y, m1x, acc[q][1]));
+        acc[q][2] = fma(-jy.x, m0, fma(j0.x, m1y, acc[q][2]));
+        acc[q][3] = fma(-jy.y, m0, fma(j0.y, m1y, acc[q][3]));
+        acc[q][4] = fma(-jz.x, m0, fma(j0.x, m1z, acc[q][4]));
+        acc[q][5] = fma(-jz.y, m0, fma(j0.y, m1z, acc[q][5]));
       }
     };
     if (K > 0) {
