@@ -1957,23 +1957,28 @@ __global__ void k_interp_tri(GridMaps g, const V2<T> *phi, double2 *U, int R) {
 // FP32 path: phi ([R][3][N], grid channel 3r + c) is first transposed to
 // node-major [N_a][3][R] (component-major, right-hand side innermost) over
 // the N_a active nodes only (those some triangle's stencil touches; every
-// other node is never read).  One workgroup per (active-node tile of 32,
-// component c, block of 32 right-hand sides): reads of 32 channels' node
-// rows, writes of 32 consecutive right-hand sides of a node through an LDS
-// tile.
+// other node is never read).  One workgroup per (active-node tile of 64,
+// component c, block of 32 right-hand sides): reads of 32 channels' runs of
+// 64 active nodes, writes of 32 consecutive right-hand sides of a node,
+// through an LDS tile (16.6 KB; a 64 x 64 tile took twice that and ran
+// slower).
 __global__ void __launch_bounds__(256) k_transpose_c64(const float2 *in, float2 *out, int R, int N, int na,
                                                        const int *act) {
-  __shared__ float2 tile[32][33];
-  const int a0 = (int)xcd_block(blockIdx.x, gridDim.x) * 32;
+  __shared__ float2 tile[32][65];   // [right-hand side][node]
+  const int a0 = (int)xcd_block(blockIdx.x, gridDim.x) * 64;
   const int c = blockIdx.y % 3, r0 = (blockIdx.y / 3) * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-  const int node = a0 + tx < na ? act[a0 + tx] : 0;
-  for (int k = ty; k < 32; k += 8) {
-    const int r = r0 + k;
-    if (r < R && a0 + tx < na) tile[k][tx] = in[(size_t)(3 * r + c) * N + node];
+  {
+    const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;   // 64 x 4
+    const bool ok = a0 + lane < na;
+    const int node = ok ? act[a0 + lane] : 0;
+    for (int k = row; k < 32; k += 4) {
+      const int r = r0 + k;
+      if (r < R && ok) tile[k][lane] = in[(size_t)(3 * r + c) * N + node];
+    }
   }
   __syncthreads();
-  for (int k = ty; k < 32; k += 8) {
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int k = ty; k < 64; k += 8) {
     const int a = a0 + k, r = r0 + tx;
     if (r < R && a < na) out[(size_t)a * 3 * R + (size_t)c * R + r] = tile[tx][k];
   }
@@ -2066,7 +2071,7 @@ template <>
 void interp_tri<float>(const GridMaps &g, const float2 *phi, double2 *U, int R, hipStream_t st, void *scratch) {
   // node-major copy of phi ([N_a][3][R] complex64) in the caller's free scratch
   float2 *phiT = (float2 *)scratch;
-  k_transpose_c64<<<dim3(cdiv(g.nact, 32), 3 * cdiv(R, 32)), 256, 0, st>>>(phi, phiT, R, g.N, g.nact, g.act);
+  k_transpose_c64<<<dim3(cdiv(g.nact, 64), 3 * cdiv(R, 32)), 256, 0, st>>>(phi, phiT, R, g.N, g.nact, g.act);
   if (g.nig > 0) k_interp_grp<<<(unsigned)g.nig * cdiv(R, 64), 192, 0, st>>>(g, phiT, U, R);
 }
 
